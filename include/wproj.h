@@ -1,0 +1,163 @@
+/*
+ * wproj.h -- C ABI of the sparse w-projection measurement operator for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Operator (Wolz et al. 2013, Section 3, Eq. 8, generalised to continuous
+ * (u, v) with a Kaiser-Bessel gridding window):
+ *
+ *     Phi   = G F Z A          y = Phi x          (visibilities from an image)
+ *     Phi^H = A Z^H F^H G^H    x = Phi^H y        (adjoint, Section 3.1: solvers
+ *                                                  need only Phi and its adjoint)
+ *
+ *   A    apodisation: a_phys(l, m) / (g(xi_l) g(xi_m)), g = FT of the KB window
+ *   Z    zero-padding of the N x N image to the Ng x Ng grid, Ng = 2N (the
+ *        upsampling U of Eq. 6, done in the image domain)
+ *   F    centred, unnormalised 2-D DFT; F^H is the unnormalised inverse
+ *   G    sparse matrix, one row per visibility (the mask M folded into the
+ *        rows, Eq. 8): the visibility's KB taps convolved with the Fourier
+ *        transform of its own w-chirp (Section 3.1), thresholded per row to
+ *        keep a fraction E of the row energy (Section 3.2).
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Pointers named "device" are HIP device memory owned by the caller; the
+ *    library never frees them.  Host pointers are named so.
+ *  - Complex values are interleaved float pairs (re, im) ("c64").
+ *  - Images are N x N, row-major, indexed [m][l] (row along v / m, column
+ *    along u / l); pixel p sits at (p - N/2) * L / N.
+ *  - The uv grid is Ng x Ng row-major, flattened index q_v * Ng + q_u; cell q
+ *    is at u = (q - Ng/2) / (2L) wavelengths.
+ *  - Visibility coordinates u, v, w are float64, in wavelengths, in the
+ *    caller's order; y is always in the caller's order.  Internally G's rows
+ *    are sorted by uv tile; G.perm maps sorted row r to caller index perm[r].
+ *  - Every call is enqueued on the given HIP stream (NULL = default stream)
+ *    and is asynchronous unless its comment says it synchronises.
+ *  - No call throws or aborts.  Arguments are validated before any launch;
+ *    on failure nothing is launched, a status < 0 is returned and
+ *    wp_last_error() gives a message (thread-local).
+ *  - N must be a power of two, 32 <= N <= 2048 (Ng <= 4096).
+ */
+#ifndef WPROJ_H
+#define WPROJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum wp_status {
+    WP_OK = 0,
+    WP_EINVAL = -1,        /* bad argument (shape, range, NaN, null pointer)      */
+    WP_ENOMEM = -2,        /* a library-owned table could not be allocated         */
+    WP_EHIP = -3,          /* a HIP runtime call or kernel launch failed           */
+    WP_ECAPACITY = -4,     /* a caller buffer or a count exceeds what is supported */
+    WP_EUNSUPPORTED = -5   /* valid request this build does not implement          */
+} wp_status;
+
+enum { WP_CHIRP_LINEAR = 0,   /* exp(+i pi w (l^2+m^2)): first order of Eq. 4 (the paper's Eq. 5) */
+       WP_CHIRP_EXACT = 1 };  /* exp(-2 pi i w (sqrt(1-l^2-m^2) - 1)) (Eq. 4)                    */
+enum { WP_TAPS_C64 = 0,       /* G values as complex float32 (8 bytes)                          */
+       WP_TAPS_BF16 = 1 };    /* G values as a (re, im) pair of bfloat16 (4 bytes), FP32 accumulate */
+enum { WP_APHYS_ONE = 0,      /* primary beam absorbed into the sky (Section 2.1)               */
+       WP_APHYS_INV_N = 1 };  /* the 1/n(l, m) factor of Eq. 1                                 */
+
+typedef struct wp_plan wp_plan;   /* opaque: geometry plus small device tables */
+
+/* Sparse G in CSR form.  All arrays are caller-owned device memory. */
+typedef struct wp_G {
+    int64_t  M;        /* rows = visibilities                                        */
+    int64_t  nnz;      /* stored taps                                                */
+    int32_t  taps;     /* WP_TAPS_C64 or WP_TAPS_BF16                                */
+    int32_t  pad_;
+    int64_t *rowptr;   /* [M+1] device, sorted-row order, rowptr[0] = 0              */
+    int32_t *col;      /* [nnz] device, flattened grid index, ascending in a row    */
+    void    *val;      /* [nnz] device, c64 or bf16 pairs                            */
+    int32_t *perm;     /* [M]   device, sorted row r is visibility perm[r]           */
+    int32_t *work;     /* [4*n_work] device, adjoint work items (tile_v, tile_u, row_begin, row_end) */
+    int64_t  n_work;
+} wp_G;
+
+/* Last error message of this thread ("" if none). */
+const char *wp_last_error(void);
+
+/* Library version string. */
+const char *wp_version(void);
+
+/*
+ * Plan: geometry and small device tables (apodisation factors, FFT twiddles).
+ *   N        image side (power of two, 32..2048); Ng = 2N
+ *   fov_L    planar field of view L = 2 sin(theta/2) (Section 4.1), 0 < L < 1
+ *   kb_W     KB support in grid cells, even, 2..16
+ *   kb_beta  KB shape; <= 0 selects beta = pi sqrt((W/2)^2 (3/2)^2 - 0.8)
+ *   chirp    WP_CHIRP_LINEAR or WP_CHIRP_EXACT
+ *   aphys    WP_APHYS_ONE or WP_APHYS_INV_N
+ * Allocates the tables on the current device; synchronises.
+ */
+wp_status wp_plan_create(wp_plan **out, int N, double fov_L, int kb_W, double kb_beta,
+                         int chirp, int aphys);
+wp_status wp_plan_destroy(wp_plan *plan);
+
+/* Ng and the bytes of the Ng x Ng c64 grid workspace every apply needs. */
+wp_status wp_plan_info(const wp_plan *plan, int64_t *Ng_out, int64_t *grid_bytes_out);
+
+/* Bytes of device workspace wp_build_G_count / wp_build_G_fill need for M visibilities. */
+wp_status wp_build_workspace_bytes(const wp_plan *plan, int64_t M, int64_t *bytes_out);
+
+/*
+ * Build G, pass 1 of 2 (Section 3.1 kernel rows, Section 3.2 energy
+ * threshold).  For each visibility: chirp of its w on the padded grid (FP64
+ * phase), 1-D chirp spectrum, KB convolution, per-row threshold tau found by
+ * bisection on the bit pattern of the row energies so that the kept entries
+ * hold a fraction E of the row energy (ties kept; E >= 1 keeps every
+ * non-zero entry); rows are then sorted by uv tile and their offsets
+ * scanned.
+ *   u, v, w    [M] device float64 in wavelengths; |u|, |v| < B = N/(2L), w finite
+ *   E          preserved energy fraction, 0 < E <= 1
+ *   workspace  device, wp_build_workspace_bytes(M) bytes, kept until pass 2
+ *   nnz_out    host: total taps; n_work_out host: adjoint work items
+ * Synchronises the stream (reads back two counts).  The linear chirp only;
+ * WP_CHIRP_EXACT returns WP_EUNSUPPORTED.
+ */
+wp_status wp_build_G_count(const wp_plan *plan, int64_t M, const double *u, const double *v,
+                           const double *w, double E, void *workspace,
+                           int64_t *nnz_out, int64_t *n_work_out, void *stream);
+
+/*
+ * Build G, pass 2 of 2: writes G->rowptr, G->perm, G->col, G->val, G->work.
+ * The caller sets G->M = M, G->nnz and G->n_work from pass 1, G->taps, and
+ * points the arrays at buffers of the sizes listed in wp_G.  Same u, v, w, E
+ * and workspace as pass 1.
+ */
+wp_status wp_build_G_fill(const wp_plan *plan, int64_t M, const double *u, const double *v,
+                          const double *w, double E, const void *workspace, wp_G *G,
+                          void *stream);
+
+/*
+ * y = Phi x  (Eq. 8 with the gridding window).
+ *   x     [N*N] c64 device          y [M] c64 device (caller order)
+ *   grid  device workspace of wp_plan_info's grid_bytes (contents overwritten)
+ */
+wp_status wp_apply_Phi(const wp_plan *plan, const wp_G *G, const void *x, void *y, void *grid,
+                       void *stream);
+
+/* x = Phi^H y  (the adjoint; x is overwritten). */
+wp_status wp_apply_PhiT(const wp_plan *plan, const wp_G *G, const void *y, void *x, void *grid,
+                        void *stream);
+
+/* Sub-steps of the two applies, exposed for testing and composition. */
+/* grid = F Z A x */
+wp_status wp_grid_forward(const wp_plan *plan, const void *x, void *grid, void *stream);
+/* x = A Z^H F^H grid  (grid is used as scratch and overwritten) */
+wp_status wp_grid_adjoint(const wp_plan *plan, void *grid, void *x, void *stream);
+/* y = G grid (degridding sparse matrix-vector product) */
+wp_status wp_degrid(const wp_plan *plan, const wp_G *G, const void *grid, void *y, void *stream);
+/* grid = G^H y (gridding: tile-binned scatter, LDS accumulation, atomics at tile borders) */
+wp_status wp_grid_scatter(const wp_plan *plan, const wp_G *G, const void *y, void *grid,
+                          void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WPROJ_H */

@@ -1,0 +1,198 @@
+"""Sparse w-projection measurement operator on MI355X (gfx950).
+
+Python face of libwproj.so (include/wproj.h): the same entry points, taking
+torch tensors for device memory and the current torch stream.  No arithmetic
+happens here.
+
+    plan = Plan(N, L)                      # geometry + device tables
+    G = build_G(plan, u, v, w, E)          # sparse w-projection matrix (two-phase build)
+    y = apply_Phi(plan, G, x)              # y = G F Z A x
+    x = apply_PhiT(plan, G, y)             # x = A Z^H F^H G^H y
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+from . import _lib
+from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR, WP_TAPS_BF16,
+                   WP_TAPS_C64, WprojError, check, load)
+
+__all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
+           "degrid", "grid_scatter", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16",
+           "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(0)
+
+
+def _dev_c64(t, n, name):
+    torch = _torch()
+    if t.dtype != torch.complex64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous complex64 CUDA tensor with {n} elements")
+    return t
+
+
+def _dev_f64(t, n, name):
+    torch = _torch()
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous float64 CUDA tensor with {n} elements")
+    return t
+
+
+class Plan:
+    """wp_plan_create / wp_plan_destroy."""
+
+    def __init__(self, N: int, fov_L: float, kb_W: int = 4, kb_beta: float = 0.0,
+                 chirp: int = WP_CHIRP_LINEAR, aphys: int = WP_APHYS_ONE):
+        lib = load()
+        h = C.c_void_p()
+        check(lib.wp_plan_create(C.byref(h), int(N), float(fov_L), int(kb_W), float(kb_beta),
+                                 int(chirp), int(aphys)), "wp_plan_create")
+        self._h = h
+        self.N = int(N)
+        ng, gb = C.c_int64(), C.c_int64()
+        check(lib.wp_plan_info(h, C.byref(ng), C.byref(gb)), "wp_plan_info")
+        self.Ng = ng.value
+        self.grid_bytes = gb.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def new_grid(self):
+        torch = _torch()
+        return torch.empty(self.Ng * self.Ng, dtype=torch.complex64, device="cuda")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().wp_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class GMatrix:
+    """CSR buffers of G (torch device tensors) and the wp_G descriptor pointing at them."""
+    M: int
+    nnz: int
+    taps: int
+    rowptr: object
+    col: object
+    val: object
+    perm: object
+    work: object
+    n_work: int
+
+    def desc(self) -> _lib.WpG:
+        d = _lib.WpG()
+        d.M, d.nnz, d.taps, d.n_work = self.M, self.nnz, self.taps, self.n_work
+        d.rowptr, d.col, d.val = self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr()
+        d.perm, d.work = self.perm.data_ptr(), self.work.data_ptr()
+        return d
+
+    def nbytes(self) -> int:
+        return sum(t.numel() * t.element_size() for t in (self.rowptr, self.col, self.val, self.perm, self.work))
+
+
+def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, stream=None) -> GMatrix:
+    """wp_build_workspace_bytes + wp_build_G_count + wp_build_G_fill (u, v, w: float64 CUDA tensors)."""
+    torch = _torch()
+    lib = load()
+    M = int(u.numel())
+    for t, nm in ((u, "u"), (v, "v"), (w, "w")):
+        _dev_f64(t, M, nm)
+    s = _stream(stream)
+    wsb = C.c_int64()
+    check(lib.wp_build_workspace_bytes(plan.handle, M, C.byref(wsb)), "wp_build_workspace_bytes")
+    ws = torch.empty(wsb.value, dtype=torch.uint8, device="cuda")
+    nnz, nwork = C.c_int64(), C.c_int64()
+    check(lib.wp_build_G_count(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws),
+                               C.byref(nnz), C.byref(nwork), s), "wp_build_G_count")
+    dev = u.device
+    G = GMatrix(M=M, nnz=nnz.value, taps=int(taps),
+                rowptr=torch.empty(M + 1, dtype=torch.int64, device=dev),
+                col=torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev),
+                val=torch.empty(max(nnz.value, 1), dtype=(torch.complex64 if taps == WP_TAPS_C64 else torch.int32),
+                                device=dev),
+                perm=torch.empty(M, dtype=torch.int32, device=dev),
+                work=torch.empty(4 * max(nwork.value, 1), dtype=torch.int32, device=dev),
+                n_work=nwork.value)
+    d = G.desc()
+    check(lib.wp_build_G_fill(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws), C.byref(d), s),
+          "wp_build_G_fill")
+    G._ws = ws          # keep the workspace alive until the stream has consumed it
+    return G
+
+
+def apply_Phi(plan: Plan, G: GMatrix, x, y=None, grid=None, stream=None):
+    torch = _torch()
+    _dev_c64(x, plan.N * plan.N, "x")
+    y = torch.empty(G.M, dtype=torch.complex64, device=x.device) if y is None else _dev_c64(y, G.M, "y")
+    grid = plan.new_grid() if grid is None else grid
+    d = G.desc()
+    check(load().wp_apply_Phi(plan.handle, C.byref(d), _ptr(x), _ptr(y), _ptr(grid), _stream(stream)),
+          "wp_apply_Phi")
+    return y
+
+
+def apply_PhiT(plan: Plan, G: GMatrix, y, x=None, grid=None, stream=None):
+    torch = _torch()
+    _dev_c64(y, G.M, "y")
+    x = torch.empty(plan.N * plan.N, dtype=torch.complex64, device=y.device) if x is None else \
+        _dev_c64(x, plan.N * plan.N, "x")
+    grid = plan.new_grid() if grid is None else grid
+    d = G.desc()
+    check(load().wp_apply_PhiT(plan.handle, C.byref(d), _ptr(y), _ptr(x), _ptr(grid), _stream(stream)),
+          "wp_apply_PhiT")
+    return x
+
+
+def grid_forward(plan: Plan, x, grid=None, stream=None):
+    _dev_c64(x, plan.N * plan.N, "x")
+    grid = plan.new_grid() if grid is None else grid
+    check(load().wp_grid_forward(plan.handle, _ptr(x), _ptr(grid), _stream(stream)), "wp_grid_forward")
+    return grid
+
+
+def grid_adjoint(plan: Plan, grid, x=None, stream=None):
+    torch = _torch()
+    _dev_c64(grid, plan.Ng * plan.Ng, "grid")
+    x = torch.empty(plan.N * plan.N, dtype=torch.complex64, device=grid.device) if x is None else x
+    check(load().wp_grid_adjoint(plan.handle, _ptr(grid), _ptr(x), _stream(stream)), "wp_grid_adjoint")
+    return x
+
+
+def degrid(plan: Plan, G: GMatrix, grid, y=None, stream=None):
+    torch = _torch()
+    _dev_c64(grid, plan.Ng * plan.Ng, "grid")
+    y = torch.empty(G.M, dtype=torch.complex64, device=grid.device) if y is None else y
+    d = G.desc()
+    check(load().wp_degrid(plan.handle, C.byref(d), _ptr(grid), _ptr(y), _stream(stream)), "wp_degrid")
+    return y
+
+
+def grid_scatter(plan: Plan, G: GMatrix, y, grid=None, stream=None):
+    _dev_c64(y, G.M, "y")
+    grid = plan.new_grid() if grid is None else grid
+    d = G.desc()
+    check(load().wp_grid_scatter(plan.handle, C.byref(d), _ptr(y), _ptr(grid), _stream(stream)),
+          "wp_grid_scatter")
+    return grid

@@ -1,0 +1,80 @@
+"""ctypes binding of libwproj.so: argument marshalling only.
+
+Every computation happens in the HIP library; this module converts torch
+tensors (device memory, streams) into the plain pointers and sizes of the C
+ABI declared in include/wproj.h, and turns error codes into exceptions.  If
+the library is missing it raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libwproj.so")
+
+WP_CHIRP_LINEAR, WP_CHIRP_EXACT = 0, 1
+WP_TAPS_C64, WP_TAPS_BF16 = 0, 1
+WP_APHYS_ONE, WP_APHYS_INV_N = 0, 1
+
+STATUS = {0: "WP_OK", -1: "WP_EINVAL", -2: "WP_ENOMEM", -3: "WP_EHIP", -4: "WP_ECAPACITY",
+          -5: "WP_EUNSUPPORTED"}
+
+# every entry point declared in include/wproj.h, with its argument types
+_vp, _i64, _i32, _d = C.c_void_p, C.c_int64, C.c_int, C.c_double
+_pi64 = C.POINTER(C.c_int64)
+
+
+class WpG(C.Structure):
+    _fields_ = [("M", C.c_int64), ("nnz", C.c_int64), ("taps", C.c_int32), ("pad_", C.c_int32),
+                ("rowptr", _vp), ("col", _vp), ("val", _vp), ("perm", _vp), ("work", _vp),
+                ("n_work", C.c_int64)]
+
+
+_PG = C.POINTER(WpG)
+
+SIGNATURES = {
+    "wp_last_error": ([], C.c_char_p),
+    "wp_version": ([], C.c_char_p),
+    "wp_plan_create": ([C.POINTER(_vp), _i32, _d, _i32, _d, _i32, _i32], _i32),
+    "wp_plan_destroy": ([_vp], _i32),
+    "wp_plan_info": ([_vp, _pi64, _pi64], _i32),
+    "wp_build_workspace_bytes": ([_vp, _i64, _pi64], _i32),
+    "wp_build_G_count": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _pi64, _pi64, _vp], _i32),
+    "wp_build_G_fill": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _PG, _vp], _i32),
+    "wp_apply_Phi": ([_vp, _PG, _vp, _vp, _vp, _vp], _i32),
+    "wp_apply_PhiT": ([_vp, _PG, _vp, _vp, _vp, _vp], _i32),
+    "wp_grid_forward": ([_vp, _vp, _vp, _vp], _i32),
+    "wp_grid_adjoint": ([_vp, _vp, _vp, _vp], _i32),
+    "wp_degrid": ([_vp, _PG, _vp, _vp, _vp], _i32),
+    "wp_grid_scatter": ([_vp, _PG, _vp, _vp, _vp], _i32),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libwproj.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise OSError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
+        lib = C.CDLL(path)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+    return _lib
+
+
+class WprojError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = load().wp_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def check(status: int, where: str):
+    if status != 0:
+        raise WprojError(status, where)

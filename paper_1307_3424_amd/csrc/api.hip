@@ -1,0 +1,229 @@
+// C ABI entry points: validation, plan tables, dispatch to the kernels.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace {
+thread_local char g_err[512] = "";
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int x) {
+    int r = 0;
+    while ((1 << r) < x) ++r;
+    return r;
+}
+
+// KB window Fourier transform, W sinh(sqrt(beta^2 - (pi W xi)^2)) / sqrt(...)
+double kb_transform(double xi, int W, double beta) {
+    const double z = beta * beta - (M_PI * W * xi) * (M_PI * W * xi);
+    if (z > 0) {
+        const double s = std::sqrt(z);
+        return W * std::sinh(s) / s;
+    }
+    if (z < 0) {
+        const double s = std::sqrt(-z);
+        return W * std::sin(s) / s;
+    }
+    return W;
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+wp_status check_plan(const wp_plan *p) {
+    if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
+    return WP_OK;
+}
+
+wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
+    if (!G) return wp_set_error(WP_EINVAL, "G is NULL");
+    if (G->M < 0 || G->M > 0x7fffffff) return wp_set_error(WP_EINVAL, "G->M = %lld out of range", (long long)G->M);
+    if (G->nnz < 0) return wp_set_error(WP_EINVAL, "G->nnz < 0");
+    if (G->taps != WP_TAPS_C64 && G->taps != WP_TAPS_BF16) return wp_set_error(WP_EINVAL, "G->taps = %d", G->taps);
+    if (G->M > 0 && (!G->rowptr || !G->perm || (G->nnz > 0 && (!G->col || !G->val))))
+        return wp_set_error(WP_EINVAL, "G has a NULL array");
+    if (need_work && G->n_work > 0 && !G->work) return wp_set_error(WP_EINVAL, "G->work is NULL");
+    if (need_work && G->n_work > 0x7fffffff) return wp_set_error(WP_ECAPACITY, "G->n_work too large");
+    (void)p;
+    return WP_OK;
+}
+}  // namespace
+
+wp_status wp_set_error(wp_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+wp_status wp_check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return wp_set_error(WP_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return WP_OK;
+}
+
+extern "C" {
+
+const char *wp_last_error(void) { return g_err; }
+
+const char *wp_version(void) { return "wproj 0.1 gfx950"; }
+
+wp_status wp_plan_create(wp_plan **out, int N, double fov_L, int kb_W, double kb_beta, int chirp, int aphys) {
+    if (!out) return wp_set_error(WP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!is_pow2(N) || N < 32 || N > 2048) return wp_set_error(WP_EINVAL, "N = %d: need a power of two in [32, 2048]", N);
+    if (!(fov_L > 0.0 && fov_L < 1.0)) return wp_set_error(WP_EINVAL, "fov_L = %g: need 0 < L < 1", fov_L);
+    if (kb_W < 2 || kb_W > 16 || (kb_W & 1)) return wp_set_error(WP_EINVAL, "kb_W = %d: need an even value in [2, 16]", kb_W);
+    if (chirp != WP_CHIRP_LINEAR && chirp != WP_CHIRP_EXACT) return wp_set_error(WP_EINVAL, "chirp = %d", chirp);
+    if (aphys != WP_APHYS_ONE && aphys != WP_APHYS_INV_N) return wp_set_error(WP_EINVAL, "aphys = %d", aphys);
+    if (!std::isfinite(kb_beta)) return wp_set_error(WP_EINVAL, "kb_beta is not finite");
+    wp_plan *p = new (std::nothrow) wp_plan();
+    if (!p) return wp_set_error(WP_ENOMEM, "plan allocation");
+    p->N = N;
+    p->Ng = 2 * N;
+    p->logNg = ilog2(p->Ng);
+    p->W = kb_W;
+    p->chirp = chirp;
+    p->aphys = aphys;
+    p->L = fov_L;
+    p->beta = kb_beta > 0 ? kb_beta : M_PI * std::sqrt((kb_W / 2.0) * (kb_W / 2.0) * 1.5 * 1.5 - 0.8);
+    p->delta = fov_L / N;
+    p->cell = 1.0 / (p->Ng * p->delta);
+    p->tile = 32;
+    p->halo = 16;
+    p->ntile = p->Ng / p->tile;
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        delete p;
+        return wp_set_error(WP_EHIP, "hipGetDevice failed");
+    }
+    // tables, computed in FP64 on the host
+    const int Ng = p->Ng;
+    float *apod = (float *)std::malloc(sizeof(float) * N);
+    float2 *tw32 = (float2 *)std::malloc(sizeof(float2) * Ng);
+    double2 *tw64 = (double2 *)std::malloc(sizeof(double2) * Ng);
+    if (!apod || !tw32 || !tw64) {
+        std::free(apod); std::free(tw32); std::free(tw64);
+        delete p;
+        return wp_set_error(WP_ENOMEM, "plan tables");
+    }
+    for (int i = 0; i < N; ++i) apod[i] = (float)(1.0 / kb_transform((i - N / 2) / (double)Ng, kb_W, p->beta));
+    for (int k = 0; k < Ng; ++k) {
+        // exp(-2 pi i k / Ng), argument reduced through the exact ratio k / Ng
+        const double a = 2.0 * M_PI * (double)k / (double)Ng;
+        tw64[k] = make_double2(std::cos(a), -std::sin(a));
+        tw32[k] = make_float2((float)tw64[k].x, (float)tw64[k].y);
+    }
+    hipError_t e = hipMalloc(&p->apod, sizeof(float) * N);
+    if (e == hipSuccess) e = hipMalloc(&p->tw32, sizeof(float2) * Ng);
+    if (e == hipSuccess) e = hipMalloc(&p->tw64, sizeof(double2) * Ng);
+    if (e == hipSuccess) e = hipMemcpy(p->apod, apod, sizeof(float) * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->tw32, tw32, sizeof(float2) * Ng, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p->tw64, tw64, sizeof(double2) * Ng, hipMemcpyHostToDevice);
+    std::free(apod); std::free(tw32); std::free(tw64);
+    if (e != hipSuccess) {
+        wp_plan_destroy(p);
+        return wp_set_error(e == hipErrorOutOfMemory ? WP_ENOMEM : WP_EHIP, "plan tables: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return WP_OK;
+}
+
+wp_status wp_plan_destroy(wp_plan *p) {
+    if (!p) return WP_OK;
+    if (p->apod) (void)hipFree(p->apod);
+    if (p->tw32) (void)hipFree(p->tw32);
+    if (p->tw64) (void)hipFree(p->tw64);
+    delete p;
+    return WP_OK;
+}
+
+wp_status wp_plan_info(const wp_plan *p, int64_t *Ng_out, int64_t *grid_bytes_out) {
+    if (wp_status s = check_plan(p)) return s;
+    if (Ng_out) *Ng_out = p->Ng;
+    if (grid_bytes_out) *grid_bytes_out = (int64_t)p->Ng * p->Ng * 8;
+    return WP_OK;
+}
+
+wp_status wp_build_workspace_bytes(const wp_plan *p, int64_t M, int64_t *bytes) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!bytes) return wp_set_error(WP_EINVAL, "bytes_out is NULL");
+    if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    *bytes = builder_workspace_bytes(p, M);
+    return WP_OK;
+}
+
+wp_status wp_build_G_count(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
+                           void *ws, int64_t *nnz_out, int64_t *n_work_out, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    if (!u || !v || !w || !ws || !nnz_out || !n_work_out) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
+    if (p->chirp != WP_CHIRP_LINEAR)
+        return wp_set_error(WP_EUNSUPPORTED, "build: only the linear chirp (separable rows) is built on the GPU");
+    return launch_build_count(p, M, u, v, w, E, ws, nnz_out, n_work_out, as_stream(stream));
+}
+
+wp_status wp_build_G_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
+                          const void *ws, wp_G *G, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    if (!u || !v || !w || !ws) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
+    if (p->chirp != WP_CHIRP_LINEAR)
+        return wp_set_error(WP_EUNSUPPORTED, "build: only the linear chirp (separable rows) is built on the GPU");
+    if (wp_status s = check_G(p, G, true)) return s;
+    if (G->M != M) return wp_set_error(WP_EINVAL, "G->M = %lld differs from M = %lld", (long long)G->M, (long long)M);
+    return launch_build_fill(p, M, u, v, w, E, ws, G, as_stream(stream));
+}
+
+wp_status wp_grid_forward(const wp_plan *p, const void *x, void *grid, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!x || !grid) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_grid_forward(p, (const float2 *)x, (float2 *)grid, as_stream(stream));
+}
+
+wp_status wp_grid_adjoint(const wp_plan *p, void *grid, void *x, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!x || !grid) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_grid_adjoint(p, (float2 *)grid, (float2 *)x, as_stream(stream));
+}
+
+wp_status wp_degrid(const wp_plan *p, const wp_G *G, const void *grid, void *y, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, false)) return s;
+    if (!grid || (G->M > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_degrid(p, G, (const float2 *)grid, (float2 *)y, as_stream(stream));
+}
+
+wp_status wp_grid_scatter(const wp_plan *p, const wp_G *G, const void *y, void *grid, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, true)) return s;
+    if (!grid || (G->M > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_scatter(p, G, (const float2 *)y, (float2 *)grid, as_stream(stream));
+}
+
+wp_status wp_apply_Phi(const wp_plan *p, const wp_G *G, const void *x, void *y, void *grid, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, false)) return s;
+    if (!x || !grid || (G->M > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    if (wp_status st = launch_grid_forward(p, (const float2 *)x, (float2 *)grid, s)) return st;
+    return launch_degrid(p, G, (const float2 *)grid, (float2 *)y, s);
+}
+
+wp_status wp_apply_PhiT(const wp_plan *p, const wp_G *G, const void *y, void *x, void *grid, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, true)) return s;
+    if (!x || !grid || (G->M > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    hipStream_t s = as_stream(stream);
+    if (wp_status st = launch_scatter(p, G, (const float2 *)y, (float2 *)grid, s)) return st;
+    return launch_grid_adjoint(p, (float2 *)grid, (float2 *)x, s);
+}
+
+}  // extern "C"

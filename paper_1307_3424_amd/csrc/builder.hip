@@ -1,0 +1,712 @@
+// Builder of the sparse w-projection matrix G (Sections 3.1 and 3.2).
+//
+// Row k of G, for a visibility at grid coordinates (u~, v~) with component w:
+//   1. chirp exp(i pi w l^2) sampled on the padded grid, l = t delta,
+//      t in [-Ng/2, Ng/2); phase argument w delta^2 t^2 in FP64 (sincospi);
+//   2. its 1-D spectrum h(d) = Ng^-1 sum_t c(t) exp(-2 pi i t d / Ng) (FP64 FFT
+//      in LDS).  The linear chirp and the KB window are both separable, so the
+//      2-D row is g(q_v, q_u) = g_v(q_v) g_u(q_u) exactly, with
+//   3. g_u(q) = sum_i KB(u~ - q'_i) h((q'_i - q) mod Ng) over the W window cells
+//      q'_i (u~ - q'_i in [-W/2, W/2)), KB(t) = I0(beta sqrt(1 - (2t/W)^2));
+//   4. energies A_a = |g_u(a)|^2, B_b = |g_v(b)|^2; a tap's energy is A_a B_b.
+//      Threshold tau = the largest value with K(tau) >= E T, where K(tau) sums
+//      the tap energies >= tau and T = K(0) (Section 3.2: keep a fraction E of
+//      the row energy).  tau is found by bisection on the IEEE-754 bit pattern
+//      of non-negative doubles (monotone), 64 steps at most; with B sorted
+//      descending and its prefix sums, K(tau) = sum_a A_a PB[#{b: A_a B_b >= tau}]
+//      costs O(Ng log Ng).  The bisection converges to a tap energy, so the kept
+//      set {A_a B_b >= tau} (ties kept) is the sort-defined set.  E >= 1 keeps
+//      every non-zero tap.
+//   5. CSR: rows are sorted by uv tile (stable radix sort of the tile id made of
+//      1-bit stable partitions), row lengths are scanned into int64 offsets,
+//      and the fill pass writes each row's taps in ascending flattened column
+//      q_v Ng + q_u, values g_v g_u rounded to complex float32 (or bf16 pairs).
+// Pass 1 (count) computes tau, row lengths, the tile sort, the offsets and the
+// adjoint work list sizes; pass 2 (fill) recomputes the row factors and writes
+// the taps.
+#include <cfloat>
+#include <cstdio>
+
+#include "fft_lds.h"
+
+namespace {
+
+constexpr int BNTH = 256;      // builder block size
+constexpr int ROWS_PER_ITEM = 32;
+
+// ---------------------------------------------------------------------------- small device helpers
+
+__device__ inline double bessel_i0(double x) {
+    // power series sum_k ((x/2)^2)^k / (k!)^2
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 200; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+__device__ inline double kb_weight(double t, int W, double beta) {
+    const double r = 1.0 - (2.0 * t / W) * (2.0 * t / W);
+    return r >= 0.0 ? bessel_i0(beta * sqrt(r)) : 0.0;
+}
+
+struct Taps {
+    int q0;              // grid index (may be < 0 or >= Ng: taken mod Ng) of the first window cell
+    const double *wt;    // W window weights (LDS)
+};
+
+// Window cells and weights of one axis; the weights go to LDS (wt_lds[W]), written by the first W threads.
+__device__ inline Taps kb_taps(double gt, int W, double beta, int Ng, double *wt_lds) {
+    const int base = (int)floor(gt) - W / 2 + 1;     // centred index of the first cell
+    if ((int)threadIdx.x < W) wt_lds[threadIdx.x] = kb_weight(gt - (double)(base + (int)threadIdx.x), W, beta);
+    Taps t;
+    t.q0 = base + Ng / 2;
+    t.wt = wt_lds;
+    return t;
+}
+
+// g(q) = Ng^-1 sum_i wt_i h((q0 + i - q) mod Ng)
+__device__ inline double2 row_factor(const double2 *h, const Taps &t, int W, int q, int Ng) {
+    double2 g = make_double2(0.0, 0.0);
+    for (int i = 0; i < W; ++i) {
+        const double2 hv = h[(t.q0 + i - q) & (Ng - 1)];
+        g.x += t.wt[i] * hv.x;
+        g.y += t.wt[i] * hv.y;
+    }
+    const double s = 1.0 / Ng;
+    return make_double2(g.x * s, g.y * s);
+}
+
+template <typename T>
+__device__ inline T block_sum(T v, T *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    T s = 0;
+    for (int i = 0; i < BNTH / 64; ++i) s += red[i];
+    return s;
+}
+
+__device__ inline double block_max(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < BNTH / 64; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+// exclusive scan of one int per thread over the block; returns the total
+__device__ inline int block_excl_scan(int v, int *red, int &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) red[wid] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < BNTH / 64; ++i) {
+        if (i < wid) off += red[i];
+        tot += red[i];
+    }
+    total = tot;
+    return off + x - v;
+}
+
+// Row setup shared by both passes: chirp, FFT, window taps.  h must hold Ng double2.
+template <int LOGNG>
+__device__ inline void chirp_spectrum(double2 *h, double wk, double delta, const double2 *tw64) {
+    constexpr int Ng = 1 << LOGNG;
+    const double a = wk * delta * delta;
+    for (int i = threadIdx.x; i < Ng; i += BNTH) {
+        const double t = (double)(i < Ng / 2 ? i : i - Ng);
+        double sn, cs;
+        sincospi(a * t * t, &sn, &cs);       // exp(i pi w delta^2 t^2)
+        h[i] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    lds_fft<double2, LOGNG, 1, BNTH, true, Ng>(h, tw64, false, threadIdx.x);
+}
+
+// K(tau): energy and count of taps with A_a B_b >= tau.  Bs sorted descending,
+// PB[i] = sum of the first i entries of Bs.
+template <int LOGNG>
+__device__ inline void kept_energy(const double *A, const double *Bs, const double *PB, double tau,
+                                   double &K, long long &cnt, double *redd, long long *redl) {
+    constexpr int Ng = 1 << LOGNG;
+    double k = 0.0;
+    long long c = 0;
+    for (int a = threadIdx.x; a < Ng; a += BNTH) {
+        const double Aa = A[a];
+        if (!(Aa * Bs[0] >= tau)) continue;
+        int lo = 1, hi = Ng;                 // largest n with Aa * Bs[n-1] >= tau
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (Aa * Bs[mid - 1] >= tau) lo = mid; else hi = mid - 1;
+        }
+        k += Aa * PB[lo];
+        c += lo;
+    }
+    K = block_sum(k, redd);
+    cnt = block_sum(c, redl);
+}
+
+// ---------------------------------------------------------------------------- pass 1: threshold and count
+
+template <int LOGNG>
+__global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u, const double *__restrict__ v,
+                                                    const double *__restrict__ w, int64_t M, double E,
+                                                    double cell, double delta, int W, double beta, int tile,
+                                                    int ntile, const double2 *__restrict__ tw64,
+                                                    double *__restrict__ tau_out, int *__restrict__ nnz_out,
+                                                    int *__restrict__ key_out, int *__restrict__ err) {
+    constexpr int Ng = 1 << LOGNG;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *h = (double2 *)smem;                 // Ng double2, later PB (Ng+1 doubles)
+    double *A = (double *)(smem + 16 * Ng);       // Ng
+    double *B = A + Ng;                           // Ng (sorted descending in place)
+    double *PB = (double *)smem;
+    __shared__ double redd[BNTH / 64];
+    __shared__ long long redl[BNTH / 64];
+    __shared__ int redi[BNTH / 64];
+    __shared__ double s_wu[16], s_wv[16];
+
+    const int64_t k = blockIdx.x;
+    const double ut = u[k] / cell, vt = v[k] / cell, wk = w[k];
+    const bool ok = isfinite(ut) && isfinite(vt) && isfinite(wk) && fabs(ut) < Ng / 2 && fabs(vt) < Ng / 2;
+    if (!ok) {
+        if (threadIdx.x == 0) {
+            atomicOr(err, 1);
+            tau_out[k] = INFINITY;
+            nnz_out[k] = 0;
+            key_out[k] = 0;
+        }
+        return;
+    }
+    const Taps tu = kb_taps(ut, W, beta, Ng, s_wu);
+    const Taps tv = kb_taps(vt, W, beta, Ng, s_wv);
+    chirp_spectrum<LOGNG>(h, wk, delta, tw64);        // ends with a barrier: the weights are visible
+    for (int q = threadIdx.x; q < Ng; q += BNTH) {
+        const double2 gu = row_factor(h, tu, W, q, Ng);
+        const double2 gv = row_factor(h, tv, W, q, Ng);
+        A[q] = gu.x * gu.x + gu.y * gu.y;
+        B[q] = gv.x * gv.x + gv.y * gv.y;
+    }
+    __syncthreads();
+    // bitonic sort of B, descending
+    for (int kk = 2; kk <= Ng; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < Ng; i += BNTH) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const double x0 = B[i], x1 = B[ixj];
+                    const bool desc = (i & kk) == 0;
+                    if (desc ? (x0 < x1) : (x0 > x1)) { B[i] = x1; B[ixj] = x0; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // prefix sums of the sorted B (sequential per wave chunk: Ng values, 256 threads)
+    {
+        constexpr int PER = (Ng + BNTH - 1) / BNTH;
+        double loc[PER];
+        double s = 0.0;
+        const int b0 = threadIdx.x * PER;
+        for (int i = 0; i < PER; ++i) {
+            loc[i] = (b0 + i < Ng) ? B[b0 + i] : 0.0;
+            s += loc[i];
+        }
+        // exclusive scan of s across the block (FP64)
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        double x = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            double y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) redd[wid] = x;
+        __syncthreads();
+        double off = 0.0;
+        for (int i = 0; i < wid; ++i) off += redd[i];
+        double run = off + x - s;
+        __syncthreads();
+        for (int i = 0; i < PER; ++i) {
+            if (b0 + i < Ng) PB[b0 + i] = run;
+            run += loc[i];
+        }
+        if (b0 + PER == Ng) PB[Ng] = run;
+        __syncthreads();
+    }
+    double T;
+    long long cnt;
+    kept_energy<LOGNG>(A, B, PB, 0.0, T, cnt, redd, redl);
+    double tau;
+    if (E >= 1.0) {
+        tau = DBL_TRUE_MIN;                        // every non-zero tap
+    } else {
+        double amax = 0.0;
+        for (int a = threadIdx.x; a < Ng; a += BNTH) amax = fmax(amax, A[a]);
+        amax = block_max(amax, redd);
+        const double target = E * T;
+        unsigned long long lo = 0ull;
+        unsigned long long hi = (unsigned long long)__double_as_longlong(amax * B[0]) + 1ull;
+        while (hi - lo > 1ull) {
+            const unsigned long long mid = lo + ((hi - lo) >> 1);
+            double Km;
+            long long cm;
+            kept_energy<LOGNG>(A, B, PB, __longlong_as_double((long long)mid), Km, cm, redd, redl);
+            if (Km >= target) lo = mid; else hi = mid;
+        }
+        tau = __longlong_as_double((long long)lo);
+    }
+    double Kt;
+    kept_energy<LOGNG>(A, B, PB, tau, Kt, cnt, redd, redl);
+    if (threadIdx.x == 0) {
+        tau_out[k] = tau;
+        nnz_out[k] = (int)cnt;
+        int tu_i = (int)floor((ut + Ng / 2) / tile), tv_i = (int)floor((vt + Ng / 2) / tile);
+        tu_i = min(max(tu_i, 0), ntile - 1);
+        tv_i = min(max(tv_i, 0), ntile - 1);
+        key_out[k] = tv_i * ntile + tu_i;
+        (void)redi;
+    }
+}
+
+// ---------------------------------------------------------------------------- pass 2: fill
+
+template <int LOGNG, bool BF16>
+__global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u, const double *__restrict__ v,
+                                                   const double *__restrict__ w, int64_t M,
+                                                   double cell, double delta, int W, double beta,
+                                                   const double2 *__restrict__ tw64, const double *__restrict__ tau_in,
+                                                   const int *__restrict__ perm, const int64_t *__restrict__ rowptr,
+                                                   int *__restrict__ col, void *__restrict__ val, int *__restrict__ err) {
+    constexpr int Ng = 1 << LOGNG;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double2 *h = (double2 *)smem;                 // Ng
+    double *A = (double *)(smem + 16 * Ng);       // Ng
+    double *B = A + Ng;                           // Ng
+    int *ca = (int *)(B + Ng);                    // Ng candidate columns (u)
+    int *cb = ca + Ng;                            // Ng candidate rows (v)
+    int *off = cb + Ng;                           // Ng per-candidate-row output offsets
+    __shared__ double redd[BNTH / 64];
+    __shared__ int redi[BNTH / 64];
+    __shared__ int s_nca, s_ncb;
+    __shared__ double s_wu[16], s_wv[16];
+
+    const int64_t r = blockIdx.x;
+    const int k = perm[r];
+    const double tau = tau_in[k];
+    const int64_t beg = rowptr[r], len = rowptr[r + 1] - beg;
+    if (len == 0) return;
+    const double ut = u[k] / cell, vt = v[k] / cell, wk = w[k];
+    const Taps tu = kb_taps(ut, W, beta, Ng, s_wu);
+    const Taps tv = kb_taps(vt, W, beta, Ng, s_wv);
+    chirp_spectrum<LOGNG>(h, wk, delta, tw64);        // ends with a barrier: the weights are visible
+    double amax = 0.0, bmax = 0.0;
+    for (int q = threadIdx.x; q < Ng; q += BNTH) {
+        const double2 gu = row_factor(h, tu, W, q, Ng);
+        const double2 gv = row_factor(h, tv, W, q, Ng);
+        A[q] = gu.x * gu.x + gu.y * gu.y;
+        B[q] = gv.x * gv.x + gv.y * gv.y;
+        amax = fmax(amax, A[q]);
+        bmax = fmax(bmax, B[q]);
+    }
+    amax = block_max(amax, redd);
+    bmax = block_max(bmax, redd);
+    // candidate compaction (ascending index); a kept tap needs A_a bmax >= tau and amax B_b >= tau
+    {
+        int na = 0, nb = 0;
+        constexpr int PER = (Ng + BNTH - 1) / BNTH;
+        const int q0 = threadIdx.x * PER;
+        for (int i = 0; i < PER; ++i) {
+            const int q = q0 + i;
+            if (q < Ng) {
+                na += (A[q] * bmax >= tau);
+                nb += (amax * B[q] >= tau);
+            }
+        }
+        int ta, tb;
+        int oa = block_excl_scan(na, redi, ta);
+        int ob = block_excl_scan(nb, redi, tb);
+        for (int i = 0; i < PER; ++i) {
+            const int q = q0 + i;
+            if (q < Ng) {
+                if (A[q] * bmax >= tau) ca[oa++] = q;
+                if (amax * B[q] >= tau) cb[ob++] = q;
+            }
+        }
+        if (threadIdx.x == 0) { s_nca = ta; s_ncb = tb; }
+        __syncthreads();
+    }
+    const int nca = s_nca, ncb = s_ncb;
+    // kept taps per candidate row, then offsets
+    {
+        constexpr int PER = (Ng + BNTH - 1) / BNTH;
+        int cntl[PER];
+        int tot = 0;
+        for (int i = 0; i < PER; ++i) {
+            const int ib = threadIdx.x * PER + i;
+            int c = 0;
+            if (ib < ncb) {
+                const double Bb = B[cb[ib]];
+                for (int ia = 0; ia < nca; ++ia) c += (A[ca[ia]] * Bb >= tau);
+            }
+            cntl[i] = c;
+            tot += c;
+        }
+        int total;
+        int o = block_excl_scan(tot, redi, total);
+        for (int i = 0; i < PER; ++i) {
+            const int ib = threadIdx.x * PER + i;
+            if (ib < ncb) off[ib] = o;
+            o += cntl[i];
+        }
+        if (threadIdx.x == 0 && total != len) atomicOr(err, 2);
+        __syncthreads();
+    }
+    // emit: one wave per candidate row, ballot-compacted, ascending a
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int ib = wid; ib < ncb; ib += BNTH / 64) {
+        const int b = cb[ib];
+        const double Bb = B[b];
+        const double2 gv = row_factor(h, tv, W, b, Ng);
+        int64_t pos = beg + off[ib];
+        for (int ia0 = 0; ia0 < nca; ia0 += 64) {
+            const int ia = ia0 + lane;
+            int a = 0;
+            bool keep = false;
+            if (ia < nca) {
+                a = ca[ia];
+                keep = A[a] * Bb >= tau;
+            }
+            const unsigned long long m = __ballot(keep);
+            if (keep) {
+                const int rank = __popcll(m & ((1ull << lane) - 1ull));
+                const double2 gu = row_factor(h, tu, W, a, Ng);
+                const double2 g = cmul(gv, gu);
+                const int64_t p = pos + rank;
+                if (p < beg + len) {
+                    col[p] = b * Ng + a;
+                    if (BF16) ((uint32_t *)val)[p] = pack_bf16x2((float)g.x, (float)g.y);
+                    else ((float2 *)val)[p] = make_float2((float)g.x, (float)g.y);
+                }
+            }
+            pos += __popcll(m);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- device-wide scan
+
+constexpr int SCAN_NTH = 256, SCAN_IPT = 8, SCAN_TILE = SCAN_NTH * SCAN_IPT;
+
+template <typename T>
+__device__ inline T block_excl_scan_T(T v, T *red, T &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) red[wid] = x;
+    __syncthreads();
+    T off = 0, tot = 0;
+    for (int i = 0; i < SCAN_NTH / 64; ++i) {
+        if (i < wid) off += red[i];
+        tot += red[i];
+    }
+    total = tot;
+    return off + x - v;
+}
+
+// out[i] = sum_{j<i} in[j] within each tile of SCAN_TILE; bsum[tile] = tile total
+template <typename Tin, typename T>
+__global__ __launch_bounds__(SCAN_NTH) void k_scan_tiles(const Tin *__restrict__ in, T *__restrict__ out, int64_t n,
+                                                         T *__restrict__ bsum) {
+    __shared__ T red[SCAN_NTH / 64];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x * SCAN_IPT;
+    T loc[SCAN_IPT];
+    T s = 0;
+    for (int i = 0; i < SCAN_IPT; ++i) {
+        loc[i] = (base + i < n) ? (T)in[base + i] : (T)0;
+        s += loc[i];
+    }
+    T total;
+    T run = block_excl_scan_T(s, red, total);
+    for (int i = 0; i < SCAN_IPT; ++i) {
+        if (base + i < n) out[base + i] = run;
+        run += loc[i];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SCAN_NTH) void k_scan_add(T *__restrict__ out, int64_t n, const T *__restrict__ boff) {
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    const T o = boff[blockIdx.x];
+    for (int i = threadIdx.x; i < SCAN_TILE; i += SCAN_NTH)
+        if (base + i < n) out[base + i] += o;
+}
+
+template <typename T>
+__global__ void k_put_total(T *__restrict__ out, int64_t n, const T *__restrict__ bsum_scanned, int64_t nb,
+                            const T *__restrict__ bsum) {
+    // out[n] = exclusive offset of the last tile + its total
+    out[n] = bsum_scanned[nb - 1] + bsum[nb - 1];
+}
+
+int64_t scan_scratch_elems(int64_t n) {
+    int64_t tot = 0;
+    while (true) {
+        int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+        tot += 2 * nb + 2;
+        if (nb <= 1) break;
+        n = nb;
+    }
+    return tot;
+}
+
+// Exclusive scan of n inputs into out[0..n], out[n] = total.  scratch holds scan_scratch_elems(n) T.
+template <typename Tin, typename T>
+void device_scan(const Tin *in, T *out, int64_t n, T *scratch, hipStream_t s) {
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    T *bsum = scratch, *boff = scratch + nb;
+    hipLaunchKernelGGL((k_scan_tiles<Tin, T>), dim3(nb), dim3(SCAN_NTH), 0, s, in, out, n, bsum);
+    if (nb > 1) {
+        device_scan<T, T>(bsum, boff, nb, scratch + 2 * nb + 2, s);
+        hipLaunchKernelGGL((k_scan_add<T>), dim3(nb), dim3(SCAN_NTH), 0, s, out, n, boff);
+    } else {
+        hipMemsetAsync(boff, 0, sizeof(T), s);
+    }
+    hipLaunchKernelGGL((k_put_total<T>), dim3(1), dim3(1), 0, s, out, n, boff, nb, bsum);
+}
+
+// ---------------------------------------------------------------------------- tile sort and layout kernels
+
+__global__ void k_iota_keys(const int *__restrict__ key, int *__restrict__ k0, int *__restrict__ i0, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) { k0[i] = key[i]; i0[i] = (int)i; }
+}
+
+__global__ void k_bit_flags(const int *__restrict__ keys, int bit, int *__restrict__ flags, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < M) flags[i] = ((keys[i] >> bit) & 1) ? 0 : 1;
+}
+
+__global__ void k_split_scatter(const int *__restrict__ kin, const int *__restrict__ iin, const int *__restrict__ zpos,
+                                int *__restrict__ kout, int *__restrict__ iout, int bit, int64_t M) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const int Z = zpos[M];
+    const int k = kin[i];
+    const int d = ((k >> bit) & 1) ? (int)(Z + i - zpos[i]) : zpos[i];
+    kout[d] = k;
+    iout[d] = iin[i];
+}
+
+__global__ void k_gather_nnz(const int *__restrict__ perm, const int *__restrict__ nnz, int64_t *__restrict__ snnz,
+                             int64_t M) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < M) snnz[r] = nnz[perm[r]];
+}
+
+__global__ void k_tile_bounds(const int *__restrict__ skey, int64_t M, int *__restrict__ tstart, int *__restrict__ tend) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    const int k = skey[r];
+    if (r == 0 || skey[r - 1] != k) tstart[k] = (int)r;
+    if (r == M - 1 || skey[r + 1] != k) tend[k] = (int)r + 1;
+}
+
+__global__ void k_tile_chunks(const int *__restrict__ tstart, const int *__restrict__ tend, int T,
+                              int *__restrict__ nchunk) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < T) nchunk[t] = (tend[t] - tstart[t] + ROWS_PER_ITEM - 1) / ROWS_PER_ITEM;
+}
+
+__global__ void k_write_items(const int *__restrict__ tstart, const int *__restrict__ tend,
+                              const int *__restrict__ choff, int T, int ntile, int *__restrict__ work) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const int s = tstart[t], e = tend[t];
+    int it = choff[t];
+    for (int r = s; r < e; r += ROWS_PER_ITEM, ++it) {
+        work[4 * it + 0] = t / ntile;
+        work[4 * it + 1] = t % ntile;
+        work[4 * it + 2] = r;
+        work[4 * it + 3] = min(r + ROWS_PER_ITEM, e);
+    }
+}
+
+inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+struct WsLayout {
+    int64_t tau, nnz, key, k0, k1, i0, i1, flags, zpos, snnz, rowptr, sc32, sc64, tstart, tend, nch, choff, err, total;
+};
+
+WsLayout ws_layout(const wp_plan *p, int64_t M) {
+    const int64_t T = (int64_t)p->ntile * p->ntile;
+    WsLayout L;
+    int64_t o = 0;
+    auto take = [&](int64_t bytes) { int64_t r = o; o += align256(bytes); return r; };
+    L.tau = take(8 * M);
+    L.nnz = take(4 * M);
+    L.key = take(4 * M);
+    L.k0 = take(4 * M);
+    L.k1 = take(4 * M);
+    L.i0 = take(4 * M);
+    L.i1 = take(4 * M);
+    L.flags = take(4 * M);
+    L.zpos = take(4 * (M + 1));
+    L.snnz = take(8 * M);
+    L.rowptr = take(8 * (M + 1));
+    L.sc32 = take(4 * scan_scratch_elems(M > T ? M : T));
+    L.sc64 = take(8 * scan_scratch_elems(M));
+    L.tstart = take(4 * T);
+    L.tend = take(4 * T);
+    L.nch = take(4 * T);
+    L.choff = take(4 * (T + 1));
+    L.err = take(16);
+    L.total = o;
+    return L;
+}
+
+template <int LOGNG>
+size_t count_lds() { return (size_t)32 << LOGNG; }
+template <int LOGNG>
+size_t fill_lds() { return (size_t)44 << LOGNG; }
+
+template <int LOGNG>
+wp_status count_rows(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
+                     unsigned char *ws, const WsLayout &L, hipStream_t s) {
+    const size_t lds = count_lds<LOGNG>();
+    if (lds > 160 * 1024) return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d exceeds the LDS budget", p->Ng);
+    hipLaunchKernelGGL((k_row_count<LOGNG>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, E, p->cell, p->delta, p->W,
+                       p->beta, p->tile, p->ntile, p->tw64, (double *)(ws + L.tau), (int *)(ws + L.nnz),
+                       (int *)(ws + L.key), (int *)(ws + L.err));
+    return wp_check_launch("build_G_count rows");
+}
+
+template <int LOGNG>
+wp_status fill_rows(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                    const unsigned char *ws, const WsLayout &L, wp_G *G, hipStream_t s) {
+    const size_t lds = fill_lds<LOGNG>();
+    if (lds > 160 * 1024) return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d exceeds the LDS budget", p->Ng);
+    int *err = (int *)(ws + L.err);
+    if (G->taps == WP_TAPS_BF16)
+        hipLaunchKernelGGL((k_row_fill<LOGNG, true>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta, p->W,
+                           p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val, err);
+    else
+        hipLaunchKernelGGL((k_row_fill<LOGNG, false>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
+                           p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val,
+                           err);
+    return wp_check_launch("build_G_fill rows");
+}
+
+}  // namespace
+
+int64_t builder_workspace_bytes(const wp_plan *p, int64_t M) { return ws_layout(p, M).total; }
+
+wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
+                             void *wsv, int64_t *nnz_total, int64_t *nwork, hipStream_t s) {
+    unsigned char *ws = (unsigned char *)wsv;
+    const WsLayout L = ws_layout(p, M);
+    const int T = p->ntile * p->ntile;
+    WP_HIP(hipMemsetAsync(ws + L.err, 0, 16, s));
+    wp_status st;
+    switch (p->logNg) {
+        case 6: st = count_rows<6>(p, M, u, v, w, E, ws, L, s); break;
+        case 7: st = count_rows<7>(p, M, u, v, w, E, ws, L, s); break;
+        case 8: st = count_rows<8>(p, M, u, v, w, E, ws, L, s); break;
+        case 9: st = count_rows<9>(p, M, u, v, w, E, ws, L, s); break;
+        case 10: st = count_rows<10>(p, M, u, v, w, E, ws, L, s); break;
+        case 11: st = count_rows<11>(p, M, u, v, w, E, ws, L, s); break;
+        case 12: st = count_rows<12>(p, M, u, v, w, E, ws, L, s); break;
+        default: return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d", p->Ng);
+    }
+    if (st != WP_OK) return st;
+    // stable sort of the rows by tile id: one stable partition per key bit
+    const int nthr = 256;
+    const dim3 gM((unsigned)((M + nthr - 1) / nthr));
+    int *k0 = (int *)(ws + L.k0), *k1 = (int *)(ws + L.k1), *i0 = (int *)(ws + L.i0), *i1 = (int *)(ws + L.i1);
+    int *flags = (int *)(ws + L.flags), *zpos = (int *)(ws + L.zpos);
+    hipLaunchKernelGGL(k_iota_keys, gM, dim3(nthr), 0, s, (const int *)(ws + L.key), k0, i0, M);
+    int bits = 0;
+    while ((1 << bits) < T) ++bits;
+    for (int b = 0; b < bits; ++b) {
+        hipLaunchKernelGGL(k_bit_flags, gM, dim3(nthr), 0, s, k0, b, flags, M);
+        device_scan<int, int>(flags, zpos, M, (int *)(ws + L.sc32), s);
+        hipLaunchKernelGGL(k_split_scatter, gM, dim3(nthr), 0, s, k0, i0, zpos, k1, i1, b, M);
+        int *t = k0; k0 = k1; k1 = t;
+        t = i0; i0 = i1; i1 = t;
+    }
+    // the sorted keys / permutation end in k0 / i0; keep them at the k0 / i0 slots
+    if (bits & 1) {
+        WP_HIP(hipMemcpyAsync(ws + L.k0, k0, 4 * M, hipMemcpyDeviceToDevice, s));
+        WP_HIP(hipMemcpyAsync(ws + L.i0, i0, 4 * M, hipMemcpyDeviceToDevice, s));
+    }
+    const int *skey = (const int *)(ws + L.k0), *perm = (const int *)(ws + L.i0);
+    hipLaunchKernelGGL(k_gather_nnz, gM, dim3(nthr), 0, s, perm, (const int *)(ws + L.nnz), (int64_t *)(ws + L.snnz), M);
+    device_scan<int64_t, int64_t>((const int64_t *)(ws + L.snnz), (int64_t *)(ws + L.rowptr), M,
+                                  (int64_t *)(ws + L.sc64), s);
+    // adjoint work items: chunks of rows inside each tile
+    WP_HIP(hipMemsetAsync(ws + L.tstart, 0, 4 * T, s));
+    WP_HIP(hipMemsetAsync(ws + L.tend, 0, 4 * T, s));
+    hipLaunchKernelGGL(k_tile_bounds, gM, dim3(nthr), 0, s, skey, M, (int *)(ws + L.tstart), (int *)(ws + L.tend));
+    const dim3 gT((unsigned)((T + nthr - 1) / nthr));
+    hipLaunchKernelGGL(k_tile_chunks, gT, dim3(nthr), 0, s, (const int *)(ws + L.tstart), (const int *)(ws + L.tend),
+                       T, (int *)(ws + L.nch));
+    device_scan<int, int>((const int *)(ws + L.nch), (int *)(ws + L.choff), T, (int *)(ws + L.sc32), s);
+    if ((st = wp_check_launch("build_G_count layout")) != WP_OK) return st;
+    int64_t host_rowptr_end = 0;
+    int host_items = 0, host_err = 0;
+    WP_HIP(hipMemcpyAsync(&host_rowptr_end, ws + L.rowptr + 8 * M, 8, hipMemcpyDeviceToHost, s));
+    WP_HIP(hipMemcpyAsync(&host_items, ws + L.choff + 4 * (int64_t)T, 4, hipMemcpyDeviceToHost, s));
+    WP_HIP(hipMemcpyAsync(&host_err, ws + L.err, 4, hipMemcpyDeviceToHost, s));
+    WP_HIP(hipStreamSynchronize(s));
+    if (host_err & 1)
+        return wp_set_error(WP_EINVAL, "build_G_count: a visibility has non-finite (u, v, w) or lies outside the band |u|,|v| < N/(2L)");
+    *nnz_total = host_rowptr_end;
+    *nwork = host_items;
+    return WP_OK;
+}
+
+wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
+                            const void *wsv, wp_G *G, hipStream_t s) {
+    (void)E;
+    const unsigned char *ws = (const unsigned char *)wsv;
+    const WsLayout L = ws_layout(p, M);
+    const int T = p->ntile * p->ntile;
+    WP_HIP(hipMemcpyAsync(G->rowptr, ws + L.rowptr, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
+    WP_HIP(hipMemcpyAsync(G->perm, ws + L.i0, 4 * M, hipMemcpyDeviceToDevice, s));
+    wp_status st;
+    switch (p->logNg) {
+        case 6: st = fill_rows<6>(p, M, u, v, w, ws, L, G, s); break;
+        case 7: st = fill_rows<7>(p, M, u, v, w, ws, L, G, s); break;
+        case 8: st = fill_rows<8>(p, M, u, v, w, ws, L, G, s); break;
+        case 9: st = fill_rows<9>(p, M, u, v, w, ws, L, G, s); break;
+        case 10: st = fill_rows<10>(p, M, u, v, w, ws, L, G, s); break;
+        case 11: st = fill_rows<11>(p, M, u, v, w, ws, L, G, s); break;
+        case 12: st = fill_rows<12>(p, M, u, v, w, ws, L, G, s); break;
+        default: return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d", p->Ng);
+    }
+    if (st != WP_OK) return st;
+    const int nthr = 256;
+    const dim3 gT((unsigned)((T + nthr - 1) / nthr));
+    hipLaunchKernelGGL(k_write_items, gT, dim3(nthr), 0, s, (const int *)(ws + L.tstart), (const int *)(ws + L.tend),
+                       (const int *)(ws + L.choff), T, p->ntile, G->work);
+    return wp_check_launch("build_G_fill layout");
+}

@@ -1,0 +1,105 @@
+// Internal definitions shared by the HIP translation units of libwproj.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wproj.h"
+
+// ---------------------------------------------------------------------------- plan
+
+struct wp_plan {
+    int N;          // image side
+    int Ng;         // padded grid side (2N)
+    int logNg;
+    int W;          // KB support (cells)
+    int chirp;      // WP_CHIRP_*
+    int aphys;      // WP_APHYS_*
+    double L;       // planar field of view
+    double beta;    // KB shape
+    double delta;   // pixel size L / N
+    double cell;    // uv cell 1 / (Ng delta) = 1 / (2L)
+    int tile;       // adjoint scatter: tile side in cells
+    int halo;       // adjoint scatter: LDS window margin per side
+    int ntile;      // tiles per axis
+    int device;
+    float *apod;    // [N]  1 / g(xi), xi = (p - N/2) / Ng       (device)
+    float2 *tw32;   // [Ng] exp(-2 pi i k / Ng), FP32             (device)
+    double2 *tw64;  // [Ng] exp(-2 pi i k / Ng), FP64             (device)
+};
+
+// ---------------------------------------------------------------------------- errors
+
+wp_status wp_set_error(wp_status s, const char *fmt, ...);
+wp_status wp_check_launch(const char *what);
+
+#define WP_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return wp_set_error(WP_EHIP, "%s: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+// ---------------------------------------------------------------------------- complex helpers
+
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {  // conj(a) * b
+    return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+template <typename T2> __device__ inline T2 cconj(T2 a) { a.y = -a.y; return a; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T2> __device__ inline T2 cmul_negi(T2 a) { T2 r; r.x = a.y; r.y = -a.x; return r; }
+template <typename T2> __device__ inline T2 cmul_posi(T2 a) { T2 r; r.x = -a.y; r.y = a.x; return r; }
+
+// bfloat16 pair (re in the low half) <-> float2
+__host__ __device__ inline uint32_t bf16_bits_rne(float f) {
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / nan
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return u >> 16;
+}
+__host__ __device__ inline uint32_t pack_bf16x2(float re, float im) {
+    return bf16_bits_rne(re) | (bf16_bits_rne(im) << 16);
+}
+__device__ inline float2 unpack_bf16x2(uint32_t p) {
+    return make_float2(__uint_as_float(p << 16), __uint_as_float(p & 0xffff0000u));
+}
+
+// ---------------------------------------------------------------------------- XCD-aware block order
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).
+// This bijection gives each XCD a contiguous range of logical blocks, so the rows
+// (sorted by uv tile) that share grid cells also share an L2.
+__device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
+    const int64_t X = 8;
+    int64_t x = b % X, i = b / X, q = nb / X, r = nb % X;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// ---------------------------------------------------------------------------- launchers (host)
+
+// FFT stages of A, Z, F and their adjoint (fft.hip)
+wp_status launch_grid_forward(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s);
+wp_status launch_grid_adjoint(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s);
+
+// sparse products (spmv.hip)
+wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, float2 *y, hipStream_t s);
+wp_status launch_scatter(const wp_plan *p, const wp_G *G, const float2 *y, float2 *grid, hipStream_t s);
+wp_status launch_fill_zero(float *buf, int64_t n, hipStream_t s);
+
+// builder (builder.hip)
+int64_t builder_workspace_bytes(const wp_plan *p, int64_t M);
+wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v,
+                             const double *w, double E, void *ws, int64_t *nnz, int64_t *nwork,
+                             hipStream_t s);
+wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v,
+                            const double *w, double E, const void *ws, wp_G *G, hipStream_t s);

@@ -1,0 +1,175 @@
+// A, Z, F and their adjoint: apodise + zero-pad + centred 2-D FFT of the image,
+// and the unnormalised inverse + crop + apodise back (Sections 2.2 and 3.1; the
+// upsampling U of Eq. 6 is done here in the image domain as zero-padding).
+//
+// Centring.  With c = Ng/2, the centred DFT
+//     X[q] = sum_j z_j exp(-2 pi i (j - c).(q - c) / Ng)
+// equals (-1)^(q_u+q_v) FFT((-1)^(j_u+j_v) z)[q] (Ng even), so the signs are
+// folded into the first and last pass.  Pruning: the padded image is non-zero
+// only in its central N rows and columns, so the forward row pass runs on N
+// rows only and the column pass reads N rows; the adjoint column pass writes
+// only those N rows and the row pass keeps the central N outputs.
+#include "fft_lds.h"
+
+namespace {
+
+constexpr int FFT_NTH = 256;
+constexpr int FFT_ELEMS = 4096;   // complex values per block (32 KB of LDS)
+
+__device__ inline float apod_at(const float *__restrict__ apod, int N, int aphys, float delta, int im,
+                                int iu) {
+    float a = apod[im] * apod[iu];
+    if (aphys == WP_APHYS_INV_N) {
+        float l = (iu - N / 2) * delta, m = (im - N / 2) * delta;
+        a *= rsqrtf(1.0f - l * l - m * m);
+    }
+    return a;
+}
+
+__device__ inline float sgn(int k) { return (k & 1) ? -1.0f : 1.0f; }
+
+// Forward, pass 1: rows.  Block handles C image rows (padded rows jv = im + N/2).
+template <int LOGNG, int C>
+__global__ __launch_bounds__(FFT_NTH) void k_fwd_rows(const float2 *__restrict__ x, float2 *__restrict__ grid,
+                                                      const float *__restrict__ apod, const float2 *__restrict__ tw,
+                                                      int aphys, float delta) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    __shared__ float2 buf[C * Ng];
+    const int tid = threadIdx.x;
+    const int im0 = blockIdx.x * C;
+    for (int e = tid; e < C * Ng; e += FFT_NTH) {
+        const int c = e / Ng, j = e % Ng, im = im0 + c;
+        float2 v = make_float2(0.f, 0.f);
+        if (j >= N / 2 && j < N / 2 + N) {
+            const int iu = j - N / 2;
+            const float s = apod_at(apod, N, aphys, delta, im, iu) * sgn(j + im + N / 2);
+            v = x[(int64_t)im * N + iu];
+            v.x *= s;
+            v.y *= s;
+        }
+        buf[c * Ng + j] = v;
+    }
+    __syncthreads();
+    lds_fft<float2, LOGNG, C, FFT_NTH, true, Ng>(buf, tw, false, tid);
+    for (int e = tid; e < C * Ng; e += FFT_NTH) {
+        const int c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
+        grid[(int64_t)jv * Ng + q] = buf[c * Ng + q];
+    }
+}
+
+// Forward, pass 2: columns (block handles C adjacent columns), in place.
+template <int LOGNG, int C>
+__global__ __launch_bounds__(FFT_NTH) void k_fwd_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    __shared__ float2 buf[Ng * C];
+    const int tid = threadIdx.x;
+    const int qu0 = blockIdx.x * C;
+    for (int e = tid; e < Ng * C; e += FFT_NTH) {
+        const int jv = e / C, c = e % C;
+        float2 v = make_float2(0.f, 0.f);
+        if (jv >= N / 2 && jv < N / 2 + N) v = grid[(int64_t)jv * Ng + qu0 + c];
+        buf[jv * C + c] = v;
+    }
+    __syncthreads();
+    lds_fft<float2, LOGNG, C, FFT_NTH, false, C>(buf, tw, false, tid);
+    for (int e = tid; e < Ng * C; e += FFT_NTH) {
+        const int qv = e / C, c = e % C;
+        float2 v = buf[qv * C + c];
+        const float s = sgn(qv + qu0 + c);
+        grid[(int64_t)qv * Ng + qu0 + c] = make_float2(v.x * s, v.y * s);
+    }
+}
+
+// Adjoint, pass 1: columns, inverse, keep the central N rows, in place.
+template <int LOGNG, int C>
+__global__ __launch_bounds__(FFT_NTH) void k_adj_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    __shared__ float2 buf[Ng * C];
+    const int tid = threadIdx.x;
+    const int qu0 = blockIdx.x * C;
+    for (int e = tid; e < Ng * C; e += FFT_NTH) {
+        const int qv = e / C, c = e % C;
+        float2 v = grid[(int64_t)qv * Ng + qu0 + c];
+        const float s = sgn(qv + qu0 + c);
+        buf[qv * C + c] = make_float2(v.x * s, v.y * s);
+    }
+    __syncthreads();
+    lds_fft<float2, LOGNG, C, FFT_NTH, false, C>(buf, tw, true, tid);
+    for (int e = tid; e < N * C; e += FFT_NTH) {
+        const int jv = N / 2 + e / C, c = e % C;
+        grid[(int64_t)jv * Ng + qu0 + c] = buf[jv * C + c];
+    }
+}
+
+// Adjoint, pass 2: rows, inverse, crop the central N, apodise, write the image.
+template <int LOGNG, int C>
+__global__ __launch_bounds__(FFT_NTH) void k_adj_rows(const float2 *__restrict__ grid, float2 *__restrict__ x,
+                                                      const float *__restrict__ apod, const float2 *__restrict__ tw,
+                                                      int aphys, float delta) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    __shared__ float2 buf[C * Ng];
+    const int tid = threadIdx.x;
+    const int im0 = blockIdx.x * C;
+    for (int e = tid; e < C * Ng; e += FFT_NTH) {
+        const int c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
+        buf[c * Ng + q] = grid[(int64_t)jv * Ng + q];
+    }
+    __syncthreads();
+    lds_fft<float2, LOGNG, C, FFT_NTH, true, Ng>(buf, tw, true, tid);
+    for (int e = tid; e < C * N; e += FFT_NTH) {
+        const int c = e / N, iu = e % N, im = im0 + c;
+        const int ju = iu + N / 2, jv = im + N / 2;
+        const float s = apod_at(apod, N, aphys, delta, im, iu) * sgn(ju + jv);
+        float2 v = buf[c * Ng + ju];
+        x[(int64_t)im * N + iu] = make_float2(v.x * s, v.y * s);
+    }
+}
+
+template <int LOGNG>
+wp_status fwd(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    constexpr int C = (FFT_ELEMS / Ng > N) ? N : FFT_ELEMS / Ng;
+    static_assert(N % C == 0 && Ng % C == 0, "tile");
+    hipLaunchKernelGGL((k_fwd_rows<LOGNG, C>), dim3(N / C), dim3(FFT_NTH), 0, s, x, grid, p->apod, p->tw32,
+                       p->aphys, (float)p->delta);
+    hipLaunchKernelGGL((k_fwd_cols<LOGNG, C>), dim3(Ng / C), dim3(FFT_NTH), 0, s, grid, p->tw32);
+    return wp_check_launch("grid_forward");
+}
+
+template <int LOGNG>
+wp_status adj(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    constexpr int C = (FFT_ELEMS / Ng > N) ? N : FFT_ELEMS / Ng;
+    hipLaunchKernelGGL((k_adj_cols<LOGNG, C>), dim3(Ng / C), dim3(FFT_NTH), 0, s, grid, p->tw32);
+    hipLaunchKernelGGL((k_adj_rows<LOGNG, C>), dim3(N / C), dim3(FFT_NTH), 0, s, grid, x, p->apod, p->tw32,
+                       p->aphys, (float)p->delta);
+    return wp_check_launch("grid_adjoint");
+}
+
+}  // namespace
+
+wp_status launch_grid_forward(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s) {
+    switch (p->logNg) {
+        case 6: return fwd<6>(p, x, grid, s);
+        case 7: return fwd<7>(p, x, grid, s);
+        case 8: return fwd<8>(p, x, grid, s);
+        case 9: return fwd<9>(p, x, grid, s);
+        case 10: return fwd<10>(p, x, grid, s);
+        case 11: return fwd<11>(p, x, grid, s);
+        case 12: return fwd<12>(p, x, grid, s);
+    }
+    return wp_set_error(WP_EUNSUPPORTED, "grid_forward: Ng = %d", p->Ng);
+}
+
+wp_status launch_grid_adjoint(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s) {
+    switch (p->logNg) {
+        case 6: return adj<6>(p, grid, x, s);
+        case 7: return adj<7>(p, grid, x, s);
+        case 8: return adj<8>(p, grid, x, s);
+        case 9: return adj<9>(p, grid, x, s);
+        case 10: return adj<10>(p, grid, x, s);
+        case 11: return adj<11>(p, grid, x, s);
+        case 12: return adj<12>(p, grid, x, s);
+    }
+    return wp_set_error(WP_EUNSUPPORTED, "grid_adjoint: Ng = %d", p->Ng);
+}

@@ -1,0 +1,65 @@
+"""The C-ABI library loads and exports every entry point of include/wproj.h (CPU only, no compute)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_1307_3424_amd as wp
+from paper_1307_3424_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def declared_functions():
+    names = set()
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?\**\s*\b(wp_[A-Za-z0-9_]+)\s*\(", src, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    lib = wp.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(_lib.SIGNATURES) == names
+
+
+def test_version_and_error_string():
+    lib = wp.load()
+    assert lib.wp_version().startswith(b"wproj")
+    assert isinstance(lib.wp_last_error(), bytes)
+
+
+@pytest.mark.parametrize("args,frag", [
+    ((100, 0.0349, 4, 0.0, 0, 0), b"power of two"),
+    ((16, 0.0349, 4, 0.0, 0, 0), b"power of two"),
+    ((64, 1.5, 4, 0.0, 0, 0), b"fov_L"),
+    ((64, 0.0349, 5, 0.0, 0, 0), b"kb_W"),
+    ((64, 0.0349, 4, 0.0, 7, 0), b"chirp"),
+    ((64, 0.0349, 4, 0.0, 0, 9), b"aphys"),
+])
+def test_plan_validation_happens_before_any_device_call(args, frag):
+    lib = wp.load()
+    h = C.c_void_p()
+    st = lib.wp_plan_create(C.byref(h), *args)
+    assert st == -1 and not h.value
+    assert frag in lib.wp_last_error()
+
+
+def test_null_arguments_rejected():
+    lib = wp.load()
+    assert lib.wp_plan_create(None, 64, 0.03, 4, 0.0, 0, 0) == -1
+    assert lib.wp_apply_Phi(None, None, None, None, None, None) == -1
+    assert lib.wp_build_G_count(None, 10, None, None, None, 0.9, None, None, None, None) == -1
+    assert lib.wp_plan_destroy(None) == 0
+
+
+def test_wp_G_layout_matches_header():
+    assert C.sizeof(_lib.WpG) == 8 * 2 + 4 * 2 + 8 * 5 + 8

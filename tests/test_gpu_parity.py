@@ -1,0 +1,284 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Tolerances: complex FP32 path, operator relative error <= 1e-5 against the
+FP64 oracle built with the same (W, beta, E, chirp); index work (row
+structure, kept sets) bit-exact except for taps tied with the row threshold
+within FP64 rounding (1e-9 relative), where either decision is correct.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import wproj
+from oracle.wproj import Setup
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1307_3424_amd as wp  # noqa: E402
+
+L = synth.fov_L()
+TOL = 1e-5
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def c64(a):
+    return dev(np.asarray(a, dtype=np.complex64).ravel())
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def build(plan, u, v, w, E, taps=wp.WP_TAPS_C64):
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), E, taps=taps)
+    torch.cuda.synchronize()
+    return G
+
+
+def gpu_rows(G):
+    rp = G.rowptr.cpu().numpy()
+    col = G.col.cpu().numpy()
+    val = G.val.cpu().numpy() if G.taps == wp.WP_TAPS_C64 else None
+    perm = G.perm.cpu().numpy()
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    return rp, col, val, perm, inv
+
+
+def check_rows(G, u, v, w, E, s, rows):
+    """Kept sets and values of the sampled rows against dense oracle rows."""
+    rp, col, val, perm, inv = gpu_rows(G)
+    ut = u * 2 * s.L          # u / du with du = 1 / (2L)
+    vt = v * 2 * s.L
+    for k in rows:
+        g = wproj.kernel_row(ut[k], vt[k], w[k], s).ravel()
+        m = (g * g.conj()).real
+        tau, _ = wproj.energy_threshold(m, E)
+        want = np.nonzero(m >= tau)[0]
+        r = inv[k]
+        got = col[rp[r]:rp[r + 1]]
+        assert np.all(np.diff(got) > 0), f"row {k}: columns not ascending"
+        diff = np.setxor1d(got, want)
+        if diff.size:
+            assert np.all(np.abs(m[diff] - tau) <= 1e-9 * tau), f"row {k}: kept sets differ beyond ties"
+        if val is not None:
+            common, ig, iw = np.intersect1d(got, want, return_indices=True)
+            gv = val[rp[r]:rp[r + 1]][ig]
+            scale = np.abs(g).max()
+            assert np.all(np.abs(gv - g[common]) <= 1e-6 * np.abs(g[common]) + 1e-7 * scale), f"row {k}: values"
+
+
+# --------------------------------------------------------------------------- A, Z, F
+
+@pytest.mark.parametrize("N", [32, 64, 256, 1024])
+def test_grid_forward_and_adjoint(N):
+    say(f"grid transforms N={N}")
+    s = Setup(N=N, L=L)
+    plan = wp.Plan(N, L)
+    rng = np.random.default_rng(N)
+    x = synth.random_complex((N, N), rng)
+    X = wp.grid_forward(plan, c64(x)).cpu().numpy().reshape(s.Ng, s.Ng)
+    assert relerr(X, wproj.grid_forward(x, s)) < TOL
+    Y = synth.random_complex((s.Ng, s.Ng), rng)
+    xa = wp.grid_adjoint(plan, c64(Y)).cpu().numpy().reshape(N, N)
+    assert relerr(xa, wproj.grid_adjoint(Y, s)) < TOL
+
+
+# --------------------------------------------------------------------------- builder
+
+def test_build_tiny_form_all_rows():
+    wl = synth.workload(0)
+    say(f"build: {wl.name} N={wl.N} M={wl.M}")
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    Go = wproj.build_rows(u, v, w, wl.E, s)
+    assert abs(G.nnz - Go.nnz) <= 1e-6 * Go.nnz
+    check_rows(G, u, v, w, wl.E, s, range(wl.M))
+
+
+def test_build_plain_form_sampled_rows():
+    wl = synth.workload(1)
+    say(f"build: {wl.name} N={wl.N} M={wl.M} (sampled rows)")
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    rows = synth.subset_rows(wl.M, 96, synth.rng_for(wl.seed, "subset"))
+    rows = np.unique(np.concatenate([rows, [0, wl.M - 1]]))
+    check_rows(G, u, v, w, wl.E, s, rows)
+    # every row appears once in the tile order, row lengths add up
+    rp, col, _, perm, _ = gpu_rows(G)
+    assert np.array_equal(np.sort(perm), np.arange(wl.M))
+    assert rp[0] == 0 and rp[-1] == G.nnz and np.all(np.diff(rp) > 0)
+    assert col.min() >= 0 and col.max() < s.Ng ** 2
+
+
+def test_work_items_cover_rows_once():
+    wl = synth.workload(1)
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    items = G.work.cpu().numpy()[:4 * G.n_work].reshape(-1, 4)
+    seen = np.zeros(wl.M, dtype=int)
+    for tv, tu, rb, re in items:
+        assert rb < re
+        seen[rb:re] += 1
+    assert np.all(seen == 1)
+    # rows of an item lie in its tile
+    perm = G.perm.cpu().numpy()
+    ut = u * 2 * wl.L + wl.Ng / 2
+    vt = v * 2 * wl.L + wl.Ng / 2
+    for tv, tu, rb, re in items[:: max(1, len(items) // 50)]:
+        ks = perm[rb:re]
+        assert np.all((vt[ks] // 32).astype(int) == tv) and np.all((ut[ks] // 32).astype(int) == tu)
+
+
+# --------------------------------------------------------------------------- Phi and Phi^H
+
+def test_phi_and_adjoint_tiny_form():
+    wl = synth.workload(0)
+    say(f"apply: {wl.name}")
+    x, u, v, w = synth.workload_inputs(wl)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    Go = wproj.build_rows(u, v, w, wl.E, s)
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    assert relerr(y, wproj.phi(Go, x, s)) < TOL
+    yv = synth.random_complex(wl.M, synth.rng_for(wl.seed, "y"))
+    xa = wp.apply_PhiT(plan, G, c64(yv)).cpu().numpy().reshape(wl.N, wl.N)
+    assert relerr(xa, wproj.phi_adjoint(Go, yv, s)) < TOL
+
+
+def test_phi_plain_form_sampled_rows():
+    wl = synth.workload(1)
+    say(f"apply: {wl.name} full size, sampled outputs")
+    x, u, v, w = synth.workload_inputs(wl)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    rows = synth.subset_rows(wl.M, 64, synth.rng_for(wl.seed, "subset", 1))
+    Go = wproj.build_rows(u, v, w, wl.E, s, rows=rows)
+    y_ref = Go @ wproj.grid_forward(x, s).ravel()
+    assert relerr(y[rows], y_ref) < TOL
+
+
+def test_phi_adjoint_plain_form_on_sampled_support():
+    """Phi^H of a y that is non-zero only on sampled rows: the oracle needs only those rows."""
+    wl = synth.workload(1)
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    rows = synth.subset_rows(wl.M, 64, synth.rng_for(wl.seed, "subset", 2))
+    yv = np.zeros(wl.M, dtype=np.complex128)
+    yv[rows] = synth.random_complex(rows.size, synth.rng_for(wl.seed, "y", 2))
+    xa = wp.apply_PhiT(plan, G, c64(yv)).cpu().numpy().reshape(wl.N, wl.N)
+    Go = wproj.build_rows(u, v, w, wl.E, s, rows=rows)
+    x_ref = wproj.phi_adjoint(Go, yv[rows], s)
+    assert relerr(xa, x_ref) < TOL
+
+
+def test_adjoint_identity_full_size():
+    wl = synth.workload(1)
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    rng = synth.rng_for(wl.seed, "x", 3)
+    x = c64(synth.random_complex(wl.N * wl.N, rng))
+    yv = c64(synth.random_complex(wl.M, rng))
+    Px = wp.apply_Phi(plan, G, x)
+    Py = wp.apply_PhiT(plan, G, yv)
+    lhs = torch.vdot(Px.to(torch.complex128), yv.to(torch.complex128)).item()
+    rhs = torch.vdot(x.to(torch.complex128), Py.to(torch.complex128)).item()
+    scale = (torch.linalg.norm(Px.to(torch.complex128)) * torch.linalg.norm(yv.to(torch.complex128))).item()
+    assert abs(lhs - rhs) / scale < 1e-5
+
+
+def test_phi_deterministic_and_adjoint_repeatable():
+    wl = synth.workload(1)
+    x, u, v, w = synth.workload_inputs(wl)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    xd = c64(x)
+    y1 = wp.apply_Phi(plan, G, xd)
+    y2 = wp.apply_Phi(plan, G, xd)
+    assert torch.equal(y1, y2)
+    a1 = wp.apply_PhiT(plan, G, y1)
+    a2 = wp.apply_PhiT(plan, G, y1)
+    assert (torch.linalg.norm(a1 - a2) / torch.linalg.norm(a1)).item() < 1e-6
+
+
+# --------------------------------------------------------------------------- edge cases
+
+def test_single_visibility_and_band_edges():
+    N = 64
+    s = Setup(N=N, L=L)
+    plan = wp.Plan(N, L)
+    B = N / (2 * L)
+    u = np.array([-B * (1 - 1e-9), B * (1 - 1e-6), 0.0, -B * 0.999, 0.3])
+    v = np.array([B * (1 - 1e-6), -B * (1 - 1e-9), 0.0, B * 0.5, -B * 0.999])
+    w = np.array([0.0, 900.0, 0.0, 26000.0, 13000.0])
+    x = synth.random_complex((N, N), np.random.default_rng(5))
+    for sel in ([0], [1], [2], [0, 1, 2, 3, 4]):
+        sel = np.array(sel)
+        G = build(plan, u[sel], v[sel], w[sel], 0.99)
+        Go = wproj.build_rows(u[sel], v[sel], w[sel], 0.99, s)
+        assert relerr(wp.apply_Phi(plan, G, c64(x)).cpu().numpy(), wproj.phi(Go, x, s)) < TOL
+        yv = synth.random_complex(sel.size, np.random.default_rng(6))
+        xa = wp.apply_PhiT(plan, G, c64(yv)).cpu().numpy().reshape(N, N)
+        assert relerr(xa, wproj.phi_adjoint(Go, yv, s)) < TOL
+
+
+def test_w_zero_and_full_energy_small_grid():
+    N = 32
+    s = Setup(N=N, L=L)
+    plan = wp.Plan(N, L)
+    u, v, _ = synth.uvw(N, 37, L, "uniform", 0.0, 0.0, np.random.default_rng(8))
+    x = synth.random_complex((N, N), np.random.default_rng(9))
+    for w, E in ((np.zeros(37), 0.99), (np.random.default_rng(10).uniform(0, N / (2 * L * L), 37), 1.0)):
+        G = build(plan, u, v, w, E)
+        Go = wproj.build_rows(u, v, w, E, s)
+        assert G.nnz == Go.nnz
+        assert relerr(wp.apply_Phi(plan, G, c64(x)).cpu().numpy(), wproj.phi(Go, x, s)) < TOL
+
+
+@pytest.mark.parametrize("E", [0.1, 0.5, 0.9, 0.999])
+def test_energy_levels(E):
+    N, M = 64, 53
+    s = Setup(N=N, L=L)
+    plan = wp.Plan(N, L)
+    u, v, w = synth.uvw(N, M, L, "gaussian", 0.25, N / (2 * L * L), np.random.default_rng(11))
+    G = build(plan, u, v, w, E)
+    check_rows(G, u, v, w, E, s, range(M))
+
+
+def test_invalid_visibilities_raise():
+    N = 64
+    plan = wp.Plan(N, L)
+    B = N / (2 * L)
+    good = np.array([0.0, 1.0, 2.0])
+    with pytest.raises(wp.WprojError, match="WP_EINVAL"):
+        wp.build_G(plan, dev(np.array([0.0, 1.1 * B, 0.0])), dev(good), dev(good), 0.9)
+    with pytest.raises(wp.WprojError, match="WP_EINVAL"):
+        wp.build_G(plan, dev(good), dev(good), dev(np.array([0.0, np.nan, 1.0])), 0.9)
+    with pytest.raises(wp.WprojError, match="WP_EINVAL"):
+        wp.build_G(plan, dev(good), dev(good), dev(good), 1.5)
+
+
+def test_exact_chirp_build_is_reported_unsupported():
+    plan = wp.Plan(64, L, chirp=wp.WP_CHIRP_EXACT)
+    z = np.zeros(3)
+    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):
+        wp.build_G(plan, dev(z), dev(z), dev(z), 0.9)
