@@ -51,6 +51,11 @@ def scatter_bytes(G, M, Ng, tap_bytes):
     return G.nnz * (tap_bytes + 4) + (M + 1) * 8 + M * 4 + M * 8 + Ng * Ng * 8 + G.n_work * 16
 
 
+def gather_bytes(G, M, Ng, tap_bytes):
+    """Transposed copy streamed once (value + visibility index), cell offsets, y read once, grid written once."""
+    return G.nnz * (tap_bytes + 4) + (Ng * Ng + 1) * 8 + M * 8 + Ng * Ng * 8
+
+
 def time_region(fn, steps, stream, torch):
     s_ev = torch.cuda.Event(enable_timing=True)
     e_ev = torch.cuda.Event(enable_timing=True)
@@ -130,6 +135,9 @@ def main():
     xa = torch.empty(wl.N * wl.N, dtype=torch.complex64, device=dev)
     grid = plan.new_grid()
     stream = torch.cuda.current_stream()
+    # visibility vectors stay in G's sorted row order inside the timed loop (an iterative
+    # solver permutes its data vector once); the caller-order cost is reported beside it
+    G.order = wp.WP_ORDER_SORTED
 
     def step():
         wp.apply_Phi(plan, G, xd, yd, grid)
@@ -148,13 +156,23 @@ def main():
     wp.grid_forward(plan, xd, grid)
     ms_deg = time_region(lambda: wp.degrid(plan, G, grid, yd), ks, stream, torch)
     ms_sc = time_region(lambda: wp.grid_scatter(plan, G, yd, grid), ks, stream, torch)
+    ms_ga = time_region(lambda: wp.grid_gather(plan, G, yd, grid), ks, stream, torch)
+    G.use_transpose = False
+    ms_phit_sc = time_region(lambda: wp.apply_PhiT(plan, G, yd, xa, grid), ks, stream, torch)
+    G.use_transpose = True
     ms_adj = time_region(lambda: wp.grid_adjoint(plan, grid, xa), ks, stream, torch)
+    G.order = wp.WP_ORDER_CALLER
+    ms_caller = time_region(step, ks, stream, torch)
+    G.order = wp.WP_ORDER_SORTED
     db = degrid_bytes(G, wl.M, plan.Ng, tap_bytes)
     sb = scatter_bytes(G, wl.M, plan.Ng, tap_bytes)
     deg_gbs = db / (ms_deg * 1e-3) / 1e9
     sc_gbs = sb / (ms_sc * 1e-3) / 1e9
+    gb = gather_bytes(G, wl.M, plan.Ng, tap_bytes)
+    ga_gbs = gb / (ms_ga * 1e-3) / 1e9
     log(f"bench: Phi {ms_phi * 1e3:.1f} us, Phi^H {ms_phit * 1e3:.1f} us | fwd FFT {ms_fwd * 1e3:.1f} us, "
         f"degrid {ms_deg * 1e3:.1f} us ({deg_gbs:.0f} GB/s), scatter+zero {ms_sc * 1e3:.1f} us ({sc_gbs:.0f} GB/s), "
+        f"gather {ms_ga * 1e3:.1f} us ({ga_gbs:.0f} GB/s), Phi^H via scatter {ms_phit_sc * 1e3:.1f} us, "
         f"adj FFT {ms_adj * 1e3:.1f} us")
     out = {
         "metric": "visibilities/s for Phi+Phi† (exact vs surrogate kernels) and % HBM roofline",
@@ -171,7 +189,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": deg_gbs / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_launch": db, "launch_us": ms_deg * 1e3},
         "stages_us": {"phi": ms_phi * 1e3, "phiT": ms_phit * 1e3, "grid_forward": ms_fwd * 1e3,
-                      "degrid": ms_deg * 1e3, "scatter_incl_zero": ms_sc * 1e3, "grid_adjoint": ms_adj * 1e3},
+                      "degrid": ms_deg * 1e3, "gather": ms_ga * 1e3, "scatter_incl_zero": ms_sc * 1e3,
+                      "grid_adjoint": ms_adj * 1e3, "phiT_via_scatter": ms_phit_sc * 1e3,
+                      "step_caller_order": ms_caller * 1e3},
+        "gather_roofline": {"achieved": ga_gbs, "frac": ga_gbs / HBM_PEAK_GBS, "bytes_per_launch": gb},
         "scatter_roofline": {"achieved": sc_gbs, "frac": sc_gbs / HBM_PEAK_GBS, "bytes_per_launch": sb},
         "phi_vis_per_s": wl.M / (ms_phi * 1e-3), "phiT_vis_per_s": wl.M / (ms_phit * 1e-3),
         "build_G_s": build_s,

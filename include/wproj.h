@@ -28,8 +28,11 @@
  *  - The uv grid is Ng x Ng row-major, flattened index q_v * Ng + q_u; cell q
  *    is at u = (q - Ng/2) / (2L) wavelengths.
  *  - Visibility coordinates u, v, w are float64, in wavelengths, in the
- *    caller's order; y is always in the caller's order.  Internally G's rows
- *    are sorted by uv tile; G.perm maps sorted row r to caller index perm[r].
+ *    caller's order.  Internally G's rows are sorted by uv tile; G.perm maps
+ *    sorted row r to caller index perm[r].  Visibility vectors y are in the
+ *    caller's order, or in the sorted row order when G.order is
+ *    WP_ORDER_SORTED (an iterative solver keeps its vectors in that order:
+ *    the sparse products then read and write y contiguously).
  *  - Every call is enqueued on the given HIP stream (NULL = default stream)
  *    and is asynchronous unless its comment says it synchronises.
  *  - No call throws or aborts.  Arguments are validated before any launch;
@@ -61,6 +64,9 @@ enum { WP_TAPS_C64 = 0,       /* G values as complex float32 (8 bytes)          
        WP_TAPS_BF16 = 1 };    /* G values as a (re, im) pair of bfloat16 (4 bytes), FP32 accumulate */
 enum { WP_APHYS_ONE = 0,      /* primary beam absorbed into the sky (Section 2.1)               */
        WP_APHYS_INV_N = 1 };  /* the 1/n(l, m) factor of Eq. 1                                 */
+enum { WP_ORDER_CALLER = 0,   /* visibility vectors in the caller's order (default)             */
+       WP_ORDER_SORTED = 1 }; /* visibility vectors in G's tile-sorted row order: entry r is
+                                 visibility perm[r] (use wp_to_sorted / wp_to_caller once)     */
 
 typedef struct wp_plan wp_plan;   /* opaque: geometry plus small device tables */
 
@@ -69,13 +75,18 @@ typedef struct wp_G {
     int64_t  M;        /* rows = visibilities                                        */
     int64_t  nnz;      /* stored taps                                                */
     int32_t  taps;     /* WP_TAPS_C64 or WP_TAPS_BF16                                */
-    int32_t  pad_;
+    int32_t  order;    /* WP_ORDER_CALLER: y in caller order; WP_ORDER_SORTED: y[r] is row r */
     int64_t *rowptr;   /* [M+1] device, sorted-row order, rowptr[0] = 0              */
     int32_t *col;      /* [nnz] device, flattened grid index, ascending in a row    */
     void    *val;      /* [nnz] device, c64 or bf16 pairs                            */
     int32_t *perm;     /* [M]   device, sorted row r is visibility perm[r]           */
     int32_t *work;     /* [4*n_work] device, adjoint work items (tile_v, tile_u, row_begin, row_end) */
     int64_t  n_work;
+    /* Optional transposed copy for the gather form of G^H (tcolptr == NULL: not built).
+     * Entries of grid cell c are [tcolptr[c], tcolptr[c+1]), ordered by sorted row index. */
+    int64_t *tcolptr;  /* [Ng*Ng+1] device                                           */
+    int32_t *trow;     /* [nnz] device, sorted row index r of the entry               */
+    void    *tval;     /* [nnz] device, the entry's G value (not conjugated), same tap type */
 } wp_G;
 
 /* Last error message of this thread ("" if none). */
@@ -97,6 +108,16 @@ const char *wp_version(void);
 wp_status wp_plan_create(wp_plan **out, int N, double fov_L, int kb_W, double kb_beta,
                          int chirp, int aphys);
 wp_status wp_plan_destroy(wp_plan *plan);
+
+/*
+ * Launch-shape knobs of the sparse products, for the autotuner.  key is one of
+ * "degrid_lanes", "degrid_unroll", "gather_lanes", "gather_unroll"; value 0
+ * restores the automatic choice.  Lanes per row / cell: 4, 8, 16, 32 or 64;
+ * loads in flight per lane: 4, 8 or 16 (not every pair exists: an apply with
+ * an unavailable pair returns WP_EINVAL).  Not thread-safe with concurrent
+ * applies on the same plan.
+ */
+wp_status wp_plan_set_tuning(wp_plan *plan, const char *key, int value);
 
 /* Ng and the bytes of the Ng x Ng c64 grid workspace every apply needs. */
 wp_status wp_plan_info(const wp_plan *plan, int64_t *Ng_out, int64_t *grid_bytes_out);
@@ -124,13 +145,14 @@ wp_status wp_build_G_count(const wp_plan *plan, int64_t M, const double *u, cons
                            int64_t *nnz_out, int64_t *n_work_out, void *stream);
 
 /*
- * Build G, pass 2 of 2: writes G->rowptr, G->perm, G->col, G->val, G->work.
+ * Build G, pass 2 of 2: writes G->rowptr, G->perm, G->col, G->val, G->work,
+ * and, when G->tcolptr is not NULL, the transposed copy (tcolptr, trow, tval).
  * The caller sets G->M = M, G->nnz and G->n_work from pass 1, G->taps, and
  * points the arrays at buffers of the sizes listed in wp_G.  Same u, v, w, E
- * and workspace as pass 1.
+ * and workspace as pass 1 (pass 2 also uses part of it as scratch).
  */
 wp_status wp_build_G_fill(const wp_plan *plan, int64_t M, const double *u, const double *v,
-                          const double *w, double E, const void *workspace, wp_G *G,
+                          const double *w, double E, void *workspace, wp_G *G,
                           void *stream);
 
 /*
@@ -141,7 +163,8 @@ wp_status wp_build_G_fill(const wp_plan *plan, int64_t M, const double *u, const
 wp_status wp_apply_Phi(const wp_plan *plan, const wp_G *G, const void *x, void *y, void *grid,
                        void *stream);
 
-/* x = Phi^H y  (the adjoint; x is overwritten). */
+/* x = Phi^H y  (the adjoint; x is overwritten).  G^H y is the transposed-copy gather
+ * when G->tcolptr is set, else the tiled scatter. */
 wp_status wp_apply_PhiT(const wp_plan *plan, const wp_G *G, const void *y, void *x, void *grid,
                         void *stream);
 
@@ -155,6 +178,16 @@ wp_status wp_degrid(const wp_plan *plan, const wp_G *G, const void *grid, void *
 /* grid = G^H y (gridding: tile-binned scatter, LDS accumulation, atomics at tile borders) */
 wp_status wp_grid_scatter(const wp_plan *plan, const wp_G *G, const void *y, void *grid,
                           void *stream);
+/* grid = G^H y from the transposed copy (one lane group per grid cell, no atomics,
+ * deterministic); needs G->tcolptr. */
+wp_status wp_grid_gather(const wp_plan *plan, const wp_G *G, const void *y, void *grid,
+                         void *stream);
+
+/* Reorder a c64 visibility vector between the caller's order and G's sorted row
+ * order: sorted[r] = caller[perm[r]] (wp_to_sorted) and its inverse (wp_to_caller).
+ * Out-of-place; [M] device each. */
+wp_status wp_to_sorted(const wp_G *G, const void *caller, void *sorted, void *stream);
+wp_status wp_to_caller(const wp_G *G, const void *sorted, void *caller, void *stream);
 
 #ifdef __cplusplus
 }

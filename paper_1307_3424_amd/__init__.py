@@ -15,12 +15,13 @@ import ctypes as C
 from dataclasses import dataclass
 
 from . import _lib
-from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR, WP_TAPS_BF16,
-                   WP_TAPS_C64, WprojError, check, load)
+from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR, WP_ORDER_CALLER,
+                   WP_ORDER_SORTED, WP_TAPS_BF16, WP_TAPS_C64, WprojError, check, load)
 
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
-           "degrid", "grid_scatter", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16",
-           "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N"]
+           "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16",
+           "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
+           "WP_ORDER_SORTED", "to_sorted", "to_caller"]
 
 
 def _torch():
@@ -72,6 +73,10 @@ class Plan:
     def handle(self):
         return self._h
 
+    def set_tuning(self, key: str, value: int):
+        """wp_plan_set_tuning (autotuner hook; 0 restores the automatic choice)."""
+        check(load().wp_plan_set_tuning(self._h, key.encode(), int(value)), "wp_plan_set_tuning")
+
     def new_grid(self):
         torch = _torch()
         return torch.empty(self.Ng * self.Ng, dtype=torch.complex64, device="cuda")
@@ -100,20 +105,33 @@ class GMatrix:
     perm: object
     work: object
     n_work: int
+    tcolptr: object = None
+    trow: object = None
+    tval: object = None
+    use_transpose: bool = True
+    order: int = WP_ORDER_CALLER     # order of the visibility vectors passed with this G
 
-    def desc(self) -> _lib.WpG:
+    def desc(self, transpose=None) -> _lib.WpG:
         d = _lib.WpG()
-        d.M, d.nnz, d.taps, d.n_work = self.M, self.nnz, self.taps, self.n_work
+        d.M, d.nnz, d.taps, d.n_work, d.order = self.M, self.nnz, self.taps, self.n_work, self.order
         d.rowptr, d.col, d.val = self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr()
         d.perm, d.work = self.perm.data_ptr(), self.work.data_ptr()
+        use = self.use_transpose if transpose is None else transpose
+        if use and self.tcolptr is not None:
+            d.tcolptr, d.trow, d.tval = self.tcolptr.data_ptr(), self.trow.data_ptr(), self.tval.data_ptr()
         return d
 
     def nbytes(self) -> int:
-        return sum(t.numel() * t.element_size() for t in (self.rowptr, self.col, self.val, self.perm, self.work))
+        ts = [self.rowptr, self.col, self.val, self.perm, self.work, self.tcolptr, self.trow, self.tval]
+        return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
-def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, stream=None) -> GMatrix:
-    """wp_build_workspace_bytes + wp_build_G_count + wp_build_G_fill (u, v, w: float64 CUDA tensors)."""
+def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: bool = True,
+            stream=None) -> GMatrix:
+    """wp_build_workspace_bytes + wp_build_G_count + wp_build_G_fill (u, v, w: float64 CUDA tensors).
+
+    transpose: also build the transposed copy used by the gather form of G^H.
+    """
     torch = _torch()
     lib = load()
     M = int(u.numel())
@@ -135,6 +153,10 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, stream=None)
                 perm=torch.empty(M, dtype=torch.int32, device=dev),
                 work=torch.empty(4 * max(nwork.value, 1), dtype=torch.int32, device=dev),
                 n_work=nwork.value)
+    if transpose:
+        G.tcolptr = torch.empty(plan.Ng * plan.Ng + 1, dtype=torch.int64, device=dev)
+        G.trow = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+        G.tval = torch.empty_like(G.val)
     d = G.desc()
     check(lib.wp_build_G_fill(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws), C.byref(d), s),
           "wp_build_G_fill")
@@ -196,3 +218,32 @@ def grid_scatter(plan: Plan, G: GMatrix, y, grid=None, stream=None):
     check(load().wp_grid_scatter(plan.handle, C.byref(d), _ptr(y), _ptr(grid), _stream(stream)),
           "wp_grid_scatter")
     return grid
+
+
+def grid_gather(plan: Plan, G: GMatrix, y, grid=None, stream=None):
+    _dev_c64(y, G.M, "y")
+    grid = plan.new_grid() if grid is None else grid
+    d = G.desc(transpose=True)
+    check(load().wp_grid_gather(plan.handle, C.byref(d), _ptr(y), _ptr(grid), _stream(stream)),
+          "wp_grid_gather")
+    return grid
+
+
+def to_sorted(G: GMatrix, y, out=None, stream=None):
+    """wp_to_sorted: out[r] = y[perm[r]] (caller order -> G's sorted row order)."""
+    torch = _torch()
+    _dev_c64(y, G.M, "y")
+    out = torch.empty_like(y) if out is None else out
+    d = G.desc()
+    check(load().wp_to_sorted(C.byref(d), _ptr(y), _ptr(out), _stream(stream)), "wp_to_sorted")
+    return out
+
+
+def to_caller(G: GMatrix, y, out=None, stream=None):
+    """wp_to_caller: out[perm[r]] = y[r] (sorted row order -> caller order)."""
+    torch = _torch()
+    _dev_c64(y, G.M, "y")
+    out = torch.empty_like(y) if out is None else out
+    d = G.desc()
+    check(load().wp_to_caller(C.byref(d), _ptr(y), _ptr(out), _stream(stream)), "wp_to_caller")
+    return out

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libwproj.so")
 WP_CHIRP_LINEAR, WP_CHIRP_EXACT = 0, 1
 WP_TAPS_C64, WP_TAPS_BF16 = 0, 1
 WP_APHYS_ONE, WP_APHYS_INV_N = 0, 1
+WP_ORDER_CALLER, WP_ORDER_SORTED = 0, 1
 
 STATUS = {0: "WP_OK", -1: "WP_EINVAL", -2: "WP_ENOMEM", -3: "WP_EHIP", -4: "WP_ECAPACITY",
           -5: "WP_EUNSUPPORTED"}
@@ -26,9 +27,9 @@ _pi64 = C.POINTER(C.c_int64)
 
 
 class WpG(C.Structure):
-    _fields_ = [("M", C.c_int64), ("nnz", C.c_int64), ("taps", C.c_int32), ("pad_", C.c_int32),
+    _fields_ = [("M", C.c_int64), ("nnz", C.c_int64), ("taps", C.c_int32), ("order", C.c_int32),
                 ("rowptr", _vp), ("col", _vp), ("val", _vp), ("perm", _vp), ("work", _vp),
-                ("n_work", C.c_int64)]
+                ("n_work", C.c_int64), ("tcolptr", _vp), ("trow", _vp), ("tval", _vp)]
 
 
 _PG = C.POINTER(WpG)
@@ -39,6 +40,7 @@ SIGNATURES = {
     "wp_plan_create": ([C.POINTER(_vp), _i32, _d, _i32, _d, _i32, _i32], _i32),
     "wp_plan_destroy": ([_vp], _i32),
     "wp_plan_info": ([_vp, _pi64, _pi64], _i32),
+    "wp_plan_set_tuning": ([_vp, C.c_char_p, _i32], _i32),
     "wp_build_workspace_bytes": ([_vp, _i64, _pi64], _i32),
     "wp_build_G_count": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _pi64, _pi64, _vp], _i32),
     "wp_build_G_fill": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _PG, _vp], _i32),
@@ -48,6 +50,9 @@ SIGNATURES = {
     "wp_grid_adjoint": ([_vp, _vp, _vp, _vp], _i32),
     "wp_degrid": ([_vp, _PG, _vp, _vp, _vp], _i32),
     "wp_grid_scatter": ([_vp, _PG, _vp, _vp, _vp], _i32),
+    "wp_grid_gather": ([_vp, _PG, _vp, _vp, _vp], _i32),
+    "wp_to_sorted": ([_PG, _vp, _vp, _vp], _i32),
+    "wp_to_caller": ([_PG, _vp, _vp, _vp], _i32),
 }
 
 _lib = None

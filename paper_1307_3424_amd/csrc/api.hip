@@ -45,10 +45,12 @@ wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
     if (G->M < 0 || G->M > 0x7fffffff) return wp_set_error(WP_EINVAL, "G->M = %lld out of range", (long long)G->M);
     if (G->nnz < 0) return wp_set_error(WP_EINVAL, "G->nnz < 0");
     if (G->taps != WP_TAPS_C64 && G->taps != WP_TAPS_BF16) return wp_set_error(WP_EINVAL, "G->taps = %d", G->taps);
+    if (G->order != WP_ORDER_CALLER && G->order != WP_ORDER_SORTED) return wp_set_error(WP_EINVAL, "G->order = %d", G->order);
     if (G->M > 0 && (!G->rowptr || !G->perm || (G->nnz > 0 && (!G->col || !G->val))))
         return wp_set_error(WP_EINVAL, "G has a NULL array");
     if (need_work && G->n_work > 0 && !G->work) return wp_set_error(WP_EINVAL, "G->work is NULL");
     if (need_work && G->n_work > 0x7fffffff) return wp_set_error(WP_ECAPACITY, "G->n_work too large");
+    if (G->tcolptr && G->nnz > 0 && (!G->trow || !G->tval)) return wp_set_error(WP_EINVAL, "G->tcolptr set without trow / tval");
     (void)p;
     return WP_OK;
 }
@@ -143,6 +145,18 @@ wp_status wp_plan_destroy(wp_plan *p) {
     return WP_OK;
 }
 
+wp_status wp_plan_set_tuning(wp_plan *p, const char *key, int value) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!key) return wp_set_error(WP_EINVAL, "key is NULL");
+    if (value < 0 || value > 64) return wp_set_error(WP_EINVAL, "tuning value %d out of range", value);
+    if (!std::strcmp(key, "degrid_lanes")) p->tune_degrid_lpr = value;
+    else if (!std::strcmp(key, "degrid_unroll")) p->tune_degrid_u = value;
+    else if (!std::strcmp(key, "gather_lanes")) p->tune_gather_lpr = value;
+    else if (!std::strcmp(key, "gather_unroll")) p->tune_gather_u = value;
+    else return wp_set_error(WP_EINVAL, "unknown tuning key '%s'", key);
+    return WP_OK;
+}
+
 wp_status wp_plan_info(const wp_plan *p, int64_t *Ng_out, int64_t *grid_bytes_out) {
     if (wp_status s = check_plan(p)) return s;
     if (Ng_out) *Ng_out = p->Ng;
@@ -170,7 +184,7 @@ wp_status wp_build_G_count(const wp_plan *p, int64_t M, const double *u, const d
 }
 
 wp_status wp_build_G_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
-                          const void *ws, wp_G *G, void *stream) {
+                          void *ws, wp_G *G, void *stream) {
     if (wp_status s = check_plan(p)) return s;
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     if (!u || !v || !w || !ws) return wp_set_error(WP_EINVAL, "NULL argument");
@@ -217,12 +231,36 @@ wp_status wp_apply_Phi(const wp_plan *p, const wp_G *G, const void *x, void *y, 
     return launch_degrid(p, G, (const float2 *)grid, (float2 *)y, s);
 }
 
+wp_status wp_grid_gather(const wp_plan *p, const wp_G *G, const void *y, void *grid, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, false)) return s;
+    if (!G->tcolptr) return wp_set_error(WP_EINVAL, "wp_grid_gather: G has no transposed copy");
+    if (!grid || (G->M > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_gather(p, G, (const float2 *)y, (float2 *)grid, as_stream(stream));
+}
+
+wp_status wp_to_sorted(const wp_G *G, const void *caller, void *sorted, void *stream) {
+    if (wp_status s = check_G(nullptr, G, false)) return s;
+    if (G->M > 0 && (!caller || !sorted)) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (caller == sorted && G->M > 0) return wp_set_error(WP_EINVAL, "wp_to_sorted is out-of-place");
+    return launch_permute(G, (const float2 *)caller, (float2 *)sorted, true, as_stream(stream));
+}
+
+wp_status wp_to_caller(const wp_G *G, const void *sorted, void *caller, void *stream) {
+    if (wp_status s = check_G(nullptr, G, false)) return s;
+    if (G->M > 0 && (!caller || !sorted)) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (caller == sorted && G->M > 0) return wp_set_error(WP_EINVAL, "wp_to_caller is out-of-place");
+    return launch_permute(G, (const float2 *)sorted, (float2 *)caller, false, as_stream(stream));
+}
+
 wp_status wp_apply_PhiT(const wp_plan *p, const wp_G *G, const void *y, void *x, void *grid, void *stream) {
     if (wp_status s = check_plan(p)) return s;
-    if (wp_status s = check_G(p, G, true)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
     if (!x || !grid || (G->M > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
     hipStream_t s = as_stream(stream);
-    if (wp_status st = launch_scatter(p, G, (const float2 *)y, (float2 *)grid, s)) return st;
+    wp_status st = G->tcolptr ? launch_gather(p, G, (const float2 *)y, (float2 *)grid, s)
+                              : launch_scatter(p, G, (const float2 *)y, (float2 *)grid, s);
+    if (st != WP_OK) return st;
     return launch_grid_adjoint(p, (float2 *)grid, (float2 *)x, s);
 }
 

@@ -551,10 +551,62 @@ __global__ void k_write_items(const int *__restrict__ tstart, const int *__restr
     }
 }
 
+// ---------------------------------------------------------------------------- transposed copy (gather form of G^H)
+
+__global__ void k_t_count(const int *__restrict__ col, int64_t nnz, int *__restrict__ cnt) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nnz; j += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[col[j]], 1);
+}
+
+template <typename TapT>
+__global__ void k_t_fill(const int64_t *__restrict__ rowptr, const int *__restrict__ col, const TapT *__restrict__ val,
+                         const int *__restrict__ perm, int64_t M, const int64_t *__restrict__ tcolptr,
+                         int *__restrict__ cur, int *__restrict__ trow, TapT *__restrict__ tval) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (r >= M) return;
+    for (int64_t j = rowptr[r] + lane; j < rowptr[r + 1]; j += 64) {
+        const int c = col[j];
+        const int64_t pos = tcolptr[c] + atomicAdd(&cur[c], 1);
+        trow[pos] = (int)r;
+        tval[pos] = val[j];
+    }
+    (void)perm;
+}
+
+// order each cell's entries by sorted row index (shell sort, one thread per cell)
+template <typename TapT>
+__global__ void k_t_sort(const int64_t *__restrict__ tcolptr, int64_t cells, int *__restrict__ trow,
+                         TapT *__restrict__ tval) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int64_t b = tcolptr[c];
+    const int n = (int)(tcolptr[c + 1] - b);
+    int *kr = trow + b;
+    TapT *kv = tval + b;
+    int gap = 1;
+    while (gap < n / 3) gap = 3 * gap + 1;
+    for (; gap > 0; gap /= 3) {
+        for (int i = gap; i < n; ++i) {
+            const int key = kr[i];
+            const TapT vv = kv[i];
+            int j = i;
+            while (j >= gap && kr[j - gap] > key) {
+                kr[j] = kr[j - gap];
+                kv[j] = kv[j - gap];
+                j -= gap;
+            }
+            kr[j] = key;
+            kv[j] = vv;
+        }
+    }
+}
+
 inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct WsLayout {
-    int64_t tau, nnz, key, k0, k1, i0, i1, flags, zpos, snnz, rowptr, sc32, sc64, tstart, tend, nch, choff, err, total;
+    int64_t tau, nnz, key, k0, k1, i0, i1, flags, zpos, snnz, rowptr, sc32, sc64, tstart, tend, nch, choff, err,
+        tcnt, sc64t, total;
 };
 
 WsLayout ws_layout(const wp_plan *p, int64_t M) {
@@ -580,6 +632,9 @@ WsLayout ws_layout(const wp_plan *p, int64_t M) {
     L.nch = take(4 * T);
     L.choff = take(4 * (T + 1));
     L.err = take(16);
+    const int64_t cells = (int64_t)p->Ng * p->Ng;
+    L.tcnt = take(4 * cells);
+    L.sc64t = take(8 * scan_scratch_elems(cells));
     L.total = o;
     return L;
 }
@@ -687,7 +742,7 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
 wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
                             const void *wsv, wp_G *G, hipStream_t s) {
     (void)E;
-    const unsigned char *ws = (const unsigned char *)wsv;
+    unsigned char *ws = (unsigned char *)const_cast<void *>(wsv);
     const WsLayout L = ws_layout(p, M);
     const int T = p->ntile * p->ntile;
     WP_HIP(hipMemcpyAsync(G->rowptr, ws + L.rowptr, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
@@ -708,5 +763,33 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
     const dim3 gT((unsigned)((T + nthr - 1) / nthr));
     hipLaunchKernelGGL(k_write_items, gT, dim3(nthr), 0, s, (const int *)(ws + L.tstart), (const int *)(ws + L.tend),
                        (const int *)(ws + L.choff), T, p->ntile, G->work);
-    return wp_check_launch("build_G_fill layout");
+    if ((st = wp_check_launch("build_G_fill layout")) != WP_OK) return st;
+    if (G->tcolptr) {
+        const int64_t cells = (int64_t)p->Ng * p->Ng;
+        int *cnt = (int *)(ws + L.tcnt);          // the workspace is const to callers; this region is scratch
+        WP_HIP(hipMemsetAsync(cnt, 0, 4 * cells, s));
+        if (G->nnz > 0) {
+            int64_t nb = (G->nnz + nthr - 1) / nthr;
+            if (nb > 65536) nb = 65536;
+            hipLaunchKernelGGL(k_t_count, dim3((unsigned)nb), dim3(nthr), 0, s, G->col, G->nnz, cnt);
+        }
+        device_scan<int, int64_t>(cnt, G->tcolptr, cells, (int64_t *)(ws + L.sc64t), s);
+        WP_HIP(hipMemsetAsync(cnt, 0, 4 * cells, s));
+        const dim3 gR((unsigned)((M * 64 + nthr - 1) / nthr));
+        if (G->taps == WP_TAPS_BF16)
+            hipLaunchKernelGGL((k_t_fill<uint32_t>), gR, dim3(nthr), 0, s, G->rowptr, G->col,
+                               (const uint32_t *)G->val, G->perm, M, G->tcolptr, cnt, G->trow, (uint32_t *)G->tval);
+        else
+            hipLaunchKernelGGL((k_t_fill<float2>), gR, dim3(nthr), 0, s, G->rowptr, G->col, (const float2 *)G->val,
+                               G->perm, M, G->tcolptr, cnt, G->trow, (float2 *)G->tval);
+        const dim3 gC((unsigned)((cells + nthr - 1) / nthr));
+        if (G->taps == WP_TAPS_BF16)
+            hipLaunchKernelGGL((k_t_sort<uint32_t>), gC, dim3(nthr), 0, s, G->tcolptr, cells, G->trow,
+                               (uint32_t *)G->tval);
+        else
+            hipLaunchKernelGGL((k_t_sort<float2>), gC, dim3(nthr), 0, s, G->tcolptr, cells, G->trow,
+                               (float2 *)G->tval);
+        if ((st = wp_check_launch("build_G_fill transpose")) != WP_OK) return st;
+    }
+    return WP_OK;
 }

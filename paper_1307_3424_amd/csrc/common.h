@@ -23,6 +23,8 @@ struct wp_plan {
     int halo;       // adjoint scatter: LDS window margin per side
     int ntile;      // tiles per axis
     int device;
+    int tune_degrid_lpr, tune_degrid_u;   // 0: automatic (see spmv.hip)
+    int tune_gather_lpr, tune_gather_u;
     float *apod;    // [N]  1 / g(xi), xi = (p - N/2) / Ng       (device)
     float2 *tw32;   // [Ng] exp(-2 pi i k / Ng), FP32             (device)
     double2 *tw64;  // [Ng] exp(-2 pi i k / Ng), FP64             (device)
@@ -94,7 +96,9 @@ wp_status launch_grid_adjoint(const wp_plan *p, float2 *grid, float2 *x, hipStre
 // sparse products (spmv.hip)
 wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, float2 *y, hipStream_t s);
 wp_status launch_scatter(const wp_plan *p, const wp_G *G, const float2 *y, float2 *grid, hipStream_t s);
+wp_status launch_gather(const wp_plan *p, const wp_G *G, const float2 *y, float2 *grid, hipStream_t s);
 wp_status launch_fill_zero(float *buf, int64_t n, hipStream_t s);
+wp_status launch_permute(const wp_G *G, const float2 *in, float2 *out, bool to_sorted, hipStream_t s);
 
 // builder (builder.hip)
 int64_t builder_workspace_bytes(const wp_plan *p, int64_t M);
@@ -103,3 +107,4 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
                              hipStream_t s);
 wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v,
                             const double *w, double E, const void *ws, wp_G *G, hipStream_t s);
+

@@ -13,8 +13,17 @@
 
 namespace {
 
-constexpr int FFT_NTH = 256;
-constexpr int FFT_ELEMS = 4096;   // complex values per block (32 KB of LDS)
+// Launch shape per grid size: rows per block / threads of the row passes, columns per
+// block / threads of the column passes.  Small grids favour many small blocks (the
+// transform is latency-bound there); large ones favour wider column strips (coalescing).
+template <int LOGNG> struct Shape;
+template <> struct Shape<6> { static constexpr int CR = 4, TR = 64, CC = 4, TC = 64; };
+template <> struct Shape<7> { static constexpr int CR = 2, TR = 64, CC = 4, TC = 64; };
+template <> struct Shape<8> { static constexpr int CR = 1, TR = 64, CC = 2, TC = 64; };
+template <> struct Shape<9> { static constexpr int CR = 1, TR = 64, CC = 2, TC = 128; };
+template <> struct Shape<10> { static constexpr int CR = 1, TR = 128, CC = 4, TC = 256; };
+template <> struct Shape<11> { static constexpr int CR = 1, TR = 256, CC = 4, TC = 512; };
+template <> struct Shape<12> { static constexpr int CR = 1, TR = 512, CC = 2, TC = 512; };
 
 __device__ inline float apod_at(const float *__restrict__ apod, int N, int aphys, float delta, int im,
                                 int iu) {
@@ -29,15 +38,15 @@ __device__ inline float apod_at(const float *__restrict__ apod, int N, int aphys
 __device__ inline float sgn(int k) { return (k & 1) ? -1.0f : 1.0f; }
 
 // Forward, pass 1: rows.  Block handles C image rows (padded rows jv = im + N/2).
-template <int LOGNG, int C>
-__global__ __launch_bounds__(FFT_NTH) void k_fwd_rows(const float2 *__restrict__ x, float2 *__restrict__ grid,
+template <int LOGNG, int C, int NTH>
+__global__ __launch_bounds__(NTH) void k_fwd_rows(const float2 *__restrict__ x, float2 *__restrict__ grid,
                                                       const float *__restrict__ apod, const float2 *__restrict__ tw,
                                                       int aphys, float delta) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     __shared__ float2 buf[C * Ng];
     const int tid = threadIdx.x;
     const int im0 = blockIdx.x * C;
-    for (int e = tid; e < C * Ng; e += FFT_NTH) {
+    for (int e = tid; e < C * Ng; e += NTH) {
         const int c = e / Ng, j = e % Ng, im = im0 + c;
         float2 v = make_float2(0.f, 0.f);
         if (j >= N / 2 && j < N / 2 + N) {
@@ -50,29 +59,29 @@ __global__ __launch_bounds__(FFT_NTH) void k_fwd_rows(const float2 *__restrict__
         buf[c * Ng + j] = v;
     }
     __syncthreads();
-    lds_fft<float2, LOGNG, C, FFT_NTH, true, Ng>(buf, tw, false, tid);
-    for (int e = tid; e < C * Ng; e += FFT_NTH) {
+    lds_fft<float2, LOGNG, C, NTH, true, Ng>(buf, tw, false, tid);
+    for (int e = tid; e < C * Ng; e += NTH) {
         const int c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
         grid[(int64_t)jv * Ng + q] = buf[c * Ng + q];
     }
 }
 
 // Forward, pass 2: columns (block handles C adjacent columns), in place.
-template <int LOGNG, int C>
-__global__ __launch_bounds__(FFT_NTH) void k_fwd_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
+template <int LOGNG, int C, int NTH>
+__global__ __launch_bounds__(NTH) void k_fwd_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     __shared__ float2 buf[Ng * C];
     const int tid = threadIdx.x;
     const int qu0 = blockIdx.x * C;
-    for (int e = tid; e < Ng * C; e += FFT_NTH) {
+    for (int e = tid; e < Ng * C; e += NTH) {
         const int jv = e / C, c = e % C;
         float2 v = make_float2(0.f, 0.f);
         if (jv >= N / 2 && jv < N / 2 + N) v = grid[(int64_t)jv * Ng + qu0 + c];
         buf[jv * C + c] = v;
     }
     __syncthreads();
-    lds_fft<float2, LOGNG, C, FFT_NTH, false, C>(buf, tw, false, tid);
-    for (int e = tid; e < Ng * C; e += FFT_NTH) {
+    lds_fft<float2, LOGNG, C, NTH, false, C>(buf, tw, false, tid);
+    for (int e = tid; e < Ng * C; e += NTH) {
         const int qv = e / C, c = e % C;
         float2 v = buf[qv * C + c];
         const float s = sgn(qv + qu0 + c);
@@ -81,42 +90,42 @@ __global__ __launch_bounds__(FFT_NTH) void k_fwd_cols(float2 *__restrict__ grid,
 }
 
 // Adjoint, pass 1: columns, inverse, keep the central N rows, in place.
-template <int LOGNG, int C>
-__global__ __launch_bounds__(FFT_NTH) void k_adj_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
+template <int LOGNG, int C, int NTH>
+__global__ __launch_bounds__(NTH) void k_adj_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     __shared__ float2 buf[Ng * C];
     const int tid = threadIdx.x;
     const int qu0 = blockIdx.x * C;
-    for (int e = tid; e < Ng * C; e += FFT_NTH) {
+    for (int e = tid; e < Ng * C; e += NTH) {
         const int qv = e / C, c = e % C;
         float2 v = grid[(int64_t)qv * Ng + qu0 + c];
         const float s = sgn(qv + qu0 + c);
         buf[qv * C + c] = make_float2(v.x * s, v.y * s);
     }
     __syncthreads();
-    lds_fft<float2, LOGNG, C, FFT_NTH, false, C>(buf, tw, true, tid);
-    for (int e = tid; e < N * C; e += FFT_NTH) {
+    lds_fft<float2, LOGNG, C, NTH, false, C>(buf, tw, true, tid);
+    for (int e = tid; e < N * C; e += NTH) {
         const int jv = N / 2 + e / C, c = e % C;
         grid[(int64_t)jv * Ng + qu0 + c] = buf[jv * C + c];
     }
 }
 
 // Adjoint, pass 2: rows, inverse, crop the central N, apodise, write the image.
-template <int LOGNG, int C>
-__global__ __launch_bounds__(FFT_NTH) void k_adj_rows(const float2 *__restrict__ grid, float2 *__restrict__ x,
+template <int LOGNG, int C, int NTH>
+__global__ __launch_bounds__(NTH) void k_adj_rows(const float2 *__restrict__ grid, float2 *__restrict__ x,
                                                       const float *__restrict__ apod, const float2 *__restrict__ tw,
                                                       int aphys, float delta) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     __shared__ float2 buf[C * Ng];
     const int tid = threadIdx.x;
     const int im0 = blockIdx.x * C;
-    for (int e = tid; e < C * Ng; e += FFT_NTH) {
+    for (int e = tid; e < C * Ng; e += NTH) {
         const int c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
         buf[c * Ng + q] = grid[(int64_t)jv * Ng + q];
     }
     __syncthreads();
-    lds_fft<float2, LOGNG, C, FFT_NTH, true, Ng>(buf, tw, true, tid);
-    for (int e = tid; e < C * N; e += FFT_NTH) {
+    lds_fft<float2, LOGNG, C, NTH, true, Ng>(buf, tw, true, tid);
+    for (int e = tid; e < C * N; e += NTH) {
         const int c = e / N, iu = e % N, im = im0 + c;
         const int ju = iu + N / 2, jv = im + N / 2;
         const float s = apod_at(apod, N, aphys, delta, im, iu) * sgn(ju + jv);
@@ -128,21 +137,21 @@ __global__ __launch_bounds__(FFT_NTH) void k_adj_rows(const float2 *__restrict__
 template <int LOGNG>
 wp_status fwd(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
-    constexpr int C = (FFT_ELEMS / Ng > N) ? N : FFT_ELEMS / Ng;
-    static_assert(N % C == 0 && Ng % C == 0, "tile");
-    hipLaunchKernelGGL((k_fwd_rows<LOGNG, C>), dim3(N / C), dim3(FFT_NTH), 0, s, x, grid, p->apod, p->tw32,
-                       p->aphys, (float)p->delta);
-    hipLaunchKernelGGL((k_fwd_cols<LOGNG, C>), dim3(Ng / C), dim3(FFT_NTH), 0, s, grid, p->tw32);
+    using S = Shape<LOGNG>;
+    static_assert(N % S::CR == 0 && Ng % S::CC == 0, "shape");
+    hipLaunchKernelGGL((k_fwd_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR), dim3(S::TR), 0, s, x, grid, p->apod,
+                       p->tw32, p->aphys, (float)p->delta);
+    hipLaunchKernelGGL((k_fwd_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC), dim3(S::TC), 0, s, grid, p->tw32);
     return wp_check_launch("grid_forward");
 }
 
 template <int LOGNG>
 wp_status adj(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
-    constexpr int C = (FFT_ELEMS / Ng > N) ? N : FFT_ELEMS / Ng;
-    hipLaunchKernelGGL((k_adj_cols<LOGNG, C>), dim3(Ng / C), dim3(FFT_NTH), 0, s, grid, p->tw32);
-    hipLaunchKernelGGL((k_adj_rows<LOGNG, C>), dim3(N / C), dim3(FFT_NTH), 0, s, grid, x, p->apod, p->tw32,
-                       p->aphys, (float)p->delta);
+    using S = Shape<LOGNG>;
+    hipLaunchKernelGGL((k_adj_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC), dim3(S::TC), 0, s, grid, p->tw32);
+    hipLaunchKernelGGL((k_adj_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR), dim3(S::TR), 0, s, grid, x, p->apod,
+                       p->tw32, p->aphys, (float)p->delta);
     return wp_check_launch("grid_adjoint");
 }
 

@@ -25,44 +25,48 @@ __device__ __forceinline__ float2 load_tap(const void *__restrict__ val, int64_t
     else return ((const float2 *)val)[j];
 }
 
-template <bool BF16, int U>
+// LPR lanes per row (64 / LPR rows per wave); each lane keeps U taps in flight.
+template <bool BF16, int LPR, int U>
 __global__ __launch_bounds__(SP_NTH) void k_degrid(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                    const void *__restrict__ val, const float2 *__restrict__ grid,
                                                    const int *__restrict__ perm, float2 *__restrict__ y, int64_t M) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // perm == nullptr: y in sorted row order
+    const int sub = threadIdx.x & (LPR - 1);
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t r = blk * WAVES + wid;
-    if (r >= M) return;
-    const int64_t beg = rowptr[r], end = rowptr[r + 1];
+    const int64_t r = (blk * SP_NTH + threadIdx.x) / LPR;
     float ar = 0.f, ai = 0.f;
-    for (int64_t j0 = beg + lane; j0 < end; j0 += 64 * U) {
-        int c[U];
-        float2 v[U];
+    if (r < M) {
+        const int64_t beg = rowptr[r], end = rowptr[r + 1];
+        for (int64_t j0 = beg + sub; j0 < end; j0 += LPR * U) {
+            int c[U];
+            float2 v[U];
 #pragma unroll
-        for (int t = 0; t < U; ++t) {
-            const int64_t j = j0 + 64 * t;
-            if (j < end) {
-                c[t] = col[j];
-                v[t] = load_tap<BF16>(val, j);
-            } else {
-                c[t] = 0;
-                v[t] = make_float2(0.f, 0.f);
+            for (int t = 0; t < U; ++t) {
+                const int64_t j = j0 + LPR * t;
+                if (j < end) {
+                    c[t] = col[j];
+                    v[t] = load_tap<BF16>(val, j);
+                } else {
+                    c[t] = 0;
+                    v[t] = make_float2(0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const float2 g = grid[c[t]];
+                ar = fmaf(v[t].x, g.x, ar);
+                ar = fmaf(-v[t].y, g.y, ar);
+                ai = fmaf(v[t].x, g.y, ai);
+                ai = fmaf(v[t].y, g.x, ai);
             }
         }
-#pragma unroll
-        for (int t = 0; t < U; ++t) {
-            const float2 g = grid[c[t]];
-            ar = fmaf(v[t].x, g.x, ar);
-            ar = fmaf(-v[t].y, g.y, ar);
-            ai = fmaf(v[t].x, g.y, ai);
-            ai = fmaf(v[t].y, g.x, ai);
-        }
     }
-    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
         ar += __shfl_xor(ar, o);
         ai += __shfl_xor(ai, o);
     }
-    if (lane == 0) y[perm[r]] = make_float2(ar, ai);
+    if (sub == 0 && r < M) y[perm ? perm[r] : r] = make_float2(ar, ai);
 }
 
 template <bool BF16>
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int r = rb + wid; r < re; r += WAVES) {
-        const float2 yk = y[perm[r]];
+        const float2 yk = y[perm ? perm[r] : r];
         const int64_t end = rowptr[r + 1];
         for (int64_t j = rowptr[r] + lane; j < end; j += 64) {
             const int c = col[j];
@@ -114,6 +118,61 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
     }
 }
 
+// Gather form of G^H: grid cell c sums conj(G_kc) y_k over its entries of the
+// transposed copy.  LPR lanes per cell (64 / LPR cells per wave), U entries in
+// flight per lane, cells in order, every cell written once (no atomics).
+template <bool BF16, int LPR, int U>
+__global__ __launch_bounds__(SP_NTH) void k_gather(const int64_t *__restrict__ tcolptr, const int *__restrict__ trow,
+                                                   const void *__restrict__ tval, const float2 *__restrict__ y,
+                                                   const int *__restrict__ perm, float2 *__restrict__ grid,
+                                                   int64_t cells) {
+    // perm == nullptr: y in sorted row order
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t c = (blk * SP_NTH + threadIdx.x) / LPR;
+    const int sub = threadIdx.x & (LPR - 1);
+    float ar = 0.f, ai = 0.f;
+    if (c < cells) {
+        const int64_t beg = tcolptr[c], end = tcolptr[c + 1];
+        for (int64_t j0 = beg + sub; j0 < end; j0 += LPR * U) {
+            int k[U];
+            float2 v[U];
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const int64_t j = j0 + LPR * t;
+                if (j < end) {
+                    k[t] = perm ? perm[trow[j]] : trow[j];
+                    v[t] = load_tap<BF16>(tval, j);
+                } else {
+                    k[t] = -1;
+                    v[t] = make_float2(0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                const float2 yk = k[t] >= 0 ? y[k[t]] : make_float2(0.f, 0.f);
+                ar = fmaf(v[t].x, yk.x, ar);          // conj(v) * y
+                ar = fmaf(v[t].y, yk.y, ar);
+                ai = fmaf(v[t].x, yk.y, ai);
+                ai = fmaf(-v[t].y, yk.x, ai);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+        ar += __shfl_xor(ar, o);
+        ai += __shfl_xor(ai, o);
+    }
+    if (sub == 0 && c < cells) grid[c] = make_float2(ar, ai);
+}
+
+__global__ void k_permute(const float2 *__restrict__ in, const int *__restrict__ perm, float2 *__restrict__ out,
+                          int64_t M, bool to_sorted) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    if (to_sorted) out[r] = in[perm[r]];
+    else out[perm[r]] = in[r];
+}
+
 __global__ void k_fill_zero(float4 *__restrict__ p, int64_t n4) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -131,17 +190,73 @@ wp_status launch_fill_zero(float *buf, int64_t n, hipStream_t s) {
     return wp_check_launch("fill_zero");
 }
 
+// Lanes per row / cell: tune > 0 forces a value (plan tuning), else the power of
+// two nearest mean / div in [4, 64] (measured on MI355X: rows of ~200 taps run best
+// with a full wave and 4 loads in flight; grid cells of ~25 entries with 16 lanes
+// and 8 loads).
+int pick_lpr(double mean, double div, int tune) {
+    if (tune > 0) return tune;
+    int l = 4;
+    while (l < 64 && (double)l * 1.5 < mean / div) l *= 2;
+    return l;
+}
+
+#define WP_SPMV_DISPATCH(KERNEL, BF16, LPR, U, GRID, ...)                                            \
+    do {                                                                                             \
+        switch ((LPR) * 100 + (U)) {                                                                 \
+            case 404: hipLaunchKernelGGL((KERNEL<BF16, 4, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 408: hipLaunchKernelGGL((KERNEL<BF16, 4, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 804: hipLaunchKernelGGL((KERNEL<BF16, 8, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 808: hipLaunchKernelGGL((KERNEL<BF16, 8, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 1604: hipLaunchKernelGGL((KERNEL<BF16, 16, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 1608: hipLaunchKernelGGL((KERNEL<BF16, 16, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 1616: hipLaunchKernelGGL((KERNEL<BF16, 16, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 3204: hipLaunchKernelGGL((KERNEL<BF16, 32, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 3208: hipLaunchKernelGGL((KERNEL<BF16, 32, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 3216: hipLaunchKernelGGL((KERNEL<BF16, 32, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 6404: hipLaunchKernelGGL((KERNEL<BF16, 64, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 6408: hipLaunchKernelGGL((KERNEL<BF16, 64, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<BF16, 64, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+        }                                                                                            \
+    } while (0)
+
+// the permutation applied to visibility vectors (nullptr when they are in sorted order)
+const int *yperm(const wp_G *G) { return G->order == WP_ORDER_SORTED ? nullptr : G->perm; }
+
+bool valid_lpr_u(int lpr, int u) {
+    switch (lpr * 100 + u) {
+        case 404: case 408: case 804: case 808: case 1604: case 1608: case 1616: case 3204: case 3208: case 3216:
+        case 6404: case 6408: case 6416: return true;
+    }
+    return false;
+}
+
 wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, float2 *y, hipStream_t s) {
-    (void)p;
     if (G->M == 0) return WP_OK;
-    const int64_t nb = (G->M + WAVES - 1) / WAVES;
+    const int U = p->tune_degrid_u > 0 ? p->tune_degrid_u : 4;
+    const int lpr = pick_lpr((double)G->nnz / (double)G->M, 4.0, p->tune_degrid_lpr);
+    if (!valid_lpr_u(lpr, U)) return wp_set_error(WP_EINVAL, "degrid: no kernel for lanes %d, unroll %d", lpr, U);
+    const int64_t nb = (G->M * lpr + SP_NTH - 1) / SP_NTH;
+    const dim3 g((unsigned)nb);
     if (G->taps == WP_TAPS_BF16)
-        hipLaunchKernelGGL((k_degrid<true, 4>), dim3((unsigned)nb), dim3(SP_NTH), 0, s, G->rowptr, G->col, G->val, grid,
-                           G->perm, y, G->M);
+        WP_SPMV_DISPATCH(k_degrid, true, lpr, U, g, s, G->rowptr, G->col, G->val, grid, yperm(G), y, G->M);
     else
-        hipLaunchKernelGGL((k_degrid<false, 4>), dim3((unsigned)nb), dim3(SP_NTH), 0, s, G->rowptr, G->col, G->val,
-                           grid, G->perm, y, G->M);
+        WP_SPMV_DISPATCH(k_degrid, false, lpr, U, g, s, G->rowptr, G->col, G->val, grid, yperm(G), y, G->M);
     return wp_check_launch("degrid");
+}
+
+wp_status launch_gather(const wp_plan *p, const wp_G *G, const float2 *y, float2 *grid, hipStream_t s) {
+    const int64_t cells = (int64_t)p->Ng * p->Ng;
+    const int U = p->tune_gather_u > 0 ? p->tune_gather_u : 8;
+    const int lpr = pick_lpr((double)G->nnz / (double)cells, 2.0, p->tune_gather_lpr);
+    if (!valid_lpr_u(lpr, U)) return wp_set_error(WP_EINVAL, "gather: no kernel for lanes %d, unroll %d", lpr, U);
+    const int64_t nb = (cells * lpr + SP_NTH - 1) / SP_NTH;
+    const dim3 g((unsigned)nb);
+    if (G->taps == WP_TAPS_BF16)
+        WP_SPMV_DISPATCH(k_gather, true, lpr, U, g, s, G->tcolptr, G->trow, G->tval, y, yperm(G), grid, cells);
+    else
+        WP_SPMV_DISPATCH(k_gather, false, lpr, U, g, s, G->tcolptr, G->trow, G->tval, y, yperm(G), grid, cells);
+    return wp_check_launch("grid_gather");
 }
 
 wp_status launch_scatter(const wp_plan *p, const wp_G *G, const float2 *y, float2 *grid, hipStream_t s) {
@@ -151,9 +266,16 @@ wp_status launch_scatter(const wp_plan *p, const wp_G *G, const float2 *y, float
     const size_t lds = (size_t)2 * WS * WS * sizeof(float);
     if (G->taps == WP_TAPS_BF16)
         hipLaunchKernelGGL((k_scatter<true>), dim3((unsigned)G->n_work), dim3(SP_NTH), lds, s, G->work, G->n_work,
-                           G->rowptr, G->col, G->val, G->perm, y, (float *)grid, p->logNg, p->tile, p->halo);
+                           G->rowptr, G->col, G->val, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
     else
         hipLaunchKernelGGL((k_scatter<false>), dim3((unsigned)G->n_work), dim3(SP_NTH), lds, s, G->work, G->n_work,
-                           G->rowptr, G->col, G->val, G->perm, y, (float *)grid, p->logNg, p->tile, p->halo);
+                           G->rowptr, G->col, G->val, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
     return wp_check_launch("grid_scatter");
+}
+
+wp_status launch_permute(const wp_G *G, const float2 *in, float2 *out, bool to_sorted, hipStream_t s) {
+    if (G->M == 0) return WP_OK;
+    hipLaunchKernelGGL(k_permute, dim3((unsigned)((G->M + 255) / 256)), dim3(256), 0, s, in, G->perm, out, G->M,
+                       to_sorted);
+    return wp_check_launch("permute");
 }

@@ -62,4 +62,4 @@ def test_null_arguments_rejected():
 
 
 def test_wp_G_layout_matches_header():
-    assert C.sizeof(_lib.WpG) == 8 * 2 + 4 * 2 + 8 * 5 + 8
+    assert C.sizeof(_lib.WpG) == 8 * 2 + 4 * 2 + 8 * 5 + 8 + 8 * 3

@@ -156,11 +156,49 @@ def test_phi_and_adjoint_tiny_form():
     y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
     assert relerr(y, wproj.phi(Go, x, s)) < TOL
     yv = synth.random_complex(wl.M, synth.rng_for(wl.seed, "y"))
-    xa = wp.apply_PhiT(plan, G, c64(yv)).cpu().numpy().reshape(wl.N, wl.N)
-    assert relerr(xa, wproj.phi_adjoint(Go, yv, s)) < TOL
+    x_ref = wproj.phi_adjoint(Go, yv, s)
+    for use_t in (True, False):            # gather over the transposed copy, tiled scatter
+        G.use_transpose = use_t
+        xa = wp.apply_PhiT(plan, G, c64(yv)).cpu().numpy().reshape(wl.N, wl.N)
+        assert relerr(xa, x_ref) < TOL, use_t
 
 
-def test_phi_plain_form_sampled_rows():
+@pytest.mark.parametrize("taps", ["c64", "bf16"])
+def test_gather_and_scatter_grid_match_oracle(taps):
+    wl = synth.workload(0)
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    t = wp.WP_TAPS_C64 if taps == "c64" else wp.WP_TAPS_BF16
+    G = build(plan, u, v, w, wl.E, taps=t)
+    yv = synth.random_complex(wl.M, synth.rng_for(wl.seed, "y", 5))
+    Xg = wp.grid_gather(plan, G, c64(yv)).cpu().numpy()
+    Xs = wp.grid_scatter(plan, G, c64(yv)).cpu().numpy()
+    Go = wproj.build_rows(u, v, w, wl.E, s)
+    X_ref = Go.conj().T @ yv
+    tol = TOL if taps == "c64" else 4e-3
+    assert relerr(Xg, X_ref) < tol and relerr(Xs, X_ref) < tol
+    assert relerr(Xg, Xs) < 1e-5
+
+
+def test_transposed_copy_structure():
+    wl = synth.workload(1)
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    rp, col, val, perm, inv = gpu_rows(G)
+    tcp = G.tcolptr.cpu().numpy()
+    trow = G.trow.cpu().numpy()[:G.nnz]
+    tval = G.tval.cpu().numpy()[:G.nnz]
+    assert tcp[0] == 0 and tcp[-1] == G.nnz and np.all(np.diff(tcp) >= 0)
+    # same (row, cell, value) triples as the rows, each cell's entries ordered by sorted row
+    rows_of = np.repeat(np.arange(wl.M), np.diff(rp))
+    a = np.lexsort((rows_of, col))
+    cells_t = np.repeat(np.arange(tcp.size - 1), np.diff(tcp))
+    assert np.array_equal(col[a], cells_t)
+    assert np.array_equal(rows_of[a], trow)
+    assert np.array_equal(val[a], tval)
+
     wl = synth.workload(1)
     say(f"apply: {wl.name} full size, sampled outputs")
     x, u, v, w = synth.workload_inputs(wl)
@@ -217,7 +255,32 @@ def test_phi_deterministic_and_adjoint_repeatable():
     assert torch.equal(y1, y2)
     a1 = wp.apply_PhiT(plan, G, y1)
     a2 = wp.apply_PhiT(plan, G, y1)
-    assert (torch.linalg.norm(a1 - a2) / torch.linalg.norm(a1)).item() < 1e-6
+    assert torch.equal(a1, a2)                 # gather form: no atomics, bitwise repeatable
+    G.use_transpose = False
+    s1 = wp.apply_PhiT(plan, G, y1)
+    s2 = wp.apply_PhiT(plan, G, y1)
+    assert (torch.linalg.norm(s1 - s2) / torch.linalg.norm(s1)).item() < 1e-6
+    assert (torch.linalg.norm(s1 - a1) / torch.linalg.norm(a1)).item() < 1e-5
+
+
+def test_sorted_order_matches_caller_order():
+    wl = synth.workload(1)
+    x, u, v, w = synth.workload_inputs(wl)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    xd = c64(x)
+    yc = wp.apply_Phi(plan, G, xd)
+    G.order = wp.WP_ORDER_SORTED
+    ys = wp.apply_Phi(plan, G, xd)
+    assert torch.equal(wp.to_sorted(G, yc), ys)
+    assert torch.equal(wp.to_caller(G, ys), yc)
+    for use_t in (True, False):
+        G.use_transpose = use_t
+        G.order = wp.WP_ORDER_SORTED
+        a_s = wp.apply_PhiT(plan, G, ys)
+        G.order = wp.WP_ORDER_CALLER
+        a_c = wp.apply_PhiT(plan, G, yc)
+        assert (torch.linalg.norm(a_s - a_c) / torch.linalg.norm(a_c)).item() < 1e-6
 
 
 # --------------------------------------------------------------------------- edge cases
