@@ -50,7 +50,8 @@ wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
         return wp_set_error(WP_EINVAL, "G has a NULL array");
     if (need_work && G->n_work > 0 && !G->work) return wp_set_error(WP_EINVAL, "G->work is NULL");
     if (need_work && G->n_work > 0x7fffffff) return wp_set_error(WP_ECAPACITY, "G->n_work too large");
-    if (G->tcolptr && G->nnz > 0 && (!G->trow || !G->tval)) return wp_set_error(WP_EINVAL, "G->tcolptr set without trow / tval");
+    if (G->tcolptr && G->nnz > 0 && (!G->trow || !G->tval))
+        return wp_set_error(WP_EINVAL, "G->tcolptr set without trow / tval");
     (void)p;
     return WP_OK;
 }

@@ -247,8 +247,9 @@ wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, flo
 
 wp_status launch_gather(const wp_plan *p, const wp_G *G, const float2 *y, float2 *grid, hipStream_t s) {
     const int64_t cells = (int64_t)p->Ng * p->Ng;
+    if (G->nnz == 0) return launch_fill_zero((float *)grid, 2 * cells, s);
     const int U = p->tune_gather_u > 0 ? p->tune_gather_u : 8;
-    const int lpr = pick_lpr((double)G->nnz / (double)cells, 2.0, p->tune_gather_lpr);
+    const int lpr = pick_lpr((double)G->nnz / (double)cells, 1.25, p->tune_gather_lpr);
     if (!valid_lpr_u(lpr, U)) return wp_set_error(WP_EINVAL, "gather: no kernel for lanes %d, unroll %d", lpr, U);
     const int64_t nb = (cells * lpr + SP_NTH - 1) / SP_NTH;
     const dim3 g((unsigned)nb);
