@@ -189,6 +189,37 @@ wp_status wp_grid_gather(const wp_plan *plan, const wp_G *G, const void *y, void
 wp_status wp_to_sorted(const wp_G *G, const void *caller, void *sorted, void *stream);
 wp_status wp_to_caller(const wp_G *G, const void *sorted, void *caller, void *stream);
 
+/* ----------------------------------------------------------------------------------------
+ * Reconstruction (Eq. 7): min ||Psi^T x||_1 s.t. ||y - Phi x||_2 <= eps, x >= 0, with Psi the
+ * Daubechies wavelets of 8 vanishing moments (Section 4.2), periodic, `levels` levels.
+ * ------------------------------------------------------------------------------------- */
+
+/* The 16 low-pass taps of Daubechies-8 (spectral factorisation, minimum phase, sum sqrt 2); host. */
+wp_status wp_db8_filter(double *h16);
+
+/* c = Psi^T x (analysis) and x = Psi c (synthesis) of a real N x N float image; x and c may
+ * alias; scratch is N*N floats of device memory.  levels >= 1 with N >> (levels-1) >= 8. */
+wp_status wp_dwt2(const wp_plan *plan, int levels, const float *x, float *c, float *scratch,
+                  void *stream);
+wp_status wp_idwt2(const wp_plan *plan, int levels, const float *c, float *x, float *scratch,
+                   void *stream);
+
+/* Device workspace of wp_power_norm2 and wp_solve for this plan and G. */
+wp_status wp_solver_workspace_bytes(const wp_plan *plan, const wp_G *G, int64_t *bytes_out);
+
+/* ||Phi||^2 by power iteration on Re Phi^H Phi from the real image x0 (device, N*N floats):
+ * iters steps; the result is written to *nu_out (host).  Synchronises the stream. */
+wp_status wp_power_norm2(const wp_plan *plan, const wp_G *G, const float *x0, int iters,
+                         void *workspace, double *nu_out, void *stream);
+
+/* Primal-dual solve (Condat / Vu splitting with dual variables for the l1 term and the
+ * l2 ball): tau = 0.49, sigma_1 = 1, sigma_2 = 1 / nu.  x (device, real N*N floats) holds
+ * the start on entry and the estimate on exit; y is c64 [M] in G's visibility order
+ * (G->order); eps is the ball radius, nu = ||Phi||^2.  Dual variables start at zero.
+ * Asynchronous: iters iterations are enqueued with no host synchronisation. */
+wp_status wp_solve(const wp_plan *plan, const wp_G *G, const void *y, double eps, double nu,
+                   int iters, int levels, float *x, void *workspace, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

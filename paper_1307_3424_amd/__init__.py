@@ -21,7 +21,7 @@ from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
-           "WP_ORDER_SORTED", "to_sorted", "to_caller"]
+           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve"]
 
 
 def _torch():
@@ -247,3 +247,69 @@ def to_caller(G: GMatrix, y, out=None, stream=None):
     d = G.desc()
     check(load().wp_to_caller(C.byref(d), _ptr(y), _ptr(out), _stream(stream)), "wp_to_caller")
     return out
+
+
+def db8_filter():
+    """wp_db8_filter: the 16 Daubechies-8 low-pass taps (host list)."""
+    h = (C.c_double * 16)()
+    check(load().wp_db8_filter(h), "wp_db8_filter")
+    return list(h)
+
+
+def _dev_f32(t, n, name):
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous float32 CUDA tensor with {n} elements")
+    return t
+
+
+def dwt2(plan: Plan, x, levels: int = 4, out=None, stream=None):
+    torch = _torch()
+    _dev_f32(x, plan.N * plan.N, "x")
+    out = torch.empty_like(x) if out is None else out
+    scratch = torch.empty_like(x)
+    check(load().wp_dwt2(plan.handle, int(levels), _ptr(x), _ptr(out), _ptr(scratch), _stream(stream)), "wp_dwt2")
+    return out
+
+
+def idwt2(plan: Plan, c, levels: int = 4, out=None, stream=None):
+    torch = _torch()
+    _dev_f32(c, plan.N * plan.N, "c")
+    out = torch.empty_like(c) if out is None else out
+    scratch = torch.empty_like(c)
+    check(load().wp_idwt2(plan.handle, int(levels), _ptr(c), _ptr(out), _ptr(scratch), _stream(stream)),
+          "wp_idwt2")
+    return out
+
+
+def _solver_ws(plan: Plan, G: GMatrix, d):
+    torch = _torch()
+    b = C.c_int64()
+    check(load().wp_solver_workspace_bytes(plan.handle, C.byref(d), C.byref(b)), "wp_solver_workspace_bytes")
+    return torch.empty(b.value, dtype=torch.uint8, device="cuda")
+
+
+def power_norm2(plan: Plan, G: GMatrix, x0, iters: int = 50, stream=None) -> float:
+    """wp_power_norm2 (synchronises)."""
+    _dev_f32(x0, plan.N * plan.N, "x0")
+    d = G.desc()
+    ws = _solver_ws(plan, G, d)
+    nu = C.c_double()
+    check(load().wp_power_norm2(plan.handle, C.byref(d), _ptr(x0), int(iters), _ptr(ws), C.byref(nu),
+                                _stream(stream)), "wp_power_norm2")
+    return nu.value
+
+
+def solve(plan: Plan, G: GMatrix, y, eps: float, nu: float, iters: int, levels: int = 4, x=None, ws=None,
+          stream=None):
+    """wp_solve: x (float32 N*N, zeros by default) is updated in place and returned."""
+    torch = _torch()
+    _dev_c64(y, G.M, "y")
+    x = torch.zeros(plan.N * plan.N, dtype=torch.float32, device=y.device) if x is None else \
+        _dev_f32(x, plan.N * plan.N, "x")
+    d = G.desc()
+    ws = _solver_ws(plan, G, d) if ws is None else ws
+    check(load().wp_solve(plan.handle, C.byref(d), _ptr(y), float(eps), float(nu), int(iters), int(levels),
+                          _ptr(x), _ptr(ws), _stream(stream)), "wp_solve")
+    x._wp_ws = ws
+    return x

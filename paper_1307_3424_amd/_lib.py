@@ -53,6 +53,12 @@ SIGNATURES = {
     "wp_grid_gather": ([_vp, _PG, _vp, _vp, _vp], _i32),
     "wp_to_sorted": ([_PG, _vp, _vp, _vp], _i32),
     "wp_to_caller": ([_PG, _vp, _vp, _vp], _i32),
+    "wp_db8_filter": ([C.POINTER(C.c_double)], _i32),
+    "wp_dwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "wp_idwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
+    "wp_solver_workspace_bytes": ([_vp, _PG, _pi64], _i32),
+    "wp_power_norm2": ([_vp, _PG, _vp, _i32, _vp, C.POINTER(C.c_double), _vp], _i32),
+    "wp_solve": ([_vp, _PG, _vp, _d, _d, _i32, _i32, _vp, _vp, _vp], _i32),
 }
 
 _lib = None

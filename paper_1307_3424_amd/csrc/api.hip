@@ -265,4 +265,51 @@ wp_status wp_apply_PhiT(const wp_plan *p, const wp_G *G, const void *y, void *x,
     return launch_grid_adjoint(p, (float2 *)grid, (float2 *)x, s);
 }
 
+wp_status wp_db8_filter(double *h16) {
+    if (!h16) return wp_set_error(WP_EINVAL, "NULL argument");
+    return filter_db8(h16);
+}
+
+wp_status wp_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *scratch, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!x || !c || !scratch) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_dwt2(p, levels, x, c, scratch, false, as_stream(stream));
+}
+
+wp_status wp_idwt2(const wp_plan *p, int levels, const float *c, float *x, float *scratch, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!x || !c || !scratch) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_dwt2(p, levels, c, x, scratch, true, as_stream(stream));
+}
+
+wp_status wp_solver_workspace_bytes(const wp_plan *p, const wp_G *G, int64_t *bytes) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
+    if (!bytes) return wp_set_error(WP_EINVAL, "NULL argument");
+    *bytes = solver_workspace_bytes(p, G->M);
+    return WP_OK;
+}
+
+wp_status wp_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, int iters, void *workspace,
+                         double *nu_out, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
+    if (!x0 || !workspace || !nu_out) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (iters < 1) return wp_set_error(WP_EINVAL, "iters = %d", iters);
+    return launch_power_norm2(p, G, x0, iters, nu_out, (unsigned char *)workspace, as_stream(stream));
+}
+
+wp_status wp_solve(const wp_plan *p, const wp_G *G, const void *y, double eps, double nu, int iters, int levels,
+                   float *x, void *workspace, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
+    if (!y || !x || !workspace) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (!(eps >= 0.0) || !(nu > 0.0) || !std::isfinite(eps) || !std::isfinite(nu))
+        return wp_set_error(WP_EINVAL, "eps = %g, nu = %g: need eps >= 0 and nu > 0, finite", eps, nu);
+    if (iters < 0) return wp_set_error(WP_EINVAL, "iters = %d", iters);
+    if (levels < 1 || (p->N >> (levels - 1)) < 8) return wp_set_error(WP_EINVAL, "levels = %d", levels);
+    return launch_solve(p, G, (const float2 *)y, eps, nu, iters, levels, x, (unsigned char *)workspace,
+                        as_stream(stream));
+}
+
 }  // extern "C"

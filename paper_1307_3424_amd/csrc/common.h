@@ -108,3 +108,12 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
 wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v,
                             const double *w, double E, const void *ws, wp_G *G, hipStream_t s);
 
+
+// solver (solver.hip)
+int64_t solver_workspace_bytes(const wp_plan *p, int64_t M);
+wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s);
+wp_status launch_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, int iters, double *nu,
+                             unsigned char *ws, hipStream_t s);
+wp_status launch_solve(const wp_plan *p, const wp_G *G, const float2 *y, double eps, double nu, int iters,
+                       int levels, float *x, unsigned char *ws, hipStream_t s);
+wp_status filter_db8(double *h);

@@ -1,0 +1,324 @@
+// Constrained l1 reconstruction (Eq. 7 in its analysis form) on the GPU.
+//
+//   min_x ||Psi^T x||_1  s.t.  ||y - Phi x||_2 <= eps,  x >= 0 (real)
+//
+// Psi: Daubechies wavelets with p = 8 vanishing moments (16 taps), periodic,
+// multi-level, rows then columns per level (Section 4.2 uses Daubechies 8).
+// Splitting: primal-dual with one dual variable per term (Condat 2013 / Vu 2013):
+//   x+  = max(0, x - tau (Psi v1 + Re Phi^H v2)) ;  xb = 2 x+ - x ;  x = x+
+//   v1  = clip(v1 + s1 Psi^T xb, -1, 1)
+//   u   = v2 + s2 Phi xb ;  v2 = u - s2 P(u / s2),  P(z) = y + (z - y) min(1, eps / ||z - y||)
+// with tau = 0.49, s1 = 1, s2 = 1 / ||Phi||^2 and ||Phi||^2 from power iteration.
+// Every step runs in the kernels below or in the operator's kernels; the host
+// loop only enqueues them (no synchronisation inside an iteration).  The
+// residual norm is reduced in FP64 on the device.
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------------------- Daubechies filter (host, FP64)
+// |m0(xi)|^2 = cos^(2p)(xi/2) Q(sin^2(xi/2)), Q(y) = sum_{k<p} C(p-1+k, k) y^k.  Each root y_i of
+// Q gives z + 1/z = 2 (1 - 2 y_i); the minimum-phase factor keeps the z with |z| < 1.  The filter is
+// the polynomial with p zeros at -1 and those z, highest power first, scaled to sum sqrt(2).
+bool daubechies(int p, double *h) {
+    using cd = std::complex<double>;
+    std::vector<double> q(p);
+    for (int k = 0; k < p; ++k) {
+        double c = 1.0;
+        for (int i = 1; i <= k; ++i) c = c * (p - 1 + i) / i;   // C(p-1+k, k)
+        q[k] = c;
+    }
+    const int deg = p - 1;
+    std::vector<cd> roots(deg);
+    // Durand-Kerner on the monic polynomial Q / q[deg]
+    for (int i = 0; i < deg; ++i) roots[i] = std::pow(cd(0.4, 0.9), i);
+    auto Qm = [&](cd yv) {
+        cd acc = 0.0;
+        for (int k = deg; k >= 0; --k) acc = acc * yv + q[k] / q[deg];
+        return acc;
+    };
+    for (int it = 0; it < 2000; ++it) {
+        double delta = 0.0;
+        for (int i = 0; i < deg; ++i) {
+            cd den = 1.0;
+            for (int j = 0; j < deg; ++j)
+                if (j != i) den *= roots[i] - roots[j];
+            const cd step = Qm(roots[i]) / den;
+            roots[i] -= step;
+            delta = std::max(delta, std::abs(step));
+        }
+        if (delta < 1e-15) break;
+    }
+    std::vector<cd> z;
+    for (int k = 0; k < p; ++k) z.push_back(-1.0);
+    for (int i = 0; i < deg; ++i) {
+        const cd b = 1.0 - 2.0 * roots[i];
+        const cd d = std::sqrt(b * b - 1.0);
+        const cd z1 = b + d, z2 = b - d;
+        z.push_back(std::abs(z1) < 1.0 ? z1 : z2);
+    }
+    // expand prod (x - z_i), coefficients highest power first
+    std::vector<cd> c(1, 1.0);
+    for (const cd &r : z) {
+        std::vector<cd> n(c.size() + 1, 0.0);
+        for (size_t i = 0; i < c.size(); ++i) {
+            n[i] += c[i];
+            n[i + 1] -= c[i] * r;
+        }
+        c.swap(n);
+    }
+    double sum = 0.0;
+    for (int i = 0; i < 2 * p; ++i) sum += c[i].real();
+    if (!(std::fabs(sum) > 0)) return false;
+    for (int i = 0; i < 2 * p; ++i) h[i] = c[i].real() * std::sqrt(2.0) / sum;
+    return true;
+}
+
+struct Filt {
+    float h[16], g[16];
+};
+
+// ---------------------------------------------------------------------------- DWT kernels (FP32)
+// One level along lines of length L inside an image of row stride S: line i, element e
+// at in[i * ls + e * es].  Analysis: a_k = sum_n h_n x_(2k+n mod L), d_k = sum_n g_n x_(2k+n mod L),
+// stored [a | d].  Synthesis (the transpose): x_m = sum over n of m's parity of
+// h_n a_((m-n)/2 mod L/2) + g_n d_((m-n)/2 mod L/2).
+__global__ void k_dwt_lines(const float *__restrict__ in, float *__restrict__ out, int L, int lines, int ls,
+                            int es, Filt f, bool synth) {
+    extern __shared__ float line[];
+    for (int i = blockIdx.x; i < lines; i += gridDim.x) {
+        for (int e = threadIdx.x; e < L; e += blockDim.x) line[e] = in[(int64_t)i * ls + (int64_t)e * es];
+        __syncthreads();
+        const int H = L / 2;
+        for (int m = threadIdx.x; m < L; m += blockDim.x) {
+            float acc = 0.f;
+            if (!synth) {
+                const int k = m < H ? m : m - H;
+                const float *w = m < H ? f.h : f.g;
+#pragma unroll
+                for (int n = 0; n < 16; ++n) acc = fmaf(w[n], line[(2 * k + n) % L], acc);
+            } else {
+#pragma unroll
+                for (int n = (m & 1); n < 16; n += 2) {
+                    int k = ((m - n) / 2) % H;
+                    if (k < 0) k += H;
+                    acc = fmaf(f.h[n], line[k], acc);
+                    acc = fmaf(f.g[n], line[H + k], acc);
+                }
+            }
+            out[(int64_t)i * ls + (int64_t)m * es] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------- iteration kernels
+
+// x+ = max(0, x - tau (psi_v1 + Re(phit_v2))); xb = 2 x+ - x; x = x+; xbc = complex(xb)
+__global__ void k_primal(float *__restrict__ x, const float *__restrict__ psi_v1, const float2 *__restrict__ phit_v2,
+                         float *__restrict__ xb, float2 *__restrict__ xbc, int64_t n, float tau,
+                         double *__restrict__ acc_zero) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *acc_zero = 0.0;
+    if (i >= n) return;
+    const float xo = x[i];
+    const float xn = fmaxf(0.f, xo - tau * (psi_v1[i] + phit_v2[i].x));
+    const float b = 2.f * xn - xo;
+    x[i] = xn;
+    xb[i] = b;
+    xbc[i] = make_float2(b, 0.f);
+}
+
+// v1 = clip(v1 + s1 d, -1, 1)
+__global__ void k_dual1(float *__restrict__ v1, const float *__restrict__ d, int64_t n, float s1) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    v1[i] = fminf(1.f, fmaxf(-1.f, v1[i] + s1 * d[i]));
+}
+
+// acc += sum |u / s2 - y|^2, u = v2 + s2 p  (FP64)
+__global__ void k_ball_norm(const float2 *__restrict__ v2, const float2 *__restrict__ p, const float2 *__restrict__ y,
+                            int64_t n, float s2, double *__restrict__ acc) {
+    __shared__ double red[NT / 64];
+    double sum = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double zr = ((double)v2[i].x + (double)s2 * p[i].x) / s2 - y[i].x;
+        const double zi = ((double)v2[i].y + (double)s2 * p[i].y) / s2 - y[i].y;
+        sum += zr * zr + zi * zi;
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        atomicAdd(acc, t);
+    }
+}
+
+// v2 = u - s2 (y + (u/s2 - y) min(1, eps / ||u/s2 - y||)), u = v2 + s2 p
+__global__ void k_dual2(float2 *__restrict__ v2, const float2 *__restrict__ p, const float2 *__restrict__ y,
+                        int64_t n, float s2, double eps, const double *__restrict__ acc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double nrm = sqrt(*acc);
+    const double sc = nrm > eps ? eps / nrm : 1.0;
+    const double ur = (double)v2[i].x + (double)s2 * p[i].x, ui = (double)v2[i].y + (double)s2 * p[i].y;
+    const double zr = ur / s2, zi = ui / s2;
+    const double pr = y[i].x + (zr - y[i].x) * sc, pi = y[i].y + (zi - y[i].y) * sc;
+    v2[i] = make_float2((float)(ur - s2 * pr), (float)(ui - s2 * pi));
+}
+
+// power iteration helpers: acc = sum x^2 (FP64); x = Re(z) / sqrt(acc_prev) etc.
+__global__ void k_sumsq_real(const float2 *__restrict__ z, int64_t n, double *__restrict__ acc) {
+    __shared__ double red[NT / 64];
+    double sum = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        sum += (double)z[i].x * z[i].x;
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        atomicAdd(acc, t);
+    }
+}
+
+__global__ void k_normalise_real(const float2 *__restrict__ z, float2 *__restrict__ xc, int64_t n,
+                                 const double *__restrict__ acc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = 1.0 / sqrt(*acc);
+    xc[i] = make_float2((float)(z[i].x * s), 0.f);
+}
+
+__global__ void k_real_to_c64(const float *__restrict__ x, float2 *__restrict__ xc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) xc[i] = make_float2(x[i], 0.f);
+}
+
+__global__ void k_zero_f64(double *a, int n) {
+    if ((int)threadIdx.x < n) a[threadIdx.x] = 0.0;
+}
+
+inline dim3 blocks_for(int64_t n) { return dim3((unsigned)((n + NT - 1) / NT)); }
+inline dim3 blocks_reduce(int64_t n) {
+    int64_t b = (n + NT - 1) / NT;
+    return dim3((unsigned)(b > 1024 ? 1024 : (b < 1 ? 1 : b)));
+}
+
+Filt make_filter(bool &ok) {
+    double h[16];
+    Filt f{};
+    ok = daubechies(8, h);
+    for (int n = 0; n < 16; ++n) {
+        f.h[n] = (float)h[n];
+        f.g[n] = (float)(((n & 1) ? -1.0 : 1.0) * h[15 - n]);
+    }
+    return f;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------- host side
+
+int64_t solver_workspace_bytes(const wp_plan *p, int64_t M) {
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng;
+    auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    return al(8 * G2) + 4 * al(4 * N2) + 2 * al(8 * N2) + 2 * al(8 * M) + al(64);
+}
+
+wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s) {
+    bool ok;
+    const Filt f = make_filter(ok);
+    if (!ok) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
+    const int N = p->N;
+    if (levels < 1 || (N >> (levels - 1)) < 8) return wp_set_error(WP_EINVAL, "levels = %d too many for N = %d", levels, N);
+    if (c != x) {
+        WP_HIP(hipMemcpyAsync(c, x, sizeof(float) * N * N, hipMemcpyDeviceToDevice, s));
+    }
+    // analysis: level by level, rows then columns on the top-left L x L block;
+    // synthesis: coarsest first, columns then rows.
+    for (int lv = 0; lv < levels; ++lv) {
+        const int L = synth ? (N >> (levels - 1 - lv)) : (N >> lv);
+        const size_t lds = sizeof(float) * L;
+        const int th = L < NT ? L : NT;
+        if (!synth) {
+            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, c, tmp, L, L, N, 1, f, false);   // rows
+            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, tmp, c, L, L, 1, N, f, false);   // columns
+        } else {
+            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, c, tmp, L, L, 1, N, f, true);    // columns
+            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, tmp, c, L, L, N, 1, f, true);    // rows
+        }
+    }
+    return wp_check_launch(synth ? "idwt2" : "dwt2");
+}
+
+wp_status launch_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, int iters, double *nu,
+                             unsigned char *ws, hipStream_t s) {
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng;
+    auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    float2 *grid = (float2 *)ws;
+    float2 *xc = (float2 *)(ws + al(8 * G2));
+    float2 *z = (float2 *)(ws + al(8 * G2) + al(8 * N2));
+    float2 *yv = (float2 *)(ws + al(8 * G2) + 2 * al(8 * N2));
+    double *acc = (double *)(ws + al(8 * G2) + 2 * al(8 * N2) + al(8 * G->M));
+    hipLaunchKernelGGL(k_real_to_c64, blocks_for(N2), dim3(NT), 0, s, x0, xc, N2);
+    // normalise the start vector
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, acc, 2);
+    hipLaunchKernelGGL(k_sumsq_real, blocks_reduce(N2), dim3(NT), 0, s, xc, N2, acc);
+    hipLaunchKernelGGL(k_normalise_real, blocks_for(N2), dim3(NT), 0, s, xc, xc, N2, acc);
+    for (int it = 0; it < iters; ++it) {
+        if (wp_status st = wp_apply_Phi(p, G, xc, yv, grid, s)) return st;
+        if (wp_status st = wp_apply_PhiT(p, G, yv, z, grid, s)) return st;
+        hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, acc, 1);
+        hipLaunchKernelGGL(k_sumsq_real, blocks_reduce(N2), dim3(NT), 0, s, z, N2, acc);
+        hipLaunchKernelGGL(k_normalise_real, blocks_for(N2), dim3(NT), 0, s, z, xc, N2, acc);
+    }
+    double host = 0.0;
+    WP_HIP(hipMemcpyAsync(&host, acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    WP_HIP(hipStreamSynchronize(s));
+    *nu = std::sqrt(host);
+    return wp_check_launch("power_norm2");
+}
+
+wp_status launch_solve(const wp_plan *p, const wp_G *G, const float2 *y, double eps, double nu, int iters,
+                       int levels, float *x, unsigned char *ws, hipStream_t s) {
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng, M = G->M;
+    auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    int64_t o = 0;
+    auto take = [&](int64_t b) { unsigned char *r = ws + o; o += al(b); return r; };
+    float2 *grid = (float2 *)take(8 * G2);
+    float *v1 = (float *)take(4 * N2);
+    float *t1 = (float *)take(4 * N2);
+    float *xb = (float *)take(4 * N2);
+    float *tmp = (float *)take(4 * N2);
+    float2 *t2 = (float2 *)take(8 * N2);
+    float2 *xbc = (float2 *)take(8 * N2);
+    float2 *v2 = (float2 *)take(8 * M);
+    float2 *pv = (float2 *)take(8 * M);
+    double *acc = (double *)take(64);
+    const float tau = 0.49f, s1 = 1.0f, s2 = (float)(1.0 / nu);
+    WP_HIP(hipMemsetAsync(v1, 0, 4 * N2, s));
+    WP_HIP(hipMemsetAsync(v2, 0, 8 * M, s));
+    for (int it = 0; it < iters; ++it) {
+        if (wp_status st = launch_dwt2(p, levels, v1, t1, tmp, true, s)) return st;           // Psi v1
+        if (wp_status st = wp_apply_PhiT(p, G, v2, t2, grid, s)) return st;                    // Phi^H v2
+        hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, t1, t2, xb, xbc, N2, tau, acc);
+        if (wp_status st = launch_dwt2(p, levels, xb, t1, tmp, false, s)) return st;          // Psi^T xb
+        hipLaunchKernelGGL(k_dual1, blocks_for(N2), dim3(NT), 0, s, v1, t1, N2, s1);
+        if (wp_status st = wp_apply_Phi(p, G, xbc, pv, grid, s)) return st;                    // Phi xb
+        hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, v2, pv, y, M, s2, acc);
+        hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, v2, pv, y, M, s2, eps, acc);
+    }
+    return wp_check_launch("solve");
+}
+
+wp_status filter_db8(double *h) { return daubechies(8, h) ? WP_OK : wp_set_error(WP_EHIP, "filter"); }

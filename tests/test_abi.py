@@ -63,3 +63,12 @@ def test_null_arguments_rejected():
 
 def test_wp_G_layout_matches_header():
     assert C.sizeof(_lib.WpG) == 8 * 2 + 4 * 2 + 8 * 5 + 8 + 8 * 3
+
+
+def test_library_db8_filter_matches_oracle_derivation():
+    """The library derives Daubechies-8 on its own (host, no GPU): same taps as the oracle."""
+    import numpy as np
+    from oracle import wavelet
+    h = np.array(wp.db8_filter())
+    assert np.abs(h - wavelet.daubechies_lowpass(8)).max() < 1e-12
+    assert abs(h.sum() - np.sqrt(2)) < 1e-13 and abs(np.dot(h, h) - 1) < 1e-13
