@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--taps", choices=["c64", "bf16"], default="c64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=384)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
 
 
@@ -54,6 +57,26 @@ def scatter_bytes(G, M, Ng, tap_bytes):
 def gather_bytes(G, M, Ng, tap_bytes):
     """Transposed copy streamed once (value + visibility index), cell offsets, y read once, grid written once."""
     return G.nnz * (tap_bytes + 4) + (Ng * Ng + 1) * 8 + M * 8 + Ng * Ng * 8
+
+
+def profiled_traffic(workload_name, kernel):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary, or None if the
+    summary is missing or the sparse-product source changed since the counters were taken."""
+    import hashlib
+    tag = {"plain-256-fp32": "plain-256"}.get(workload_name)
+    path = os.path.join(ROOT, "profiles", f"spmv_{tag}_traffic.md")
+    if tag is None or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith(("#", "|", "`")):
+            k, v = line.strip().split("=", 1)
+            kv[k] = v
+    src = open(os.path.join(ROOT, "paper_1307_3424_amd", "csrc", "spmv.hip"), "rb").read()
+    if kv.get("spmv_source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+        return None
+    v = kv.get(f"traffic_bytes.{kernel}")
+    return float(v) if v is not None else None
 
 
 def time_region(fn, steps, stream, torch):
@@ -101,6 +124,37 @@ def cpu_baseline(wl, x, u, v, w, rows_n):
             "sample": f"{rows.size} of {wl.M} rows (seeded subset), sparse products scaled x{scale:.1f}, "
                       f"full FP64 FFTs; NumPy FFT and SciPy CSR products are single-threaded",
             "cpu": platform.processor() or platform.machine(), "host_threads": os.cpu_count()}
+
+
+def full_solve(wp, torch, plan, G, wl, x, xd, dev):
+    """Reconstruction of the workload's sky from y = Phi x + n (30 dB) with its iteration count."""
+    import synth
+    G.order = wp.WP_ORDER_SORTED
+    y0 = wp.apply_Phi(plan, G, xd)
+    rms = float(torch.sqrt(torch.mean(torch.abs(y0.to(torch.complex128)) ** 2)))
+    sig = 10 ** (-wl.snr_in_db / 20) * rms
+    n = synth.noise(wl.M, sig, synth.rng_for(wl.seed, "noise"))
+    nd = wp.to_sorted(G, torch.from_numpy(n.astype(np.complex64)).to(dev))
+    y = y0 + nd
+    eps = float(np.sqrt(sig ** 2 * (wl.M + 2 * np.sqrt(wl.M))))
+    x0 = torch.from_numpy(synth.rng_for(wl.seed, "x").normal(size=wl.N * wl.N).astype(np.float32)).to(dev)
+    t0 = time.perf_counter()
+    nu = wp.power_norm2(plan, G, x0, 50)
+    t_pow = time.perf_counter() - t0
+    xr = torch.zeros(wl.N * wl.N, dtype=torch.float32, device=dev)
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s_ev.record()
+    wp.solve(plan, G, y, eps, nu, wl.iters, 4, x=xr)
+    e_ev.record()
+    torch.cuda.synchronize()
+    t_solve = s_ev.elapsed_time(e_ev) * 1e-3
+    xr_h = xr.cpu().numpy().reshape(wl.N, wl.N).astype(np.float64)
+    snr = float(20 * np.log10(np.std(x) / np.std(x - xr_h)))
+    log(f"bench: solve {wl.iters} iterations in {t_solve * 1e3:.1f} ms (+ power iteration {t_pow * 1e3:.1f} ms), "
+        f"SNR_out {snr:.2f} dB")
+    return {"iterations": wl.iters, "solve_s": t_solve, "power_iteration_s": t_pow, "per_iteration_us":
+            t_solve / wl.iters * 1e6, "snr_out_db": snr, "snr_in_db": wl.snr_in_db, "dictionary": "Db8, 4 levels"}
 
 
 def main():
@@ -174,6 +228,15 @@ def main():
         f"degrid {ms_deg * 1e3:.1f} us ({deg_gbs:.0f} GB/s), scatter+zero {ms_sc * 1e3:.1f} us ({sc_gbs:.0f} GB/s), "
         f"gather {ms_ga * 1e3:.1f} us ({ga_gbs:.0f} GB/s), Phi^H via scatter {ms_phit_sc * 1e3:.1f} us, "
         f"adj FFT {ms_adj * 1e3:.1f} us")
+    # the roofline object describes the sparse product that takes longest in a step
+    if ms_ga >= ms_deg:
+        dominant = {"bound": "hbm", "kernel": "gather (Phi^H sparse product, transposed copy)", "achieved": ga_gbs,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ga_gbs / HBM_PEAK_GBS,
+                    "traffic": profiled_traffic(wl.name, "k_gather"), "bytes_per_launch": gb, "launch_us": ms_ga * 1e3}
+    else:
+        dominant = {"bound": "hbm", "kernel": "degrid (Phi sparse product)", "achieved": deg_gbs,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": deg_gbs / HBM_PEAK_GBS,
+                    "traffic": profiled_traffic(wl.name, "k_degrid"), "bytes_per_launch": db, "launch_us": ms_deg * 1e3}
     out = {
         "metric": "visibilities/s for Phi+Phi† (exact vs surrogate kernels) and % HBM roofline",
         "value": wl.M / (ms * 1e-3),
@@ -185,18 +248,27 @@ def main():
         "config": {"workload": wl.name, "N": wl.N, "Ng": plan.Ng, "M": wl.M, "E": wl.E, "kb_W": wl.W,
                    "uv": f"{wl.uv} sigma={wl.uv_sigma}B", "w_top": wl.w_top, "kernel": "exact (stored G)",
                    "nnz": G.nnz, "nnz_per_vis": G.nnz / wl.M, "G_bytes": G.nbytes()},
-        "roofline": {"bound": "hbm", "kernel": "degrid (Phi sparse product)", "achieved": deg_gbs,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": deg_gbs / HBM_PEAK_GBS, "traffic": None,
-                     "bytes_per_launch": db, "launch_us": ms_deg * 1e3},
+        "roofline": dominant,
+        "degrid_roofline": {"achieved": deg_gbs, "frac": deg_gbs / HBM_PEAK_GBS, "bytes_per_launch": db,
+                            "launch_us": ms_deg * 1e3, "traffic": profiled_traffic(wl.name, "k_degrid")},
         "stages_us": {"phi": ms_phi * 1e3, "phiT": ms_phit * 1e3, "grid_forward": ms_fwd * 1e3,
                       "degrid": ms_deg * 1e3, "gather": ms_ga * 1e3, "scatter_incl_zero": ms_sc * 1e3,
                       "grid_adjoint": ms_adj * 1e3, "phiT_via_scatter": ms_phit_sc * 1e3,
                       "step_caller_order": ms_caller * 1e3},
-        "gather_roofline": {"achieved": ga_gbs, "frac": ga_gbs / HBM_PEAK_GBS, "bytes_per_launch": gb},
+        "gather_roofline": {"achieved": ga_gbs, "frac": ga_gbs / HBM_PEAK_GBS, "bytes_per_launch": gb,
+                            "traffic": profiled_traffic(wl.name, "k_gather")},
         "scatter_roofline": {"achieved": sc_gbs, "frac": sc_gbs / HBM_PEAK_GBS, "bytes_per_launch": sb},
         "phi_vis_per_s": wl.M / (ms_phi * 1e-3), "phiT_vis_per_s": wl.M / (ms_phit * 1e-3),
         "build_G_s": build_s,
     }
+    if args.copy_probe:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = a.numel() * 4
+    if wl.iters and not args.no_solve:
+        out["solve"] = full_solve(wp, torch, plan, G, wl, x, xd, dev)
     if not args.no_cpu:
         log("bench: timing the FP64 oracle on a bounded sample (CPU)")
         out["cpu_baseline"] = cpu_baseline(wl, x, u, v, w, args.cpu_rows)
