@@ -190,6 +190,33 @@ wp_status wp_to_sorted(const wp_G *G, const void *caller, void *sorted, void *st
 wp_status wp_to_caller(const wp_G *G, const void *sorted, void *caller, void *stream);
 
 /* ----------------------------------------------------------------------------------------
+ * Batches of independent problems sharing one plan (e.g. frequency channels, each with its
+ * own visibilities and G).  Images are stored contiguously (problem p at x + p*N*N), grids
+ * likewise (p*Ng*Ng), visibilities concatenated in problem order (problem p starts at the sum
+ * of the earlier M).  Each sparse product is ONE persistent launch whose workgroups take
+ * (problem, chunk) work items from a device queue; the FFTs are one launch pair for all.
+ * ------------------------------------------------------------------------------------- */
+typedef struct wp_batch wp_batch;
+
+/* Bind P >= 1 problems (array of P wp_G; same tap type; the arrays stay caller-owned and must
+ * outlive the batch).  The adjoint needs every G's transposed copy.  Allocates small device
+ * tables (descriptors, work lists, one counter); synchronises. */
+wp_status wp_batch_create(wp_batch **out, const wp_plan *plan, int P, const wp_G *G);
+wp_status wp_batch_destroy(wp_batch *batch);
+/* Total visibilities and the current launch shapes: [degrid lanes, unroll, rows per item,
+ * gather lanes, unroll, cells per item]. */
+wp_status wp_batch_info(const wp_batch *batch, int64_t *M_total, int *shapes6);
+/* y = Phi_p x_p for every problem; x: P*N*N c64, y: M_total c64, grids: P*Ng*Ng c64 workspace.
+ * Launches on one batch object must not run concurrently (they share the work counter). */
+wp_status wp_apply_Phi_batch(wp_batch *batch, const void *x, void *y, void *grids, void *stream);
+wp_status wp_apply_PhiT_batch(wp_batch *batch, const void *y, void *x, void *grids, void *stream);
+/* Autotuner: times the candidate launch shapes of both persistent products on these buffers
+ * (HIP events, 5 timed launches each) and keeps the fastest; best_us2[0..1] receive their
+ * times (host).  Synchronises; overwrites y and grids. */
+wp_status wp_batch_autotune(wp_batch *batch, const void *x, void *y, void *grids, void *stream,
+                            float *best_us2);
+
+/* ----------------------------------------------------------------------------------------
  * Reconstruction (Eq. 7): min ||Psi^T x||_1 s.t. ||y - Phi x||_2 <= eps, x >= 0, with Psi the
  * Daubechies wavelets of 8 vanishing moments (Section 4.2), periodic, `levels` levels.
  * ------------------------------------------------------------------------------------- */

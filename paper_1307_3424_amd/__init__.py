@@ -21,7 +21,7 @@ from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
-           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve"]
+           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "Batch"]
 
 
 def _torch():
@@ -313,3 +313,57 @@ def solve(plan: Plan, G: GMatrix, y, eps: float, nu: float, iters: int, levels: 
                           _ptr(x), _ptr(ws), _stream(stream)), "wp_solve")
     x._wp_ws = ws
     return x
+
+
+class Batch:
+    """wp_batch_*: P problems sharing one plan, one persistent launch per sparse product."""
+
+    def __init__(self, plan: Plan, Gs):
+        self.plan = plan
+        self.Gs = list(Gs)
+        arr = (_lib.WpG * len(self.Gs))(*[G.desc() for G in self.Gs])
+        h = C.c_void_p()
+        check(load().wp_batch_create(C.byref(h), plan.handle, len(self.Gs), arr), "wp_batch_create")
+        self._h = h
+        self.M_total = sum(G.M for G in self.Gs)
+
+    def shapes(self):
+        m = C.c_int64()
+        sh = (C.c_int * 6)()
+        check(load().wp_batch_info(self._h, C.byref(m), sh), "wp_batch_info")
+        return list(sh)
+
+    def new_buffers(self):
+        torch = _torch()
+        P, N, Ng = len(self.Gs), self.plan.N, self.plan.Ng
+        x = torch.zeros(P * N * N, dtype=torch.complex64, device="cuda")
+        y = torch.zeros(self.M_total, dtype=torch.complex64, device="cuda")
+        grids = torch.empty(P * Ng * Ng, dtype=torch.complex64, device="cuda")
+        return x, y, grids
+
+    def apply_Phi(self, x, y, grids, stream=None):
+        check(load().wp_apply_Phi_batch(self._h, _ptr(x), _ptr(y), _ptr(grids), _stream(stream)),
+              "wp_apply_Phi_batch")
+        return y
+
+    def apply_PhiT(self, y, x, grids, stream=None):
+        check(load().wp_apply_PhiT_batch(self._h, _ptr(y), _ptr(x), _ptr(grids), _stream(stream)),
+              "wp_apply_PhiT_batch")
+        return x
+
+    def autotune(self, x, y, grids, stream=None):
+        best = (C.c_float * 2)()
+        check(load().wp_batch_autotune(self._h, _ptr(x), _ptr(y), _ptr(grids), _stream(stream), best),
+              "wp_batch_autotune")
+        return list(best)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().wp_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -54,6 +54,12 @@ SIGNATURES = {
     "wp_to_sorted": ([_PG, _vp, _vp, _vp], _i32),
     "wp_to_caller": ([_PG, _vp, _vp, _vp], _i32),
     "wp_db8_filter": ([C.POINTER(C.c_double)], _i32),
+    "wp_batch_create": ([C.POINTER(_vp), _vp, _i32, _PG], _i32),
+    "wp_batch_destroy": ([_vp], _i32),
+    "wp_batch_info": ([_vp, _pi64, C.POINTER(C.c_int)], _i32),
+    "wp_apply_Phi_batch": ([_vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_apply_PhiT_batch": ([_vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_batch_autotune": ([_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_float)], _i32),
     "wp_dwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_idwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_solver_workspace_bytes": ([_vp, _PG, _pi64], _i32),

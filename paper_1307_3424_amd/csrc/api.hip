@@ -265,6 +265,46 @@ wp_status wp_apply_PhiT(const wp_plan *p, const wp_G *G, const void *y, void *x,
     return launch_grid_adjoint(p, (float2 *)grid, (float2 *)x, s);
 }
 
+wp_status wp_batch_create(wp_batch **out, const wp_plan *p, int P, const wp_G *G) {
+    if (!out) return wp_set_error(WP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (wp_status s = check_plan(p)) return s;
+    if (P < 1 || !G) return wp_set_error(WP_EINVAL, "batch: P = %d, G = %p", P, (const void *)G);
+    for (int i = 0; i < P; ++i)
+        if (wp_status s = check_G(p, &G[i], false)) return s;
+    return batch_create(out, p, P, G);
+}
+
+wp_status wp_batch_destroy(wp_batch *b) {
+    batch_destroy(b);
+    return WP_OK;
+}
+
+wp_status wp_batch_info(const wp_batch *b, int64_t *M_total, int *shapes6) {
+    if (!b) return wp_set_error(WP_EINVAL, "batch is NULL");
+    if (M_total) *M_total = batch_total_vis(b);
+    if (shapes6) batch_shapes(b, shapes6);
+    return WP_OK;
+}
+
+wp_status wp_apply_Phi_batch(wp_batch *b, const void *x, void *y, void *grids, void *stream) {
+    if (!b) return wp_set_error(WP_EINVAL, "batch is NULL");
+    if (!x || !y || !grids) return wp_set_error(WP_EINVAL, "NULL argument");
+    return batch_phi(b, (const float2 *)x, (float2 *)y, (float2 *)grids, as_stream(stream));
+}
+
+wp_status wp_apply_PhiT_batch(wp_batch *b, const void *y, void *x, void *grids, void *stream) {
+    if (!b) return wp_set_error(WP_EINVAL, "batch is NULL");
+    if (!x || !y || !grids) return wp_set_error(WP_EINVAL, "NULL argument");
+    return batch_phiT(b, (const float2 *)y, (float2 *)x, (float2 *)grids, as_stream(stream));
+}
+
+wp_status wp_batch_autotune(wp_batch *b, const void *x, void *y, void *grids, void *stream, float *best_us2) {
+    if (!b) return wp_set_error(WP_EINVAL, "batch is NULL");
+    if (!x || !y || !grids || !best_us2) return wp_set_error(WP_EINVAL, "NULL argument");
+    return batch_autotune(b, (const float2 *)x, (float2 *)y, (float2 *)grids, as_stream(stream), best_us2);
+}
+
 wp_status wp_db8_filter(double *h16) {
     if (!h16) return wp_set_error(WP_EINVAL, "NULL argument");
     return filter_db8(h16);

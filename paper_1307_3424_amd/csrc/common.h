@@ -90,8 +90,9 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
 // ---------------------------------------------------------------------------- launchers (host)
 
 // FFT stages of A, Z, F and their adjoint (fft.hip)
-wp_status launch_grid_forward(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s);
-wp_status launch_grid_adjoint(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s);
+// batch > 1: `batch` images / grids stored contiguously (N*N and Ng*Ng apart)
+wp_status launch_grid_forward(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s, int batch = 1);
+wp_status launch_grid_adjoint(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s, int batch = 1);
 
 // sparse products (spmv.hip)
 wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, float2 *y, hipStream_t s);
@@ -117,3 +118,12 @@ wp_status launch_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, i
 wp_status launch_solve(const wp_plan *p, const wp_G *G, const float2 *y, double eps, double nu, int iters,
                        int levels, float *x, unsigned char *ws, hipStream_t s);
 wp_status filter_db8(double *h);
+
+// batch of problems (batch.hip)
+wp_status batch_create(wp_batch **out, const wp_plan *p, int P, const wp_G *G);
+void batch_destroy(wp_batch *b);
+int64_t batch_total_vis(const wp_batch *b);
+wp_status batch_phi(wp_batch *b, const float2 *x, float2 *y, float2 *grids, hipStream_t s);
+wp_status batch_phiT(wp_batch *b, const float2 *y, float2 *x, float2 *grids, hipStream_t s);
+wp_status batch_autotune(wp_batch *b, const float2 *x, float2 *y, float2 *grids, hipStream_t s, float *best_us);
+void batch_shapes(const wp_batch *b, int *out6);

@@ -46,6 +46,8 @@ __global__ __launch_bounds__(NTH) void k_fwd_rows(const float2 *__restrict__ x, 
     __shared__ float2 buf[C * Ng];
     const int tid = threadIdx.x;
     const int im0 = blockIdx.x * C;
+    x += (int64_t)blockIdx.y * N * N;
+    grid += (int64_t)blockIdx.y * Ng * Ng;
     for (int e = tid; e < C * Ng; e += NTH) {
         const int c = e / Ng, j = e % Ng, im = im0 + c;
         float2 v = make_float2(0.f, 0.f);
@@ -72,7 +74,8 @@ __global__ __launch_bounds__(NTH) void k_fwd_cols(float2 *__restrict__ grid, con
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     __shared__ float2 buf[Ng * C];
     const int tid = threadIdx.x;
-    const int qu0 = blockIdx.x * C;
+    const int qu0 = xcd_block(blockIdx.x, gridDim.x) * C;
+    grid += (int64_t)blockIdx.y * Ng * Ng;
     for (int e = tid; e < Ng * C; e += NTH) {
         const int jv = e / C, c = e % C;
         float2 v = make_float2(0.f, 0.f);
@@ -95,7 +98,8 @@ __global__ __launch_bounds__(NTH) void k_adj_cols(float2 *__restrict__ grid, con
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     __shared__ float2 buf[Ng * C];
     const int tid = threadIdx.x;
-    const int qu0 = blockIdx.x * C;
+    const int qu0 = xcd_block(blockIdx.x, gridDim.x) * C;
+    grid += (int64_t)blockIdx.y * Ng * Ng;
     for (int e = tid; e < Ng * C; e += NTH) {
         const int qv = e / C, c = e % C;
         float2 v = grid[(int64_t)qv * Ng + qu0 + c];
@@ -119,6 +123,8 @@ __global__ __launch_bounds__(NTH) void k_adj_rows(const float2 *__restrict__ gri
     __shared__ float2 buf[C * Ng];
     const int tid = threadIdx.x;
     const int im0 = blockIdx.x * C;
+    grid += (int64_t)blockIdx.y * Ng * Ng;
+    x += (int64_t)blockIdx.y * N * N;
     for (int e = tid; e < C * Ng; e += NTH) {
         const int c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
         buf[c * Ng + q] = grid[(int64_t)jv * Ng + q];
@@ -135,50 +141,50 @@ __global__ __launch_bounds__(NTH) void k_adj_rows(const float2 *__restrict__ gri
 }
 
 template <int LOGNG>
-wp_status fwd(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s) {
+wp_status fwd(const wp_plan *p, const float2 *x, float2 *grid, int batch, hipStream_t s) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     using S = Shape<LOGNG>;
     static_assert(N % S::CR == 0 && Ng % S::CC == 0, "shape");
-    hipLaunchKernelGGL((k_fwd_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR), dim3(S::TR), 0, s, x, grid, p->apod,
-                       p->tw32, p->aphys, (float)p->delta);
-    hipLaunchKernelGGL((k_fwd_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC), dim3(S::TC), 0, s, grid, p->tw32);
+    hipLaunchKernelGGL((k_fwd_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, x, grid,
+                       p->apod, p->tw32, p->aphys, (float)p->delta);
+    hipLaunchKernelGGL((k_fwd_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC, batch), dim3(S::TC), 0, s, grid, p->tw32);
     return wp_check_launch("grid_forward");
 }
 
 template <int LOGNG>
-wp_status adj(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s) {
+wp_status adj(const wp_plan *p, float2 *grid, float2 *x, int batch, hipStream_t s) {
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     using S = Shape<LOGNG>;
-    hipLaunchKernelGGL((k_adj_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC), dim3(S::TC), 0, s, grid, p->tw32);
-    hipLaunchKernelGGL((k_adj_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR), dim3(S::TR), 0, s, grid, x, p->apod,
-                       p->tw32, p->aphys, (float)p->delta);
+    hipLaunchKernelGGL((k_adj_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC, batch), dim3(S::TC), 0, s, grid, p->tw32);
+    hipLaunchKernelGGL((k_adj_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, grid, x,
+                       p->apod, p->tw32, p->aphys, (float)p->delta);
     return wp_check_launch("grid_adjoint");
 }
 
 }  // namespace
 
-wp_status launch_grid_forward(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s) {
+wp_status launch_grid_forward(const wp_plan *p, const float2 *x, float2 *grid, hipStream_t s, int batch) {
     switch (p->logNg) {
-        case 6: return fwd<6>(p, x, grid, s);
-        case 7: return fwd<7>(p, x, grid, s);
-        case 8: return fwd<8>(p, x, grid, s);
-        case 9: return fwd<9>(p, x, grid, s);
-        case 10: return fwd<10>(p, x, grid, s);
-        case 11: return fwd<11>(p, x, grid, s);
-        case 12: return fwd<12>(p, x, grid, s);
+        case 6: return fwd<6>(p, x, grid, batch, s);
+        case 7: return fwd<7>(p, x, grid, batch, s);
+        case 8: return fwd<8>(p, x, grid, batch, s);
+        case 9: return fwd<9>(p, x, grid, batch, s);
+        case 10: return fwd<10>(p, x, grid, batch, s);
+        case 11: return fwd<11>(p, x, grid, batch, s);
+        case 12: return fwd<12>(p, x, grid, batch, s);
     }
     return wp_set_error(WP_EUNSUPPORTED, "grid_forward: Ng = %d", p->Ng);
 }
 
-wp_status launch_grid_adjoint(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s) {
+wp_status launch_grid_adjoint(const wp_plan *p, float2 *grid, float2 *x, hipStream_t s, int batch) {
     switch (p->logNg) {
-        case 6: return adj<6>(p, grid, x, s);
-        case 7: return adj<7>(p, grid, x, s);
-        case 8: return adj<8>(p, grid, x, s);
-        case 9: return adj<9>(p, grid, x, s);
-        case 10: return adj<10>(p, grid, x, s);
-        case 11: return adj<11>(p, grid, x, s);
-        case 12: return adj<12>(p, grid, x, s);
+        case 6: return adj<6>(p, grid, x, batch, s);
+        case 7: return adj<7>(p, grid, x, batch, s);
+        case 8: return adj<8>(p, grid, x, batch, s);
+        case 9: return adj<9>(p, grid, x, batch, s);
+        case 10: return adj<10>(p, grid, x, batch, s);
+        case 11: return adj<11>(p, grid, x, batch, s);
+        case 12: return adj<12>(p, grid, x, batch, s);
     }
     return wp_set_error(WP_EUNSUPPORTED, "grid_adjoint: Ng = %d", p->Ng);
 }
