@@ -35,10 +35,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", type=int, default=1)
-    ap.add_argument("--taps", choices=["c64", "bf16"], default="c64")
+    ap.add_argument("--taps", choices=["c64", "bf16", "i16"], default="c64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--channels", type=int, default=0, help="batched form: first K channels only (0: all)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -157,6 +158,84 @@ def full_solve(wp, torch, plan, G, wl, x, xd, dev):
             t_solve / wl.iters * 1e6, "snr_out_db": snr, "snr_in_db": wl.snr_in_db, "dictionary": "Db8, 4 levels"}
 
 
+def bench_batched(args, wl):
+    """Batched form: all channels' Phi / Phi^H in one persistent launch each vs one launch per channel."""
+    import torch
+    import paper_1307_3424_amd as wp
+    import synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    P = len(wl.channels) if args.channels <= 0 else min(args.channels, len(wl.channels))
+    log(f"bench: workload {wl.name} N={wl.N} channels={P} M_total={sum(wl.channels[:P])}")
+    plan = wp.Plan(wl.N, wl.L, kb_W=wl.W)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Gs, skies = [], []
+    t0 = time.perf_counter()
+    for c in range(P):
+        wtop = wl.w_top * wl.w_scale[c]
+        u, v, w = synth.uvw(wl.N, wl.channels[c], wl.L, wl.uv, wl.uv_sigma, wtop, synth.rng_for(wl.seed, "uvw", c))
+        G = wp.build_G(plan, t(u), t(v), t(w), wl.E)
+        G.order = wp.WP_ORDER_SORTED
+        del G._ws
+        Gs.append(G)
+        skies.append(synth.sky(wl.N, wl.n_blobs, wl.n_points, synth.rng_for(wl.seed, "sky", c)))
+        if c % 8 == 7:
+            torch.cuda.synchronize()
+            log(f"bench: built {c + 1}/{P} channels ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    nnz = sum(G.nnz for G in Gs)
+    log(f"bench: {P} G built in {build_s:.1f} s, nnz={nnz} ({nnz / sum(G.M for G in Gs):.1f}/vis), "
+        f"{sum(G.nbytes() for G in Gs) / 1e9:.1f} GB")
+    B = wp.Batch(plan, Gs)
+    x, y, grids = B.new_buffers()
+    x.copy_(t(np.concatenate([s_.ravel() for s_ in skies]).astype(np.complex64)))
+    xa = torch.empty_like(x)
+    best = B.autotune(x, y, grids)
+    shapes = B.shapes()
+    log(f"bench: autotuned shapes {shapes}, best degrid {best[0]:.0f} us, gather {best[1]:.0f} us")
+    stream = torch.cuda.current_stream()
+    N2, Ng2 = wl.N * wl.N, plan.Ng * plan.Ng
+    offs = np.concatenate([[0], np.cumsum([G.M for G in Gs])])
+
+    def batched():
+        B.apply_Phi(x, y, grids)
+        B.apply_PhiT(y, xa, grids)
+
+    def sequential():
+        for p_, G in enumerate(Gs):
+            wp.apply_Phi(plan, G, x[p_ * N2:(p_ + 1) * N2], y[offs[p_]:offs[p_ + 1]], grids[:Ng2])
+            wp.apply_PhiT(plan, G, y[offs[p_]:offs[p_ + 1]], xa[p_ * N2:(p_ + 1) * N2], grids[:Ng2])
+
+    for _ in range(args.warmup):
+        batched()
+    ms_b = time_region(batched, args.steps, stream, torch)
+    for _ in range(max(1, args.warmup // 4)):
+        sequential()
+    ms_s = time_region(sequential, max(3, args.steps // 4), stream, torch)
+    ms_phi = time_region(lambda: B.apply_Phi(x, y, grids), args.steps, stream, torch)
+    M_tot = int(offs[-1])
+    tap_b = 8
+    deg_bytes = nnz * (tap_b + 4) + sum((G.M + 1) * 8 + G.M * 8 for G in Gs) + P * Ng2 * 8
+    log(f"bench: batched {ms_b:.3f} ms per Phi+Phi^H, sequential {ms_s:.3f} ms ({ms_s / ms_b:.2f}x)")
+    out = {
+        "metric": "visibilities/s for Phi+Phi† (exact vs surrogate kernels) and % HBM roofline",
+        "value": M_tot / (ms_b * 1e-3), "unit": "visibilities/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic (seeded skies and baselines per channel)",
+        "config": {"workload": wl.name, "N": wl.N, "channels": P, "M_total": M_tot, "E": wl.E,
+                   "w_scale": [wl.w_scale[0], wl.w_scale[P - 1]], "nnz": nnz, "kernel": "exact (stored G)"},
+        "sequential_ms_per_step": ms_s, "speedup_vs_sequential": ms_s / ms_b,
+        "sequential_vis_per_s": M_tot / (ms_s * 1e-3),
+        "autotuned_shapes": {"degrid": shapes[:3], "gather": shapes[3:]},
+        "autotune_best_us": best, "phi_ms": ms_phi,
+        "degrid_roofline": {"achieved": deg_bytes / (best[0] * 1e-6) / 1e9,
+                            "frac": deg_bytes / (best[0] * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": deg_bytes},
+        "build_G_s": build_s,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -168,14 +247,14 @@ def main():
 
     wl = synth.workload(args.workload)
     if wl.channels is not None:
-        raise SystemExit("the batched form is benchmarked by its own script")
+        return bench_batched(args, wl)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"bench: workload {wl.name} N={wl.N} M={wl.M} E={wl.E} taps={args.taps}")
     x, u, v, w = synth.workload_inputs(wl)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     plan = wp.Plan(wl.N, wl.L, kb_W=wl.W)
-    taps = wp.WP_TAPS_C64 if args.taps == "c64" else wp.WP_TAPS_BF16
+    taps = {"c64": wp.WP_TAPS_C64, "bf16": wp.WP_TAPS_BF16, "i16": wp.WP_TAPS_I16}[args.taps]
     tap_bytes = 8 if taps == wp.WP_TAPS_C64 else 4
     ud, vd, wd = t(u), t(v), t(w)
     torch.cuda.synchronize()
@@ -243,7 +322,8 @@ def main():
         "unit": "visibilities/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c64" if taps == wp.WP_TAPS_C64 else "bf16x2-taps/f32-accumulate",
+        "dtype": {"c64": "c64", "bf16": "bf16x2-taps/f32-accumulate",
+                  "i16": "int16x2-block-float-taps/f32-accumulate"}[args.taps],
         "data": "synthetic (seeded sky and baselines; the paper's M31 / 30Dor images are not used)",
         "config": {"workload": wl.name, "N": wl.N, "Ng": plan.Ng, "M": wl.M, "E": wl.E, "kb_W": wl.W,
                    "uv": f"{wl.uv} sigma={wl.uv_sigma}B", "w_top": wl.w_top, "kernel": "exact (stored G)",

@@ -61,7 +61,9 @@ typedef enum wp_status {
 enum { WP_CHIRP_LINEAR = 0,   /* exp(+i pi w (l^2+m^2)): first order of Eq. 4 (the paper's Eq. 5) */
        WP_CHIRP_EXACT = 1 };  /* exp(-2 pi i w (sqrt(1-l^2-m^2) - 1)) (Eq. 4)                    */
 enum { WP_TAPS_C64 = 0,       /* G values as complex float32 (8 bytes)                          */
-       WP_TAPS_BF16 = 1 };    /* G values as a (re, im) pair of bfloat16 (4 bytes), FP32 accumulate */
+       WP_TAPS_BF16 = 1,      /* G values as a (re, im) pair of bfloat16 (4 bytes), FP32 accumulate */
+       WP_TAPS_I16 = 2 };     /* G values as a (re, im) pair of int16 times the row's scale
+                                 rscale[r] (block floating point: 4 bytes per tap + 4 per row)   */
 enum { WP_APHYS_ONE = 0,      /* primary beam absorbed into the sky (Section 2.1)               */
        WP_APHYS_INV_N = 1 };  /* the 1/n(l, m) factor of Eq. 1                                 */
 enum { WP_ORDER_CALLER = 0,   /* visibility vectors in the caller's order (default)             */
@@ -82,6 +84,8 @@ typedef struct wp_G {
     int32_t *perm;     /* [M]   device, sorted row r is visibility perm[r]           */
     int32_t *work;     /* [4*n_work] device, adjoint work items (tile_v, tile_u, row_begin, row_end) */
     int64_t  n_work;
+    float   *rscale;   /* [M] device, per sorted row scale of WP_TAPS_I16 values (else may be NULL):
+                          tap = rscale[r] * (re, im), |re|, |im| <= 32767                      */
     /* Optional transposed copy for the gather form of G^H (tcolptr == NULL: not built).
      * Entries of grid cell c are [tcolptr[c], tcolptr[c+1]), ordered by sorted row index. */
     int64_t *tcolptr;  /* [Ng*Ng+1] device                                           */

@@ -20,12 +20,12 @@ Kaiser-Bessel gridding window):
           (indices modulo Ng).  This is exact: sum_q g_k(q) X[q] equals KB
           interpolation of F(z * c_k) at (u~_k, v~_k).
 4. sparsify  keep, per row, the largest |g_k|^2 entries holding a fraction E
-          of the row's energy sum |g_k|^2 (Section 3.2): sort the energies in
+          of the row's energy sum |g_k|^2 (Section 3.2): take the energies in
           decreasing order, find the first position where the running sum
           reaches E times the total, take that entry's energy as the threshold
           tau and keep every entry >= tau (ties kept); E >= 1 keeps every
           non-zero entry.  No renormalisation.  The paper reaches tau by
-          bisection; the sort gives the same threshold.
+          bisection; the ordered running sum gives the same threshold.
 5. CSR    kept entries of each row in ascending flattened column q_v*Ng + q_u.
 
 Adjoint: Phi^H = A Z^H F^H G^H with F^H the unnormalised inverse DFT.
@@ -179,17 +179,30 @@ def kernel_row(ut: float, vt: float, w: float, s: Setup) -> np.ndarray:
 # ----------------------------------------------------------------------------- sparsification
 
 def energy_threshold(m: np.ndarray, E: float):
-    """(tau, total) of Section 3.2's rule; entries m >= tau are kept."""
+    """(tau, total) of Section 3.2's rule; entries m >= tau are kept.
+
+    total is the row energy sum; the entries are taken in decreasing order and
+    tau is the first one at which the running sum reaches E * total.  Only the
+    largest entries are ever sorted: the K largest (K = 1024, 4096, ...) are
+    selected, sorted and summed until their sum reaches E * total, so the
+    crossing lies among them and the running sums are exactly those of a full
+    sort.
+    """
     m = np.asarray(m, dtype=np.float64).ravel()
-    srt = np.sort(m)[::-1]
-    cs = np.cumsum(srt)
-    total = cs[-1]
+    total = float(m.sum())
     if E >= 1.0:
-        pos = srt[srt > 0]
-        return (pos[-1] if pos.size else np.inf), total
-    k = int(np.searchsorted(cs, E * total, side="left"))
-    k = min(k, srt.size - 1)
-    return srt[k], total
+        pos = m[m > 0]
+        return (pos.min() if pos.size else np.inf), total
+    n = m.size
+    K = min(n, 1024)
+    while True:
+        top = m if K >= n else np.partition(m, n - K)[n - K:]
+        srt = np.sort(top)[::-1]
+        cs = np.cumsum(srt)
+        if cs[-1] >= E * total or K >= n:
+            k = min(int(np.searchsorted(cs, E * total, side="left")), srt.size - 1)
+            return srt[k], total
+        K = min(n, 4 * K)
 
 
 def sparsify(m: np.ndarray, E: float) -> np.ndarray:
@@ -240,3 +253,10 @@ def phi_adjoint(G: sp.csr_matrix, y: np.ndarray, s: Setup) -> np.ndarray:
     """x = A Z^H F^H G^H y."""
     X = (G.conj().T @ np.asarray(y, dtype=np.complex128)).reshape(s.Ng, s.Ng)
     return grid_adjoint(X, s)
+
+
+def build_rows_csr_parts(args):
+    """Worker form of build_rows for process pools: returns (indptr, indices, data, nrows)."""
+    u, v, w, E, s, rows = args
+    G = build_rows(u, v, w, E, s, rows=rows)
+    return G.indptr, G.indices, G.data, G.shape[0]

@@ -16,10 +16,10 @@ from dataclasses import dataclass
 
 from . import _lib
 from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR, WP_ORDER_CALLER,
-                   WP_ORDER_SORTED, WP_TAPS_BF16, WP_TAPS_C64, WprojError, check, load)
+                   WP_ORDER_SORTED, WP_TAPS_BF16, WP_TAPS_C64, WP_TAPS_I16, WprojError, check, load)
 
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
-           "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16",
+           "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16", "WP_TAPS_I16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
            "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "Batch"]
 
@@ -108,6 +108,7 @@ class GMatrix:
     tcolptr: object = None
     trow: object = None
     tval: object = None
+    rscale: object = None
     use_transpose: bool = True
     order: int = WP_ORDER_CALLER     # order of the visibility vectors passed with this G
 
@@ -116,13 +117,16 @@ class GMatrix:
         d.M, d.nnz, d.taps, d.n_work, d.order = self.M, self.nnz, self.taps, self.n_work, self.order
         d.rowptr, d.col, d.val = self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr()
         d.perm, d.work = self.perm.data_ptr(), self.work.data_ptr()
+        if self.rscale is not None:
+            d.rscale = self.rscale.data_ptr()
         use = self.use_transpose if transpose is None else transpose
         if use and self.tcolptr is not None:
             d.tcolptr, d.trow, d.tval = self.tcolptr.data_ptr(), self.trow.data_ptr(), self.tval.data_ptr()
         return d
 
     def nbytes(self) -> int:
-        ts = [self.rowptr, self.col, self.val, self.perm, self.work, self.tcolptr, self.trow, self.tval]
+        ts = [self.rowptr, self.col, self.val, self.perm, self.work, self.tcolptr, self.trow, self.tval,
+              self.rscale]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
@@ -153,6 +157,8 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: b
                 perm=torch.empty(M, dtype=torch.int32, device=dev),
                 work=torch.empty(4 * max(nwork.value, 1), dtype=torch.int32, device=dev),
                 n_work=nwork.value)
+    if taps == WP_TAPS_I16:
+        G.rscale = torch.empty(M, dtype=torch.float32, device=dev)
     if transpose:
         G.tcolptr = torch.empty(plan.Ng * plan.Ng + 1, dtype=torch.int64, device=dev)
         G.trow = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)

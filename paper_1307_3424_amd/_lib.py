@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libwproj.so")
 
 WP_CHIRP_LINEAR, WP_CHIRP_EXACT = 0, 1
-WP_TAPS_C64, WP_TAPS_BF16 = 0, 1
+WP_TAPS_C64, WP_TAPS_BF16, WP_TAPS_I16 = 0, 1, 2
 WP_APHYS_ONE, WP_APHYS_INV_N = 0, 1
 WP_ORDER_CALLER, WP_ORDER_SORTED = 0, 1
 
@@ -29,7 +29,7 @@ _pi64 = C.POINTER(C.c_int64)
 class WpG(C.Structure):
     _fields_ = [("M", C.c_int64), ("nnz", C.c_int64), ("taps", C.c_int32), ("order", C.c_int32),
                 ("rowptr", _vp), ("col", _vp), ("val", _vp), ("perm", _vp), ("work", _vp),
-                ("n_work", C.c_int64), ("tcolptr", _vp), ("trow", _vp), ("tval", _vp)]
+                ("n_work", C.c_int64), ("rscale", _vp), ("tcolptr", _vp), ("trow", _vp), ("tval", _vp)]
 
 
 _PG = C.POINTER(WpG)

@@ -44,7 +44,9 @@ wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
     if (!G) return wp_set_error(WP_EINVAL, "G is NULL");
     if (G->M < 0 || G->M > 0x7fffffff) return wp_set_error(WP_EINVAL, "G->M = %lld out of range", (long long)G->M);
     if (G->nnz < 0) return wp_set_error(WP_EINVAL, "G->nnz < 0");
-    if (G->taps != WP_TAPS_C64 && G->taps != WP_TAPS_BF16) return wp_set_error(WP_EINVAL, "G->taps = %d", G->taps);
+    if (G->taps != WP_TAPS_C64 && G->taps != WP_TAPS_BF16 && G->taps != WP_TAPS_I16)
+        return wp_set_error(WP_EINVAL, "G->taps = %d", G->taps);
+    if (G->taps == WP_TAPS_I16 && G->M > 0 && !G->rscale) return wp_set_error(WP_EINVAL, "WP_TAPS_I16 needs G->rscale");
     if (G->order != WP_ORDER_CALLER && G->order != WP_ORDER_SORTED) return wp_set_error(WP_EINVAL, "G->order = %d", G->order);
     if (G->M > 0 && (!G->rowptr || !G->perm || (G->nnz > 0 && (!G->col || !G->val))))
         return wp_set_error(WP_EINVAL, "G has a NULL array");

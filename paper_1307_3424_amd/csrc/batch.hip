@@ -29,15 +29,10 @@ struct ProbDesc {
     const int64_t *tcolptr;
     const int *trow;
     const void *tval;
+    const float *rscale;
     int64_t M;
     int64_t y_off;
 };
-
-template <bool BF16>
-__device__ __forceinline__ float2 ld_tap(const void *__restrict__ val, int64_t j) {
-    if constexpr (BF16) return unpack_bf16x2(((const uint32_t *)val)[j]);
-    else return ((const float2 *)val)[j];
-}
 
 __device__ __forceinline__ int next_item(unsigned long long *counter, unsigned long long base, int *slot) {
     if (threadIdx.x == 0) {
@@ -50,7 +45,7 @@ __device__ __forceinline__ int next_item(unsigned long long *counter, unsigned l
     return it;
 }
 
-template <bool BF16, int LPR, int U>
+template <int TK, int LPR, int U>
 __global__ __launch_bounds__(BT) void k_degrid_persist(const ProbDesc *__restrict__ pd, const int2 *__restrict__ items,
                                                        int n_items, int R, unsigned long long *counter,
                                                        unsigned long long base, const float2 *__restrict__ grids,
@@ -76,7 +71,7 @@ __global__ __launch_bounds__(BT) void k_degrid_persist(const ProbDesc *__restric
                     const int64_t j = j0 + LPR * t;
                     if (j < end) {
                         c[t] = d.col[j];
-                        v[t] = ld_tap<BF16>(d.val, j);
+                        v[t] = load_tap_raw<TK>(d.val, j);
                     } else {
                         c[t] = 0;
                         v[t] = make_float2(0.f, 0.f);
@@ -96,12 +91,18 @@ __global__ __launch_bounds__(BT) void k_degrid_persist(const ProbDesc *__restric
                 ar += __shfl_xor(ar, o);
                 ai += __shfl_xor(ai, o);
             }
-            if (sub == 0) y[d.y_off + (d.perm ? d.perm[r] : r)] = make_float2(ar, ai);
+            if (sub == 0) {
+                if constexpr (TK == WP_TAPS_I16) {
+                    ar *= d.rscale[r];
+                    ai *= d.rscale[r];
+                }
+                y[d.y_off + (d.perm ? d.perm[r] : r)] = make_float2(ar, ai);
+            }
         }
     }
 }
 
-template <bool BF16, int LPR, int U>
+template <int TK, int LPR, int U>
 __global__ __launch_bounds__(BT) void k_gather_persist(const ProbDesc *__restrict__ pd, const int2 *__restrict__ items,
                                                        int n_items, int C, int64_t cells, unsigned long long *counter,
                                                        unsigned long long base, const float2 *__restrict__ y,
@@ -130,8 +131,13 @@ __global__ __launch_bounds__(BT) void k_gather_persist(const ProbDesc *__restric
                     for (int t = 0; t < U; ++t) {
                         const int64_t j = j0 + LPR * t;
                         if (j < end) {
-                            k[t] = d.perm ? d.perm[d.trow[j]] : d.trow[j];
-                            v[t] = ld_tap<BF16>(d.tval, j);
+                            const int rr = d.trow[j];
+                            k[t] = d.perm ? d.perm[rr] : rr;
+                            v[t] = load_tap_raw<TK>(d.tval, j);
+                            if constexpr (TK == WP_TAPS_I16) {
+                                v[t].x *= d.rscale[rr];
+                                v[t].y *= d.rscale[rr];
+                            }
                         } else {
                             k[t] = -1;
                             v[t] = make_float2(0.f, 0.f);
@@ -181,12 +187,12 @@ struct wp_batch {
 
 namespace {
 
-template <bool BF16>
+template <int TK>
 wp_status launch_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s) {
     const int64_t G2 = (int64_t)b->plan->Ng * b->plan->Ng;
     const dim3 g(b->nblocks), t(BT);
 #define DEG(L, U)                                                                                                   \
-    hipLaunchKernelGGL((k_degrid_persist<BF16, L, U>), g, t, 0, s, b->d_desc, b->d_items_deg, b->n_items_deg,      \
+    hipLaunchKernelGGL((k_degrid_persist<TK, L, U>), g, t, 0, s, b->d_desc, b->d_items_deg, b->n_items_deg,      \
                        b->deg.chunk, b->d_counter, b->base, grids, G2, y)
     switch (b->deg.lpr * 100 + b->deg.u) {
         case 1604: DEG(16, 4); break;
@@ -203,12 +209,12 @@ wp_status launch_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s)
     return WP_OK;
 }
 
-template <bool BF16>
+template <int TK>
 wp_status launch_gat(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s) {
     const int64_t G2 = (int64_t)b->plan->Ng * b->plan->Ng;
     const dim3 g(b->nblocks), t(BT);
 #define GAT(L, U)                                                                                                   \
-    hipLaunchKernelGGL((k_gather_persist<BF16, L, U>), g, t, 0, s, b->d_desc, b->d_items_gat, b->n_items_gat,      \
+    hipLaunchKernelGGL((k_gather_persist<TK, L, U>), g, t, 0, s, b->d_desc, b->d_items_gat, b->n_items_gat,      \
                        b->gat.chunk, G2, b->d_counter, b->base, y, grids, G2)
     switch (b->gat.lpr * 100 + b->gat.u) {
         case 804: GAT(8, 4); break;
@@ -223,6 +229,18 @@ wp_status launch_gat(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s)
     if (wp_status st = wp_check_launch("batch gather")) return st;
     b->base += (unsigned long long)b->n_items_gat + (unsigned long long)b->nblocks;
     return WP_OK;
+}
+
+wp_status run_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s) {
+    if (b->taps == WP_TAPS_BF16) return launch_deg<WP_TAPS_BF16>(b, grids, y, s);
+    if (b->taps == WP_TAPS_I16) return launch_deg<WP_TAPS_I16>(b, grids, y, s);
+    return launch_deg<WP_TAPS_C64>(b, grids, y, s);
+}
+
+wp_status run_gat(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s) {
+    if (b->taps == WP_TAPS_BF16) return launch_gat<WP_TAPS_BF16>(b, y, grids, s);
+    if (b->taps == WP_TAPS_I16) return launch_gat<WP_TAPS_I16>(b, y, grids, s);
+    return launch_gat<WP_TAPS_C64>(b, y, grids, s);
 }
 
 wp_status make_items(wp_batch *b, bool deg) {
@@ -265,7 +283,7 @@ wp_status batch_create(wp_batch **out, const wp_plan *p, int P, const wp_G *G) {
         b->M[i] = G[i].M;
         b->y_off[i] = off;
         desc[i] = ProbDesc{G[i].rowptr, G[i].col, G[i].val, G[i].order == WP_ORDER_SORTED ? nullptr : G[i].perm,
-                           G[i].tcolptr, G[i].trow, G[i].tval, G[i].M, off};
+                           G[i].tcolptr, G[i].trow, G[i].tval, G[i].rscale, G[i].M, off};
         off += G[i].M;
     }
     b->M_total = off;
@@ -304,12 +322,12 @@ int64_t batch_total_vis(const wp_batch *b) { return b->M_total; }
 
 wp_status batch_phi(wp_batch *b, const float2 *x, float2 *y, float2 *grids, hipStream_t s) {
     if (wp_status st = launch_grid_forward(b->plan, x, grids, s, b->P)) return st;
-    return b->taps == WP_TAPS_BF16 ? launch_deg<true>(b, grids, y, s) : launch_deg<false>(b, grids, y, s);
+    return run_deg(b, grids, y, s);
 }
 
 wp_status batch_phiT(wp_batch *b, const float2 *y, float2 *x, float2 *grids, hipStream_t s) {
     if (!b->transpose) return wp_set_error(WP_EUNSUPPORTED, "batch adjoint needs the transposed copy of every G");
-    wp_status st = b->taps == WP_TAPS_BF16 ? launch_gat<true>(b, y, grids, s) : launch_gat<false>(b, y, grids, s);
+    wp_status st = run_gat(b, y, grids, s);
     if (st != WP_OK) return st;
     return launch_grid_adjoint(b->plan, grids, x, s, b->P);
 }
@@ -324,8 +342,8 @@ wp_status batch_autotune(wp_batch *b, const float2 *x, float2 *y, float2 *grids,
         for (int i = 0; i < 7; ++i) {
             if (i == 2) WP_HIP(hipEventRecord(e0, s));
             wp_status st;
-            if (deg) st = b->taps == WP_TAPS_BF16 ? launch_deg<true>(b, grids, y, s) : launch_deg<false>(b, grids, y, s);
-            else st = b->taps == WP_TAPS_BF16 ? launch_gat<true>(b, y, grids, s) : launch_gat<false>(b, y, grids, s);
+            if (deg) st = run_deg(b, grids, y, s);
+            else st = run_gat(b, y, grids, s);
             if (st != WP_OK) return st;
         }
         WP_HIP(hipEventRecord(e1, s));

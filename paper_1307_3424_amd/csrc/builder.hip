@@ -285,13 +285,14 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
 
 // ---------------------------------------------------------------------------- pass 2: fill
 
-template <int LOGNG, bool BF16>
+template <int LOGNG, int TK>
 __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u, const double *__restrict__ v,
                                                    const double *__restrict__ w, int64_t M,
                                                    double cell, double delta, int W, double beta,
                                                    const double2 *__restrict__ tw64, const double *__restrict__ tau_in,
                                                    const int *__restrict__ perm, const int64_t *__restrict__ rowptr,
-                                                   int *__restrict__ col, void *__restrict__ val, int *__restrict__ err) {
+                                                   int *__restrict__ col, void *__restrict__ val,
+                                                   float *__restrict__ rscale, int *__restrict__ err) {
     constexpr int Ng = 1 << LOGNG;
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *h = (double2 *)smem;                 // Ng
@@ -325,6 +326,9 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
     }
     amax = block_max(amax, redd);
     bmax = block_max(bmax, redd);
+    // int16 block floating point: every tap |g| <= sqrt(amax bmax), so re / s and im / s fit in +-32767
+    const double i16_scale = sqrt(amax * bmax) / 32767.0;
+    if (TK == WP_TAPS_I16 && threadIdx.x == 0) rscale[r] = (float)i16_scale;
     // candidate compaction (ascending index); a kept tap needs A_a bmax >= tau and amax B_b >= tau
     {
         int na = 0, nb = 0;
@@ -399,7 +403,9 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
                 const int64_t p = pos + rank;
                 if (p < beg + len) {
                     col[p] = b * Ng + a;
-                    if (BF16) ((uint32_t *)val)[p] = pack_bf16x2((float)g.x, (float)g.y);
+                    if (TK == WP_TAPS_BF16) ((uint32_t *)val)[p] = pack_bf16x2((float)g.x, (float)g.y);
+                    else if (TK == WP_TAPS_I16)
+                        ((uint32_t *)val)[p] = pack_i16x2((float)(g.x / i16_scale), (float)(g.y / i16_scale));
                     else ((float2 *)val)[p] = make_float2((float)g.x, (float)g.y);
                 }
             }
@@ -662,12 +668,17 @@ wp_status fill_rows(const wp_plan *p, int64_t M, const double *u, const double *
     if (lds > 160 * 1024) return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d exceeds the LDS budget", p->Ng);
     int *err = (int *)(ws + L.err);
     if (G->taps == WP_TAPS_BF16)
-        hipLaunchKernelGGL((k_row_fill<LOGNG, true>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta, p->W,
-                           p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val, err);
-    else
-        hipLaunchKernelGGL((k_row_fill<LOGNG, false>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
+        hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_BF16>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
                            p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val,
-                           err);
+                           G->rscale, err);
+    else if (G->taps == WP_TAPS_I16)
+        hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_I16>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
+                           p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val,
+                           G->rscale, err);
+    else
+        hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_C64>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
+                           p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val,
+                           G->rscale, err);
     return wp_check_launch("build_G_fill rows");
 }
 
@@ -776,14 +787,14 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
         device_scan<int, int64_t>(cnt, G->tcolptr, cells, (int64_t *)(ws + L.sc64t), s);
         WP_HIP(hipMemsetAsync(cnt, 0, 4 * cells, s));
         const dim3 gR((unsigned)((M * 64 + nthr - 1) / nthr));
-        if (G->taps == WP_TAPS_BF16)
+        if (G->taps != WP_TAPS_C64)
             hipLaunchKernelGGL((k_t_fill<uint32_t>), gR, dim3(nthr), 0, s, G->rowptr, G->col,
                                (const uint32_t *)G->val, G->perm, M, G->tcolptr, cnt, G->trow, (uint32_t *)G->tval);
         else
             hipLaunchKernelGGL((k_t_fill<float2>), gR, dim3(nthr), 0, s, G->rowptr, G->col, (const float2 *)G->val,
                                G->perm, M, G->tcolptr, cnt, G->trow, (float2 *)G->tval);
         const dim3 gC((unsigned)((cells + nthr - 1) / nthr));
-        if (G->taps == WP_TAPS_BF16)
+        if (G->taps != WP_TAPS_C64)
             hipLaunchKernelGGL((k_t_sort<uint32_t>), gC, dim3(nthr), 0, s, G->tcolptr, cells, G->trow,
                                (uint32_t *)G->tval);
         else

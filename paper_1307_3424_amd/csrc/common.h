@@ -76,6 +76,22 @@ __host__ __device__ inline uint32_t pack_bf16x2(float re, float im) {
 __device__ inline float2 unpack_bf16x2(uint32_t p) {
     return make_float2(__uint_as_float(p << 16), __uint_as_float(p & 0xffff0000u));
 }
+// int16 pair (re in the low half), unscaled
+__host__ __device__ inline uint32_t pack_i16x2(float re, float im) {
+    const int a = (int)fminf(32767.f, fmaxf(-32767.f, rintf(re)));
+    const int b = (int)fminf(32767.f, fmaxf(-32767.f, rintf(im)));
+    return ((uint32_t)(uint16_t)(int16_t)a) | ((uint32_t)(uint16_t)(int16_t)b << 16);
+}
+__device__ inline float2 unpack_i16x2(uint32_t p) {
+    return make_float2((float)(int16_t)(p & 0xffffu), (float)(int16_t)(p >> 16));
+}
+// raw tap value of kind TK (WP_TAPS_*); int16 taps come back unscaled
+template <int TK>
+__device__ __forceinline__ float2 load_tap_raw(const void *__restrict__ val, int64_t j) {
+    if constexpr (TK == WP_TAPS_C64) return ((const float2 *)val)[j];
+    else if constexpr (TK == WP_TAPS_BF16) return unpack_bf16x2(((const uint32_t *)val)[j]);
+    else return unpack_i16x2(((const uint32_t *)val)[j]);
+}
 
 // ---------------------------------------------------------------------------- XCD-aware block order
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD b % 8).

@@ -19,16 +19,12 @@ namespace {
 constexpr int SP_NTH = 256;
 constexpr int WAVES = SP_NTH / 64;
 
-template <bool BF16>
-__device__ __forceinline__ float2 load_tap(const void *__restrict__ val, int64_t j) {
-    if constexpr (BF16) return unpack_bf16x2(((const uint32_t *)val)[j]);
-    else return ((const float2 *)val)[j];
-}
 
 // LPR lanes per row (64 / LPR rows per wave); each lane keeps U taps in flight.
-template <bool BF16, int LPR, int U>
+template <int TK, int LPR, int U>
 __global__ __launch_bounds__(SP_NTH) void k_degrid(const int64_t *__restrict__ rowptr, const int *__restrict__ col,
-                                                   const void *__restrict__ val, const float2 *__restrict__ grid,
+                                                   const void *__restrict__ val, const float *__restrict__ rscale,
+                                                   const float2 *__restrict__ grid,
                                                    const int *__restrict__ perm, float2 *__restrict__ y, int64_t M) {
     // perm == nullptr: y in sorted row order
     const int sub = threadIdx.x & (LPR - 1);
@@ -45,7 +41,7 @@ __global__ __launch_bounds__(SP_NTH) void k_degrid(const int64_t *__restrict__ r
                 const int64_t j = j0 + LPR * t;
                 if (j < end) {
                     c[t] = col[j];
-                    v[t] = load_tap<BF16>(val, j);
+                    v[t] = load_tap_raw<TK>(val, j);
                 } else {
                     c[t] = 0;
                     v[t] = make_float2(0.f, 0.f);
@@ -66,13 +62,21 @@ __global__ __launch_bounds__(SP_NTH) void k_degrid(const int64_t *__restrict__ r
         ar += __shfl_xor(ar, o);
         ai += __shfl_xor(ai, o);
     }
-    if (sub == 0 && r < M) y[perm ? perm[r] : r] = make_float2(ar, ai);
+    if (sub == 0 && r < M) {
+        if constexpr (TK == WP_TAPS_I16) {
+            const float sc = rscale[r];
+            ar *= sc;
+            ai *= sc;
+        }
+        y[perm ? perm[r] : r] = make_float2(ar, ai);
+    }
 }
 
-template <bool BF16>
+template <int TK>
 __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work, int64_t n_work,
                                                     const int64_t *__restrict__ rowptr, const int *__restrict__ col,
-                                                    const void *__restrict__ val, const int *__restrict__ perm,
+                                                    const void *__restrict__ val, const float *__restrict__ rscale,
+                                                    const int *__restrict__ perm,
                                                     const float2 *__restrict__ y, float *__restrict__ grid, int logNg,
                                                     int tile, int halo) {
     extern __shared__ float win[];                  // [2][WS][WS]: real plane, imaginary plane
@@ -87,11 +91,15 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int r = rb + wid; r < re; r += WAVES) {
-        const float2 yk = y[perm ? perm[r] : r];
+        float2 yk = y[perm ? perm[r] : r];
+        if constexpr (TK == WP_TAPS_I16) {
+            yk.x *= rscale[r];
+            yk.y *= rscale[r];
+        }
         const int64_t end = rowptr[r + 1];
         for (int64_t j = rowptr[r] + lane; j < end; j += 64) {
             const int c = col[j];
-            const float2 v = load_tap<BF16>(val, j);
+            const float2 v = load_tap_raw<TK>(val, j);
             const float cr = v.x * yk.x + v.y * yk.y;      // conj(v) * y
             const float ci = v.x * yk.y - v.y * yk.x;
             const int dv = ((c >> logNg) - v0) & mask;
@@ -121,9 +129,10 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
 // Gather form of G^H: grid cell c sums conj(G_kc) y_k over its entries of the
 // transposed copy.  LPR lanes per cell (64 / LPR cells per wave), U entries in
 // flight per lane, cells in order, every cell written once (no atomics).
-template <bool BF16, int LPR, int U>
+template <int TK, int LPR, int U>
 __global__ __launch_bounds__(SP_NTH) void k_gather(const int64_t *__restrict__ tcolptr, const int *__restrict__ trow,
-                                                   const void *__restrict__ tval, const float2 *__restrict__ y,
+                                                   const void *__restrict__ tval, const float *__restrict__ rscale,
+                                                   const float2 *__restrict__ y,
                                                    const int *__restrict__ perm, float2 *__restrict__ grid,
                                                    int64_t cells) {
     // perm == nullptr: y in sorted row order
@@ -140,8 +149,14 @@ __global__ __launch_bounds__(SP_NTH) void k_gather(const int64_t *__restrict__ t
             for (int t = 0; t < U; ++t) {
                 const int64_t j = j0 + LPR * t;
                 if (j < end) {
-                    k[t] = perm ? perm[trow[j]] : trow[j];
-                    v[t] = load_tap<BF16>(tval, j);
+                    const int r = trow[j];
+                    k[t] = perm ? perm[r] : r;
+                    v[t] = load_tap_raw<TK>(tval, j);
+                    if constexpr (TK == WP_TAPS_I16) {
+                        const float sc = rscale[r];
+                        v[t].x *= sc;
+                        v[t].y *= sc;
+                    }
                 } else {
                     k[t] = -1;
                     v[t] = make_float2(0.f, 0.f);
@@ -201,22 +216,22 @@ int pick_lpr(double mean, double div, int tune) {
     return l;
 }
 
-#define WP_SPMV_DISPATCH(KERNEL, BF16, LPR, U, GRID, ...)                                            \
+#define WP_SPMV_DISPATCH(KERNEL, TK, LPR, U, GRID, ...)                                            \
     do {                                                                                             \
         switch ((LPR) * 100 + (U)) {                                                                 \
-            case 404: hipLaunchKernelGGL((KERNEL<BF16, 4, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
-            case 408: hipLaunchKernelGGL((KERNEL<BF16, 4, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
-            case 804: hipLaunchKernelGGL((KERNEL<BF16, 8, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
-            case 808: hipLaunchKernelGGL((KERNEL<BF16, 8, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
-            case 1604: hipLaunchKernelGGL((KERNEL<BF16, 16, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            case 1608: hipLaunchKernelGGL((KERNEL<BF16, 16, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            case 1616: hipLaunchKernelGGL((KERNEL<BF16, 16, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            case 3204: hipLaunchKernelGGL((KERNEL<BF16, 32, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            case 3208: hipLaunchKernelGGL((KERNEL<BF16, 32, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            case 3216: hipLaunchKernelGGL((KERNEL<BF16, 32, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            case 6404: hipLaunchKernelGGL((KERNEL<BF16, 64, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            case 6408: hipLaunchKernelGGL((KERNEL<BF16, 64, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
-            default: hipLaunchKernelGGL((KERNEL<BF16, 64, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 404: hipLaunchKernelGGL((KERNEL<TK, 4, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 408: hipLaunchKernelGGL((KERNEL<TK, 4, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 804: hipLaunchKernelGGL((KERNEL<TK, 8, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 808: hipLaunchKernelGGL((KERNEL<TK, 8, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break;   \
+            case 1604: hipLaunchKernelGGL((KERNEL<TK, 16, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 1608: hipLaunchKernelGGL((KERNEL<TK, 16, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 1616: hipLaunchKernelGGL((KERNEL<TK, 16, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 3204: hipLaunchKernelGGL((KERNEL<TK, 32, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 3208: hipLaunchKernelGGL((KERNEL<TK, 32, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 3216: hipLaunchKernelGGL((KERNEL<TK, 32, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 6404: hipLaunchKernelGGL((KERNEL<TK, 64, 4>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            case 6408: hipLaunchKernelGGL((KERNEL<TK, 64, 8>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
+            default: hipLaunchKernelGGL((KERNEL<TK, 64, 16>), GRID, dim3(SP_NTH), 0, __VA_ARGS__); break; \
         }                                                                                            \
     } while (0)
 
@@ -239,9 +254,14 @@ wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, flo
     const int64_t nb = (G->M * lpr + SP_NTH - 1) / SP_NTH;
     const dim3 g((unsigned)nb);
     if (G->taps == WP_TAPS_BF16)
-        WP_SPMV_DISPATCH(k_degrid, true, lpr, U, g, s, G->rowptr, G->col, G->val, grid, yperm(G), y, G->M);
+        WP_SPMV_DISPATCH(k_degrid, WP_TAPS_BF16, lpr, U, g, s, G->rowptr, G->col, G->val, G->rscale, grid, yperm(G),
+                         y, G->M);
+    else if (G->taps == WP_TAPS_I16)
+        WP_SPMV_DISPATCH(k_degrid, WP_TAPS_I16, lpr, U, g, s, G->rowptr, G->col, G->val, G->rscale, grid, yperm(G),
+                         y, G->M);
     else
-        WP_SPMV_DISPATCH(k_degrid, false, lpr, U, g, s, G->rowptr, G->col, G->val, grid, yperm(G), y, G->M);
+        WP_SPMV_DISPATCH(k_degrid, WP_TAPS_C64, lpr, U, g, s, G->rowptr, G->col, G->val, G->rscale, grid, yperm(G),
+                         y, G->M);
     return wp_check_launch("degrid");
 }
 
@@ -254,9 +274,14 @@ wp_status launch_gather(const wp_plan *p, const wp_G *G, const float2 *y, float2
     const int64_t nb = (cells * lpr + SP_NTH - 1) / SP_NTH;
     const dim3 g((unsigned)nb);
     if (G->taps == WP_TAPS_BF16)
-        WP_SPMV_DISPATCH(k_gather, true, lpr, U, g, s, G->tcolptr, G->trow, G->tval, y, yperm(G), grid, cells);
+        WP_SPMV_DISPATCH(k_gather, WP_TAPS_BF16, lpr, U, g, s, G->tcolptr, G->trow, G->tval, G->rscale, y, yperm(G),
+                         grid, cells);
+    else if (G->taps == WP_TAPS_I16)
+        WP_SPMV_DISPATCH(k_gather, WP_TAPS_I16, lpr, U, g, s, G->tcolptr, G->trow, G->tval, G->rscale, y, yperm(G),
+                         grid, cells);
     else
-        WP_SPMV_DISPATCH(k_gather, false, lpr, U, g, s, G->tcolptr, G->trow, G->tval, y, yperm(G), grid, cells);
+        WP_SPMV_DISPATCH(k_gather, WP_TAPS_C64, lpr, U, g, s, G->tcolptr, G->trow, G->tval, G->rscale, y, yperm(G),
+                         grid, cells);
     return wp_check_launch("grid_gather");
 }
 
@@ -265,12 +290,16 @@ wp_status launch_scatter(const wp_plan *p, const wp_G *G, const float2 *y, float
     if (st != WP_OK || G->n_work == 0) return st;
     const int WS = p->tile + 2 * p->halo;
     const size_t lds = (size_t)2 * WS * WS * sizeof(float);
+    const dim3 gw((unsigned)G->n_work), bw(SP_NTH);
     if (G->taps == WP_TAPS_BF16)
-        hipLaunchKernelGGL((k_scatter<true>), dim3((unsigned)G->n_work), dim3(SP_NTH), lds, s, G->work, G->n_work,
-                           G->rowptr, G->col, G->val, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
+        hipLaunchKernelGGL((k_scatter<WP_TAPS_BF16>), gw, bw, lds, s, G->work, G->n_work, G->rowptr, G->col, G->val,
+                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
+    else if (G->taps == WP_TAPS_I16)
+        hipLaunchKernelGGL((k_scatter<WP_TAPS_I16>), gw, bw, lds, s, G->work, G->n_work, G->rowptr, G->col, G->val,
+                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
     else
-        hipLaunchKernelGGL((k_scatter<false>), dim3((unsigned)G->n_work), dim3(SP_NTH), lds, s, G->work, G->n_work,
-                           G->rowptr, G->col, G->val, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
+        hipLaunchKernelGGL((k_scatter<WP_TAPS_C64>), gw, bw, lds, s, G->work, G->n_work, G->rowptr, G->col, G->val,
+                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
     return wp_check_launch("grid_scatter");
 }
 

@@ -62,7 +62,7 @@ def test_null_arguments_rejected():
 
 
 def test_wp_G_layout_matches_header():
-    assert C.sizeof(_lib.WpG) == 8 * 2 + 4 * 2 + 8 * 5 + 8 + 8 * 3
+    assert C.sizeof(_lib.WpG) == 8 * 2 + 4 * 2 + 8 * 5 + 8 + 8 + 8 * 3
 
 
 def test_library_db8_filter_matches_oracle_derivation():

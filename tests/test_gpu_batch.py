@@ -33,13 +33,14 @@ def _problems(N, counts, seed=3):
     return out
 
 
-@pytest.mark.parametrize("order", [wp.WP_ORDER_CALLER, wp.WP_ORDER_SORTED])
-def test_batch_matches_single_problem_applies_and_oracle(order):
+@pytest.mark.parametrize("order,taps", [(wp.WP_ORDER_CALLER, wp.WP_TAPS_C64), (wp.WP_ORDER_SORTED, wp.WP_TAPS_C64),
+                                        (wp.WP_ORDER_SORTED, wp.WP_TAPS_I16)])
+def test_batch_matches_single_problem_applies_and_oracle(order, taps):
     N, counts = 128, [57, 3001, 1, 700, 12000]
-    print(f"batch N={N} counts={counts} order={order}", flush=True)
+    print(f"batch N={N} counts={counts} order={order} taps={taps}", flush=True)
     plan = wp.Plan(N, L)
     probs = _problems(N, counts)
-    Gs = [wp.build_G(plan, dev(u), dev(v), dev(w), 0.99) for u, v, w in probs]
+    Gs = [wp.build_G(plan, dev(u), dev(v), dev(w), 0.99, taps=taps) for u, v, w in probs]
     for G in Gs:
         G.order = order
     torch.cuda.synchronize()

@@ -163,22 +163,24 @@ def test_phi_and_adjoint_tiny_form():
         assert relerr(xa, x_ref) < TOL, use_t
 
 
-@pytest.mark.parametrize("taps", ["c64", "bf16"])
+@pytest.mark.parametrize("taps", ["c64", "bf16", "i16"])
 def test_gather_and_scatter_grid_match_oracle(taps):
     wl = synth.workload(0)
     _, u, v, w = synth.workload_inputs(wl, with_sky=False)
     s = Setup(N=wl.N, L=wl.L)
     plan = wp.Plan(wl.N, wl.L)
-    t = wp.WP_TAPS_C64 if taps == "c64" else wp.WP_TAPS_BF16
+    t = {"c64": wp.WP_TAPS_C64, "bf16": wp.WP_TAPS_BF16, "i16": wp.WP_TAPS_I16}[taps]
     G = build(plan, u, v, w, wl.E, taps=t)
     yv = synth.random_complex(wl.M, synth.rng_for(wl.seed, "y", 5))
     Xg = wp.grid_gather(plan, G, c64(yv)).cpu().numpy()
     Xs = wp.grid_scatter(plan, G, c64(yv)).cpu().numpy()
     Go = wproj.build_rows(u, v, w, wl.E, s)
     X_ref = Go.conj().T @ yv
-    tol = TOL if taps == "c64" else 4e-3
+    tol = {"c64": TOL, "bf16": 4e-3, "i16": 1e-4}[taps]
     assert relerr(Xg, X_ref) < tol and relerr(Xs, X_ref) < tol
     assert relerr(Xg, Xs) < 1e-5
+    x = synth.sky(wl.N, 4, 6, synth.rng_for(wl.seed, "sky", 5))
+    assert relerr(wp.apply_Phi(plan, G, c64(x)).cpu().numpy(), wproj.phi(Go, x, s)) < tol
 
 
 def test_transposed_copy_structure():
