@@ -17,8 +17,9 @@
 //      costs O(Ng log Ng).  The bisection converges to a tap energy, so the kept
 //      set {A_a B_b >= tau} (ties kept) is the sort-defined set.  E >= 1 keeps
 //      every non-zero tap.
-//   5. CSR: rows are sorted by uv tile (stable radix sort of the tile id made of
-//      1-bit stable partitions), row lengths are scanned into int64 offsets,
+//   5. CSR: rows are sorted by the Z-order code of their centre cell (stable radix
+//      sort made of 1-bit stable partitions; every aligned 32 x 32 tile of cells is
+//      then a contiguous range of rows), row lengths are scanned into int64 offsets,
 //      and the fill pass writes each row's taps in ascending flattened column
 //      q_v Ng + q_u, values g_v g_u rounded to complex float32 (or bf16 pairs).
 // Pass 1 (count) computes tau, row lengths, the tile sort, the offsets and the
@@ -35,6 +36,21 @@ constexpr int BNTH = 256;      // builder block size
 constexpr int ROWS_PER_ITEM = 32;
 
 // ---------------------------------------------------------------------------- small device helpers
+
+// Z-order (Morton) code of a cell: bits of u in the even positions, bits of v in the odd ones.
+// Every aligned power-of-two block of cells is one contiguous range of codes.
+__host__ __device__ inline int morton2(int v, int u) {
+    int code = 0;
+    for (int b = 0; b < 12; ++b) code |= (((u >> b) & 1) << (2 * b)) | (((v >> b) & 1) << (2 * b + 1));
+    return code;
+}
+__host__ __device__ inline void demorton2(int code, int &v, int &u) {
+    u = v = 0;
+    for (int b = 0; b < 12; ++b) {
+        u |= ((code >> (2 * b)) & 1) << b;
+        v |= ((code >> (2 * b + 1)) & 1) << b;
+    }
+}
 
 __device__ inline double bessel_i0(double x) {
     // power series sum_k ((x/2)^2)^k / (k!)^2
@@ -275,10 +291,13 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
     if (threadIdx.x == 0) {
         tau_out[k] = tau;
         nnz_out[k] = (int)cnt;
-        int tu_i = (int)floor((ut + Ng / 2) / tile), tv_i = (int)floor((vt + Ng / 2) / tile);
-        tu_i = min(max(tu_i, 0), ntile - 1);
-        tv_i = min(max(tv_i, 0), ntile - 1);
-        key_out[k] = tv_i * ntile + tu_i;
+        // rows are sorted by the Z-order code of their centre cell (tiles of the scatter are then
+        // contiguous ranges, and rows close in the uv plane are close in memory)
+        const int cu = min(max((int)floor(ut + Ng / 2), 0), Ng - 1);
+        const int cv = min(max((int)floor(vt + Ng / 2), 0), Ng - 1);
+        key_out[k] = morton2(cv, cu);
+        (void)tile;
+        (void)ntile;
         (void)redi;
     }
 }
@@ -529,12 +548,14 @@ __global__ void k_gather_nnz(const int *__restrict__ perm, const int *__restrict
     if (r < M) snnz[r] = nnz[perm[r]];
 }
 
-__global__ void k_tile_bounds(const int *__restrict__ skey, int64_t M, int *__restrict__ tstart, int *__restrict__ tend) {
+// row range of every tile: the tile's Z-order code is the row key shifted by the tile's bits
+__global__ void k_tile_bounds(const int *__restrict__ skey, int64_t M, int shift, int *__restrict__ tstart,
+                              int *__restrict__ tend) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= M) return;
-    const int k = skey[r];
-    if (r == 0 || skey[r - 1] != k) tstart[k] = (int)r;
-    if (r == M - 1 || skey[r + 1] != k) tend[k] = (int)r + 1;
+    const int k = skey[r] >> shift;
+    if (r == 0 || (skey[r - 1] >> shift) != k) tstart[k] = (int)r;
+    if (r == M - 1 || (skey[r + 1] >> shift) != k) tend[k] = (int)r + 1;
 }
 
 __global__ void k_tile_chunks(const int *__restrict__ tstart, const int *__restrict__ tend, int T,
@@ -549,9 +570,12 @@ __global__ void k_write_items(const int *__restrict__ tstart, const int *__restr
     if (t >= T) return;
     const int s = tstart[t], e = tend[t];
     int it = choff[t];
+    int tv, tu;
+    demorton2(t, tv, tu);
+    (void)ntile;
     for (int r = s; r < e; r += ROWS_PER_ITEM, ++it) {
-        work[4 * it + 0] = t / ntile;
-        work[4 * it + 1] = t % ntile;
+        work[4 * it + 0] = tv;
+        work[4 * it + 1] = tu;
         work[4 * it + 2] = r;
         work[4 * it + 3] = min(r + ROWS_PER_ITEM, e);
     }
@@ -704,14 +728,13 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
         default: return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d", p->Ng);
     }
     if (st != WP_OK) return st;
-    // stable sort of the rows by tile id: one stable partition per key bit
+    // stable sort of the rows by the Z-order code of their centre cell: one stable partition per key bit
     const int nthr = 256;
     const dim3 gM((unsigned)((M + nthr - 1) / nthr));
     int *k0 = (int *)(ws + L.k0), *k1 = (int *)(ws + L.k1), *i0 = (int *)(ws + L.i0), *i1 = (int *)(ws + L.i1);
     int *flags = (int *)(ws + L.flags), *zpos = (int *)(ws + L.zpos);
     hipLaunchKernelGGL(k_iota_keys, gM, dim3(nthr), 0, s, (const int *)(ws + L.key), k0, i0, M);
-    int bits = 0;
-    while ((1 << bits) < T) ++bits;
+    const int bits = 2 * p->logNg;            // Z-order code of the centre cell
     for (int b = 0; b < bits; ++b) {
         hipLaunchKernelGGL(k_bit_flags, gM, dim3(nthr), 0, s, k0, b, flags, M);
         device_scan<int, int>(flags, zpos, M, (int *)(ws + L.sc32), s);
@@ -731,7 +754,10 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
     // adjoint work items: chunks of rows inside each tile
     WP_HIP(hipMemsetAsync(ws + L.tstart, 0, 4 * T, s));
     WP_HIP(hipMemsetAsync(ws + L.tend, 0, 4 * T, s));
-    hipLaunchKernelGGL(k_tile_bounds, gM, dim3(nthr), 0, s, skey, M, (int *)(ws + L.tstart), (int *)(ws + L.tend));
+    int tbits = 0;
+    while ((1 << tbits) < p->tile) ++tbits;
+    hipLaunchKernelGGL(k_tile_bounds, gM, dim3(nthr), 0, s, skey, M, 2 * tbits, (int *)(ws + L.tstart),
+                       (int *)(ws + L.tend));
     const dim3 gT((unsigned)((T + nthr - 1) / nthr));
     hipLaunchKernelGGL(k_tile_chunks, gT, dim3(nthr), 0, s, (const int *)(ws + L.tstart), (const int *)(ws + L.tend),
                        T, (int *)(ws + L.nch));
