@@ -221,6 +221,74 @@ wp_status wp_batch_autotune(wp_batch *batch, const void *x, void *y, void *grids
                             float *best_us2);
 
 /* ----------------------------------------------------------------------------------------
+ * Learned surrogate of the rows of G.  A row (Section 3.1 kernel, Section 3.2 energy rule)
+ * depends on the visibility only through w and the offset (du, dv) = (u~, v~) - c of its grid
+ * coordinate from the nearest cell c = floor(u~ + 1/2): the row of u~ = c + du is the row of
+ * du shifted by c.  The surrogate network maps the features
+ *     f = (2 w / w_top - 1, 2 du, 2 dv)
+ * through an MLP 3 -> 256 -> 256 -> 256 -> 2048 with GELU (x Phi(x), error-function form)
+ * after the hidden layers, to the taps of the 32 x 32 box of cells (c_v - 16 .. c_v + 15) x
+ * (c_u - 16 .. c_u + 15) (mod Ng): output 2p (2p + 1) is s_out times the real (imaginary)
+ * part of box cell p = 32 oy + ox.  Parameters are packed in FP32 (wp_mlp_param_count()
+ * floats) in the order W1 [256][3], b1 [256], W2 [256][256], b2, W3 [256][256], b3,
+ * W4 [2048][256], b4 [2048], row-major, W_l mapping layer l-1 to layer l.
+ * Products W_l a_{l-1} (l = 2..4) and the backward products take bfloat16 operands with FP32
+ * accumulation on MFMA; the first layer, biases, GELU, loss, bias / W1 gradients and Adam are
+ * FP32.  Training loss: mean over the 2048 outputs of (o - t)^2, t = exact taps / s_out.
+ * The object owns its parameters, Adam moments and activation buffers for up to max_batch
+ * rows; calls on one object must not overlap.
+ * ------------------------------------------------------------------------------------- */
+typedef struct wp_mlp wp_mlp;
+
+/* Number of FP32 parameters (658944). */
+int64_t wp_mlp_param_count(void);
+/* Allocate a network with activation buffers for max_batch rows (multiple of 64, <= 2^20);
+ * parameters start at zero.  Synchronous. */
+wp_status wp_mlp_create(wp_mlp **out, int max_batch);
+wp_status wp_mlp_destroy(wp_mlp *mlp);
+/* Copy the packed parameters from HOST memory, set the feature scale w_top (> 0) and the
+ * output scale s_out (> 0), and reset Adam (step 0, zero moments).  Synchronous. */
+wp_status wp_mlp_set_params(wp_mlp *mlp, const float *params_host, double w_top, double s_out);
+/* Copy the packed parameters to HOST memory; w_top / s_out may be NULL.  Synchronous. */
+wp_status wp_mlp_get_params(const wp_mlp *mlp, float *params_host, double *w_top, double *s_out);
+/* feat[3k..3k+2] = f of visibility k (device float32 [3n]) from u, v, w (device float64 [n]);
+ * a non-finite coordinate or |u~|, |v~| >= Ng/2 sets bit 0 of *err (device int, caller
+ * zeroes it). */
+wp_status wp_mlp_features(const wp_plan *plan, const wp_mlp *mlp, int64_t n, const double *u,
+                          const double *v, const double *w, float *feat, int *err, void *stream);
+/* out[n][2048] = network outputs (device float32) of feat[n][3]; 0 <= n <= max_batch. */
+wp_status wp_mlp_forward(wp_mlp *mlp, int n, const float *feat, float *out, void *stream);
+/* Gradients of the loss for targets target[n][2048] (device float32, exact taps / s_out):
+ * copied to grads (device float32 [param_count], may be NULL); *loss (host, may be NULL)
+ * receives the loss, which synchronises the stream.  n: multiple of 64 in [64, max_batch]. */
+wp_status wp_mlp_gradients(wp_mlp *mlp, int n, const float *feat, const float *target,
+                           float *grads, double *loss, void *stream);
+/* One Adam step (Kingma & Ba 2015, bias-corrected) with the gradients of the last
+ * wp_mlp_gradients or training step. */
+wp_status wp_mlp_adam_step(wp_mlp *mlp, float lr, float beta1, float beta2, float eps,
+                           void *stream);
+/* Train on n samples (feat [n][3], target [n][2048], device) for `epochs` passes of
+ * floor(n / batch) minibatches; each pass visits the samples in the order (a i + c) mod n
+ * with a coprime to n, changing per pass.  Adam (0.9, 0.999, 1e-8); learning rate
+ * lr_max * min(1, t / warm) * (1 + cos(pi t / T)) / 2 over T steps, warm = T / 32.
+ * loss_hist (HOST, may be NULL) receives each pass's mean loss, which synchronises once per
+ * pass. */
+wp_status wp_mlp_train(wp_mlp *mlp, int64_t n, const float *feat, const float *target, int batch,
+                       int epochs, float lr_max, double *loss_hist, void *stream);
+/* Training targets from exact rows: G (complex64 taps, built by wp_build_G_* from u, v of the
+ * samples) scattered into each visibility's box and divided by s_out: target[k][2048]
+ * (device float32, caller order k; cells of the box outside the row are 0), lost[k] = row
+ * energy outside the box / row energy (device float32). */
+wp_status wp_mlp_box_targets(const wp_plan *plan, const wp_G *G, const double *u, const double *v,
+                             double s_out, float *target, float *lost, void *stream);
+/* Per-row energy error of the surrogate against exact rows G (complex64 taps):
+ * eps[k] = ||t_k - g_k||^2 / ||g_k||^2 (device float32 [G->M], caller order), t_k the network's
+ * box taps for feat[k] (device float32 [3 G->M]), row entries outside the box counting in full.
+ * Runs the network in chunks of max_batch rows (overwrites its activation buffers). */
+wp_status wp_mlp_row_errors(const wp_plan *plan, wp_mlp *mlp, const wp_G *G, const double *u,
+                            const double *v, const float *feat, float *eps, void *stream);
+
+/* ----------------------------------------------------------------------------------------
  * Reconstruction (Eq. 7): min ||Psi^T x||_1 s.t. ||y - Phi x||_2 <= eps, x >= 0, with Psi the
  * Daubechies wavelets of 8 vanishing moments (Section 4.2), periodic, `levels` levels.
  * ------------------------------------------------------------------------------------- */

@@ -331,3 +331,21 @@ def row_errors(net: Net, u, v, w, G, s, q=_ident) -> np.ndarray:
         a, b = G.indptr[k], G.indptr[k + 1]
         out[k] = energy_error(t[k], G.indices[a:b], G.data[a:b], int(cu[k]), int(cv[k]), s.Ng)
     return out
+
+
+def from_packed(p, w_top: float = 1.0, s_out: float = 1.0, H: int = HIDDEN, n_out: int = N_OUT) -> Net:
+    """Net from a flat parameter vector in the order W1 [H,3], b1, W2 [H,H], b2, W3, b3, W4 [n_out,H], b4."""
+    p = np.asarray(p, dtype=np.float64)
+    shapes = [(H, 3), (H,), (H, H), (H,), (H, H), (H,), (n_out, H), (n_out,)]
+    out, o = [], 0
+    for sh in shapes:
+        n = int(np.prod(sh))
+        out.append(p[o:o + n].reshape(sh))
+        o += n
+    if o != p.size:
+        raise ValueError(f"expected {o} parameters, got {p.size}")
+    return Net(*out, s_out=s_out, w_top=w_top)
+
+
+def to_packed(net: Net) -> np.ndarray:
+    return np.concatenate([getattr(net, k).ravel() for k in net.NAMES])

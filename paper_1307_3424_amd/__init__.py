@@ -21,7 +21,7 @@ from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16", "WP_TAPS_I16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
-           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "Batch"]
+           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "Batch", "Mlp"]
 
 
 def _torch():
@@ -366,6 +366,129 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().wp_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _dev_f32n(t, n, name):
+    torch = _torch()
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous float32 CUDA tensor with {n} elements")
+    return t
+
+
+class Mlp:
+    """wp_mlp_*: the surrogate network (parameters, Adam moments and activations on the device)."""
+
+    H, BOX, NOUT = 256, 32, 2048
+
+    def __init__(self, max_batch: int = 8192):
+        h = C.c_void_p()
+        check(load().wp_mlp_create(C.byref(h), int(max_batch)), "wp_mlp_create")
+        self._h = h
+        self.max_batch = int(max_batch)
+
+    @staticmethod
+    def param_count() -> int:
+        return int(load().wp_mlp_param_count())
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_params(self, params, w_top: float, s_out: float):
+        import numpy as np
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.param_count():
+            raise ValueError(f"params: need {self.param_count()} floats")
+        check(load().wp_mlp_set_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float)), float(w_top),
+                                       float(s_out)), "wp_mlp_set_params")
+
+    def get_params(self):
+        import numpy as np
+        p = np.empty(self.param_count(), dtype=np.float32)
+        wt, so = C.c_double(), C.c_double()
+        check(load().wp_mlp_get_params(self._h, p.ctypes.data_as(C.POINTER(C.c_float)), C.byref(wt), C.byref(so)),
+              "wp_mlp_get_params")
+        return p, wt.value, so.value
+
+    def features(self, plan: Plan, u, v, w, out=None, stream=None):
+        torch = _torch()
+        n = u.numel()
+        for t, nm in ((u, "u"), (v, "v"), (w, "w")):
+            _dev_f64(t, n, nm)
+        out = torch.empty(3 * n, dtype=torch.float32, device="cuda") if out is None else _dev_f32n(out, 3 * n, "out")
+        err = torch.zeros(1, dtype=torch.int32, device="cuda")
+        check(load().wp_mlp_features(plan.handle, self._h, n, _ptr(u), _ptr(v), _ptr(w), _ptr(out), _ptr(err),
+                                     _stream(stream)), "wp_mlp_features")
+        if int(err.item()) != 0:
+            raise WprojError(-1, "wp_mlp_features: a coordinate is not finite or lies outside the grid")
+        return out
+
+    def forward(self, feat, out=None, stream=None):
+        torch = _torch()
+        n = feat.numel() // 3
+        _dev_f32n(feat, 3 * n, "feat")
+        out = torch.empty(n * self.NOUT, dtype=torch.float32, device="cuda") if out is None else \
+            _dev_f32n(out, n * self.NOUT, "out")
+        check(load().wp_mlp_forward(self._h, n, _ptr(feat), _ptr(out), _stream(stream)), "wp_mlp_forward")
+        return out
+
+    def gradients(self, feat, target, grads=None, stream=None):
+        torch = _torch()
+        n = feat.numel() // 3
+        _dev_f32n(feat, 3 * n, "feat")
+        _dev_f32n(target, n * self.NOUT, "target")
+        grads = torch.empty(self.param_count(), dtype=torch.float32, device="cuda") if grads is None else \
+            _dev_f32n(grads, self.param_count(), "grads")
+        loss = C.c_double()
+        check(load().wp_mlp_gradients(self._h, n, _ptr(feat), _ptr(target), _ptr(grads), C.byref(loss),
+                                      _stream(stream)), "wp_mlp_gradients")
+        return grads, loss.value
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, stream=None):
+        check(load().wp_mlp_adam_step(self._h, float(lr), float(beta1), float(beta2), float(eps), _stream(stream)),
+              "wp_mlp_adam_step")
+
+    def train(self, feat, target, batch: int, epochs: int, lr_max: float, stream=None):
+        n = feat.numel() // 3
+        _dev_f32n(feat, 3 * n, "feat")
+        _dev_f32n(target, n * self.NOUT, "target")
+        hist = (C.c_double * int(epochs))()
+        check(load().wp_mlp_train(self._h, n, _ptr(feat), _ptr(target), int(batch), int(epochs), float(lr_max), hist,
+                                  _stream(stream)), "wp_mlp_train")
+        return list(hist)
+
+    def box_targets(self, plan: Plan, G: GMatrix, u, v, s_out: float, stream=None):
+        torch = _torch()
+        _dev_f64(u, G.M, "u")
+        _dev_f64(v, G.M, "v")
+        target = torch.empty(G.M * self.NOUT, dtype=torch.float32, device="cuda")
+        lost = torch.empty(G.M, dtype=torch.float32, device="cuda")
+        d = G.desc()
+        check(load().wp_mlp_box_targets(plan.handle, C.byref(d), _ptr(u), _ptr(v), float(s_out), _ptr(target),
+                                        _ptr(lost), _stream(stream)), "wp_mlp_box_targets")
+        return target, lost
+
+    def row_errors(self, plan: Plan, G: GMatrix, u, v, feat, stream=None):
+        torch = _torch()
+        _dev_f64(u, G.M, "u")
+        _dev_f64(v, G.M, "v")
+        _dev_f32n(feat, 3 * G.M, "feat")
+        eps = torch.empty(G.M, dtype=torch.float32, device="cuda")
+        d = G.desc()
+        check(load().wp_mlp_row_errors(plan.handle, self._h, C.byref(d), _ptr(u), _ptr(v), _ptr(feat), _ptr(eps),
+                                       _stream(stream)), "wp_mlp_row_errors")
+        return eps
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().wp_mlp_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

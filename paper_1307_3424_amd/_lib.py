@@ -60,6 +60,18 @@ SIGNATURES = {
     "wp_apply_Phi_batch": ([_vp, _vp, _vp, _vp, _vp], _i32),
     "wp_apply_PhiT_batch": ([_vp, _vp, _vp, _vp, _vp], _i32),
     "wp_batch_autotune": ([_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_float)], _i32),
+    "wp_mlp_param_count": ([], _i64),
+    "wp_mlp_create": ([C.POINTER(_vp), _i32], _i32),
+    "wp_mlp_destroy": ([_vp], _i32),
+    "wp_mlp_set_params": ([_vp, C.POINTER(C.c_float), _d, _d], _i32),
+    "wp_mlp_get_params": ([_vp, C.POINTER(C.c_float), C.POINTER(C.c_double), C.POINTER(C.c_double)], _i32),
+    "wp_mlp_features": ([_vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_mlp_forward": ([_vp, _i32, _vp, _vp, _vp], _i32),
+    "wp_mlp_gradients": ([_vp, _i32, _vp, _vp, _vp, C.POINTER(C.c_double), _vp], _i32),
+    "wp_mlp_adam_step": ([_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp], _i32),
+    "wp_mlp_train": ([_vp, _i64, _vp, _vp, _i32, _i32, C.c_float, C.POINTER(C.c_double), _vp], _i32),
+    "wp_mlp_box_targets": ([_vp, _PG, _vp, _vp, _d, _vp, _vp, _vp], _i32),
+    "wp_mlp_row_errors": ([_vp, _vp, _PG, _vp, _vp, _vp, _vp, _vp], _i32),
     "wp_dwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_idwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_solver_workspace_bytes": ([_vp, _PG, _pi64], _i32),

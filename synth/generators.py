@@ -85,3 +85,16 @@ def workload_inputs(wl, with_sky: bool = True):
 
 def random_complex(shape, rng: np.random.Generator) -> np.ndarray:
     return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+
+def mlp_init(seed: int, hidden: int = 256, n_out: int = 2048) -> np.ndarray:
+    """Packed float32 initial parameters of the surrogate network, layers 3 -> hidden -> hidden ->
+    hidden -> n_out: every weight and bias uniform in +-1/sqrt(fan_in), drawn layer by layer
+    (W then b) in the order W1, b1, W2, b2, W3, b3, W4, b4 (row-major, W_l is [out, in])."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n, k in ((hidden, 3), (hidden, hidden), (hidden, hidden), (n_out, hidden)):
+        a = 1.0 / np.sqrt(k)
+        parts.append(rng.uniform(-a, a, n * k))
+        parts.append(rng.uniform(-a, a, n))
+    return np.concatenate(parts).astype(np.float32)
