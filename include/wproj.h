@@ -275,6 +275,10 @@ wp_status wp_mlp_adam_step(wp_mlp *mlp, float lr, float beta1, float beta2, floa
  * pass. */
 wp_status wp_mlp_train(wp_mlp *mlp, int64_t n, const float *feat, const float *target, int batch,
                        int epochs, float lr_max, double *loss_hist, void *stream);
+/* Output scale for training: s_out = sqrt(T0 / 1024), T0 the energy of the row of a visibility
+ * on a cell centre, (sum over its KB window cells of KB^2)^2 (shifted chirp spectra are
+ * orthonormal, so a row's energy depends only on its window weights).  Host result. */
+wp_status wp_mlp_output_scale(const wp_plan *plan, double *s_out);
 /* Training targets from exact rows: G (complex64 taps, built by wp_build_G_* from u, v of the
  * samples) scattered into each visibility's box and divided by s_out: target[k][2048]
  * (device float32, caller order k; cells of the box outside the row are 0), lost[k] = row
@@ -287,6 +291,57 @@ wp_status wp_mlp_box_targets(const wp_plan *plan, const wp_G *G, const double *u
  * Runs the network in chunks of max_batch rows (overwrites its activation buffers). */
 wp_status wp_mlp_row_errors(const wp_plan *plan, wp_mlp *mlp, const wp_G *G, const double *u,
                             const double *v, const float *feat, float *eps, void *stream);
+
+/* ----------------------------------------------------------------------------------------
+ * Surrogate operator.  Rows of visibilities whose per-row energy error (wp_mlp_row_errors)
+ * is at most tol come from the surrogate network; the others ("fallback") from an exact G
+ * the caller builds for them.  The network's taps are linear in its last hidden layer, so
+ * the output layer is applied per occupied grid cell instead of per visibility: degridding
+ * computes r_c = (W4 box of X) for every occupied nearest cell c and y_k = s_out (h_k . r_c
+ * + b4 . box), gridding computes s_c = sum over the cell's visibilities of h_k y_k and adds
+ * s_out (W4^H s_c + conj(b4) sum y_k) onto the cell's box; both are bfloat16 MFMA products
+ * with FP32 accumulation.  The hidden layers h_k run once, in wp_surrogate_create; the taps
+ * are never stored.
+ * Visibility order ("slots"): slots [0, Ms) are the surrogate rows sorted by the Z-order code
+ * of their nearest cell; slots [Ms, M) the fallback rows, in the order of the coordinates
+ * that wp_surrogate_fallback_coords returns.  The fallback G must be built from exactly those
+ * coordinates; its own G.order then decides the order within [Ms, M).
+ * ------------------------------------------------------------------------------------- */
+typedef struct wp_surrogate wp_surrogate;
+
+/* Set up the surrogate operator for M visibilities (u, v, w: device float64, caller order):
+ * features, the network's hidden layers (in chunks of mlp's max_batch, overwriting its
+ * activation buffers), the cell tables and the output-layer matrices (a snapshot of the
+ * network's current parameters).  eps (device float32 [M], caller order, may be NULL: no
+ * fallback) are the per-row energy errors; rows with eps > tol or eps not a number fall back.
+ * *Mf_out (host, may be NULL) receives the number of fallback rows.  Allocates device
+ * memory owned by the object; synchronises.  WP_ECAPACITY if one cell holds more than 12800
+ * visibilities. */
+wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *plan, wp_mlp *mlp, int64_t M,
+                              const double *u, const double *v, const double *w, const float *eps,
+                              double tol, int64_t *Mf_out, void *stream);
+wp_status wp_surrogate_destroy(wp_surrogate *sur);
+/* info5 (host): M, Ms (surrogate rows), Mf (fallback rows), occupied cells,
+ * (degridding groups << 32) | gridding groups. */
+wp_status wp_surrogate_info(const wp_surrogate *sur, int64_t *info5);
+/* slot_vis[r] = caller index of slot r (device int32 [M]). */
+wp_status wp_surrogate_slots(const wp_surrogate *sur, int *slot_vis, void *stream);
+/* Coordinates of the fallback rows in slot order (device float64 [Mf] each). */
+wp_status wp_surrogate_fallback_coords(const wp_surrogate *sur, double *u, double *v, double *w,
+                                       void *stream);
+/* y[0, Ms) = surrogate rows times the grid (device c64 Ng*Ng); y[Ms, M) untouched. */
+wp_status wp_surrogate_degrid(const wp_plan *plan, const wp_surrogate *sur, const void *grid,
+                              void *y, void *stream);
+/* grid += surrogate rows^H y[0, Ms) (atomic adds; the grid must hold its other terms first). */
+wp_status wp_surrogate_grid_add(const wp_plan *plan, const wp_surrogate *sur, const void *y,
+                                void *grid, void *stream);
+/* y = Phi_s x (slot order) and x = Phi_s^H y, with Gf the exact G of the Mf fallback rows (NULL
+ * if Mf = 0; its adjoint needs the transposed copy or the work items).  x: N*N c64, y: M c64,
+ * grid: Ng*Ng c64 workspace (all device). */
+wp_status wp_surrogate_apply_Phi(const wp_plan *plan, const wp_surrogate *sur, const wp_G *Gf,
+                                 const void *x, void *y, void *grid, void *stream);
+wp_status wp_surrogate_apply_PhiT(const wp_plan *plan, const wp_surrogate *sur, const wp_G *Gf,
+                                  const void *y, void *x, void *grid, void *stream);
 
 /* ----------------------------------------------------------------------------------------
  * Reconstruction (Eq. 7): min ||Psi^T x||_1 s.t. ||y - Phi x||_2 <= eps, x >= 0, with Psi the

@@ -21,7 +21,7 @@ from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16", "WP_TAPS_I16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
-           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "Batch", "Mlp"]
+           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "Batch", "Mlp", "Surrogate"]
 
 
 def _torch():
@@ -464,6 +464,12 @@ class Mlp:
                                   _stream(stream)), "wp_mlp_train")
         return list(hist)
 
+    @staticmethod
+    def output_scale(plan: Plan) -> float:
+        s = C.c_double()
+        check(load().wp_mlp_output_scale(plan.handle, C.byref(s)), "wp_mlp_output_scale")
+        return s.value
+
     def box_targets(self, plan: Plan, G: GMatrix, u, v, s_out: float, stream=None):
         torch = _torch()
         _dev_f64(u, G.M, "u")
@@ -489,6 +495,96 @@ class Mlp:
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().wp_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Surrogate:
+    """wp_surrogate_*: Phi / Phi^H with network rows where the per-row energy error is at most tol and exact
+    fallback rows elsewhere.  Visibility vectors are in slot order (see slots())."""
+
+    def __init__(self, plan: Plan, mlp: Mlp, u, v, w, eps=None, tol: float = 1e-3, stream=None):
+        M = u.numel()
+        for t, nm in ((u, "u"), (v, "v"), (w, "w")):
+            _dev_f64(t, M, nm)
+        if eps is not None:
+            _dev_f32n(eps, M, "eps")
+        h = C.c_void_p()
+        mf = C.c_int64()
+        check(load().wp_surrogate_create(C.byref(h), plan.handle, mlp.handle, M, _ptr(u), _ptr(v), _ptr(w), _ptr(eps),
+                                         float(tol), C.byref(mf), _stream(stream)), "wp_surrogate_create")
+        self._h = h
+        self.plan = plan
+        info = (C.c_int64 * 5)()
+        check(load().wp_surrogate_info(h, info), "wp_surrogate_info")
+        self.M, self.Ms, self.Mf, self.ncell = int(info[0]), int(info[1]), int(info[2]), int(info[3])
+        self.groups = (int(info[4]) >> 32, int(info[4]) & 0xffffffff)
+
+    def slots(self, stream=None):
+        torch = _torch()
+        out = torch.empty(self.M, dtype=torch.int32, device="cuda")
+        check(load().wp_surrogate_slots(self._h, _ptr(out), _stream(stream)), "wp_surrogate_slots")
+        return out
+
+    def fallback_coords(self, stream=None):
+        torch = _torch()
+        u, v, w = (torch.empty(self.Mf, dtype=torch.float64, device="cuda") for _ in range(3))
+        check(load().wp_surrogate_fallback_coords(self._h, _ptr(u), _ptr(v), _ptr(w), _stream(stream)),
+              "wp_surrogate_fallback_coords")
+        return u, v, w
+
+    def degrid(self, grid, y=None, stream=None):
+        torch = _torch()
+        _dev_c64(grid, self.plan.Ng ** 2, "grid")
+        y = torch.zeros(self.M, dtype=torch.complex64, device="cuda") if y is None else _dev_c64(y, self.M, "y")
+        check(load().wp_surrogate_degrid(self.plan.handle, self._h, _ptr(grid), _ptr(y), _stream(stream)),
+              "wp_surrogate_degrid")
+        return y
+
+    def grid_add(self, y, grid, stream=None):
+        _dev_c64(y, self.M, "y")
+        _dev_c64(grid, self.plan.Ng ** 2, "grid")
+        check(load().wp_surrogate_grid_add(self.plan.handle, self._h, _ptr(y), _ptr(grid), _stream(stream)),
+              "wp_surrogate_grid_add")
+        return grid
+
+    def _gf(self, Gf):
+        if self.Mf == 0:
+            return None
+        if Gf is None:
+            raise ValueError(f"{self.Mf} fallback rows need their exact G")
+        return C.byref(Gf.desc())
+
+    def apply_Phi(self, x, y=None, grid=None, Gf=None, stream=None):
+        torch = _torch()
+        N = self.plan.N
+        _dev_c64(x, N * N, "x")
+        y = torch.empty(self.M, dtype=torch.complex64, device="cuda") if y is None else _dev_c64(y, self.M, "y")
+        grid = self.plan.new_grid() if grid is None else grid
+        gf = self._gf(Gf)
+        check(load().wp_surrogate_apply_Phi(self.plan.handle, self._h, gf, _ptr(x), _ptr(y), _ptr(grid),
+                                            _stream(stream)), "wp_surrogate_apply_Phi")
+        return y
+
+    def apply_PhiT(self, y, x=None, grid=None, Gf=None, stream=None):
+        torch = _torch()
+        N = self.plan.N
+        _dev_c64(y, self.M, "y")
+        x = torch.empty(N * N, dtype=torch.complex64, device="cuda") if x is None else _dev_c64(x, N * N, "x")
+        grid = self.plan.new_grid() if grid is None else grid
+        gf = self._gf(Gf)
+        check(load().wp_surrogate_apply_PhiT(self.plan.handle, self._h, gf, _ptr(y), _ptr(x), _ptr(grid),
+                                             _stream(stream)), "wp_surrogate_apply_PhiT")
+        return x
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().wp_surrogate_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

@@ -70,8 +70,18 @@ SIGNATURES = {
     "wp_mlp_gradients": ([_vp, _i32, _vp, _vp, _vp, C.POINTER(C.c_double), _vp], _i32),
     "wp_mlp_adam_step": ([_vp, C.c_float, C.c_float, C.c_float, C.c_float, _vp], _i32),
     "wp_mlp_train": ([_vp, _i64, _vp, _vp, _i32, _i32, C.c_float, C.POINTER(C.c_double), _vp], _i32),
+    "wp_mlp_output_scale": ([_vp, C.POINTER(C.c_double)], _i32),
     "wp_mlp_box_targets": ([_vp, _PG, _vp, _vp, _d, _vp, _vp, _vp], _i32),
     "wp_mlp_row_errors": ([_vp, _vp, _PG, _vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_surrogate_create": ([C.POINTER(_vp), _vp, _vp, _i64, _vp, _vp, _vp, _vp, _d, _pi64, _vp], _i32),
+    "wp_surrogate_destroy": ([_vp], _i32),
+    "wp_surrogate_info": ([_vp, _pi64], _i32),
+    "wp_surrogate_slots": ([_vp, _vp, _vp], _i32),
+    "wp_surrogate_fallback_coords": ([_vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_surrogate_degrid": ([_vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_surrogate_grid_add": ([_vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_surrogate_apply_Phi": ([_vp, _vp, _PG, _vp, _vp, _vp, _vp], _i32),
+    "wp_surrogate_apply_PhiT": ([_vp, _vp, _PG, _vp, _vp, _vp, _vp], _i32),
     "wp_dwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_idwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_solver_workspace_bytes": ([_vp, _PG, _pi64], _i32),

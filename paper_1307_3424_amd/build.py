@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libwproj.so")
-SOURCES = ["api.hip", "fft.hip", "builder.hip", "spmv.hip", "solver.hip", "batch.hip", "mlp.hip"]
+SOURCES = ["api.hip", "fft.hip", "builder.hip", "spmv.hip", "solver.hip", "batch.hip", "mlp.hip", "surrogate.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

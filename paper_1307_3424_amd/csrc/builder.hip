@@ -37,20 +37,6 @@ constexpr int ROWS_PER_ITEM = 32;
 
 // ---------------------------------------------------------------------------- small device helpers
 
-// Z-order (Morton) code of a cell: bits of u in the even positions, bits of v in the odd ones.
-// Every aligned power-of-two block of cells is one contiguous range of codes.
-__host__ __device__ inline int morton2(int v, int u) {
-    int code = 0;
-    for (int b = 0; b < 12; ++b) code |= (((u >> b) & 1) << (2 * b)) | (((v >> b) & 1) << (2 * b + 1));
-    return code;
-}
-__host__ __device__ inline void demorton2(int code, int &v, int &u) {
-    u = v = 0;
-    for (int b = 0; b < 12; ++b) {
-        u |= ((code >> (2 * b)) & 1) << b;
-        v |= ((code >> (2 * b + 1)) & 1) << b;
-    }
-}
 
 __device__ inline double bessel_i0(double x) {
     // power series sum_k ((x/2)^2)^k / (k!)^2
@@ -95,6 +81,10 @@ __device__ inline double2 row_factor(const double2 *h, const Taps &t, int W, int
     const double s = 1.0 / Ng;
     return make_double2(g.x * s, g.y * s);
 }
+
+// |g|^2 with one explicit fused multiply-add, so that every kernel that evaluates it
+// (both passes of the builder) gets the same bits
+__device__ inline double energy(double2 g) { return fma(g.x, g.x, g.y * g.y); }
 
 template <typename T>
 __device__ inline T block_sum(T v, T *red) {
@@ -215,8 +205,8 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
     for (int q = threadIdx.x; q < Ng; q += BNTH) {
         const double2 gu = row_factor(h, tu, W, q, Ng);
         const double2 gv = row_factor(h, tv, W, q, Ng);
-        A[q] = gu.x * gu.x + gu.y * gu.y;
-        B[q] = gv.x * gv.x + gv.y * gv.y;
+        A[q] = energy(gu);
+        B[q] = energy(gv);
     }
     __syncthreads();
     // bitonic sort of B, descending
@@ -313,13 +303,13 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
                                                    int *__restrict__ col, void *__restrict__ val,
                                                    float *__restrict__ rscale, int *__restrict__ err) {
     constexpr int Ng = 1 << LOGNG;
+    constexpr int PER = (Ng + BNTH - 1) / BNTH;
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *h = (double2 *)smem;                 // Ng
-    double *A = (double *)(smem + 16 * Ng);       // Ng
-    double *B = A + Ng;                           // Ng
-    int *ca = (int *)(B + Ng);                    // Ng candidate columns (u)
-    int *cb = ca + Ng;                            // Ng candidate rows (v)
-    int *off = cb + Ng;                           // Ng per-candidate-row output offsets
+    double *A = (double *)(smem + 16 * Ng);       // Ng energies along u (those along v are recomputed)
+    int *off = (int *)(A + Ng);                   // Ng per-candidate-row output offsets
+    uint16_t *ca = (uint16_t *)(off + Ng);        // Ng candidate columns (u)
+    uint16_t *cb = ca + Ng;                       // Ng candidate rows (v)
     __shared__ double redd[BNTH / 64];
     __shared__ int redi[BNTH / 64];
     __shared__ int s_nca, s_ncb;
@@ -335,15 +325,20 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
     const Taps tv = kb_taps(vt, W, beta, Ng, s_wv);
     chirp_spectrum<LOGNG>(h, wk, delta, tw64);        // ends with a barrier: the weights are visible
     double amax = 0.0, bmax = 0.0;
+    double bq[PER];                                    // energies along v of this thread's cells q0 + i
+    const int q0 = threadIdx.x * PER;
     for (int q = threadIdx.x; q < Ng; q += BNTH) {
-        const double2 gu = row_factor(h, tu, W, q, Ng);
-        const double2 gv = row_factor(h, tv, W, q, Ng);
-        A[q] = gu.x * gu.x + gu.y * gu.y;
-        B[q] = gv.x * gv.x + gv.y * gv.y;
-        amax = fmax(amax, A[q]);
-        bmax = fmax(bmax, B[q]);
+        const double Aq = energy(row_factor(h, tu, W, q, Ng));
+        A[q] = Aq;
+        amax = fmax(amax, Aq);
     }
-    amax = block_max(amax, redd);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int q = q0 + i;
+        bq[i] = q < Ng ? energy(row_factor(h, tv, W, q, Ng)) : 0.0;
+        bmax = fmax(bmax, bq[i]);
+    }
+    amax = block_max(amax, redd);                      // its barriers also publish A
     bmax = block_max(bmax, redd);
     // int16 block floating point: every tap |g| <= sqrt(amax bmax), so re / s and im / s fit in +-32767
     const double i16_scale = sqrt(amax * bmax) / 32767.0;
@@ -351,23 +346,23 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
     // candidate compaction (ascending index); a kept tap needs A_a bmax >= tau and amax B_b >= tau
     {
         int na = 0, nb = 0;
-        constexpr int PER = (Ng + BNTH - 1) / BNTH;
-        const int q0 = threadIdx.x * PER;
+#pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int q = q0 + i;
             if (q < Ng) {
                 na += (A[q] * bmax >= tau);
-                nb += (amax * B[q] >= tau);
+                nb += (amax * bq[i] >= tau);
             }
         }
         int ta, tb;
         int oa = block_excl_scan(na, redi, ta);
         int ob = block_excl_scan(nb, redi, tb);
+#pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int q = q0 + i;
             if (q < Ng) {
-                if (A[q] * bmax >= tau) ca[oa++] = q;
-                if (amax * B[q] >= tau) cb[ob++] = q;
+                if (A[q] * bmax >= tau) ca[oa++] = (uint16_t)q;
+                if (amax * bq[i] >= tau) cb[ob++] = (uint16_t)q;
             }
         }
         if (threadIdx.x == 0) { s_nca = ta; s_ncb = tb; }
@@ -376,14 +371,13 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
     const int nca = s_nca, ncb = s_ncb;
     // kept taps per candidate row, then offsets
     {
-        constexpr int PER = (Ng + BNTH - 1) / BNTH;
         int cntl[PER];
         int tot = 0;
         for (int i = 0; i < PER; ++i) {
             const int ib = threadIdx.x * PER + i;
             int c = 0;
             if (ib < ncb) {
-                const double Bb = B[cb[ib]];
+                const double Bb = energy(row_factor(h, tv, W, cb[ib], Ng));
                 for (int ia = 0; ia < nca; ++ia) c += (A[ca[ia]] * Bb >= tau);
             }
             cntl[i] = c;
@@ -403,8 +397,8 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int ib = wid; ib < ncb; ib += BNTH / 64) {
         const int b = cb[ib];
-        const double Bb = B[b];
         const double2 gv = row_factor(h, tv, W, b, Ng);
+        const double Bb = energy(gv);
         int64_t pos = beg + off[ib];
         for (int ia0 = 0; ia0 < nca; ia0 += 64) {
             const int ia = ia0 + lane;
@@ -672,7 +666,7 @@ WsLayout ws_layout(const wp_plan *p, int64_t M) {
 template <int LOGNG>
 size_t count_lds() { return (size_t)32 << LOGNG; }
 template <int LOGNG>
-size_t fill_lds() { return (size_t)44 << LOGNG; }
+size_t fill_lds() { return (size_t)32 << LOGNG; }
 
 template <int LOGNG>
 wp_status count_rows(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
@@ -707,6 +701,42 @@ wp_status fill_rows(const wp_plan *p, int64_t M, const double *u, const double *
 }
 
 }  // namespace
+
+static int64_t al256(int64_t b) { return (b + 255) & ~(int64_t)255; }
+
+int64_t scan_workspace_bytes(int64_t n) { return al256(4 * scan_scratch_elems(n)); }
+
+wp_status launch_scan_int(const int *in, int *out, int64_t n, void *ws, hipStream_t s) {
+    if (n <= 0) return wp_set_error(WP_EINVAL, "scan of %lld elements", (long long)n);
+    device_scan<int, int>(in, out, n, (int *)ws, s);
+    return wp_check_launch("scan");
+}
+
+int64_t sort_workspace_bytes(int64_t n) {
+    return 4 * al256(4 * (n + 1)) + scan_workspace_bytes(n);
+}
+
+wp_status launch_sort_pairs(const int *key, int64_t n, int bits, int *keys_out, int *idx_out, void *wsv,
+                            hipStream_t s) {
+    if (n <= 0) return wp_set_error(WP_EINVAL, "sort of %lld elements", (long long)n);
+    if (bits < 1 || bits > 31) return wp_set_error(WP_EINVAL, "sort of %d key bits", bits);
+    unsigned char *ws = (unsigned char *)wsv;
+    const int64_t blk = al256(4 * (n + 1));
+    int *k1 = (int *)ws, *i1 = (int *)(ws + blk), *flags = (int *)(ws + 2 * blk), *zpos = (int *)(ws + 3 * blk);
+    int *scratch = (int *)(ws + 4 * blk);
+    int *k0 = keys_out, *i0 = idx_out;
+    const dim3 g((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(k_iota_keys, g, dim3(256), 0, s, key, k0, i0, n);
+    const int passes = bits + (bits & 1);     // even: the result ends in keys_out / idx_out
+    for (int b = 0; b < passes; ++b) {
+        hipLaunchKernelGGL(k_bit_flags, g, dim3(256), 0, s, k0, b, flags, n);
+        device_scan<int, int>(flags, zpos, n, scratch, s);
+        hipLaunchKernelGGL(k_split_scatter, g, dim3(256), 0, s, k0, i0, zpos, k1, i1, b, n);
+        int *t = k0; k0 = k1; k1 = t;
+        t = i0; i0 = i1; i1 = t;
+    }
+    return wp_check_launch("sort");
+}
 
 int64_t builder_workspace_bytes(const wp_plan *p, int64_t M) { return ws_layout(p, M).total; }
 

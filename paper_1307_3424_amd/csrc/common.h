@@ -103,6 +103,23 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t nb) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// ---------------------------------------------------------------------------- Z-order
+
+// Z-order (Morton) code of a cell: bits of u in the even positions, bits of v in the odd ones.
+// Every aligned power-of-two block of cells is one contiguous range of codes.
+__host__ __device__ inline int morton2(int v, int u) {
+    int code = 0;
+    for (int b = 0; b < 12; ++b) code |= (((u >> b) & 1) << (2 * b)) | (((v >> b) & 1) << (2 * b + 1));
+    return code;
+}
+__host__ __device__ inline void demorton2(int code, int &v, int &u) {
+    u = v = 0;
+    for (int b = 0; b < 12; ++b) {
+        u |= ((code >> (2 * b)) & 1) << b;
+        v |= ((code >> (2 * b + 1)) & 1) << b;
+    }
+}
+
 // ---------------------------------------------------------------------------- launchers (host)
 
 // FFT stages of A, Z, F and their adjoint (fft.hip)
@@ -118,6 +135,14 @@ wp_status launch_fill_zero(float *buf, int64_t n, hipStream_t s);
 wp_status launch_permute(const wp_G *G, const float2 *in, float2 *out, bool to_sorted, hipStream_t s);
 
 // builder (builder.hip)
+// stable sort of n (key, index) pairs by the low `bits` bits of key: on return keys_out[i] is the
+// i-th smallest key and idx_out[i] the input position it came from; ws: sort_workspace_bytes(n)
+int64_t sort_workspace_bytes(int64_t n);
+wp_status launch_sort_pairs(const int *key, int64_t n, int bits, int *keys_out, int *idx_out, void *ws,
+                            hipStream_t s);
+// exclusive scan of n ints into out[0..n] (out[n] = total); ws: scan_workspace_bytes(n)
+int64_t scan_workspace_bytes(int64_t n);
+wp_status launch_scan_int(const int *in, int *out, int64_t n, void *ws, hipStream_t s);
 int64_t builder_workspace_bytes(const wp_plan *p, int64_t M);
 wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v,
                              const double *w, double E, void *ws, int64_t *nnz, int64_t *nwork,

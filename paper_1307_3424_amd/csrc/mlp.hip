@@ -583,6 +583,30 @@ wp_status wp_mlp_train(wp_mlp *m, int64_t n, const float *feat, const float *tar
     return WP_OK;
 }
 
+wp_status wp_mlp_output_scale(const wp_plan *p, double *s_out) {
+    if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
+    if (!s_out) return wp_set_error(WP_EINVAL, "s_out is NULL");
+    // A row's energy is (sum over the u window of KB^2) (sum over the v window of KB^2): shifts of
+    // the chirp spectrum are orthonormal because the chirp has unit modulus on the padded grid.
+    // T0: that energy for a visibility on a cell centre; s_out = sqrt(T0 / BOX^2).
+    double e = 0.0;
+    const int base = -p->W / 2 + 1;
+    for (int i = 0; i < p->W; ++i) {
+        const double t = -(double)(base + i);
+        const double r = 1.0 - (2.0 * t / p->W) * (2.0 * t / p->W);
+        if (r < 0.0) continue;
+        const double x = p->beta * std::sqrt(r);
+        double term = 1.0, sum = 1.0;          // I0(x) = sum (x/2)^2k / (k!)^2
+        for (int k = 1; k < 200 && term > 1e-17 * sum; ++k) {
+            term *= (x * x / 4.0) / ((double)k * (double)k);
+            sum += term;
+        }
+        e += sum * sum;
+    }
+    *s_out = std::sqrt(e * e / (double)(BOX * BOX));
+    return WP_OK;
+}
+
 wp_status wp_mlp_box_targets(const wp_plan *p, const wp_G *G, const double *u, const double *v, double s_out,
                              float *target, float *lost, void *stream) {
     if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");

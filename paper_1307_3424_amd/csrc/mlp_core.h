@@ -78,9 +78,10 @@ __device__ __forceinline__ void stage_tile(uint16_t *s, const uint16_t *__restri
     }
 }
 
-// acc[fm][fn] += A rows [arow0 + 32 fm, +32) times B rows [brow0 + 32 fn, +32), one BK-deep step.
-// Lane l feeds A[row l % 32][k 8 (l / 32) .. +7] and B[row l % 32][same k].
-template <int FM, int FN>
+// acc[fm][fn] += A rows [arow0 + 32 fm, +32) times B rows [brow0 + 32 fn, +32), one BK-deep step;
+// LDS row strides SA and SB (elements).  Lane l feeds A[row l % 32][k 8 (l / 32) .. +7] and
+// B[row l % 32][same k].
+template <int FM, int FN, int SA = LDK, int SB = LDK>
 __device__ __forceinline__ void mma_bk(f32x16 (&acc)[FM][FN], const uint16_t *As, const uint16_t *Bs, int arow0,
                                        int brow0, int lane) {
 #pragma unroll
@@ -89,10 +90,10 @@ __device__ __forceinline__ void mma_bk(f32x16 (&acc)[FM][FN], const uint16_t *As
         const int ko = kk + 8 * (lane >> 5), ro = lane & 31;
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm)
-            a[fm] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(As + (arow0 + 32 * fm + ro) * LDK + ko));
+            a[fm] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(As + (arow0 + 32 * fm + ro) * SA + ko));
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn)
-            b[fn] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(Bs + (brow0 + 32 * fn + ro) * LDK + ko));
+            b[fn] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(Bs + (brow0 + 32 * fn + ro) * SB + ko));
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm)
 #pragma unroll

@@ -1,0 +1,663 @@
+// Surrogate measurement operator: Phi and Phi^H where the rows of the visibilities
+// that pass the per-row energy check come from the surrogate network, and the other
+// rows from an exact G built for them (the fallback).
+//
+// The network's taps are linear in its last hidden layer h_k (256 values per
+// visibility) -- t_k(p) = s_out (sum_j (W4[2p][j] + i W4[2p+1][j]) h_kj + b4[2p] + i b4[2p+1])
+// for box cell p -- so the output layer (4/5 of the network's arithmetic) can be moved
+// from the visibilities to the occupied grid cells.  For the visibilities in nearest
+// cell c:
+//   degrid  y_k = s_out (sum_j h_kj r_c[j] + beta_c),
+//           r_c[j] = sum_p (W4[2p][j] + i W4[2p+1][j]) X(c + p),  beta_c = sum_p b4_p X(c + p);
+//   grid    sum_{k in c} conj(t_k(p)) y_k = s_out (sum_j (W4[2p][j] - i W4[2p+1][j]) s_c[j] + conj(b4_p) Y_c),
+//           s_c[j] = sum_{k in c} h_kj y_k,  Y_c = sum_{k in c} y_k.
+// r is one dense product per group of cells, [cells x 2048 box values] x [2048 x 512], and
+// the box contributions one per 8 x 8 tile of cells, [cells x 512] x [512 x 2048], both on
+// bfloat16 MFMA with FP32 accumulation.  The hidden layers run once, at set-up.  The taps
+// are never stored.
+//
+// Visibility order ("slots"): slots [0, Ms) hold the surrogate rows sorted by the Z-order
+// code of their nearest cell; slots [Ms, M) the fallback rows in the caller's order, which
+// is the order of the coordinates wp_surrogate_fallback_coords returns (build the fallback
+// G from those, in caller order, or keep its sorted order consistently).
+#include <cmath>
+#include <vector>
+
+#include "mlp_core.h"
+
+using namespace mlpc;
+
+struct wp_surrogate {
+    int device;
+    int logNg;
+    int64_t M, Ms, Mf, ncell;
+    int ngrp_d, ngrp_a;
+    float s_out;
+    int *slot_vis;      // [M] caller index of each slot
+    int *cell_key;      // [ncell] Z-order code of each occupied cell (v, u grid indices)
+    int *cell_start;    // [ncell + 1] first slot of each cell
+    int *grp_d;         // [ngrp_d + 1] first cell of each degridding group
+    int *grp_a;         // [ngrp_a + 1] first cell of each gridding group (one 8 x 8 tile)
+    uint16_t *h3;       // [Ms H] last hidden layer, bfloat16, slot order
+    uint16_t *Bdeg;     // [2H][NOUT] bfloat16: r = Bdeg x box
+    uint16_t *Bgrd;     // [NOUT][2H] bfloat16: box contributions = Bgrd x s
+    float *b4;          // [NOUT] output bias
+    double *fb;         // [3 Mf] fallback u, v, w (slot order)
+};
+
+namespace {
+
+constexpr int DG = 128;             // cells per degridding group
+constexpr int DNT = 512;            // threads of both products (8 waves)
+constexpr int ND = 2 * H;           // 512 outputs of the degridding product (r re, r im)
+constexpr int KDEP = NOUT;          // its depth: 1024 box cells x (re, im)
+constexpr size_t DEG_LDS = (size_t)(2 * DG + 2 * ND) * LDK * 2;
+constexpr int VMAX = (int)(DEG_LDS / 8);   // visibilities per degridding group (LDS accumulators)
+
+constexpr int TS = 8;               // gridding tile side (cells)
+constexpr int AG = TS * TS;         // cells per gridding group
+constexpr int WIN = TS + BOX - 1;   // LDS window side
+constexpr int LDS_A = ND + 8;       // row stride of the resident A operand (s, 512 values)
+constexpr int GN = 256;             // gridding outputs per chunk
+constexpr size_t GRD_LDS = (size_t)AG * LDS_A * 2 + (size_t)2 * GN * LDK * 2 + (size_t)WIN * WIN * 8;
+
+__device__ inline int cell_index(double gt, int Ng) {
+    const long long c = (long long)floor(gt + 0.5) + Ng / 2;
+    return (int)(((c % Ng) + Ng) % Ng);
+}
+
+// key: Z-order code of the nearest cell, or `fallback_key` (larger than every code) for a
+// row whose energy error exceeds tol (or is not a number)
+__global__ void k_slot_keys(const double *__restrict__ u, const double *__restrict__ v, int64_t M, double cell,
+                            int logNg, const float *__restrict__ eps, float tol, int fallback_key,
+                            int *__restrict__ key, int *__restrict__ isfb) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= M) return;
+    const int Ng = 1 << logNg;
+    const bool fb = eps && !(eps[k] <= tol);
+    key[k] = fb ? fallback_key : morton2(cell_index(v[k] / cell, Ng), cell_index(u[k] / cell, Ng));
+    isfb[k] = fb ? 1 : 0;
+}
+
+// new-cell flags over the sorted surrogate slots
+__global__ void k_cell_flags(const int *__restrict__ skey, int64_t Ms, int *__restrict__ flag) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < Ms) flag[j] = (j == 0 || skey[j] != skey[j - 1]) ? 1 : 0;
+}
+
+__global__ void k_cell_table(const int *__restrict__ skey, const int *__restrict__ flag, const int *__restrict__ cid,
+                             int64_t Ms, int *__restrict__ cell_key, int *__restrict__ cell_start) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= Ms) return;
+    if (flag[j]) {
+        cell_key[cid[j]] = skey[j];
+        cell_start[cid[j]] = (int)j;
+    }
+    if (j == Ms - 1) cell_start[cid[Ms]] = (int)Ms;
+}
+
+__global__ void k_feat_slots(const float *__restrict__ feat, const int *__restrict__ slot_vis, int64_t j0, int n,
+                             float *__restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < 3 * n) out[i] = feat[3 * (int64_t)slot_vis[j0 + i / 3] + i % 3];
+}
+
+__global__ void k_fallback_coords(const double *__restrict__ u, const double *__restrict__ v,
+                                  const double *__restrict__ w, const int *__restrict__ slot_vis, int64_t Ms,
+                                  int64_t Mf, double *__restrict__ fb) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= Mf) return;
+    const int k = slot_vis[Ms + i];
+    fb[i] = u[k];
+    fb[Mf + i] = v[k];
+    fb[2 * Mf + i] = w[k];
+}
+
+// Bdeg[n][kk] (n < 256: r re of hidden n; n >= 256: r im of hidden n - 256; kk = 2p + c) and
+// Bgrd[o][k] (o = 2p + c; k < 256: s re, k >= 256: s im), from W4 (FP32) rounded to bfloat16
+__global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bdeg, uint16_t *__restrict__ Bgrd) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)NOUT * H) return;
+    const int p = (int)(e / H), j = (int)(e % H);      // box cell p, hidden j
+    if (p >= BOX * BOX) return;
+    const float wr = W4[(int64_t)(2 * p) * H + j], wi = W4[(int64_t)(2 * p + 1) * H + j];
+    const uint16_t br = to_bf16(wr), bi = to_bf16(wi), nbi = to_bf16(-wi);
+    Bdeg[(int64_t)j * KDEP + 2 * p] = br;
+    Bdeg[(int64_t)j * KDEP + 2 * p + 1] = nbi;
+    Bdeg[(int64_t)(H + j) * KDEP + 2 * p] = bi;
+    Bdeg[(int64_t)(H + j) * KDEP + 2 * p + 1] = br;
+    Bgrd[(int64_t)(2 * p) * ND + j] = br;
+    Bgrd[(int64_t)(2 * p) * ND + H + j] = bi;
+    Bgrd[(int64_t)(2 * p + 1) * ND + j] = nbi;
+    Bgrd[(int64_t)(2 * p + 1) * ND + H + j] = br;
+}
+
+// ---------------------------------------------------------------------------- degridding
+
+// One workgroup per group of <= DG occupied cells (consecutive in Z-order): R = A Bdeg^T with
+// A[i][2p + c] = the box of cell i (bfloat16), then y_k for every visibility of the group.
+// Waves: 2 along cells (64 each) x 4 along outputs (128 each); double-buffered LDS stages.
+__global__ __launch_bounds__(DNT) void k_sur_degrid(const float2 *__restrict__ grid, int logNg,
+                                                    const int *__restrict__ grp, int ngrp,
+                                                    const int *__restrict__ cell_key,
+                                                    const int *__restrict__ cell_start,
+                                                    const uint16_t *__restrict__ h3,
+                                                    const uint16_t *__restrict__ Bdeg, const float *__restrict__ b4,
+                                                    float s_out, float2 *__restrict__ y) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *As = (uint16_t *)smem;                 // [2][DG][LDK]
+    uint16_t *Bs = As + 2 * DG * LDK;                // [2][ND][LDK]
+    float2 *yacc = (float2 *)smem;                   // after the product: [VMAX]
+    __shared__ int s_cv[DG], s_cu[DG], s_cs[DG + 1];
+    __shared__ float2 s_beta[DG];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    const int g = (int)xcd_block(blockIdx.x, ngrp);
+    const int c0 = grp[g], nc = grp[g + 1] - c0;
+    const int Ng = 1 << logNg;
+    for (int i = tid; i < DG; i += DNT) {
+        int cv = 0, cu = 0;
+        if (i < nc) demorton2(cell_key[c0 + i], cv, cu);
+        s_cv[i] = cv;
+        s_cu[i] = cu;
+    }
+    for (int i = tid; i <= nc; i += DNT) s_cs[i] = cell_start[c0 + i];
+    __syncthreads();
+
+    // staging of A: thread -> cell si, 4 consecutive box cells of the step's 16
+    const int si = tid >> 2, sq = tid & 3;
+    const bool slive = si < nc;
+    const int scv = s_cv[si], scu = s_cu[si];
+    float2 areg[4];
+    u32x4 breg[4];
+    float2 bacc = make_float2(0.f, 0.f);
+    auto load = [&](int t) {
+        const int oy = t >> 1, ox0 = 16 * (t & 1) + 4 * sq;
+        const int64_t row = (int64_t)((scv + oy - BOX / 2) & (Ng - 1)) * Ng;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int gx = (scu + ox0 + e - BOX / 2) & (Ng - 1);
+            areg[e] = slive ? grid[row + gx] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
+            breg[q] = *(const u32x4 *)(Bdeg + (int64_t)n * KDEP + 32 * t + kc);
+        }
+    };
+    auto store = [&](int t, int buf) {
+        const int oy = t >> 1, ox0 = 16 * (t & 1) + 4 * sq;
+        u32x4 a;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            a[e] = (uint32_t)to_bf16(areg[e].x) | ((uint32_t)to_bf16(areg[e].y) << 16);
+            const int p = oy * BOX + ox0 + e;
+            const float br = b4[2 * p], bi = b4[2 * p + 1];
+            bacc.x += br * areg[e].x - bi * areg[e].y;
+            bacc.y += br * areg[e].y + bi * areg[e].x;
+        }
+        *(u32x4 *)(As + buf * DG * LDK + si * LDK + 8 * sq) = a;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
+            *(u32x4 *)(Bs + buf * ND * LDK + n * LDK + kc) = breg[q];
+        }
+    };
+
+    f32x16 acc[2][4];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    constexpr int NSTEP = KDEP / BK;
+    load(0);
+    store(0, 0);
+    __syncthreads();
+    for (int t = 0; t < NSTEP; ++t) {
+        const int cur = t & 1;
+        if (t + 1 < NSTEP) load(t + 1);
+        mma_bk<2, 4>(acc, As + cur * DG * LDK, Bs + cur * ND * LDK, 64 * wm, 128 * wn, lane);
+        if (t + 1 < NSTEP) store(t + 1, cur ^ 1);
+        __syncthreads();
+    }
+    // bias term of each cell: the 4 staging threads of a cell are consecutive lanes
+    bacc.x += __shfl_xor(bacc.x, 1);
+    bacc.y += __shfl_xor(bacc.y, 1);
+    bacc.x += __shfl_xor(bacc.x, 2);
+    bacc.y += __shfl_xor(bacc.y, 2);
+    if (sq == 0) s_beta[si] = bacc;
+    const int v0 = s_cs[0], nv = s_cs[nc] - v0;
+    for (int i = tid; i < nv; i += DNT) yacc[i] = make_float2(0.f, 0.f);
+    __syncthreads();
+    // y partial sums: this wave's 128 outputs are hidden units 128 (wn & 1) + [0, 128) of
+    // r re (wn < 2) or r im (wn >= 2); each half-wave holds one cell per register
+    const int part = wn >> 1, hbase = 128 * (wn & 1) + (lane & 31);
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 64 * wm + 32 * fm + acc_row(r, lane);
+            const int jb = i < nc ? s_cs[i] : 0, cnt = i < nc ? s_cs[i + 1] - jb : 0;
+            int mx = cnt;
+            for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
+            for (int n = 0; n < mx; ++n) {
+                float sum = 0.0f;
+                if (n < cnt) {
+                    const uint16_t *hr = h3 + (int64_t)(jb + n) * H + hbase;
+#pragma unroll
+                    for (int fn = 0; fn < 4; ++fn) sum += from_bf16(hr[32 * fn]) * acc[fm][fn][r];
+                }
+                for (int o = 16; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+                if (n < cnt && (lane & 31) == 0) {
+                    float *dst = (float *)&yacc[jb + n - v0] + part;
+                    atomicAdd(dst, sum);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < nv; i += DNT) {
+        int lo = 0, hi = nc - 1;           // cell of visibility v0 + i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_cs[mid] <= v0 + i) lo = mid; else hi = mid - 1;
+        }
+        const float2 a = yacc[i], b = s_beta[lo];
+        y[v0 + i] = make_float2(s_out * (a.x + b.x), s_out * (a.y + b.y));
+    }
+}
+
+// ---------------------------------------------------------------------------- gridding
+
+// One workgroup per 8 x 8 tile of cells with occupied cells: A[i] = s of cell i (resident in
+// LDS), box contributions = A Bgrd^T in chunks of GN outputs, accumulated into an LDS window of
+// the tile's boxes and added to the grid with atomics.  Waves: 2 along cells x 4 along outputs.
+__global__ __launch_bounds__(DNT) void k_sur_grid(const float2 *__restrict__ y, int logNg,
+                                                  const int *__restrict__ grp, int ngrp,
+                                                  const int *__restrict__ cell_key,
+                                                  const int *__restrict__ cell_start,
+                                                  const uint16_t *__restrict__ h3,
+                                                  const uint16_t *__restrict__ Bgrd, const float *__restrict__ b4,
+                                                  float s_out, float2 *__restrict__ grid) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint16_t *Sa = (uint16_t *)smem;                               // [AG][LDS_A]
+    uint16_t *Bs = Sa + AG * LDS_A;                                // [2][GN][LDK]
+    float2 *win = (float2 *)(Bs + 2 * GN * LDK);                   // [WIN][WIN]
+    __shared__ int s_cv[AG], s_cu[AG];
+    __shared__ float2 s_Y[AG];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 2, wn = wave & 3;
+    const int g = (int)xcd_block(blockIdx.x, ngrp);
+    const int c0 = grp[g], nc = grp[g + 1] - c0;
+    const int Ng = 1 << logNg;
+    int tv0, tu0;
+    demorton2(cell_key[c0] & ~(AG - 1), tv0, tu0);
+    for (int i = tid; i < AG; i += DNT) {
+        int cv = 0, cu = 0;
+        if (i < nc) demorton2(cell_key[c0 + i], cv, cu);
+        s_cv[i] = cv - tv0;
+        s_cu[i] = cu - tu0;
+    }
+    for (int e = tid; e < WIN * WIN; e += DNT) win[e] = make_float2(0.f, 0.f);
+    // s of each cell: thread -> cell i = tid / 8, hidden units [32 (tid % 8), +32)
+    {
+        const int i = tid >> 3, j0 = 32 * (tid & 7);
+        float sr[32], sm[32];
+#pragma unroll
+        for (int q = 0; q < 32; ++q) sr[q] = sm[q] = 0.0f;
+        float2 Y = make_float2(0.f, 0.f);
+        if (i < nc) {
+            const int jb = cell_start[c0 + i], je = cell_start[c0 + i + 1];
+            for (int k = jb; k < je; ++k) {
+                const float2 yk = y[k];
+                Y.x += yk.x;
+                Y.y += yk.y;
+                const u32x4 *hr = (const u32x4 *)(h3 + (int64_t)k * H + j0);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const u32x4 hv = hr[c];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float h0 = __uint_as_float(hv[e] << 16), h1 = __uint_as_float(hv[e] & 0xffff0000u);
+                        sr[8 * c + 2 * e] += h0 * yk.x;
+                        sm[8 * c + 2 * e] += h0 * yk.y;
+                        sr[8 * c + 2 * e + 1] += h1 * yk.x;
+                        sm[8 * c + 2 * e + 1] += h1 * yk.y;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            u32x4 pr, pm;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                pr[e] = (uint32_t)to_bf16(sr[8 * c + 2 * e]) | ((uint32_t)to_bf16(sr[8 * c + 2 * e + 1]) << 16);
+                pm[e] = (uint32_t)to_bf16(sm[8 * c + 2 * e]) | ((uint32_t)to_bf16(sm[8 * c + 2 * e + 1]) << 16);
+            }
+            *(u32x4 *)(Sa + i * LDS_A + j0 + 8 * c) = pr;
+            *(u32x4 *)(Sa + i * LDS_A + H + j0 + 8 * c) = pm;
+        }
+        if ((tid & 7) == 0) s_Y[i] = Y;
+    }
+    // B chunks: GN rows x BK = 1024 chunks of 8, two per thread
+    u32x4 breg[2];
+    constexpr int KSTEP = ND / BK;             // 16 steps per output chunk
+    constexpr int NCHUNK = NOUT / GN;          // 8 chunks
+    auto loadB = [&](int t) {
+        const int ch = t / KSTEP, ks = t % KSTEP;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
+            breg[q] = *(const u32x4 *)(Bgrd + (int64_t)(GN * ch + n) * ND + BK * ks + kc);
+        }
+    };
+    auto storeB = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
+            *(u32x4 *)(Bs + buf * GN * LDK + n * LDK + kc) = breg[q];
+        }
+    };
+    f32x16 acc[1][2];
+    auto zero = [&]() {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[0][b][r] = 0.0f;
+    };
+    zero();
+    loadB(0);
+    storeB(0);
+    __syncthreads();
+    constexpr int NT_ = NCHUNK * KSTEP;
+    for (int t = 0; t < NT_; ++t) {
+        const int cur = t & 1, ks = t % KSTEP, ch = t / KSTEP;
+        if (t + 1 < NT_) loadB(t + 1);
+        mma_bk<1, 2, LDS_A, LDK>(acc, Sa + BK * ks, Bs + cur * GN * LDK, 32 * wm, 64 * wn, lane);
+        if (ks == KSTEP - 1) {
+            // outputs o = GN ch + 64 wn + 32 fn + lane % 32 of cell i: box cell p = o / 2, part o % 2
+#pragma unroll
+            for (int fn = 0; fn < 2; ++fn) {
+                const int o = GN * ch + 64 * wn + 32 * fn + (lane & 31);
+                const int p = o >> 1, comp = o & 1;
+                const int oy = p >> 5, ox = p & (BOX - 1);
+                const float br = b4[2 * p], bi = b4[2 * p + 1];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int i = 32 * wm + acc_row(r, lane);
+                    if (i < nc) {
+                        const float2 Y = s_Y[i];
+                        const float bias = comp == 0 ? br * Y.x + bi * Y.y : br * Y.y - bi * Y.x;
+                        float *dst = (float *)&win[(s_cv[i] + oy) * WIN + s_cu[i] + ox] + comp;
+                        atomicAdd(dst, s_out * (acc[0][fn][r] + bias));
+                    }
+                }
+            }
+            zero();
+        }
+        if (t + 1 < NT_) storeB(cur ^ 1);
+        __syncthreads();
+    }
+    for (int e = tid; e < WIN * WIN; e += DNT) {
+        const float2 val = win[e];
+        if (val.x != 0.0f || val.y != 0.0f) {
+            const int gy = (tv0 - BOX / 2 + e / WIN) & (Ng - 1), gx = (tu0 - BOX / 2 + e % WIN) & (Ng - 1);
+            float *dst = (float *)&grid[(int64_t)gy * Ng + gx];
+            atomicAdd(dst, val.x);
+            atomicAdd(dst + 1, val.y);
+        }
+    }
+}
+
+wp_status check_sur(const wp_plan *p, const wp_surrogate *s) {
+    if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
+    if (!s) return wp_set_error(WP_EINVAL, "surrogate is NULL");
+    if (s->logNg != p->logNg) return wp_set_error(WP_EINVAL, "surrogate built for another grid size");
+    return WP_OK;
+}
+
+wp_status sur_degrid(const wp_plan *p, const wp_surrogate *S, const float2 *grid, float2 *y, hipStream_t s) {
+    if (S->Ms == 0) return WP_OK;
+    hipLaunchKernelGGL(k_sur_degrid, dim3(S->ngrp_d), dim3(DNT), DEG_LDS, s, grid, p->logNg, S->grp_d, S->ngrp_d,
+                       S->cell_key, S->cell_start, S->h3, S->Bdeg, S->b4, S->s_out, y);
+    return wp_check_launch("k_sur_degrid");
+}
+
+wp_status sur_grid_add(const wp_plan *p, const wp_surrogate *S, const float2 *y, float2 *grid, hipStream_t s) {
+    if (S->Ms == 0) return WP_OK;
+    hipLaunchKernelGGL(k_sur_grid, dim3(S->ngrp_a), dim3(DNT), GRD_LDS, s, y, p->logNg, S->grp_a, S->ngrp_a,
+                       S->cell_key, S->cell_start, S->h3, S->Bgrd, S->b4, S->s_out, grid);
+    return wp_check_launch("k_sur_grid");
+}
+
+wp_status check_fallback(const wp_surrogate *S, const wp_G *Gf) {
+    if (S->Mf == 0) return WP_OK;
+    if (!Gf) return wp_set_error(WP_EINVAL, "%lld fallback rows need their exact G", (long long)S->Mf);
+    if (Gf->M != S->Mf) return wp_set_error(WP_EINVAL, "fallback G has %lld rows, expected %lld", (long long)Gf->M,
+                                            (long long)S->Mf);
+    return WP_OK;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, int64_t M, const double *u,
+                              const double *v, const double *w, const float *eps, double tol, int64_t *Mf_out,
+                              void *stream) {
+    if (!out) return wp_set_error(WP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
+    if (!m) return wp_set_error(WP_EINVAL, "mlp is NULL");
+    if (M < 1 || M > 0x7ffffffe) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    if (!u || !v || !w) return wp_set_error(WP_EINVAL, "NULL coordinates");
+    if (p->Ng < 2 * BOX) return wp_set_error(WP_EINVAL, "Ng = %d < %d", p->Ng, 2 * BOX);
+    if (!(tol >= 0.0)) return wp_set_error(WP_EINVAL, "tol must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    const int bits = 2 * p->logNg;
+    DevBuf feat, key, isfb, skey, sidx, sws, flag, cid, err;
+    WP_HIP(hipMalloc(&feat.p, 12 * M));
+    WP_HIP(hipMalloc(&key.p, 4 * M));
+    WP_HIP(hipMalloc(&isfb.p, 4 * (M + 1)));
+    WP_HIP(hipMalloc(&skey.p, 4 * M));
+    WP_HIP(hipMalloc(&sidx.p, 4 * M));
+    WP_HIP(hipMalloc(&sws.p, std::max(sort_workspace_bytes(M), scan_workspace_bytes(M + 1))));
+    WP_HIP(hipMalloc(&flag.p, 4 * (M + 1)));
+    WP_HIP(hipMalloc(&cid.p, 4 * (M + 1)));
+    WP_HIP(hipMalloc(&err.p, 4));
+    WP_HIP(hipMemsetAsync(err.p, 0, 4, s));
+    wp_status st = wp_mlp_features(p, m, M, u, v, w, (float *)feat.p, (int *)err.p, s);
+    if (st != WP_OK) return st;
+    const int gM = (int)((M + 255) / 256);
+    hipLaunchKernelGGL(k_slot_keys, dim3(gM), dim3(256), 0, s, u, v, M, p->cell, p->logNg, eps, (float)tol, 1 << bits,
+                       (int *)key.p, (int *)isfb.p);
+    if ((st = wp_check_launch("k_slot_keys")) != WP_OK) return st;
+    if ((st = launch_sort_pairs((const int *)key.p, M, bits + 1, (int *)skey.p, (int *)sidx.p, sws.p, s)) != WP_OK)
+        return st;
+    if ((st = launch_scan_int((const int *)isfb.p, (int *)flag.p, M, sws.p, s)) != WP_OK) return st;
+    int h_err = 0, h_mf = 0;
+    WP_HIP(hipMemcpyAsync(&h_err, err.p, 4, hipMemcpyDeviceToHost, s));
+    WP_HIP(hipMemcpyAsync(&h_mf, (int *)flag.p + M, 4, hipMemcpyDeviceToHost, s));
+    WP_HIP(hipStreamSynchronize(s));
+    if (h_err) return wp_set_error(WP_EINVAL, "a coordinate is not finite or lies outside the grid");
+
+    wp_surrogate *S = (wp_surrogate *)calloc(1, sizeof(wp_surrogate));
+    if (!S) return wp_set_error(WP_ENOMEM, "surrogate allocation");
+    auto fail = [&](wp_status code, const char *what) {
+        wp_surrogate_destroy(S);
+        return wp_set_error(code, "surrogate create: %s", what);
+    };
+    (void)hipGetDevice(&S->device);
+    S->logNg = p->logNg;
+    S->M = M;
+    S->Mf = h_mf;
+    S->Ms = M - h_mf;
+    S->s_out = (float)m->s_out;
+    if (hipMalloc((void **)&S->slot_vis, 4 * M) != hipSuccess) return fail(WP_ENOMEM, "slots");
+    WP_HIP(hipMemcpyAsync(S->slot_vis, sidx.p, 4 * M, hipMemcpyDeviceToDevice, s));
+    if (S->Mf > 0) {
+        if (hipMalloc((void **)&S->fb, 24 * S->Mf) != hipSuccess) return fail(WP_ENOMEM, "fallback coordinates");
+        hipLaunchKernelGGL(k_fallback_coords, dim3((unsigned)((S->Mf + 255) / 256)), dim3(256), 0, s, u, v, w,
+                           S->slot_vis, S->Ms, S->Mf, S->fb);
+    }
+    if (hipMalloc((void **)&S->Bdeg, (size_t)ND * KDEP * 2) != hipSuccess ||
+        hipMalloc((void **)&S->Bgrd, (size_t)NOUT * ND * 2) != hipSuccess ||
+        hipMalloc((void **)&S->b4, (size_t)NOUT * 4) != hipSuccess)
+        return fail(WP_ENOMEM, "weights");
+    hipLaunchKernelGGL(k_make_B, dim3((unsigned)((NOUT * H + 255) / 256)), dim3(256), 0, s, m->params + OW4, S->Bdeg,
+                       S->Bgrd);
+    WP_HIP(hipMemcpyAsync(S->b4, m->params + OB4, NOUT * 4, hipMemcpyDeviceToDevice, s));
+    if (S->Ms > 0) {
+        const int64_t Ms = S->Ms;
+        const int gS = (int)((Ms + 255) / 256);
+        hipLaunchKernelGGL(k_cell_flags, dim3(gS), dim3(256), 0, s, (const int *)skey.p, Ms, (int *)flag.p);
+        if ((st = launch_scan_int((const int *)flag.p, (int *)cid.p, Ms, sws.p, s)) != WP_OK) {
+            wp_surrogate_destroy(S);
+            return st;
+        }
+        int h_nc = 0;
+        WP_HIP(hipMemcpyAsync(&h_nc, (int *)cid.p + Ms, 4, hipMemcpyDeviceToHost, s));
+        WP_HIP(hipStreamSynchronize(s));
+        S->ncell = h_nc;
+        if (hipMalloc((void **)&S->cell_key, 4 * (size_t)h_nc) != hipSuccess ||
+            hipMalloc((void **)&S->cell_start, 4 * (size_t)(h_nc + 1)) != hipSuccess)
+            return fail(WP_ENOMEM, "cell table");
+        hipLaunchKernelGGL(k_cell_table, dim3(gS), dim3(256), 0, s, (const int *)skey.p, (const int *)flag.p,
+                           (const int *)cid.p, Ms, S->cell_key, S->cell_start);
+        // groups, on the host: degridding groups of <= DG cells and <= VMAX visibilities;
+        // gridding groups = the occupied cells of one 8 x 8 tile
+        std::vector<int> ckey(h_nc), cstart(h_nc + 1);
+        WP_HIP(hipMemcpyAsync(ckey.data(), S->cell_key, 4 * (size_t)h_nc, hipMemcpyDeviceToHost, s));
+        WP_HIP(hipMemcpyAsync(cstart.data(), S->cell_start, 4 * (size_t)(h_nc + 1), hipMemcpyDeviceToHost, s));
+        WP_HIP(hipStreamSynchronize(s));
+        std::vector<int> gd{0}, ga{0};
+        for (int c = 0; c < h_nc; ++c) {
+            if (cstart[c + 1] - cstart[c] > VMAX) return fail(WP_ECAPACITY, "a cell holds more visibilities than a group");
+            const int g0 = gd.back();
+            if (c - g0 >= DG || cstart[c + 1] - cstart[g0] > VMAX) gd.push_back(c);
+            if (c > ga.back() && (ckey[c] / AG) != (ckey[ga.back()] / AG)) ga.push_back(c);
+        }
+        gd.push_back(h_nc);
+        ga.push_back(h_nc);
+        S->ngrp_d = (int)gd.size() - 1;
+        S->ngrp_a = (int)ga.size() - 1;
+        if (hipMalloc((void **)&S->grp_d, 4 * gd.size()) != hipSuccess ||
+            hipMalloc((void **)&S->grp_a, 4 * ga.size()) != hipSuccess)
+            return fail(WP_ENOMEM, "groups");
+        WP_HIP(hipMemcpyAsync(S->grp_d, gd.data(), 4 * gd.size(), hipMemcpyHostToDevice, s));
+        WP_HIP(hipMemcpyAsync(S->grp_a, ga.data(), 4 * ga.size(), hipMemcpyHostToDevice, s));
+        WP_HIP(hipStreamSynchronize(s));
+        // last hidden layer of every surrogate row, in slot order
+        if (hipMalloc((void **)&S->h3, (size_t)Ms * H * 2) != hipSuccess) return fail(WP_ENOMEM, "hidden features");
+        for (int64_t j0 = 0; j0 < Ms; j0 += m->max_batch) {
+            const int n = (int)std::min<int64_t>(m->max_batch, Ms - j0);
+            hipLaunchKernelGGL(k_feat_slots, dim3((3 * n + 255) / 256), dim3(256), 0, s, (const float *)feat.p,
+                               S->slot_vis, j0, n, m->xb);
+            if ((st = mlp_forward(m, n, m->xb, nullptr, s)) != WP_OK) {
+                wp_surrogate_destroy(S);
+                return st;
+            }
+            WP_HIP(hipMemcpyAsync(S->h3 + j0 * H, m->a3, (size_t)n * H * 2, hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if ((st = wp_check_launch("surrogate create")) != WP_OK) {
+        wp_surrogate_destroy(S);
+        return st;
+    }
+    WP_HIP(hipStreamSynchronize(s));
+    if (Mf_out) *Mf_out = S->Mf;
+    *out = S;
+    return WP_OK;
+}
+
+wp_status wp_surrogate_destroy(wp_surrogate *S) {
+    if (!S) return WP_OK;
+    void *bufs[] = {S->slot_vis, S->cell_key, S->cell_start, S->grp_d, S->grp_a, S->h3, S->Bdeg, S->Bgrd, S->b4, S->fb};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    free(S);
+    return WP_OK;
+}
+
+wp_status wp_surrogate_info(const wp_surrogate *S, int64_t *info5) {
+    if (!S || !info5) return wp_set_error(WP_EINVAL, "NULL argument");
+    info5[0] = S->M;
+    info5[1] = S->Ms;
+    info5[2] = S->Mf;
+    info5[3] = S->ncell;
+    info5[4] = (int64_t)S->ngrp_d << 32 | (int64_t)S->ngrp_a;
+    return WP_OK;
+}
+
+wp_status wp_surrogate_slots(const wp_surrogate *S, int *slot_vis, void *stream) {
+    if (!S || !slot_vis) return wp_set_error(WP_EINVAL, "NULL argument");
+    WP_HIP(hipMemcpyAsync(slot_vis, S->slot_vis, 4 * S->M, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return WP_OK;
+}
+
+wp_status wp_surrogate_fallback_coords(const wp_surrogate *S, double *u, double *v, double *w, void *stream) {
+    if (!S) return wp_set_error(WP_EINVAL, "surrogate is NULL");
+    if (S->Mf == 0) return WP_OK;
+    if (!u || !v || !w) return wp_set_error(WP_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    WP_HIP(hipMemcpyAsync(u, S->fb, 8 * S->Mf, hipMemcpyDeviceToDevice, s));
+    WP_HIP(hipMemcpyAsync(v, S->fb + S->Mf, 8 * S->Mf, hipMemcpyDeviceToDevice, s));
+    WP_HIP(hipMemcpyAsync(w, S->fb + 2 * S->Mf, 8 * S->Mf, hipMemcpyDeviceToDevice, s));
+    return WP_OK;
+}
+
+wp_status wp_surrogate_degrid(const wp_plan *p, const wp_surrogate *S, const void *grid, void *y, void *stream) {
+    if (wp_status st = check_sur(p, S)) return st;
+    if (!grid || (S->Ms > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    return sur_degrid(p, S, (const float2 *)grid, (float2 *)y, (hipStream_t)stream);
+}
+
+wp_status wp_surrogate_grid_add(const wp_plan *p, const wp_surrogate *S, const void *y, void *grid, void *stream) {
+    if (wp_status st = check_sur(p, S)) return st;
+    if (!grid || (S->Ms > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    return sur_grid_add(p, S, (const float2 *)y, (float2 *)grid, (hipStream_t)stream);
+}
+
+wp_status wp_surrogate_apply_Phi(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const void *x, void *y,
+                                 void *grid, void *stream) {
+    if (wp_status st = check_sur(p, S)) return st;
+    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (!x || !y || !grid) return wp_set_error(WP_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    wp_status st = launch_grid_forward(p, (const float2 *)x, (float2 *)grid, s);
+    if (st != WP_OK) return st;
+    if ((st = sur_degrid(p, S, (const float2 *)grid, (float2 *)y, s)) != WP_OK) return st;
+    if (S->Mf > 0) return launch_degrid(p, Gf, (const float2 *)grid, (float2 *)y + S->Ms, s);
+    return WP_OK;
+}
+
+wp_status wp_surrogate_apply_PhiT(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const void *y, void *x,
+                                  void *grid, void *stream) {
+    if (wp_status st = check_sur(p, S)) return st;
+    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (!x || !y || !grid) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (S->Mf > 0 && !Gf->tcolptr && (Gf->n_work > 0 && !Gf->work))
+        return wp_set_error(WP_EINVAL, "fallback G needs its transposed copy or work items");
+    hipStream_t s = (hipStream_t)stream;
+    wp_status st;
+    if (S->Mf > 0)
+        st = Gf->tcolptr ? launch_gather(p, Gf, (const float2 *)y + S->Ms, (float2 *)grid, s)
+                         : launch_scatter(p, Gf, (const float2 *)y + S->Ms, (float2 *)grid, s);
+    else
+        st = launch_fill_zero((float *)grid, 2 * (int64_t)p->Ng * p->Ng, s);
+    if (st != WP_OK) return st;
+    if ((st = sur_grid_add(p, S, (const float2 *)y, (float2 *)grid, s)) != WP_OK) return st;
+    return launch_grid_adjoint(p, (float2 *)grid, (float2 *)x, s);
+}
+
+}  // extern "C"
