@@ -343,6 +343,21 @@ wp_status wp_surrogate_apply_Phi(const wp_plan *plan, const wp_surrogate *sur, c
 wp_status wp_surrogate_apply_PhiT(const wp_plan *plan, const wp_surrogate *sur, const wp_G *Gf,
                                   const void *y, void *x, void *grid, void *stream);
 
+/* out[r] = in[caller index of slot r] (device c64 [M], distinct buffers): a caller-order
+ * visibility vector in slot order; slots [Ms, M) follow Gf's order (Gf->perm when
+ * Gf->order is WP_ORDER_SORTED). */
+wp_status wp_surrogate_to_slots(const wp_surrogate *sur, const wp_G *Gf, const void *in, void *out,
+                                void *stream);
+/* The solver entry points below with the surrogate operator (y in slot order). */
+wp_status wp_surrogate_solver_workspace_bytes(const wp_plan *plan, const wp_surrogate *sur,
+                                              int64_t *bytes_out);
+wp_status wp_surrogate_power_norm2(const wp_plan *plan, const wp_surrogate *sur, const wp_G *Gf,
+                                   const float *x0, int iters, void *workspace, double *nu_out,
+                                   void *stream);
+wp_status wp_surrogate_solve(const wp_plan *plan, const wp_surrogate *sur, const wp_G *Gf,
+                             const void *y, double eps, double nu, int iters, int levels, float *x,
+                             void *workspace, void *stream);
+
 /* ----------------------------------------------------------------------------------------
  * Reconstruction (Eq. 7): min ||Psi^T x||_1 s.t. ||y - Phi x||_2 <= eps, x >= 0, with Psi the
  * Daubechies wavelets of 8 vanishing moments (Section 4.2), periodic, `levels` levels.

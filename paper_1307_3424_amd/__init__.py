@@ -582,6 +582,40 @@ class Surrogate:
                                              _stream(stream)), "wp_surrogate_apply_PhiT")
         return x
 
+    def to_slots(self, y_caller, Gf=None, out=None, stream=None):
+        torch = _torch()
+        _dev_c64(y_caller, self.M, "y_caller")
+        out = torch.empty(self.M, dtype=torch.complex64, device="cuda") if out is None else _dev_c64(out, self.M, "out")
+        check(load().wp_surrogate_to_slots(self._h, self._gf(Gf), _ptr(y_caller), _ptr(out), _stream(stream)),
+              "wp_surrogate_to_slots")
+        return out
+
+    def _solver_ws(self):
+        torch = _torch()
+        b = C.c_int64()
+        check(load().wp_surrogate_solver_workspace_bytes(self.plan.handle, self._h, C.byref(b)),
+              "wp_surrogate_solver_workspace_bytes")
+        return torch.empty(b.value, dtype=torch.uint8, device="cuda")
+
+    def power_norm2(self, x0, iters: int = 50, Gf=None, stream=None) -> float:
+        ws = self._solver_ws()
+        nu = C.c_double()
+        check(load().wp_surrogate_power_norm2(self.plan.handle, self._h, self._gf(Gf), _ptr(x0), int(iters), _ptr(ws),
+                                              C.byref(nu), _stream(stream)), "wp_surrogate_power_norm2")
+        return nu.value
+
+    def solve(self, y_slots, eps: float, nu: float, iters: int, levels: int = 4, x=None, Gf=None, stream=None):
+        torch = _torch()
+        N = self.plan.N
+        _dev_c64(y_slots, self.M, "y_slots")
+        x = torch.zeros(N * N, dtype=torch.float32, device="cuda") if x is None else x
+        ws = self._solver_ws()
+        check(load().wp_surrogate_solve(self.plan.handle, self._h, self._gf(Gf), _ptr(y_slots), float(eps), float(nu),
+                                        int(iters), int(levels), _ptr(x), _ptr(ws), _stream(stream)),
+              "wp_surrogate_solve")
+        x._wp_ws = ws
+        return x
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().wp_surrogate_destroy(self._h)

@@ -82,6 +82,10 @@ SIGNATURES = {
     "wp_surrogate_grid_add": ([_vp, _vp, _vp, _vp, _vp], _i32),
     "wp_surrogate_apply_Phi": ([_vp, _vp, _PG, _vp, _vp, _vp, _vp], _i32),
     "wp_surrogate_apply_PhiT": ([_vp, _vp, _PG, _vp, _vp, _vp, _vp], _i32),
+    "wp_surrogate_to_slots": ([_vp, _PG, _vp, _vp, _vp], _i32),
+    "wp_surrogate_solver_workspace_bytes": ([_vp, _vp, _pi64], _i32),
+    "wp_surrogate_power_norm2": ([_vp, _vp, _PG, _vp, _i32, _vp, C.POINTER(C.c_double), _vp], _i32),
+    "wp_surrogate_solve": ([_vp, _vp, _PG, _vp, _d, _d, _i32, _i32, _vp, _vp, _vp], _i32),
     "wp_dwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_idwt2": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_solver_workspace_bytes": ([_vp, _PG, _pi64], _i32),

@@ -338,7 +338,8 @@ wp_status wp_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, int i
     if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
     if (!x0 || !workspace || !nu_out) return wp_set_error(WP_EINVAL, "NULL argument");
     if (iters < 1) return wp_set_error(WP_EINVAL, "iters = %d", iters);
-    return launch_power_norm2(p, G, x0, iters, nu_out, (unsigned char *)workspace, as_stream(stream));
+    return launch_power_norm2(p, wp_operator{G, nullptr, G->M}, x0, iters, nu_out, (unsigned char *)workspace,
+                              as_stream(stream));
 }
 
 wp_status wp_solve(const wp_plan *p, const wp_G *G, const void *y, double eps, double nu, int iters, int levels,
@@ -350,7 +351,8 @@ wp_status wp_solve(const wp_plan *p, const wp_G *G, const void *y, double eps, d
         return wp_set_error(WP_EINVAL, "eps = %g, nu = %g: need eps >= 0 and nu > 0, finite", eps, nu);
     if (iters < 0) return wp_set_error(WP_EINVAL, "iters = %d", iters);
     if (levels < 1 || (p->N >> (levels - 1)) < 8) return wp_set_error(WP_EINVAL, "levels = %d", levels);
-    return launch_solve(p, G, (const float2 *)y, eps, nu, iters, levels, x, (unsigned char *)workspace,
+    return launch_solve(p, wp_operator{G, nullptr, G->M}, (const float2 *)y, eps, nu, iters, levels, x,
+                        (unsigned char *)workspace,
                         as_stream(stream));
 }
 

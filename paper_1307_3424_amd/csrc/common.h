@@ -152,11 +152,20 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
 
 
 // solver (solver.hip)
+// The measurement operator the solver iterates with: the exact form (G) or the surrogate form
+// (S, with G the exact rows of its fallback visibilities, NULL when there are none).
+struct wp_operator {
+    const wp_G *G;
+    const wp_surrogate *S;
+    int64_t M;
+};
+wp_status op_phi(const wp_plan *p, const wp_operator &op, const float2 *x, float2 *y, float2 *grid, hipStream_t s);
+wp_status op_phiT(const wp_plan *p, const wp_operator &op, const float2 *y, float2 *x, float2 *grid, hipStream_t s);
 int64_t solver_workspace_bytes(const wp_plan *p, int64_t M);
 wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s);
-wp_status launch_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, int iters, double *nu,
+wp_status launch_power_norm2(const wp_plan *p, const wp_operator &op, const float *x0, int iters, double *nu,
                              unsigned char *ws, hipStream_t s);
-wp_status launch_solve(const wp_plan *p, const wp_G *G, const float2 *y, double eps, double nu, int iters,
+wp_status launch_solve(const wp_plan *p, const wp_operator &op, const float2 *y, double eps, double nu, int iters,
                        int levels, float *x, unsigned char *ws, hipStream_t s);
 wp_status filter_db8(double *h);
 

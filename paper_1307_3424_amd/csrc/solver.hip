@@ -261,7 +261,15 @@ wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, fl
     return wp_check_launch(synth ? "idwt2" : "dwt2");
 }
 
-wp_status launch_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, int iters, double *nu,
+wp_status op_phi(const wp_plan *p, const wp_operator &op, const float2 *x, float2 *y, float2 *grid, hipStream_t s) {
+    return op.S ? wp_surrogate_apply_Phi(p, op.S, op.G, x, y, grid, s) : wp_apply_Phi(p, op.G, x, y, grid, s);
+}
+
+wp_status op_phiT(const wp_plan *p, const wp_operator &op, const float2 *y, float2 *x, float2 *grid, hipStream_t s) {
+    return op.S ? wp_surrogate_apply_PhiT(p, op.S, op.G, y, x, grid, s) : wp_apply_PhiT(p, op.G, y, x, grid, s);
+}
+
+wp_status launch_power_norm2(const wp_plan *p, const wp_operator &op, const float *x0, int iters, double *nu,
                              unsigned char *ws, hipStream_t s) {
     const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng;
     auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
@@ -269,15 +277,15 @@ wp_status launch_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, i
     float2 *xc = (float2 *)(ws + al(8 * G2));
     float2 *z = (float2 *)(ws + al(8 * G2) + al(8 * N2));
     float2 *yv = (float2 *)(ws + al(8 * G2) + 2 * al(8 * N2));
-    double *acc = (double *)(ws + al(8 * G2) + 2 * al(8 * N2) + al(8 * G->M));
+    double *acc = (double *)(ws + al(8 * G2) + 2 * al(8 * N2) + al(8 * op.M));
     hipLaunchKernelGGL(k_real_to_c64, blocks_for(N2), dim3(NT), 0, s, x0, xc, N2);
     // normalise the start vector
     hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, acc, 2);
     hipLaunchKernelGGL(k_sumsq_real, blocks_reduce(N2), dim3(NT), 0, s, xc, N2, acc);
     hipLaunchKernelGGL(k_normalise_real, blocks_for(N2), dim3(NT), 0, s, xc, xc, N2, acc);
     for (int it = 0; it < iters; ++it) {
-        if (wp_status st = wp_apply_Phi(p, G, xc, yv, grid, s)) return st;
-        if (wp_status st = wp_apply_PhiT(p, G, yv, z, grid, s)) return st;
+        if (wp_status st = op_phi(p, op, xc, yv, grid, s)) return st;
+        if (wp_status st = op_phiT(p, op, yv, z, grid, s)) return st;
         hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, acc, 1);
         hipLaunchKernelGGL(k_sumsq_real, blocks_reduce(N2), dim3(NT), 0, s, z, N2, acc);
         hipLaunchKernelGGL(k_normalise_real, blocks_for(N2), dim3(NT), 0, s, z, xc, N2, acc);
@@ -289,9 +297,9 @@ wp_status launch_power_norm2(const wp_plan *p, const wp_G *G, const float *x0, i
     return wp_check_launch("power_norm2");
 }
 
-wp_status launch_solve(const wp_plan *p, const wp_G *G, const float2 *y, double eps, double nu, int iters,
+wp_status launch_solve(const wp_plan *p, const wp_operator &op, const float2 *y, double eps, double nu, int iters,
                        int levels, float *x, unsigned char *ws, hipStream_t s) {
-    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng, M = G->M;
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng, M = op.M;
     auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
     int64_t o = 0;
     auto take = [&](int64_t b) { unsigned char *r = ws + o; o += al(b); return r; };
@@ -310,11 +318,11 @@ wp_status launch_solve(const wp_plan *p, const wp_G *G, const float2 *y, double 
     WP_HIP(hipMemsetAsync(v2, 0, 8 * M, s));
     for (int it = 0; it < iters; ++it) {
         if (wp_status st = launch_dwt2(p, levels, v1, t1, tmp, true, s)) return st;           // Psi v1
-        if (wp_status st = wp_apply_PhiT(p, G, v2, t2, grid, s)) return st;                    // Phi^H v2
+        if (wp_status st = op_phiT(p, op, v2, t2, grid, s)) return st;                        // Phi^H v2
         hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, t1, t2, xb, xbc, N2, tau, acc);
         if (wp_status st = launch_dwt2(p, levels, xb, t1, tmp, false, s)) return st;          // Psi^T xb
         hipLaunchKernelGGL(k_dual1, blocks_for(N2), dim3(NT), 0, s, v1, t1, N2, s1);
-        if (wp_status st = wp_apply_Phi(p, G, xbc, pv, grid, s)) return st;                    // Phi xb
+        if (wp_status st = op_phi(p, op, xbc, pv, grid, s)) return st;                        // Phi xb
         hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, v2, pv, y, M, s2, acc);
         hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, v2, pv, y, M, s2, eps, acc);
     }

@@ -441,6 +441,15 @@ wp_status check_fallback(const wp_surrogate *S, const wp_G *Gf) {
     return WP_OK;
 }
 
+// out[r] = in[caller index of slot r]; fallback slots follow the fallback G's order
+__global__ void k_to_slots(const float2 *__restrict__ in, const int *__restrict__ slot_vis, int64_t Ms, int64_t M,
+                           const int *__restrict__ fperm, float2 *__restrict__ out) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= M) return;
+    const int64_t s = r < Ms ? r : Ms + (fperm ? fperm[r - Ms] : r - Ms);
+    out[r] = in[slot_vis[s]];
+}
+
 struct DevBuf {
     void *p = nullptr;
     ~DevBuf() {
@@ -658,6 +667,42 @@ wp_status wp_surrogate_apply_PhiT(const wp_plan *p, const wp_surrogate *S, const
     if (st != WP_OK) return st;
     if ((st = sur_grid_add(p, S, (const float2 *)y, (float2 *)grid, s)) != WP_OK) return st;
     return launch_grid_adjoint(p, (float2 *)grid, (float2 *)x, s);
+}
+
+wp_status wp_surrogate_to_slots(const wp_surrogate *S, const wp_G *Gf, const void *in, void *out, void *stream) {
+    if (!S) return wp_set_error(WP_EINVAL, "surrogate is NULL");
+    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (!in || !out || in == out) return wp_set_error(WP_EINVAL, "need distinct input and output vectors");
+    const int *fperm = (S->Mf > 0 && Gf->order == WP_ORDER_SORTED) ? Gf->perm : nullptr;
+    hipLaunchKernelGGL(k_to_slots, dim3((unsigned)((S->M + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       (const float2 *)in, S->slot_vis, S->Ms, S->M, fperm, (float2 *)out);
+    return wp_check_launch("k_to_slots");
+}
+
+wp_status wp_surrogate_solver_workspace_bytes(const wp_plan *p, const wp_surrogate *S, int64_t *bytes) {
+    if (wp_status st = check_sur(p, S)) return st;
+    if (!bytes) return wp_set_error(WP_EINVAL, "bytes is NULL");
+    *bytes = solver_workspace_bytes(p, S->M);
+    return WP_OK;
+}
+
+wp_status wp_surrogate_power_norm2(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const float *x0,
+                                   int iters, void *workspace, double *nu_out, void *stream) {
+    if (wp_status st = check_sur(p, S)) return st;
+    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (!x0 || !workspace || !nu_out || iters < 1) return wp_set_error(WP_EINVAL, "bad argument");
+    return launch_power_norm2(p, wp_operator{Gf, S, S->M}, x0, iters, nu_out, (unsigned char *)workspace,
+                              (hipStream_t)stream);
+}
+
+wp_status wp_surrogate_solve(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const void *y, double eps,
+                             double nu, int iters, int levels, float *x, void *workspace, void *stream) {
+    if (wp_status st = check_sur(p, S)) return st;
+    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (!y || !x || !workspace || iters < 0 || !(nu > 0.0) || !(eps >= 0.0))
+        return wp_set_error(WP_EINVAL, "bad argument");
+    return launch_solve(p, wp_operator{Gf, S, S->M}, (const float2 *)y, eps, nu, iters, levels, x,
+                        (unsigned char *)workspace, (hipStream_t)stream);
 }
 
 }  // extern "C"

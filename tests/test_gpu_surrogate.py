@@ -179,3 +179,59 @@ def test_single_visibility_and_capacity(setup):
     same = [_dev(np.full(M, a[0])) for a in (d["u"], d["v"], d["w"])]
     with pytest.raises(W.WprojError):
         W.Surrogate(plan, mlp, *same)
+
+
+def test_to_slots_with_sorted_fallback(setup):
+    d = setup
+    eps = _fallback_setup(d, every=3)
+    sur = W.Surrogate(d["plan"], d["mlp"], _dev(d["u"]), _dev(d["v"]), _dev(d["w"]), eps=_dev(eps), tol=0.5)
+    fu, fv, fw = sur.fallback_coords()
+    Gf = W.build_G(d["plan"], fu, fv, fw, 0.99)
+    Gf.order = W.WP_ORDER_SORTED
+    yc = gen.random_complex(d["M"], np.random.default_rng(27)).astype(np.complex64)
+    ys = sur.to_slots(_dev(yc), Gf=Gf).cpu().numpy()
+    slot = sur.slots().cpu().numpy()
+    perm = Gf.perm.cpu().numpy()
+    Ms = sur.Ms
+    assert np.array_equal(ys[:Ms], yc[slot[:Ms]])
+    assert np.array_equal(ys[Ms:], yc[slot[Ms + perm]])
+    sur.close()
+
+
+def test_surrogate_solve_matches_oracle():
+    import synth
+    from oracle import metrics, solver
+    wl = synth.workload(0)
+    x, u, v, w = synth.workload_inputs(wl)
+    s = wproj.Setup(N=wl.N, L=wl.L)
+    plan = W.Plan(wl.N, wl.L)
+    mlp = W.Mlp(max_batch=1024)
+    s_out = W.Mlp.output_scale(plan)
+    params = gen.mlp_init(31)
+    mlp.set_params(params, wl.w_top, s_out)
+    net = S.from_packed(params, w_top=wl.w_top, s_out=s_out)
+    rows_eps = np.zeros(wl.M, dtype=np.float32)
+    rows_eps[::3] = 1.0
+    use_exact = rows_eps > 0.5
+    Gr = wproj.build_rows(u, v, w, wl.E, s)
+    A = lambda z: S.phi_s(net, u, v, w, z, s, Gr, use_exact, q=S.round_bf16)
+    AH = lambda r: S.phi_s_adjoint(net, u, v, w, r, s, Gr, use_exact, q=S.round_bf16)
+    y0 = A(x)
+    sig = metrics.noise_sigma(y0, wl.snr_in_db)
+    y = y0 + synth.noise(wl.M, sig, synth.rng_for(wl.seed, "noise"))
+    eps = metrics.l2_ball_radius(sig, wl.M)
+    x0 = synth.rng_for(wl.seed, "x").normal(size=(wl.N, wl.N))
+    sur = W.Surrogate(plan, mlp, _dev(u), _dev(v), _dev(w), eps=_dev(rows_eps), tol=0.5)
+    fu, fv, fw = sur.fallback_coords()
+    Gf = W.build_G(plan, fu, fv, fw, wl.E)
+    Gf.order = W.WP_ORDER_SORTED
+    nu_ref = solver.power_norm2(A, AH, x0, 30)
+    nu_gpu = sur.power_norm2(_dev(x0.astype(np.float32).ravel()), 30, Gf=Gf)
+    # bfloat16 box values and cell sums in the surrogate rows: ~1e-3 per application
+    assert abs(nu_gpu - nu_ref) / nu_ref < 1e-2
+    ys = sur.to_slots(_dev(y.astype(np.complex64)), Gf=Gf)
+    x5 = sur.solve(ys, eps, nu_ref, 5, Gf=Gf).cpu().numpy().reshape(wl.N, wl.N)
+    x5_ref = solver.solve(y, A, AH, (wl.N, wl.N), eps, nu_ref, 5)
+    assert np.linalg.norm(x5 - x5_ref) / np.linalg.norm(x5_ref) < 1e-2
+    sur.close()
+    mlp.close()
