@@ -23,6 +23,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
+MFMA_BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bfloat16 MFMA, TFLOP/s
 
 
 def log(msg):
@@ -40,6 +41,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--channels", type=int, default=0, help="batched form: first K channels only (0: all)")
+    ap.add_argument("--train-epochs", type=int, default=300, help="surrogate form: training passes")
+    ap.add_argument("--tol", type=float, default=1e-3, help="surrogate form: per-row energy error tolerance")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -236,6 +239,196 @@ def bench_batched(args, wl):
     print(json.dumps(out), flush=True)
 
 
+def _solve_snr(torch, x, xr, N):
+    xr_h = xr.cpu().numpy().reshape(N, N).astype(np.float64)
+    return float(20 * np.log10(np.std(x) / np.std(x - xr_h)))
+
+
+def bench_surrogate(args, wl):
+    """Surrogate form: the exact operator and the surrogate operator (network rows where the per-row
+    energy error is at most tol, exact fallback rows elsewhere) on the same visibilities, timed the
+    same way, with the accuracy of the surrogate against the exact operator and a reconstruction by
+    each."""
+    import torch
+    import paper_1307_3424_amd as wp
+    import synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    log(f"bench: workload {wl.name} N={wl.N} M={wl.M} E={wl.E}: exact and surrogate forms")
+    x, u, v, w = synth.workload_inputs(wl)
+    plan = wp.Plan(wl.N, wl.L, kb_W=wl.W)
+    ud, vd, wd = t(u), t(v), t(w)
+    xd = t(x.astype(np.complex64).ravel())
+    stream = torch.cuda.current_stream()
+    sync = torch.cuda.synchronize
+    # ---- exact form
+    sync()
+    t0 = time.perf_counter()
+    G = wp.build_G(plan, ud, vd, wd, wl.E)
+    sync()
+    build_s = time.perf_counter() - t0
+    G.order = wp.WP_ORDER_SORTED
+    log(f"bench: exact G built in {build_s:.1f} s, nnz={G.nnz} ({G.nnz / wl.M:.1f}/vis)")
+    yd = torch.empty(wl.M, dtype=torch.complex64, device=dev)
+    xa = torch.empty(wl.N * wl.N, dtype=torch.complex64, device=dev)
+    grid = plan.new_grid()
+    step_e = lambda: (wp.apply_Phi(plan, G, xd, yd, grid), wp.apply_PhiT(plan, G, yd, xa, grid))
+    for _ in range(args.warmup):
+        step_e()
+    ms_e = time_region(step_e, args.steps, stream, torch)
+    ms_phi_e = time_region(lambda: wp.apply_Phi(plan, G, xd, yd, grid), args.steps, stream, torch)
+    ms_phit_e = time_region(lambda: wp.apply_PhiT(plan, G, yd, xa, grid), args.steps, stream, torch)
+    wp.grid_forward(plan, xd, grid)
+    ms_deg_e = time_region(lambda: wp.degrid(plan, G, grid, yd), args.steps, stream, torch)
+    ms_ga_e = time_region(lambda: wp.grid_gather(plan, G, yd, grid), args.steps, stream, torch)
+    log(f"bench: exact Phi+Phi^H {ms_e:.2f} ms (Phi {ms_phi_e:.2f}, Phi^H {ms_phit_e:.2f}; degrid {ms_deg_e:.2f}, "
+        f"gather {ms_ga_e:.2f})")
+    # ---- network trained on rows the builder makes
+    rng = synth.rng_for(wl.seed, "train")
+    tu, tv, tw = (t(a) for a in synth.training_positions(wl, wl.train_samples, rng))
+    sync()
+    t0 = time.perf_counter()
+    Gt = wp.build_G(plan, tu, tv, tw, wl.E, transpose=False)
+    mlp = wp.Mlp(max_batch=8192)
+    s_out = wp.Mlp.output_scale(plan)
+    mlp.set_params(synth.mlp_init(wl.seed), wl.w_top, s_out)
+    T, lost = mlp.box_targets(plan, Gt, tu, tv, s_out)
+    ft = mlp.features(plan, tu, tv, tw)
+    lost_max = float(lost.max())
+    del Gt, lost
+    sync()
+    data_s = time.perf_counter() - t0
+    log(f"bench: {wl.train_samples} exact training rows in {data_s:.1f} s (largest energy outside the box "
+        f"{lost_max:.2e}); training {args.train_epochs} passes")
+    t0 = time.perf_counter()
+    hist = mlp.train(ft, T, 8192, args.train_epochs, 2e-3)
+    sync()
+    train_s = time.perf_counter() - t0
+    del T, ft
+    log(f"bench: trained in {train_s:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    # ---- per-row check against the exact rows, surrogate set-up, fallback G
+    t0 = time.perf_counter()
+    feat = mlp.features(plan, ud, vd, wd)
+    eps_rows = mlp.row_errors(plan, G, ud, vd, feat)
+    sync()
+    check_s = time.perf_counter() - t0
+    e_h = eps_rows.cpu().numpy()
+    del feat
+    t0 = time.perf_counter()
+    sur = wp.Surrogate(plan, mlp, ud, vd, wd, eps=eps_rows, tol=args.tol)
+    Gf = None
+    if sur.Mf:
+        fu, fv, fw = sur.fallback_coords()
+        Gf = wp.build_G(plan, fu, fv, fw, wl.E)
+        Gf.order = wp.WP_ORDER_SORTED
+        del fu, fv, fw
+    sync()
+    setup_s = time.perf_counter() - t0
+    log(f"bench: per-row check {check_s:.2f} s: {sur.Ms} network rows ({sur.Ms / wl.M:.1%}), {sur.Mf} exact "
+        f"fallback rows, {sur.ncell} occupied cells; surrogate set-up {setup_s:.1f} s")
+    ys = torch.zeros(wl.M, dtype=torch.complex64, device=dev)
+    step_s = lambda: (sur.apply_Phi(xd, ys, grid, Gf=Gf), sur.apply_PhiT(ys, xa, grid, Gf=Gf))
+    for _ in range(args.warmup):
+        step_s()
+    ms_s = time_region(step_s, args.steps, stream, torch)
+    ms_phi_s = time_region(lambda: sur.apply_Phi(xd, ys, grid, Gf=Gf), args.steps, stream, torch)
+    ms_phit_s = time_region(lambda: sur.apply_PhiT(ys, xa, grid, Gf=Gf), args.steps, stream, torch)
+    wp.grid_forward(plan, xd, grid)
+    ms_sdeg = time_region(lambda: sur.degrid(grid, ys), args.steps, stream, torch)
+    grid2 = plan.new_grid()
+    ms_sgrid = time_region(lambda: sur.grid_add(ys, grid2), args.steps, stream, torch)
+    ms_fdeg = ms_fga = 0.0
+    if Gf is not None:
+        yf = torch.empty(sur.Mf, dtype=torch.complex64, device=dev)
+        ms_fdeg = time_region(lambda: wp.degrid(plan, Gf, grid, yf), args.steps, stream, torch)
+        ms_fga = time_region(lambda: wp.grid_gather(plan, Gf, yf, grid2), args.steps, stream, torch)
+    log(f"bench: surrogate Phi+Phi^H {ms_s:.2f} ms (Phi {ms_phi_s:.2f}, Phi^H {ms_phit_s:.2f}; network degrid "
+        f"{ms_sdeg:.2f}, network grid {ms_sgrid:.2f}, fallback degrid {ms_fdeg:.2f}, fallback gather {ms_fga:.2f})")
+    # ---- accuracy of the surrogate operator against the exact one
+    y_e = wp.to_caller(G, wp.apply_Phi(plan, G, xd))
+    y_s = sur.apply_Phi(xd, Gf=Gf)
+    y_e_slots = sur.to_slots(y_e, Gf=Gf)
+    phi_err = float(torch.linalg.norm(y_s - y_e_slots) / torch.linalg.norm(y_e_slots))
+    yc = t(synth.random_complex(wl.M, synth.rng_for(wl.seed, "y", 4)).astype(np.complex64))
+    xa_e = wp.apply_PhiT(plan, G, wp.to_sorted(G, yc))
+    xa_s = sur.apply_PhiT(sur.to_slots(yc, Gf=Gf), Gf=Gf)
+    phit_err = float(torch.linalg.norm(xa_s - xa_e) / torch.linalg.norm(xa_e))
+    log(f"bench: surrogate vs exact operator: Phi rel. error {phi_err:.3e}, Phi^H rel. error {phit_err:.3e}")
+    # ---- reconstruction with each operator from the same data (30 dB, exact operator)
+    rms = float(torch.sqrt(torch.mean(torch.abs(y_e.to(torch.complex128)) ** 2)))
+    sig = 10 ** (-wl.snr_in_db / 20) * rms
+    y_meas = y_e + t(synth.noise(wl.M, sig, synth.rng_for(wl.seed, "noise")).astype(np.complex64))
+    ball = float(np.sqrt(sig ** 2 * (wl.M + 2 * np.sqrt(wl.M))))
+    x0 = t(synth.rng_for(wl.seed, "x").normal(size=wl.N * wl.N).astype(np.float32))
+    solves = {}
+    for form in ("exact", "surrogate"):
+        sync()
+        t0 = time.perf_counter()
+        if form == "exact":
+            nu = wp.power_norm2(plan, G, x0, 50)
+            yv = wp.to_sorted(G, y_meas)
+        else:
+            nu = sur.power_norm2(x0, 50, Gf=Gf)
+            yv = sur.to_slots(y_meas, Gf=Gf)
+        sync()
+        t_pow = time.perf_counter() - t0
+        xr = torch.zeros(wl.N * wl.N, dtype=torch.float32, device=dev)
+        s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sync()
+        s_ev.record()
+        if form == "exact":
+            wp.solve(plan, G, yv, ball, nu, wl.iters, 4, x=xr)
+        else:
+            sur.solve(yv, ball, nu, wl.iters, 4, x=xr, Gf=Gf)
+        e_ev.record()
+        sync()
+        t_solve = s_ev.elapsed_time(e_ev) * 1e-3
+        snr = _solve_snr(torch, x, xr, wl.N)
+        solves[form] = {"iterations": wl.iters, "solve_s": t_solve, "power_iteration_s": t_pow, "nu": nu,
+                        "snr_out_db": snr}
+        log(f"bench: {form} solve {wl.iters} iterations in {t_solve:.2f} s, SNR_out {snr:.2f} dB")
+    # ---- roofline: the surrogate's products are MFMA work (2 x 2048 x 512 per occupied cell)
+    flop = 2.0 * 2048 * 512 * sur.ncell
+    deg_tf = flop / (ms_sdeg * 1e-3) / 1e12
+    grd_tf = flop / (ms_sgrid * 1e-3) / 1e12
+    dom = ("grid", grd_tf, ms_sgrid) if ms_sgrid >= ms_sdeg else ("degrid", deg_tf, ms_sdeg)
+    out = {
+        "metric": "visibilities/s for Phi+Phi† (exact vs surrogate kernels) and % HBM roofline",
+        "value": wl.M / (ms_s * 1e-3),
+        "unit": "visibilities/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_s,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-mfma/f32-accumulate (network rows), c64 (fallback rows)",
+        "data": "synthetic (seeded sky and baselines; the paper's M31 / 30Dor images are not used)",
+        "config": {"workload": wl.name, "N": wl.N, "Ng": plan.Ng, "M": wl.M, "E": wl.E, "kb_W": wl.W,
+                   "uv": f"{wl.uv} sigma={wl.uv_sigma}B", "w_top": wl.w_top, "kernel": "surrogate network + exact fallback",
+                   "network": "MLP 3-256-256-256-2048 GELU, bf16 products", "train_samples": wl.train_samples,
+                   "train_epochs": args.train_epochs, "tol": args.tol},
+        "roofline": {"bound": "mfma", "kernel": f"surrogate {dom[0]} (per-cell output-layer product)",
+                     "achieved": dom[1], "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": dom[1] / MFMA_BF16_PEAK_TFLOPS, "traffic": None, "flop_per_launch": flop,
+                     "launch_us": dom[2] * 1e3},
+        "surrogate": {"rows_network": sur.Ms, "rows_fallback": sur.Mf, "occupied_cells": sur.ncell,
+                      "row_error_median": float(np.median(e_h)), "row_error_p90": float(np.quantile(e_h, 0.9)),
+                      "frac_rows_within_tol": sur.Ms / wl.M, "phi_rel_error_vs_exact": phi_err,
+                      "phiT_rel_error_vs_exact": phit_err, "train_s": train_s, "train_data_s": data_s,
+                      "train_loss_first_last": [hist[0], hist[-1]], "check_s": check_s, "setup_s": setup_s,
+                      "stages_ms": {"phi": ms_phi_s, "phiT": ms_phit_s, "network_degrid": ms_sdeg,
+                                    "network_grid": ms_sgrid, "fallback_degrid": ms_fdeg, "fallback_gather": ms_fga},
+                      "degrid_tflops": deg_tf, "grid_tflops": grd_tf},
+        "exact": {"value": wl.M / (ms_e * 1e-3), "ms_per_step": ms_e, "build_G_s": build_s, "nnz": G.nnz,
+                  "stages_ms": {"phi": ms_phi_e, "phiT": ms_phit_e, "degrid": ms_deg_e,
+                                "gather": ms_ga_e},
+                  "degrid_gbs": degrid_bytes(G, wl.M, plan.Ng, 8) / (ms_deg_e * 1e-3) / 1e9,
+                  "gather_gbs": gather_bytes(G, wl.M, plan.Ng, 8) / (ms_ga_e * 1e-3) / 1e9},
+        "surrogate_over_exact": ms_e / ms_s,
+        "solve": solves,
+        "solve_snr_gap_db": solves["surrogate"]["snr_out_db"] - solves["exact"]["snr_out_db"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -248,6 +441,8 @@ def main():
     wl = synth.workload(args.workload)
     if wl.channels is not None:
         return bench_batched(args, wl)
+    if wl.train_samples:
+        return bench_surrogate(args, wl)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log(f"bench: workload {wl.name} N={wl.N} M={wl.M} E={wl.E} taps={args.taps}")

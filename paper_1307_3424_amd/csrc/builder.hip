@@ -34,6 +34,7 @@ namespace {
 
 constexpr int BNTH = 256;      // builder block size
 constexpr int ROWS_PER_ITEM = 32;
+constexpr int64_t ROW_CHUNK = 1 << 22;     // rows per launch of the per-row kernels
 
 // ---------------------------------------------------------------------------- small device helpers
 
@@ -175,7 +176,7 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
                                                     double cell, double delta, int W, double beta, int tile,
                                                     int ntile, const double2 *__restrict__ tw64,
                                                     double *__restrict__ tau_out, int *__restrict__ nnz_out,
-                                                    int *__restrict__ key_out, int *__restrict__ err) {
+                                                    int *__restrict__ key_out, int *__restrict__ err, int64_t r0) {
     constexpr int Ng = 1 << LOGNG;
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *h = (double2 *)smem;                 // Ng double2, later PB (Ng+1 doubles)
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
     __shared__ int redi[BNTH / 64];
     __shared__ double s_wu[16], s_wv[16];
 
-    const int64_t k = blockIdx.x;
+    const int64_t k = r0 + blockIdx.x;
     const double ut = u[k] / cell, vt = v[k] / cell, wk = w[k];
     const bool ok = isfinite(ut) && isfinite(vt) && isfinite(wk) && fabs(ut) < Ng / 2 && fabs(vt) < Ng / 2;
     if (!ok) {
@@ -301,7 +302,7 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
                                                    const double2 *__restrict__ tw64, const double *__restrict__ tau_in,
                                                    const int *__restrict__ perm, const int64_t *__restrict__ rowptr,
                                                    int *__restrict__ col, void *__restrict__ val,
-                                                   float *__restrict__ rscale, int *__restrict__ err) {
+                                                   float *__restrict__ rscale, int *__restrict__ err, int64_t r0) {
     constexpr int Ng = 1 << LOGNG;
     constexpr int PER = (Ng + BNTH - 1) / BNTH;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
     __shared__ int s_nca, s_ncb;
     __shared__ double s_wu[16], s_wv[16];
 
-    const int64_t r = blockIdx.x;
+    const int64_t r = r0 + blockIdx.x;
     const int k = perm[r];
     const double tau = tau_in[k];
     const int64_t beg = rowptr[r], len = rowptr[r + 1] - beg;
@@ -673,9 +674,14 @@ wp_status count_rows(const wp_plan *p, int64_t M, const double *u, const double 
                      unsigned char *ws, const WsLayout &L, hipStream_t s) {
     const size_t lds = count_lds<LOGNG>();
     if (lds > 160 * 1024) return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d exceeds the LDS budget", p->Ng);
-    hipLaunchKernelGGL((k_row_count<LOGNG>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, E, p->cell, p->delta, p->W,
-                       p->beta, p->tile, p->ntile, p->tw64, (double *)(ws + L.tau), (int *)(ws + L.nnz),
-                       (int *)(ws + L.key), (int *)(ws + L.err));
+    // one workgroup per row, in launches of at most ROW_CHUNK rows (a grid dimension holds
+    // fewer than 2^32 work-items)
+    for (int64_t r0 = 0; r0 < M; r0 += ROW_CHUNK) {
+        const int64_t n = std::min<int64_t>(ROW_CHUNK, M - r0);
+        hipLaunchKernelGGL((k_row_count<LOGNG>), dim3((unsigned)n), dim3(BNTH), lds, s, u, v, w, M, E, p->cell,
+                           p->delta, p->W, p->beta, p->tile, p->ntile, p->tw64, (double *)(ws + L.tau),
+                           (int *)(ws + L.nnz), (int *)(ws + L.key), (int *)(ws + L.err), r0);
+    }
     return wp_check_launch("build_G_count rows");
 }
 
@@ -685,18 +691,21 @@ wp_status fill_rows(const wp_plan *p, int64_t M, const double *u, const double *
     const size_t lds = fill_lds<LOGNG>();
     if (lds > 160 * 1024) return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d exceeds the LDS budget", p->Ng);
     int *err = (int *)(ws + L.err);
-    if (G->taps == WP_TAPS_BF16)
-        hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_BF16>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
-                           p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val,
-                           G->rscale, err);
-    else if (G->taps == WP_TAPS_I16)
-        hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_I16>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
-                           p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val,
-                           G->rscale, err);
-    else
-        hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_C64>), dim3(M), dim3(BNTH), lds, s, u, v, w, M, p->cell, p->delta,
-                           p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr, G->col, G->val,
-                           G->rscale, err);
+    for (int64_t r0 = 0; r0 < M; r0 += ROW_CHUNK) {
+        const dim3 g((unsigned)std::min<int64_t>(ROW_CHUNK, M - r0));
+        if (G->taps == WP_TAPS_BF16)
+            hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_BF16>), g, dim3(BNTH), lds, s, u, v, w, M, p->cell,
+                               p->delta, p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr,
+                               G->col, G->val, G->rscale, err, r0);
+        else if (G->taps == WP_TAPS_I16)
+            hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_I16>), g, dim3(BNTH), lds, s, u, v, w, M, p->cell,
+                               p->delta, p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr,
+                               G->col, G->val, G->rscale, err, r0);
+        else
+            hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_C64>), g, dim3(BNTH), lds, s, u, v, w, M, p->cell,
+                               p->delta, p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr,
+                               G->col, G->val, G->rscale, err, r0);
+    }
     return wp_check_launch("build_G_fill rows");
 }
 

@@ -10,7 +10,8 @@ The geometry constants follow the experimental set-up of the paper
 L = 2 sin(theta/2), band limit B = N / (2L).
 """
 from .configs import CONFIGS, Workload, fov_L, band_limit, workload
-from .generators import sky, uvw, noise, subset_rows, rng_for, workload_inputs, random_complex
+from .generators import (sky, uvw, noise, subset_rows, rng_for, workload_inputs, random_complex, mlp_init,
+                         training_positions)
 
-__all__ = ["CONFIGS", "Workload", "fov_L", "band_limit", "workload",
+__all__ = ["CONFIGS", "Workload", "fov_L", "band_limit", "workload", "mlp_init", "training_positions",
            "sky", "uvw", "noise", "subset_rows", "rng_for", "workload_inputs", "random_complex"]

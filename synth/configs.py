@@ -58,6 +58,7 @@ class Workload:
     taps: str = "c64"        # "c64" or "bf16"
     channels: Optional[Tuple[int, ...]] = None  # batched form: per-channel visibility counts
     w_scale: Optional[Tuple[float, ...]] = None  # batched form: per-channel w_top multipliers
+    train_samples: int = 0   # surrogate form: exact rows the network is trained on
 
     @property
     def L(self) -> float:
@@ -100,7 +101,8 @@ def _make():
                       w_top=w_for_support(32, 4, L) / 2.0, n_blobs=33, n_points=67,
                       channels=counts, w_scale=tuple(1.0 + c / 47.0 for c in range(48)))
     cfg[4] = Workload(name="surrogate-2048", index=4, N=2048, M=16777216, uv="gaussian", uv_sigma=0.25,
-                      w_top=w_for_support(32, 4, L), n_blobs=33, n_points=67)
+                      w_top=w_for_support(32, 4, L), n_blobs=33, n_points=67, iters=200,
+                      train_samples=2_000_000)
     return cfg
 
 

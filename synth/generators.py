@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import numpy as np
 
-_STREAM = {"sky": 1, "uvw": 2, "noise": 3, "x": 4, "y": 5, "subset": 6, "mlp": 7}
+_STREAM = {"sky": 1, "uvw": 2, "noise": 3, "x": 4, "y": 5, "subset": 6, "mlp": 7, "train": 8}
 
 
 def rng_for(seed: int, stream: str, sub: int = 0) -> np.random.Generator:
@@ -98,3 +98,13 @@ def mlp_init(seed: int, hidden: int = 256, n_out: int = 2048) -> np.ndarray:
         parts.append(rng.uniform(-a, a, n * k))
         parts.append(rng.uniform(-a, a, n))
     return np.concatenate(parts).astype(np.float32)
+
+
+def training_positions(wl, n: int, rng: np.random.Generator):
+    """(u, v, w) of n training visibilities: w ~ U[0, w_top), offsets du, dv ~ U[-1/2, 1/2) cells
+    from the grid's centre cell (u = du / (2L) wavelengths)."""
+    cell = 1.0 / (2.0 * wl.L)
+    w = rng.uniform(0.0, wl.w_top, n)
+    du = rng.uniform(-0.5, 0.5, n)
+    dv = rng.uniform(-0.5, 0.5, n)
+    return du * cell, dv * cell, w
