@@ -315,8 +315,7 @@ typedef struct wp_surrogate wp_surrogate;
  * network's current parameters).  eps (device float32 [M], caller order, may be NULL: no
  * fallback) are the per-row energy errors; rows with eps > tol or eps not a number fall back.
  * *Mf_out (host, may be NULL) receives the number of fallback rows.  Allocates device
- * memory owned by the object; synchronises.  WP_ECAPACITY if one cell holds more than 12800
- * visibilities. */
+ * memory owned by the object; synchronises. */
 wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *plan, wp_mlp *mlp, int64_t M,
                               const double *u, const double *v, const double *w, const float *eps,
                               double tol, int64_t *Mf_out, void *stream);

@@ -37,7 +37,8 @@ struct wp_surrogate {
     int *cell_key;      // [ncell] Z-order code of each occupied cell (v, u grid indices)
     int *cell_start;    // [ncell + 1] first slot of each cell
     int *grp_d;         // [ngrp_d + 1] first cell of each degridding group
-    int *grp_a;         // [ngrp_a + 1] first cell of each gridding group (one 8 x 8 tile)
+    int *grp_a;         // [ngrp_a + 1] first cell of each gridding group
+    int2 *grp_org;      // [ngrp_a] grid (v, u) of each gridding group's LDS window origin
     uint16_t *h3;       // [Ms H] last hidden layer, bfloat16, slot order
     uint16_t *Bdeg;     // [2H][NOUT] bfloat16: r = Bdeg x box
     uint16_t *Bgrd;     // [NOUT][2H] bfloat16: box contributions = Bgrd x s
@@ -48,18 +49,20 @@ struct wp_surrogate {
 namespace {
 
 constexpr int DG = 128;             // cells per degridding group
-constexpr int DNT = 512;            // threads of both products (8 waves)
-constexpr int ND = 2 * H;           // 512 outputs of the degridding product (r re, r im)
-constexpr int KDEP = NOUT;          // its depth: 1024 box cells x (re, im)
-constexpr size_t DEG_LDS = (size_t)(2 * DG + 2 * ND) * LDK * 2;
-constexpr int VMAX = (int)(DEG_LDS / 8);   // visibilities per degridding group (LDS accumulators)
+constexpr int DNT = 512;            // threads of a degridding workgroup (8 waves)
+constexpr int ND = 2 * H;           // 512 outputs per cell (r re, r im) / depth of the gridding product
+constexpr int DBN = H;              // outputs per degridding workgroup: r re (part 0) or r im (part 1)
+constexpr int KDEP = NOUT;          // degridding depth: 1024 box cells x (re, im)
+constexpr size_t DEG_LDS = (size_t)(2 * DG + 2 * DBN) * LDK * 2;
+constexpr int RPASS = 32;           // cells per epilogue pass of the degridding
+constexpr int RLD = DBN + 4;        // FP32 row stride of r in LDS
+static_assert((size_t)RPASS * RLD * 4 <= DEG_LDS, "epilogue rows must fit the staging buffers");
 
-constexpr int TS = 8;               // gridding tile side (cells)
-constexpr int AG = TS * TS;         // cells per gridding group
-constexpr int WIN = TS + BOX - 1;   // LDS window side
-constexpr int LDS_A = ND + 8;       // row stride of the resident A operand (s, 512 values)
-constexpr int GN = 256;             // gridding outputs per chunk
-constexpr size_t GRD_LDS = (size_t)AG * LDS_A * 2 + (size_t)2 * GN * LDK * 2 + (size_t)WIN * WIN * 8;
+constexpr int AG = 32;              // cells per gridding group
+constexpr int ANT = 256;            // threads of a gridding workgroup (4 waves)
+constexpr int WV = 64, WU = 64;     // LDS window (cells); a group's cells span at most WV - BOX + 1 rows
+constexpr int SLD = ND + 8;         // row stride of the staged A operand (s, 512 values)
+constexpr size_t GRD_LDS = (size_t)AG * SLD * 2 + (size_t)WV * WU * 8;
 
 __device__ inline int cell_index(double gt, int Ng) {
     const long long c = (long long)floor(gt + 0.5) + Ng / 2;
@@ -134,24 +137,29 @@ __global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bd
 
 // ---------------------------------------------------------------------------- degridding
 
-// One workgroup per group of <= DG occupied cells (consecutive in Z-order): R = A Bdeg^T with
-// A[i][2p + c] = the box of cell i (bfloat16), then y_k for every visibility of the group.
-// Waves: 2 along cells (64 each) x 4 along outputs (128 each); double-buffered LDS stages.
-__global__ __launch_bounds__(DNT) void k_sur_degrid(const float2 *__restrict__ grid, int logNg,
-                                                    const int *__restrict__ grp, int ngrp,
-                                                    const int *__restrict__ cell_key,
-                                                    const int *__restrict__ cell_start,
-                                                    const uint16_t *__restrict__ h3,
-                                                    const uint16_t *__restrict__ Bdeg, const float *__restrict__ b4,
-                                                    float s_out, float2 *__restrict__ y) {
+// Two workgroups per group of <= DG occupied cells (consecutive in Z-order): part 0 forms
+// r re = A Bdeg[0:256]^T and writes Re y, part 1 forms r im and writes Im y, A[i][2p + c] = the box
+// of cell i in bfloat16.  Waves: 2 along cells (64 each) x 4 along outputs (64 each);
+// double-buffered LDS stages with the next stage's loads in flight during the MFMAs.  Epilogue:
+// 32 cells of r at a time in LDS (FP32), then one visibility per wave: a coalesced load of its
+// hidden layer, a dot product and a wave reduction.
+__global__ __launch_bounds__(DNT, 4) void k_sur_degrid(const float2 *__restrict__ grid, int logNg,
+                                                       const int *__restrict__ grp, int ngrp,
+                                                       const int *__restrict__ cell_key,
+                                                       const int *__restrict__ cell_start,
+                                                       const uint16_t *__restrict__ h3,
+                                                       const uint16_t *__restrict__ Bdeg,
+                                                       const float *__restrict__ b4, float s_out,
+                                                       float2 *__restrict__ y) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t *As = (uint16_t *)smem;                 // [2][DG][LDK]
-    uint16_t *Bs = As + 2 * DG * LDK;                // [2][ND][LDK]
-    float2 *yacc = (float2 *)smem;                   // after the product: [VMAX]
+    uint16_t *Bs = As + 2 * DG * LDK;                // [2][DBN][LDK]
+    float *Rl = (float *)smem;                       // after the product: [RPASS][RLD]
     __shared__ int s_cv[DG], s_cu[DG], s_cs[DG + 1];
-    __shared__ float2 s_beta[DG];
+    __shared__ float s_beta[DG];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 2, wn = wave & 3;
+    const int part = blockIdx.y;
     const int g = (int)xcd_block(blockIdx.x, ngrp);
     const int c0 = grp[g], nc = grp[g + 1] - c0;
     const int Ng = 1 << logNg;
@@ -168,9 +176,10 @@ __global__ __launch_bounds__(DNT) void k_sur_degrid(const float2 *__restrict__ g
     const int si = tid >> 2, sq = tid & 3;
     const bool slive = si < nc;
     const int scv = s_cv[si], scu = s_cu[si];
+    const uint16_t *Bpart = Bdeg + (int64_t)part * DBN * KDEP;
     float2 areg[4];
-    u32x4 breg[4];
-    float2 bacc = make_float2(0.f, 0.f);
+    u32x4 breg[2];
+    float bacc = 0.0f;
     auto load = [&](int t) {
         const int oy = t >> 1, ox0 = 16 * (t & 1) + 4 * sq;
         const int64_t row = (int64_t)((scv + oy - BOX / 2) & (Ng - 1)) * Ng;
@@ -180,9 +189,9 @@ __global__ __launch_bounds__(DNT) void k_sur_degrid(const float2 *__restrict__ g
             areg[e] = slive ? grid[row + gx] : make_float2(0.f, 0.f);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 2; ++q) {
             const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
-            breg[q] = *(const u32x4 *)(Bdeg + (int64_t)n * KDEP + 32 * t + kc);
+            breg[q] = *(const u32x4 *)(Bpart + (int64_t)n * KDEP + 32 * t + kc);
         }
     };
     auto store = [&](int t, int buf) {
@@ -193,22 +202,21 @@ __global__ __launch_bounds__(DNT) void k_sur_degrid(const float2 *__restrict__ g
             a[e] = (uint32_t)to_bf16(areg[e].x) | ((uint32_t)to_bf16(areg[e].y) << 16);
             const int p = oy * BOX + ox0 + e;
             const float br = b4[2 * p], bi = b4[2 * p + 1];
-            bacc.x += br * areg[e].x - bi * areg[e].y;
-            bacc.y += br * areg[e].y + bi * areg[e].x;
+            bacc += part == 0 ? br * areg[e].x - bi * areg[e].y : br * areg[e].y + bi * areg[e].x;
         }
         *(u32x4 *)(As + buf * DG * LDK + si * LDK + 8 * sq) = a;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < 2; ++q) {
             const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
-            *(u32x4 *)(Bs + buf * ND * LDK + n * LDK + kc) = breg[q];
+            *(u32x4 *)(Bs + buf * DBN * LDK + n * LDK + kc) = breg[q];
         }
     };
 
-    f32x16 acc[2][4];
+    f32x16 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
     constexpr int NSTEP = KDEP / BK;
@@ -218,193 +226,161 @@ __global__ __launch_bounds__(DNT) void k_sur_degrid(const float2 *__restrict__ g
     for (int t = 0; t < NSTEP; ++t) {
         const int cur = t & 1;
         if (t + 1 < NSTEP) load(t + 1);
-        mma_bk<2, 4>(acc, As + cur * DG * LDK, Bs + cur * ND * LDK, 64 * wm, 128 * wn, lane);
+        mma_bk<2, 2>(acc, As + cur * DG * LDK, Bs + cur * DBN * LDK, 64 * wm, 64 * wn, lane);
         if (t + 1 < NSTEP) store(t + 1, cur ^ 1);
         __syncthreads();
     }
     // bias term of each cell: the 4 staging threads of a cell are consecutive lanes
-    bacc.x += __shfl_xor(bacc.x, 1);
-    bacc.y += __shfl_xor(bacc.y, 1);
-    bacc.x += __shfl_xor(bacc.x, 2);
-    bacc.y += __shfl_xor(bacc.y, 2);
+    bacc += __shfl_xor(bacc, 1);
+    bacc += __shfl_xor(bacc, 2);
     if (sq == 0) s_beta[si] = bacc;
-    const int v0 = s_cs[0], nv = s_cs[nc] - v0;
-    for (int i = tid; i < nv; i += DNT) yacc[i] = make_float2(0.f, 0.f);
-    __syncthreads();
-    // y partial sums: this wave's 128 outputs are hidden units 128 (wn & 1) + [0, 128) of
-    // r re (wn < 2) or r im (wn >= 2); each half-wave holds one cell per register
-    const int part = wn >> 1, hbase = 128 * (wn & 1) + (lane & 31);
+    for (int pass = 0; pass < DG / RPASS; ++pass) {
+        const int c_lo = RPASS * pass;
+        if (c_lo >= nc) break;                       // uniform over the workgroup
+        const int c_hi = min(c_lo + RPASS, nc);
+        if (wm == (pass >> 1)) {
+            const int fm = pass & 1;
 #pragma unroll
-    for (int fm = 0; fm < 2; ++fm) {
+            for (int fn = 0; fn < 2; ++fn)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = 64 * wm + 32 * fm + acc_row(r, lane);
-            const int jb = i < nc ? s_cs[i] : 0, cnt = i < nc ? s_cs[i + 1] - jb : 0;
-            int mx = cnt;
-            for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o));
-            for (int n = 0; n < mx; ++n) {
-                float sum = 0.0f;
-                if (n < cnt) {
-                    const uint16_t *hr = h3 + (int64_t)(jb + n) * H + hbase;
+                for (int r = 0; r < 16; ++r)
+                    Rl[acc_row(r, lane) * RLD + 64 * wn + 32 * fn + (lane & 31)] = acc[fm][fn][r];
+        }
+        __syncthreads();
+        const int vb = s_cs[c_lo], ve = s_cs[c_hi];
+        for (int v0 = vb + wave; v0 < ve; v0 += 4 * (DNT / 64)) {
+            uint2 hv[4];
 #pragma unroll
-                    for (int fn = 0; fn < 4; ++fn) sum += from_bf16(hr[32 * fn]) * acc[fm][fn][r];
+            for (int q = 0; q < 4; ++q) {
+                const int v = v0 + q * (DNT / 64);
+                hv[q] = v < ve ? *(const uint2 *)(h3 + (int64_t)v * H + 4 * lane) : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int v = v0 + q * (DNT / 64);
+                if (v >= ve) break;                  // uniform over the wave
+                int lo = c_lo, hi = c_hi - 1;        // cell of visibility v
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_cs[mid] <= v) lo = mid; else hi = mid - 1;
                 }
-                for (int o = 16; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-                if (n < cnt && (lane & 31) == 0) {
-                    float *dst = (float *)&yacc[jb + n - v0] + part;
-                    atomicAdd(dst, sum);
-                }
+                const float4 rr = *(const float4 *)(Rl + (lo - c_lo) * RLD + 4 * lane);
+                float sum = __uint_as_float(hv[q].x << 16) * rr.x + __uint_as_float(hv[q].x & 0xffff0000u) * rr.y +
+                            __uint_as_float(hv[q].y << 16) * rr.z + __uint_as_float(hv[q].y & 0xffff0000u) * rr.w;
+                for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+                if (lane == 0) ((float *)&y[v])[part] = s_out * (sum + s_beta[lo]);
             }
         }
-    }
-    __syncthreads();
-    for (int i = tid; i < nv; i += DNT) {
-        int lo = 0, hi = nc - 1;           // cell of visibility v0 + i
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_cs[mid] <= v0 + i) lo = mid; else hi = mid - 1;
-        }
-        const float2 a = yacc[i], b = s_beta[lo];
-        y[v0 + i] = make_float2(s_out * (a.x + b.x), s_out * (a.y + b.y));
+        __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------- gridding
 
-// One workgroup per 8 x 8 tile of cells with occupied cells: A[i] = s of cell i (resident in
-// LDS), box contributions = A Bgrd^T in chunks of GN outputs, accumulated into an LDS window of
-// the tile's boxes and added to the grid with atomics.  Waves: 2 along cells x 4 along outputs.
-__global__ __launch_bounds__(DNT) void k_sur_grid(const float2 *__restrict__ y, int logNg,
-                                                  const int *__restrict__ grp, int ngrp,
-                                                  const int *__restrict__ cell_key,
-                                                  const int *__restrict__ cell_start,
-                                                  const uint16_t *__restrict__ h3,
-                                                  const uint16_t *__restrict__ Bgrd, const float *__restrict__ b4,
-                                                  float s_out, float2 *__restrict__ grid) {
+// One workgroup per group of <= AG consecutive occupied cells whose boxes fit the LDS window:
+// A[i] = s of cell i (bfloat16, staged in LDS, then held in registers by every wave), box
+// contributions = A Bgrd^T in blocks of 32 outputs (wave w takes blocks w, w + 4, ...; the weight
+// fragments come from L2 straight into registers), accumulated in the window and added to the
+// grid with atomics.
+__global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ y, int logNg,
+                                                     const int *__restrict__ grp, const int2 *__restrict__ org,
+                                                     int ngrp, const int *__restrict__ cell_key,
+                                                     const int *__restrict__ cell_start,
+                                                     const uint16_t *__restrict__ h3,
+                                                     const uint16_t *__restrict__ Bgrd, const float *__restrict__ b4,
+                                                     float s_out, float2 *__restrict__ grid) {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint16_t *Sa = (uint16_t *)smem;                               // [AG][LDS_A]
-    uint16_t *Bs = Sa + AG * LDS_A;                                // [2][GN][LDK]
-    float2 *win = (float2 *)(Bs + 2 * GN * LDK);                   // [WIN][WIN]
-    __shared__ int s_cv[AG], s_cu[AG];
+    uint16_t *Sa = (uint16_t *)smem;                               // [AG][SLD]
+    float2 *win = (float2 *)(smem + (size_t)AG * SLD * 2);         // [WV][WU]
+    __shared__ int s_wv[AG], s_wu[AG];
     __shared__ float2 s_Y[AG];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 2, wn = wave & 3;
-    const int g = (int)xcd_block(blockIdx.x, ngrp);
+    const int g = blockIdx.x;
     const int c0 = grp[g], nc = grp[g + 1] - c0;
+    const int2 o = org[g];                          // window origin: (min v - 16, min u - 16) of the group's cells
     const int Ng = 1 << logNg;
-    int tv0, tu0;
-    demorton2(cell_key[c0] & ~(AG - 1), tv0, tu0);
-    for (int i = tid; i < AG; i += DNT) {
+    for (int i = tid; i < AG; i += ANT) {
         int cv = 0, cu = 0;
         if (i < nc) demorton2(cell_key[c0 + i], cv, cu);
-        s_cv[i] = cv - tv0;
-        s_cu[i] = cu - tu0;
+        s_wv[i] = i < nc ? cv - (o.x + BOX / 2) : 0;
+        s_wu[i] = i < nc ? cu - (o.y + BOX / 2) : 0;
     }
-    for (int e = tid; e < WIN * WIN; e += DNT) win[e] = make_float2(0.f, 0.f);
-    // s of each cell: thread -> cell i = tid / 8, hidden units [32 (tid % 8), +32)
-    {
-        const int i = tid >> 3, j0 = 32 * (tid & 7);
-        float sr[32], sm[32];
-#pragma unroll
-        for (int q = 0; q < 32; ++q) sr[q] = sm[q] = 0.0f;
+    for (int e = tid; e < WV * WU; e += ANT) win[e] = make_float2(0.f, 0.f);
+    // s of each cell: wave w takes cells w, w + 4, ...; lane l hidden units 4l .. 4l + 3
+    for (int i = wave; i < AG; i += ANT / 64) {
+        float sr[4] = {0.f, 0.f, 0.f, 0.f}, sm[4] = {0.f, 0.f, 0.f, 0.f};
         float2 Y = make_float2(0.f, 0.f);
         if (i < nc) {
             const int jb = cell_start[c0 + i], je = cell_start[c0 + i + 1];
-            for (int k = jb; k < je; ++k) {
-                const float2 yk = y[k];
-                Y.x += yk.x;
-                Y.y += yk.y;
-                const u32x4 *hr = (const u32x4 *)(h3 + (int64_t)k * H + j0);
+            for (int k0 = jb; k0 < je; k0 += 4) {
+                uint2 hv[4];
+                float2 yk[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const u32x4 hv = hr[c];
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = k0 + q < je;
+                    hv[q] = ok ? *(const uint2 *)(h3 + (int64_t)(k0 + q) * H + 4 * lane) : make_uint2(0u, 0u);
+                    yk[q] = ok ? y[k0 + q] : make_float2(0.f, 0.f);
+                }
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const float h0 = __uint_as_float(hv[e] << 16), h1 = __uint_as_float(hv[e] & 0xffff0000u);
-                        sr[8 * c + 2 * e] += h0 * yk.x;
-                        sm[8 * c + 2 * e] += h0 * yk.y;
-                        sr[8 * c + 2 * e + 1] += h1 * yk.x;
-                        sm[8 * c + 2 * e + 1] += h1 * yk.y;
-                    }
+                for (int q = 0; q < 4; ++q) {
+                    const float h0 = __uint_as_float(hv[q].x << 16), h1 = __uint_as_float(hv[q].x & 0xffff0000u);
+                    const float h2 = __uint_as_float(hv[q].y << 16), h3v = __uint_as_float(hv[q].y & 0xffff0000u);
+                    sr[0] += h0 * yk[q].x; sm[0] += h0 * yk[q].y;
+                    sr[1] += h1 * yk[q].x; sm[1] += h1 * yk[q].y;
+                    sr[2] += h2 * yk[q].x; sm[2] += h2 * yk[q].y;
+                    sr[3] += h3v * yk[q].x; sm[3] += h3v * yk[q].y;
+                    Y.x += yk[q].x;
+                    Y.y += yk[q].y;
                 }
             }
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            u32x4 pr, pm;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                pr[e] = (uint32_t)to_bf16(sr[8 * c + 2 * e]) | ((uint32_t)to_bf16(sr[8 * c + 2 * e + 1]) << 16);
-                pm[e] = (uint32_t)to_bf16(sm[8 * c + 2 * e]) | ((uint32_t)to_bf16(sm[8 * c + 2 * e + 1]) << 16);
-            }
-            *(u32x4 *)(Sa + i * LDS_A + j0 + 8 * c) = pr;
-            *(u32x4 *)(Sa + i * LDS_A + H + j0 + 8 * c) = pm;
-        }
-        if ((tid & 7) == 0) s_Y[i] = Y;
+        uint2 pr, pm;
+        pr.x = (uint32_t)to_bf16(sr[0]) | ((uint32_t)to_bf16(sr[1]) << 16);
+        pr.y = (uint32_t)to_bf16(sr[2]) | ((uint32_t)to_bf16(sr[3]) << 16);
+        pm.x = (uint32_t)to_bf16(sm[0]) | ((uint32_t)to_bf16(sm[1]) << 16);
+        pm.y = (uint32_t)to_bf16(sm[2]) | ((uint32_t)to_bf16(sm[3]) << 16);
+        *(uint2 *)(Sa + i * SLD + 4 * lane) = pr;
+        *(uint2 *)(Sa + i * SLD + H + 4 * lane) = pm;
+        if (lane == 0) s_Y[i] = Y;
     }
-    // B chunks: GN rows x BK = 1024 chunks of 8, two per thread
-    u32x4 breg[2];
-    constexpr int KSTEP = ND / BK;             // 16 steps per output chunk
-    constexpr int NCHUNK = NOUT / GN;          // 8 chunks
-    auto loadB = [&](int t) {
-        const int ch = t / KSTEP, ks = t % KSTEP;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
-            breg[q] = *(const u32x4 *)(Bgrd + (int64_t)(GN * ch + n) * ND + BK * ks + kc);
-        }
-    };
-    auto storeB = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
-            *(u32x4 *)(Bs + buf * GN * LDK + n * LDK + kc) = breg[q];
-        }
-    };
-    f32x16 acc[1][2];
-    auto zero = [&]() {
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[0][b][r] = 0.0f;
-    };
-    zero();
-    loadB(0);
-    storeB(0);
     __syncthreads();
-    constexpr int NT_ = NCHUNK * KSTEP;
-    for (int t = 0; t < NT_; ++t) {
-        const int cur = t & 1, ks = t % KSTEP, ch = t / KSTEP;
-        if (t + 1 < NT_) loadB(t + 1);
-        mma_bk<1, 2, LDS_A, LDK>(acc, Sa + BK * ks, Bs + cur * GN * LDK, 32 * wm, 64 * wn, lane);
-        if (ks == KSTEP - 1) {
-            // outputs o = GN ch + 64 wn + 32 fn + lane % 32 of cell i: box cell p = o / 2, part o % 2
+    // the whole A operand of the group in registers: 32 steps of 16
+    constexpr int KS = ND / 16;
+    bf16x8 a[KS];
+    const int ro = lane & 31, ko = 8 * (lane >> 5);
 #pragma unroll
-            for (int fn = 0; fn < 2; ++fn) {
-                const int o = GN * ch + 64 * wn + 32 * fn + (lane & 31);
-                const int p = o >> 1, comp = o & 1;
-                const int oy = p >> 5, ox = p & (BOX - 1);
-                const float br = b4[2 * p], bi = b4[2 * p + 1];
+    for (int ks = 0; ks < KS; ++ks) a[ks] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(Sa + ro * SLD + 16 * ks + ko));
+    for (int blk = wave; blk < NOUT / 32; blk += ANT / 64) {
+        f32x16 acc;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int i = 32 * wm + acc_row(r, lane);
-                    if (i < nc) {
-                        const float2 Y = s_Y[i];
-                        const float bias = comp == 0 ? br * Y.x + bi * Y.y : br * Y.y - bi * Y.x;
-                        float *dst = (float *)&win[(s_cv[i] + oy) * WIN + s_cu[i] + ox] + comp;
-                        atomicAdd(dst, s_out * (acc[0][fn][r] + bias));
-                    }
-                }
-            }
-            zero();
+        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+        const uint16_t *brow = Bgrd + (int64_t)(32 * blk + ro) * ND + ko;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 b = __builtin_bit_cast(bf16x8, *(const u32x4 *)(brow + 16 * ks));
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
         }
-        if (t + 1 < NT_) storeB(cur ^ 1);
-        __syncthreads();
+        // output o = 32 blk + lane % 32 of cell i: box cell p = o / 2, component o % 2
+        const int oo = 32 * blk + ro;
+        const int p = oo >> 1, comp = oo & 1;
+        const int oy = p >> 5, ox = p & (BOX - 1);
+        const float br = b4[2 * p], bi = b4[2 * p + 1];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = acc_row(r, lane);
+            if (i < nc) {
+                const float2 Y = s_Y[i];
+                const float bias = comp == 0 ? br * Y.x + bi * Y.y : br * Y.y - bi * Y.x;
+                float *dst = (float *)&win[(s_wv[i] + oy) * WU + s_wu[i] + ox] + comp;
+                atomicAdd(dst, s_out * (acc[r] + bias));
+            }
+        }
     }
-    for (int e = tid; e < WIN * WIN; e += DNT) {
+    __syncthreads();
+    for (int e = tid; e < WV * WU; e += ANT) {
         const float2 val = win[e];
         if (val.x != 0.0f || val.y != 0.0f) {
-            const int gy = (tv0 - BOX / 2 + e / WIN) & (Ng - 1), gx = (tu0 - BOX / 2 + e % WIN) & (Ng - 1);
+            const int gy = (o.x + e / WU) & (Ng - 1), gx = (o.y + e % WU) & (Ng - 1);
             float *dst = (float *)&grid[(int64_t)gy * Ng + gx];
             atomicAdd(dst, val.x);
             atomicAdd(dst + 1, val.y);
@@ -421,15 +397,15 @@ wp_status check_sur(const wp_plan *p, const wp_surrogate *s) {
 
 wp_status sur_degrid(const wp_plan *p, const wp_surrogate *S, const float2 *grid, float2 *y, hipStream_t s) {
     if (S->Ms == 0) return WP_OK;
-    hipLaunchKernelGGL(k_sur_degrid, dim3(S->ngrp_d), dim3(DNT), DEG_LDS, s, grid, p->logNg, S->grp_d, S->ngrp_d,
+    hipLaunchKernelGGL(k_sur_degrid, dim3(S->ngrp_d, 2), dim3(DNT), DEG_LDS, s, grid, p->logNg, S->grp_d, S->ngrp_d,
                        S->cell_key, S->cell_start, S->h3, S->Bdeg, S->b4, S->s_out, y);
     return wp_check_launch("k_sur_degrid");
 }
 
 wp_status sur_grid_add(const wp_plan *p, const wp_surrogate *S, const float2 *y, float2 *grid, hipStream_t s) {
     if (S->Ms == 0) return WP_OK;
-    hipLaunchKernelGGL(k_sur_grid, dim3(S->ngrp_a), dim3(DNT), GRD_LDS, s, y, p->logNg, S->grp_a, S->ngrp_a,
-                       S->cell_key, S->cell_start, S->h3, S->Bgrd, S->b4, S->s_out, grid);
+    hipLaunchKernelGGL(k_sur_grid, dim3(S->ngrp_a), dim3(ANT), GRD_LDS, s, y, p->logNg, S->grp_a, S->grp_org,
+                       S->ngrp_a, S->cell_key, S->cell_start, S->h3, S->Bgrd, S->b4, S->s_out, grid);
     return wp_check_launch("k_sur_grid");
 }
 
@@ -543,28 +519,43 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
             return fail(WP_ENOMEM, "cell table");
         hipLaunchKernelGGL(k_cell_table, dim3(gS), dim3(256), 0, s, (const int *)skey.p, (const int *)flag.p,
                            (const int *)cid.p, Ms, S->cell_key, S->cell_start);
-        // groups, on the host: degridding groups of <= DG cells and <= VMAX visibilities;
-        // gridding groups = the occupied cells of one 8 x 8 tile
+        // groups, on the host: degridding groups of <= DG consecutive cells; gridding groups of
+        // <= AG consecutive cells whose rows and columns each span at most WV - BOX (WU - BOX) + 1
         std::vector<int> ckey(h_nc), cstart(h_nc + 1);
         WP_HIP(hipMemcpyAsync(ckey.data(), S->cell_key, 4 * (size_t)h_nc, hipMemcpyDeviceToHost, s));
         WP_HIP(hipMemcpyAsync(cstart.data(), S->cell_start, 4 * (size_t)(h_nc + 1), hipMemcpyDeviceToHost, s));
         WP_HIP(hipStreamSynchronize(s));
-        std::vector<int> gd{0}, ga{0};
+        std::vector<int> gd, ga;
+        std::vector<int2> go;
+        int vmin = 0, vmax = 0, umin = 0, umax = 0;
         for (int c = 0; c < h_nc; ++c) {
-            if (cstart[c + 1] - cstart[c] > VMAX) return fail(WP_ECAPACITY, "a cell holds more visibilities than a group");
-            const int g0 = gd.back();
-            if (c - g0 >= DG || cstart[c + 1] - cstart[g0] > VMAX) gd.push_back(c);
-            if (c > ga.back() && (ckey[c] / AG) != (ckey[ga.back()] / AG)) ga.push_back(c);
+            if (c % DG == 0) gd.push_back(c);
+            int cv, cu;
+            demorton2(ckey[c], cv, cu);
+            const bool fits = !ga.empty() && c - ga.back() < AG && std::max(vmax, cv) - std::min(vmin, cv) <= WV - BOX &&
+                              std::max(umax, cu) - std::min(umin, cu) <= WU - BOX;
+            if (fits) {
+                vmin = std::min(vmin, cv); vmax = std::max(vmax, cv);
+                umin = std::min(umin, cu); umax = std::max(umax, cu);
+            } else {
+                if (!ga.empty()) go.push_back(make_int2(vmin - BOX / 2, umin - BOX / 2));
+                ga.push_back(c);
+                vmin = vmax = cv;
+                umin = umax = cu;
+            }
         }
+        go.push_back(make_int2(vmin - BOX / 2, umin - BOX / 2));
         gd.push_back(h_nc);
         ga.push_back(h_nc);
         S->ngrp_d = (int)gd.size() - 1;
         S->ngrp_a = (int)ga.size() - 1;
         if (hipMalloc((void **)&S->grp_d, 4 * gd.size()) != hipSuccess ||
-            hipMalloc((void **)&S->grp_a, 4 * ga.size()) != hipSuccess)
+            hipMalloc((void **)&S->grp_a, 4 * ga.size()) != hipSuccess ||
+            hipMalloc((void **)&S->grp_org, sizeof(int2) * go.size()) != hipSuccess)
             return fail(WP_ENOMEM, "groups");
         WP_HIP(hipMemcpyAsync(S->grp_d, gd.data(), 4 * gd.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipMemcpyAsync(S->grp_a, ga.data(), 4 * ga.size(), hipMemcpyHostToDevice, s));
+        WP_HIP(hipMemcpyAsync(S->grp_org, go.data(), sizeof(int2) * go.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipStreamSynchronize(s));
         // last hidden layer of every surrogate row, in slot order
         if (hipMalloc((void **)&S->h3, (size_t)Ms * H * 2) != hipSuccess) return fail(WP_ENOMEM, "hidden features");
@@ -591,7 +582,8 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
 
 wp_status wp_surrogate_destroy(wp_surrogate *S) {
     if (!S) return WP_OK;
-    void *bufs[] = {S->slot_vis, S->cell_key, S->cell_start, S->grp_d, S->grp_a, S->h3, S->Bdeg, S->Bgrd, S->b4, S->fb};
+    void *bufs[] = {S->slot_vis, S->cell_key, S->cell_start, S->grp_d, S->grp_a, S->grp_org, S->h3, S->Bdeg,
+                    S->Bgrd, S->b4, S->fb};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(S);

@@ -161,7 +161,7 @@ def test_all_rows_fall_back(setup):
     sur.close()
 
 
-def test_single_visibility_and_capacity(setup):
+def test_single_visibility_and_crowded_cell(setup):
     d = setup
     plan, mlp = d["plan"], d["mlp"]
     one = [_dev(a[:1]) for a in (d["u"], d["v"], d["w"])]
@@ -174,11 +174,23 @@ def test_single_visibility_and_capacity(setup):
     cols, t = S.surrogate_rows(d["net"], d["u"][:1], d["v"][:1], d["w"][:1], d["s"], q=S.round_bf16)
     assert abs(y[0] - np.sum(t[0] * X[cols[0]])) <= 1e-5 * np.sum(np.abs(t[0]))
     sur.close()
-    # more visibilities in one cell than a degridding group holds
+    # many visibilities in one cell (one degridding group, one gridding group)
     M = 12801
     same = [_dev(np.full(M, a[0])) for a in (d["u"], d["v"], d["w"])]
-    with pytest.raises(W.WprojError):
-        W.Surrogate(plan, mlp, *same)
+    sur = W.Surrogate(plan, mlp, *same)
+    assert sur.ncell == 1 and sur.groups == (1, 1)
+    y = sur.degrid(_dev(X)).cpu().numpy()
+    ref = np.sum(t[0] * X[cols[0]])
+    assert np.all(y == y[0])
+    assert abs(y[0] - ref) <= 1e-5 * np.sum(np.abs(t[0]))
+    yy = np.full(M, 1.0 + 0.5j, dtype=np.complex64)
+    g = torch.zeros(Ng * Ng, dtype=torch.complex64, device="cuda")
+    got = sur.grid_add(_dev(yy), g).cpu().numpy()
+    refg = np.zeros(Ng * Ng, dtype=np.complex128)
+    np.add.at(refg, cols[0], np.conj(t[0]) * (M * (1.0 + 0.5j)))
+    # the cell sum s_c = M h y is rounded to bfloat16 once: relative 2^-9
+    assert np.linalg.norm(got - refg) <= 4e-3 * np.linalg.norm(refg)
+    sur.close()
 
 
 def test_to_slots_with_sorted_fallback(setup):
