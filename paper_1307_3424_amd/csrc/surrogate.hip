@@ -27,6 +27,20 @@
 
 using namespace mlpc;
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// loads of data read once per product (hidden layers, visibilities): non-temporal, so that they do
+// not evict the output-layer weights that every workgroup reads
+__device__ __forceinline__ uint2 nt_load_u2(const uint16_t *p) {
+    const u32x2 v = __builtin_nontemporal_load((const u32x2 *)p);
+    return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ float2 nt_load_f2(const float2 *p) {
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const f32x2 v = __builtin_nontemporal_load((const f32x2 *)p);
+    return make_float2(v.x, v.y);
+}
+
 struct wp_surrogate {
     int device;
     int logNg;
@@ -116,8 +130,19 @@ __global__ void k_fallback_coords(const double *__restrict__ u, const double *__
     fb[2 * Mf + i] = w[k];
 }
 
-// Bdeg[n][kk] (n < 256: r re of hidden n; n >= 256: r im of hidden n - 256; kk = 2p + c) and
-// Bgrd[o][k] (o = 2p + c; k < 256: s re, k >= 256: s im), from W4 (FP32) rounded to bfloat16
+// The two output-layer matrices, rounded to bfloat16, stored in the order the products read them:
+//   Bdeg[n][kk] (n < 256: r re of hidden n, n >= 256: r im of hidden n - 256; kk = 2p + c) as
+//     [part = n / 256][step t = kk / 32][n % 256][kk % 32]: one degridding stage is contiguous;
+//   Bgrd[o][k] (o = 2p + c; k < 256: s re, k >= 256: s im) as
+//     [block o / 32][step k / 16][lane = o % 32 + 32 ((k % 16) / 8)][k % 8]: one MFMA fragment of
+//     a wave is 1 KB contiguous.
+__device__ inline int64_t deg_index(int n, int kk) {
+    return ((int64_t)((n / H) * (KDEP / 32) + kk / 32) * H + (n % H)) * 32 + (kk % 32);
+}
+__device__ inline int64_t grd_index(int o, int k) {
+    return ((int64_t)((o / 32) * (ND / 16) + k / 16) * 64 + (o % 32) + 32 * ((k % 16) / 8)) * 8 + (k % 8);
+}
+
 __global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bdeg, uint16_t *__restrict__ Bgrd) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)NOUT * H) return;
@@ -125,14 +150,14 @@ __global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bd
     if (p >= BOX * BOX) return;
     const float wr = W4[(int64_t)(2 * p) * H + j], wi = W4[(int64_t)(2 * p + 1) * H + j];
     const uint16_t br = to_bf16(wr), bi = to_bf16(wi), nbi = to_bf16(-wi);
-    Bdeg[(int64_t)j * KDEP + 2 * p] = br;
-    Bdeg[(int64_t)j * KDEP + 2 * p + 1] = nbi;
-    Bdeg[(int64_t)(H + j) * KDEP + 2 * p] = bi;
-    Bdeg[(int64_t)(H + j) * KDEP + 2 * p + 1] = br;
-    Bgrd[(int64_t)(2 * p) * ND + j] = br;
-    Bgrd[(int64_t)(2 * p) * ND + H + j] = bi;
-    Bgrd[(int64_t)(2 * p + 1) * ND + j] = nbi;
-    Bgrd[(int64_t)(2 * p + 1) * ND + H + j] = br;
+    Bdeg[deg_index(j, 2 * p)] = br;
+    Bdeg[deg_index(j, 2 * p + 1)] = nbi;
+    Bdeg[deg_index(H + j, 2 * p)] = bi;
+    Bdeg[deg_index(H + j, 2 * p + 1)] = br;
+    Bgrd[grd_index(2 * p, j)] = br;
+    Bgrd[grd_index(2 * p, H + j)] = bi;
+    Bgrd[grd_index(2 * p + 1, j)] = nbi;
+    Bgrd[grd_index(2 * p + 1, H + j)] = br;
 }
 
 // ---------------------------------------------------------------------------- degridding
@@ -157,9 +182,11 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid(const float2 *__restrict_
     float *Rl = (float *)smem;                       // after the product: [RPASS][RLD]
     __shared__ int s_cv[DG], s_cu[DG], s_cs[DG + 1];
     __shared__ float s_beta[DG];
+    __shared__ float2 s_b4[BOX * BOX];               // output bias (no global loads inside the loop)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 2, wn = wave & 3;
     const int part = blockIdx.y;
+    for (int i = tid; i < BOX * BOX; i += DNT) s_b4[i] = ((const float2 *)b4)[i];
     const int g = (int)xcd_block(blockIdx.x, ngrp);
     const int c0 = grp[g], nc = grp[g + 1] - c0;
     const int Ng = 1 << logNg;
@@ -176,7 +203,7 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid(const float2 *__restrict_
     const int si = tid >> 2, sq = tid & 3;
     const bool slive = si < nc;
     const int scv = s_cv[si], scu = s_cu[si];
-    const uint16_t *Bpart = Bdeg + (int64_t)part * DBN * KDEP;
+    const uint16_t *Bpart = Bdeg + (int64_t)part * DBN * KDEP;   // [step][256][32]
     float2 areg[4];
     u32x4 breg[2];
     float bacc = 0.0f;
@@ -191,7 +218,7 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid(const float2 *__restrict_
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const int c = tid + DNT * q, n = c >> 2, kc = (c & 3) * 8;
-            breg[q] = *(const u32x4 *)(Bpart + (int64_t)n * KDEP + 32 * t + kc);
+            breg[q] = *(const u32x4 *)(Bpart + ((int64_t)t * DBN + n) * 32 + kc);
         }
     };
     auto store = [&](int t, int buf) {
@@ -200,9 +227,8 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid(const float2 *__restrict_
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             a[e] = (uint32_t)to_bf16(areg[e].x) | ((uint32_t)to_bf16(areg[e].y) << 16);
-            const int p = oy * BOX + ox0 + e;
-            const float br = b4[2 * p], bi = b4[2 * p + 1];
-            bacc += part == 0 ? br * areg[e].x - bi * areg[e].y : br * areg[e].y + bi * areg[e].x;
+            const float2 bb = s_b4[oy * BOX + ox0 + e];
+            bacc += part == 0 ? bb.x * areg[e].x - bb.y * areg[e].y : bb.x * areg[e].y + bb.y * areg[e].x;
         }
         *(u32x4 *)(As + buf * DG * LDK + si * LDK + 8 * sq) = a;
 #pragma unroll
@@ -253,7 +279,7 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid(const float2 *__restrict_
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int v = v0 + q * (DNT / 64);
-                hv[q] = v < ve ? *(const uint2 *)(h3 + (int64_t)v * H + 4 * lane) : make_uint2(0u, 0u);
+                hv[q] = v < ve ? nt_load_u2(h3 + (int64_t)v * H + 4 * lane) : make_uint2(0u, 0u);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -294,7 +320,9 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
     float2 *win = (float2 *)(smem + (size_t)AG * SLD * 2);         // [WV][WU]
     __shared__ int s_wv[AG], s_wu[AG];
     __shared__ float2 s_Y[AG];
+    __shared__ float2 s_b4[BOX * BOX];               // output bias (no global loads inside the loop)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < BOX * BOX; i += ANT) s_b4[i] = ((const float2 *)b4)[i];
     const int g = blockIdx.x;
     const int c0 = grp[g], nc = grp[g + 1] - c0;
     const int2 o = org[g];                          // window origin: (min v - 16, min u - 16) of the group's cells
@@ -318,8 +346,8 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const bool ok = k0 + q < je;
-                    hv[q] = ok ? *(const uint2 *)(h3 + (int64_t)(k0 + q) * H + 4 * lane) : make_uint2(0u, 0u);
-                    yk[q] = ok ? y[k0 + q] : make_float2(0.f, 0.f);
+                    hv[q] = ok ? nt_load_u2(h3 + (int64_t)(k0 + q) * H + 4 * lane) : make_uint2(0u, 0u);
+                    yk[q] = ok ? nt_load_f2(y + k0 + q) : make_float2(0.f, 0.f);
                 }
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
@@ -350,29 +378,48 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
     const int ro = lane & 31, ko = 8 * (lane >> 5);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) a[ks] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(Sa + ro * SLD + 16 * ks + ko));
-    for (int blk = wave; blk < NOUT / 32; blk += ANT / 64) {
-        f32x16 acc;
+    // per accumulator register r, this lane's cell i = acc_row(r, lane) is the same for every block:
+    // its window offset and sum of y, in registers (-1: no cell)
+    int wb[16];
+    float2 Yr[16];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
-        const uint16_t *brow = Bgrd + (int64_t)(32 * blk + ro) * ND + ko;
+    for (int r = 0; r < 16; ++r) {
+        const int i = acc_row(r, lane);
+        wb[r] = i < nc ? s_wv[i] * WU + s_wu[i] : -1;
+        Yr[r] = s_Y[i];
+    }
+    // two blocks of 32 outputs per pass (two independent accumulation chains, twice the loads in flight)
+    for (int blk0 = 2 * wave; blk0 < NOUT / 32; blk0 += 2 * (ANT / 64)) {
+        f32x16 acc[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[h][r] = 0.0f;
+        const uint16_t *brow0 = Bgrd + ((int64_t)blk0 * KS * 64 + lane) * 8;      // fragment-major
+        const uint16_t *brow1 = brow0 + (int64_t)KS * 64 * 8;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const bf16x8 b = __builtin_bit_cast(bf16x8, *(const u32x4 *)(brow + 16 * ks));
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b, acc, 0, 0, 0);
+            const bf16x8 b0 = __builtin_bit_cast(bf16x8, *(const u32x4 *)(brow0 + 512 * ks));
+            const bf16x8 b1 = __builtin_bit_cast(bf16x8, *(const u32x4 *)(brow1 + 512 * ks));
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b0, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ks], b1, acc[1], 0, 0, 0);
         }
-        // output o = 32 blk + lane % 32 of cell i: box cell p = o / 2, component o % 2
-        const int oo = 32 * blk + ro;
-        const int p = oo >> 1, comp = oo & 1;
-        const int oy = p >> 5, ox = p & (BOX - 1);
-        const float br = b4[2 * p], bi = b4[2 * p + 1];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = acc_row(r, lane);
-            if (i < nc) {
-                const float2 Y = s_Y[i];
-                const float bias = comp == 0 ? br * Y.x + bi * Y.y : br * Y.y - bi * Y.x;
-                float *dst = (float *)&win[(s_wv[i] + oy) * WU + s_wu[i] + ox] + comp;
-                atomicAdd(dst, s_out * (acc[r] + bias));
+        for (int h = 0; h < 2; ++h) {
+            // output o = 32 blk + lane % 32 of cell i: box cell p = o / 2, component o % 2
+            const int oo = 32 * (blk0 + h) + ro;
+            const int p = oo >> 1, comp = oo & 1;
+            const int oy = p >> 5, ox = p & (BOX - 1);
+            const float br = s_b4[p].x, bi = s_b4[p].y;
+            const int woff = oy * WU + ox;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if (wb[r] >= 0) {
+                    const float2 Y = Yr[r];
+                    const float bias = comp == 0 ? br * Y.x + bi * Y.y : br * Y.y - bi * Y.x;
+                    float *dst = (float *)&win[wb[r] + woff] + comp;
+                    atomicAdd(dst, s_out * (acc[h][r] + bias));
+                }
             }
         }
     }
