@@ -5,9 +5,11 @@
 // counter until the queue is empty, which balances problems of very uneven size.
 //
 // The work counter is never reset: it only grows, and each launch receives the
-// counter value it starts from (`base`).  A launch takes exactly n_items + nblocks
-// tickets (every workgroup takes one more ticket than it has items), so the host
-// knows the next base without reading the counter back and needs no reset launch.
+// counter value it starts from (`base`).  A workgroup asks for its next ticket as soon
+// as it has read the current one (the atomic's latency overlaps the item's work), so
+// it takes two tickets more than it has items and a launch takes exactly
+// n_items + 2 nblocks tickets: the host knows the next base without reading the
+// counter back and needs no reset launch.
 //
 // Launch shapes (rows or cells per item, lanes per row or cell, loads in flight)
 // are chosen by wp_batch_autotune, which times every candidate with HIP events.
@@ -34,10 +36,17 @@ struct ProbDesc {
     int64_t y_off;
 };
 
-__device__ __forceinline__ int next_item(unsigned long long *counter, unsigned long long base, int *slot) {
+// The workgroup's current item; thread 0 keeps the ticket of the following one in `ahead` (asked for
+// here, used on the next call).  Start with ahead = first_ticket(...).
+__device__ __forceinline__ long long first_ticket(unsigned long long *counter, unsigned long long base) {
+    return threadIdx.x == 0 ? (long long)(atomicAdd(counter, 1ull) - base) : 0;
+}
+__device__ __forceinline__ int next_item(unsigned long long *counter, unsigned long long base, int *slot,
+                                         long long &ahead) {
     if (threadIdx.x == 0) {
-        const long long t = (long long)(atomicAdd(counter, 1ull) - base);
+        const long long t = ahead;
         *slot = (t < 0 || t > 0x7fffffffLL) ? 0x7fffffff : (int)t;     // out of range: stop
+        ahead = (long long)(atomicAdd(counter, 1ull) - base);
     }
     __syncthreads();
     const int it = *slot;
@@ -53,8 +62,9 @@ __global__ __launch_bounds__(BT) void k_degrid_persist(const ProbDesc *__restric
     __shared__ int slot;
     const int grp = threadIdx.x / LPR, sub = threadIdx.x & (LPR - 1);
     constexpr int NGRP = BT / LPR;
+    long long ahead = first_ticket(counter, base);
     for (;;) {
-        const int it = next_item(counter, base, &slot);
+        const int it = next_item(counter, base, &slot, ahead);
         if (it >= n_items) break;
         const int2 w = items[it];
         const ProbDesc d = pd[w.x];
@@ -110,8 +120,9 @@ __global__ __launch_bounds__(BT) void k_gather_persist(const ProbDesc *__restric
     __shared__ int slot;
     const int grp = threadIdx.x / LPR, sub = threadIdx.x & (LPR - 1);
     constexpr int NGRP = BT / LPR;
+    long long ahead = first_ticket(counter, base);
     for (;;) {
-        const int it = next_item(counter, base, &slot);
+        const int it = next_item(counter, base, &slot, ahead);
         if (it >= n_items) break;
         const int2 w = items[it];
         const ProbDesc d = pd[w.x];
@@ -205,7 +216,7 @@ wp_status launch_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s)
     }
 #undef DEG
     if (wp_status st = wp_check_launch("batch degrid")) return st;
-    b->base += (unsigned long long)b->n_items_deg + (unsigned long long)b->nblocks;
+    b->base += (unsigned long long)b->n_items_deg + 2ull * (unsigned long long)b->nblocks;
     return WP_OK;
 }
 
@@ -227,7 +238,7 @@ wp_status launch_gat(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s)
     }
 #undef GAT
     if (wp_status st = wp_check_launch("batch gather")) return st;
-    b->base += (unsigned long long)b->n_items_gat + (unsigned long long)b->nblocks;
+    b->base += (unsigned long long)b->n_items_gat + 2ull * (unsigned long long)b->nblocks;
     return WP_OK;
 }
 
