@@ -100,6 +100,9 @@ def load(path: str = LIB_PATH):
     """Load libwproj.so (raises OSError if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname: importing it first makes
+        # the library bind to that runtime instead of loading a second one beside it
+        import torch  # noqa: F401
         if not os.path.exists(path):
             raise OSError(f"{path} is missing: build it first (python -c 'import __graft_entry__ as g; g.build()')")
         lib = C.CDLL(path)

@@ -72,3 +72,18 @@ def test_library_db8_filter_matches_oracle_derivation():
     h = np.array(wp.db8_filter())
     assert np.abs(h - wavelet.daubechies_lowpass(8)).max() < 1e-12
     assert abs(h.sum() - np.sqrt(2)) < 1e-13 and abs(np.dot(h, h) - 1) < 1e-13
+
+
+def test_library_shares_the_hip_runtime_of_torch():
+    """Loading the library before torch must not bring in a second HIP runtime:
+    two runtimes in one process make the library's device calls fail."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1307_3424_amd._lib as L; L.load()\n"
+        "paths = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+        "print(len(paths)); print(*sorted(paths))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.split()[0] == "1", out.stdout
