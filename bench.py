@@ -59,8 +59,10 @@ def scatter_bytes(G, M, Ng, tap_bytes):
 
 
 def gather_bytes(G, M, Ng, tap_bytes):
-    """Transposed copy streamed once (value + visibility index), cell offsets, y read once, grid written once."""
-    return G.nnz * (tap_bytes + 4) + (Ng * Ng + 1) * 8 + M * 8 + Ng * Ng * 8
+    """Transposed copy streamed once (value + visibility index), cell offsets and block table, y read once,
+    grid written once."""
+    table = 16 * (G.n_tblk + 1) if G.tblk is not None else 0
+    return G.nnz * (tap_bytes + 4) + (Ng * Ng + 1) * 8 + table + M * 8 + Ng * Ng * 8
 
 
 def profiled_traffic(workload_name, kernel):

@@ -91,6 +91,14 @@ typedef struct wp_G {
     int64_t *tcolptr;  /* [Ng*Ng+1] device                                           */
     int32_t *trow;     /* [nnz] device, sorted row index r of the entry               */
     void    *tval;     /* [nnz] device, the entry's G value (not conjugated), same tap type */
+    /* Optional block table of the transposed copy (tblk == NULL: the gather runs one lane
+     * group per cell).  Blocks are runs of at most 64 consecutive cells whose entries start
+     * within one stretch of 512 entries; block i is (first cell, first entry) at
+     * tblk[2i], tblk[2i+1], and the pair after the last block, and every later one up to
+     * index n_tblk, is (Ng*Ng, nnz).  One wavefront sums one block.  n_tblk comes from
+     * wp_gather_table_size; wp_build_G_fill writes the table with the transposed copy. */
+    int64_t *tblk;     /* [2*(n_tblk+1)] device                                      */
+    int64_t  n_tblk;
 } wp_G;
 
 /* Last error message of this thread ("" if none). */
@@ -118,13 +126,19 @@ wp_status wp_plan_destroy(wp_plan *plan);
  * "degrid_lanes", "degrid_unroll", "gather_lanes", "gather_unroll"; value 0
  * restores the automatic choice.  Lanes per row / cell: 4, 8, 16, 32 or 64;
  * loads in flight per lane: 4, 8 or 16 (not every pair exists: an apply with
- * an unavailable pair returns WP_EINVAL).  Not thread-safe with concurrent
+ * an unavailable pair returns WP_EINVAL); the gather knobs apply to the form
+ * without a block table.  "gather_chunk": entries a wavefront of the blocked
+ * gather stages at a time (256, 512 or 1024).  Not thread-safe with concurrent
  * applies on the same plan.
  */
 wp_status wp_plan_set_tuning(wp_plan *plan, const char *key, int value);
 
 /* Ng and the bytes of the Ng x Ng c64 grid workspace every apply needs. */
 wp_status wp_plan_info(const wp_plan *plan, int64_t *Ng_out, int64_t *grid_bytes_out);
+
+/* n_tblk of a G with nnz taps: an upper bound on its number of gather blocks (the table
+ * has 2*(n_tblk+1) int64 entries). */
+wp_status wp_gather_table_size(const wp_plan *plan, int64_t nnz, int64_t *n_tblk_out);
 
 /* Bytes of device workspace wp_build_G_count / wp_build_G_fill need for M visibilities. */
 wp_status wp_build_workspace_bytes(const wp_plan *plan, int64_t M, int64_t *bytes_out);
@@ -150,7 +164,9 @@ wp_status wp_build_G_count(const wp_plan *plan, int64_t M, const double *u, cons
 
 /*
  * Build G, pass 2 of 2: writes G->rowptr, G->perm, G->col, G->val, G->work,
- * and, when G->tcolptr is not NULL, the transposed copy (tcolptr, trow, tval).
+ * and, when G->tcolptr is not NULL, the transposed copy (tcolptr, trow, tval) and,
+ * when G->tblk is not NULL too, its block table (G->n_tblk must then equal
+ * wp_gather_table_size's value, else WP_EINVAL).
  * The caller sets G->M = M, G->nnz and G->n_work from pass 1, G->taps, and
  * points the arrays at buffers of the sizes listed in wp_G.  Same u, v, w, E
  * and workspace as pass 1 (pass 2 also uses part of it as scratch).
@@ -182,8 +198,9 @@ wp_status wp_degrid(const wp_plan *plan, const wp_G *G, const void *grid, void *
 /* grid = G^H y (gridding: tile-binned scatter, LDS accumulation, atomics at tile borders) */
 wp_status wp_grid_scatter(const wp_plan *plan, const wp_G *G, const void *y, void *grid,
                           void *stream);
-/* grid = G^H y from the transposed copy (one lane group per grid cell, no atomics,
- * deterministic); needs G->tcolptr. */
+/* grid = G^H y from the transposed copy (no atomics, deterministic); needs G->tcolptr.
+ * With G->tblk and fewer than 512 entries per cell on average, one wavefront per block
+ * of cells; else one lane group per cell. */
 wp_status wp_grid_gather(const wp_plan *plan, const wp_G *G, const void *y, void *grid,
                          void *stream);
 

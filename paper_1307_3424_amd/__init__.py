@@ -109,7 +109,10 @@ class GMatrix:
     trow: object = None
     tval: object = None
     rscale: object = None
+    tblk: object = None              # block table of the transposed copy
+    n_tblk: int = 0
     use_transpose: bool = True
+    use_blocks: bool = True          # blocked gather when the table exists
     order: int = WP_ORDER_CALLER     # order of the visibility vectors passed with this G
 
     def desc(self, transpose=None) -> _lib.WpG:
@@ -122,11 +125,13 @@ class GMatrix:
         use = self.use_transpose if transpose is None else transpose
         if use and self.tcolptr is not None:
             d.tcolptr, d.trow, d.tval = self.tcolptr.data_ptr(), self.trow.data_ptr(), self.tval.data_ptr()
+            if self.use_blocks and self.tblk is not None:
+                d.tblk, d.n_tblk = self.tblk.data_ptr(), self.n_tblk
         return d
 
     def nbytes(self) -> int:
         ts = [self.rowptr, self.col, self.val, self.perm, self.work, self.tcolptr, self.trow, self.tval,
-              self.rscale]
+              self.rscale, self.tblk]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
@@ -163,6 +168,10 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: b
         G.tcolptr = torch.empty(plan.Ng * plan.Ng + 1, dtype=torch.int64, device=dev)
         G.trow = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
         G.tval = torch.empty_like(G.val)
+        nt = C.c_int64()
+        check(lib.wp_gather_table_size(plan.handle, nnz.value, C.byref(nt)), "wp_gather_table_size")
+        G.n_tblk = nt.value
+        G.tblk = torch.empty(2 * (nt.value + 1), dtype=torch.int64, device=dev)
     d = G.desc()
     check(lib.wp_build_G_fill(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws), C.byref(d), s),
           "wp_build_G_fill")

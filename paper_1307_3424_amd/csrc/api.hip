@@ -54,7 +54,12 @@ wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
     if (need_work && G->n_work > 0x7fffffff) return wp_set_error(WP_ECAPACITY, "G->n_work too large");
     if (G->tcolptr && G->nnz > 0 && (!G->trow || !G->tval))
         return wp_set_error(WP_EINVAL, "G->tcolptr set without trow / tval");
-    (void)p;
+    if (G->tblk && !G->tcolptr) return wp_set_error(WP_EINVAL, "G->tblk set without the transposed copy");
+    if (G->tblk && p) {
+        const int64_t want = gather_table_slots(G->nnz, (int64_t)p->Ng * p->Ng);
+        if (G->n_tblk != want)
+            return wp_set_error(WP_EINVAL, "G->n_tblk = %lld, expected %lld", (long long)G->n_tblk, (long long)want);
+    }
     return WP_OK;
 }
 }  // namespace
@@ -151,6 +156,12 @@ wp_status wp_plan_destroy(wp_plan *p) {
 wp_status wp_plan_set_tuning(wp_plan *p, const char *key, int value) {
     if (wp_status s = check_plan(p)) return s;
     if (!key) return wp_set_error(WP_EINVAL, "key is NULL");
+    if (!std::strcmp(key, "gather_chunk")) {
+        if (value != 0 && value != 256 && value != 512 && value != 1024)
+            return wp_set_error(WP_EINVAL, "gather_chunk %d: 0, 256, 512 or 1024", value);
+        p->tune_gather_chunk = value;
+        return WP_OK;
+    }
     if (value < 0 || value > 64) return wp_set_error(WP_EINVAL, "tuning value %d out of range", value);
     if (!std::strcmp(key, "degrid_lanes")) p->tune_degrid_lpr = value;
     else if (!std::strcmp(key, "degrid_unroll")) p->tune_degrid_u = value;
@@ -164,6 +175,14 @@ wp_status wp_plan_info(const wp_plan *p, int64_t *Ng_out, int64_t *grid_bytes_ou
     if (wp_status s = check_plan(p)) return s;
     if (Ng_out) *Ng_out = p->Ng;
     if (grid_bytes_out) *grid_bytes_out = (int64_t)p->Ng * p->Ng * 8;
+    return WP_OK;
+}
+
+wp_status wp_gather_table_size(const wp_plan *p, int64_t nnz, int64_t *n) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!n) return wp_set_error(WP_EINVAL, "n_tblk_out is NULL");
+    if (nnz < 0) return wp_set_error(WP_EINVAL, "nnz < 0");
+    *n = gather_table_slots(nnz, (int64_t)p->Ng * p->Ng);
     return WP_OK;
 }
 

@@ -627,11 +627,39 @@ __global__ void k_t_sort(const int64_t *__restrict__ tcolptr, int64_t cells, int
     }
 }
 
+// gather blocks: flag the cells that start a block ...
+__global__ void k_gb_flags(const int64_t *__restrict__ tcolptr, int64_t cells, int *__restrict__ flag) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells) return;
+    const int64_t slot = tcolptr[c] / GB_ENT + c / GB_CELLS;
+    flag[c] = (c == 0 || slot != tcolptr[c - 1] / GB_ENT + (c - 1) / GB_CELLS) ? 1 : 0;
+}
+
+// ... and write (first cell, first entry) of block pos[c] for each of them; the pairs from the
+// block count up to index n_tblk are (cells, nnz)
+__global__ void k_gb_write(const int64_t *__restrict__ tcolptr, const int *__restrict__ flag,
+                           const int *__restrict__ pos, int64_t cells, int64_t nnz, int64_t n_tblk,
+                           int64_t *__restrict__ tblk) {
+    const int64_t n = cells > n_tblk + 1 ? cells : n_tblk + 1;
+    const int64_t total = pos[cells];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < cells && flag[i]) {
+            const int64_t b = pos[i];
+            tblk[2 * b] = i;
+            tblk[2 * b + 1] = tcolptr[i];
+        }
+        if (i >= total && i <= n_tblk) {
+            tblk[2 * i] = cells;
+            tblk[2 * i + 1] = nnz;
+        }
+    }
+}
+
 inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct WsLayout {
     int64_t tau, nnz, key, k0, k1, i0, i1, flags, zpos, snnz, rowptr, sc32, sc64, tstart, tend, nch, choff, err,
-        tcnt, sc64t, total;
+        tcnt, sc64t, gpos, total;
 };
 
 WsLayout ws_layout(const wp_plan *p, int64_t M) {
@@ -660,6 +688,7 @@ WsLayout ws_layout(const wp_plan *p, int64_t M) {
     const int64_t cells = (int64_t)p->Ng * p->Ng;
     L.tcnt = take(4 * cells);
     L.sc64t = take(8 * scan_scratch_elems(cells));
+    L.gpos = take(4 * (cells + 1));
     L.total = o;
     return L;
 }
@@ -866,6 +895,18 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
             hipLaunchKernelGGL((k_t_sort<float2>), gC, dim3(nthr), 0, s, G->tcolptr, cells, G->trow,
                                (float2 *)G->tval);
         if ((st = wp_check_launch("build_G_fill transpose")) != WP_OK) return st;
+        if (G->tblk) {
+            // cnt (free again) holds the block-start flags; their scan gives each block's index
+            hipLaunchKernelGGL(k_gb_flags, gC, dim3(nthr), 0, s, G->tcolptr, cells, cnt);
+            int *gpos = (int *)(ws + L.gpos);
+            device_scan<int, int>(cnt, gpos, cells, (int *)(ws + L.sc64t), s);
+            const int64_t n = cells > G->n_tblk + 1 ? cells : G->n_tblk + 1;
+            int64_t nb = (n + nthr - 1) / nthr;
+            if (nb > 65536) nb = 65536;
+            hipLaunchKernelGGL(k_gb_write, dim3((unsigned)nb), dim3(nthr), 0, s, G->tcolptr, cnt, gpos, cells,
+                               G->nnz, G->n_tblk, G->tblk);
+            if ((st = wp_check_launch("build_G_fill gather blocks")) != WP_OK) return st;
+        }
     }
     return WP_OK;
 }

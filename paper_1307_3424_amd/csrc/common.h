@@ -25,6 +25,7 @@ struct wp_plan {
     int device;
     int tune_degrid_lpr, tune_degrid_u;   // 0: automatic (see spmv.hip)
     int tune_gather_lpr, tune_gather_u;
+    int tune_gather_chunk;                // entries per chunk of the blocked gather (256, 512, 1024)
     float *apod;    // [N]  1 / g(xi), xi = (p - N/2) / Ng       (device)
     float2 *tw32;   // [Ng] exp(-2 pi i k / Ng), FP32             (device)
     double2 *tw64;  // [Ng] exp(-2 pi i k / Ng), FP64             (device)
@@ -119,6 +120,16 @@ __host__ __device__ inline void demorton2(int code, int &v, int &u) {
         v |= ((code >> (2 * b + 1)) & 1) << b;
     }
 }
+
+// ---------------------------------------------------------------------------- gather blocks
+// The blocked gather walks the transposed copy in runs of consecutive grid cells: cell c starts
+// a block when slot(c) = floor(tcolptr[c] / GB_ENT) + floor(c / GB_CELLS) differs from
+// slot(c - 1).  Both terms are non-decreasing in c, so a block holds at most GB_CELLS cells
+// whose entries start within one stretch of GB_ENT entries (its last cell may run past it),
+// and there are at most gather_table_slots blocks.
+constexpr int GB_ENT = 512;
+constexpr int GB_CELLS = 64;
+inline int64_t gather_table_slots(int64_t nnz, int64_t cells) { return nnz / GB_ENT + (cells - 1) / GB_CELLS + 1; }
 
 // ---------------------------------------------------------------------------- launchers (host)
 

@@ -12,6 +12,9 @@
 //   window go straight to global atomics; the window is then added to the grid
 //   with one global atomic per non-zero cell, so global atomics happen only
 //   where work items overlap (tile borders and halos).
+// Gather  the same product from the transposed copy, every cell written once: one
+//   wavefront per block of short cells (full-wave loads whatever the cell lengths),
+//   or one lane group per cell when cells are long.
 #include "common.h"
 
 namespace {
@@ -182,6 +185,90 @@ __global__ __launch_bounds__(SP_NTH) void k_gather(const int64_t *__restrict__ t
     if (sub == 0 && c < cells) grid[c] = make_float2(ar, ai);
 }
 
+// Blocked gather form of G^H: one wavefront per block of the block table (at most GB_CELLS
+// consecutive cells, entries starting within GB_ENT).  The wave streams the block's entries in
+// chunks of GB_ENT with unit stride across its lanes, forms conj(G) y, and parks the products in
+// its own LDS slice; then groups of L lanes (L = 64 / cells, rounded to a power of two) each sum
+// one cell's stretch of the chunk.  Every load instruction carries a full wave of entries
+// whatever the cell lengths; no workgroup barrier, no atomics, one fixed summation order.
+constexpr int GW_WAVES = SP_NTH / 64;
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int TK, int CH>
+__global__ __launch_bounds__(SP_NTH) void k_gather_wave(const int64_t *__restrict__ tblk, int64_t nblk,
+                                                        const int64_t *__restrict__ tcolptr,
+                                                        const int *__restrict__ trow, const void *__restrict__ tval,
+                                                        const float *__restrict__ rscale,
+                                                        const float2 *__restrict__ y, const int *__restrict__ perm,
+                                                        float2 *__restrict__ grid) {
+    __shared__ float2 s_p[GW_WAVES][CH];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t bi = (int64_t)blockIdx.x * GW_WAVES + wv;
+    if (bi >= nblk) return;               // waves leave on their own: nothing below syncs the workgroup
+    const int64_t ca = tblk[2 * bi], ea = tblk[2 * bi + 1], cb = tblk[2 * bi + 2], eb = tblk[2 * bi + 3];
+    const int nc = (int)(cb - ca);
+    if (nc <= 0) return;
+    int L = 64;
+    while (L > 1 && L * nc > 64) L >>= 1;
+    const int q = lane / L, sub = lane & (L - 1);
+    int64_t qb = 0, qe = 0;               // entries of this lane group's cell
+    if (q < nc) {
+        qb = tcolptr[ca + q];
+        qe = tcolptr[ca + q + 1];
+    }
+    float2 *sp = s_p[wv];
+    float ar = 0.f, ai = 0.f;
+    for (int64_t c0 = ea; c0 < eb; c0 += CH) {
+        const int n = (int)min((int64_t)CH, eb - c0);
+        constexpr int PER = CH / 64;
+        int k[PER];
+        float2 v[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = t * 64 + lane;
+            if (e < n) {
+                k[t] = trow[c0 + e];
+                v[t] = load_tap_raw<TK>(tval, c0 + e);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int e = t * 64 + lane;
+            if (e < n) {
+                const int r = k[t];
+                float2 g = v[t];
+                if constexpr (TK == WP_TAPS_I16) {
+                    const float sc = rscale[r];
+                    g.x *= sc;
+                    g.y *= sc;
+                }
+                const float2 yk = y[perm ? perm[r] : r];
+                sp[e] = make_float2(fmaf(g.x, yk.x, g.y * yk.y), fmaf(g.x, yk.y, -g.y * yk.x));   // conj(G) y
+            }
+        }
+        wave_sync();
+        if (q < nc) {
+            const int lo = (int)(max(qb, c0) - c0), hi = (int)(min(qe, c0 + n) - c0);
+            for (int e = lo + sub; e < hi; e += L) {
+                const float2 p = sp[e];
+                ar += p.x;
+                ai += p.y;
+            }
+        }
+        wave_sync();                      // the next chunk overwrites the slice
+    }
+    for (int o = L / 2; o > 0; o >>= 1) {
+        ar += __shfl_xor(ar, o);
+        ai += __shfl_xor(ai, o);
+    }
+    if (sub == 0 && q < nc) grid[ca + q] = make_float2(ar, ai);
+}
+
 __global__ void k_permute(const float2 *__restrict__ in, const int *__restrict__ perm, float2 *__restrict__ out,
                           int64_t M, bool to_sorted) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -270,9 +357,30 @@ wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, flo
 wp_status launch_gather(const wp_plan *p, const wp_G *G, const float2 *y, float2 *grid, hipStream_t s) {
     const int64_t cells = (int64_t)p->Ng * p->Ng;
     if (G->nnz == 0) return launch_fill_zero((float *)grid, 2 * cells, s);
+    // measured on MI355X: blocks win while cells are short (26 entries: 20 vs 31 us; 210: 9.0 vs
+    // 9.1 ms); with ~900 entries per cell the lane groups already run full and win (9.6 vs 10.2 ms)
+    const double mean = (double)G->nnz / (double)cells;
+    if (G->tblk && mean < 512.0) {
+        const int64_t nblk = G->n_tblk;
+        const dim3 gb((unsigned)((nblk + GW_WAVES - 1) / GW_WAVES));
+        const int ch = p->tune_gather_chunk > 0 ? p->tune_gather_chunk : 512;
+#define WP_GW(TKV, CHV) hipLaunchKernelGGL((k_gather_wave<TKV, CHV>), gb, dim3(SP_NTH), 0, s, G->tblk, nblk, \
+                                           G->tcolptr, G->trow, G->tval, G->rscale, y, yperm(G), grid)
+#define WP_GW_CH(TKV)                                    \
+    do {                                                 \
+        if (ch == 256) WP_GW(TKV, 256);                  \
+        else if (ch == 1024) WP_GW(TKV, 1024);           \
+        else WP_GW(TKV, 512);                            \
+    } while (0)
+        if (G->taps == WP_TAPS_BF16) WP_GW_CH(WP_TAPS_BF16);
+        else if (G->taps == WP_TAPS_I16) WP_GW_CH(WP_TAPS_I16);
+        else WP_GW_CH(WP_TAPS_C64);
+#undef WP_GW_CH
+#undef WP_GW
+        return wp_check_launch("grid_gather blocks");
+    }
     // measured on MI355X: 32 lanes per cell; 4 loads in flight for cells of ~25 entries,
     // 16 for cells of ~900
-    const double mean = (double)G->nnz / (double)cells;
     const int U = p->tune_gather_u > 0 ? p->tune_gather_u : (mean < 128 ? 4 : (mean < 512 ? 8 : 16));
     const int lpr = p->tune_gather_lpr > 0 ? p->tune_gather_lpr : (mean < 12 ? 16 : 32);
     if (!valid_lpr_u(lpr, U)) return wp_set_error(WP_EINVAL, "gather: no kernel for lanes %d, unroll %d", lpr, U);

@@ -461,6 +461,8 @@ wp_status check_fallback(const wp_surrogate *S, const wp_G *Gf) {
     if (!Gf) return wp_set_error(WP_EINVAL, "%lld fallback rows need their exact G", (long long)S->Mf);
     if (Gf->M != S->Mf) return wp_set_error(WP_EINVAL, "fallback G has %lld rows, expected %lld", (long long)Gf->M,
                                             (long long)S->Mf);
+    if (Gf->tblk && (!Gf->tcolptr || Gf->n_tblk != gather_table_slots(Gf->nnz, (int64_t)1 << (2 * S->logNg))))
+        return wp_set_error(WP_EINVAL, "fallback G: block table without the transposed copy or of the wrong size");
     return WP_OK;
 }
 

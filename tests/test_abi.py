@@ -61,8 +61,19 @@ def test_null_arguments_rejected():
     assert lib.wp_plan_destroy(None) == 0
 
 
-def test_wp_G_layout_matches_header():
-    assert C.sizeof(_lib.WpG) == 8 * 2 + 4 * 2 + 8 * 5 + 8 + 8 + 8 * 3
+def test_wp_G_layout_matches_header(tmp_path):
+    """Size and field offsets of the binding's wp_G equal what a C compiler makes of the header."""
+    import subprocess
+    fields = [f for f, _ in _lib.WpG._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"wproj.h\"\nint main(void) {\n"
+                   + 'printf("%zu\\n", sizeof(wp_G));\n'
+                   + "".join(f'printf("%zu\\n", offsetof(wp_G, {f}));\n' for f in fields) + "return 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert out[0] == C.sizeof(_lib.WpG)
+    assert out[1:] == [getattr(_lib.WpG, f).offset for f in fields]
 
 
 def test_library_db8_filter_matches_oracle_derivation():

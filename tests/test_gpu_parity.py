@@ -174,13 +174,59 @@ def test_gather_and_scatter_grid_match_oracle(taps):
     yv = synth.random_complex(wl.M, synth.rng_for(wl.seed, "y", 5))
     Xg = wp.grid_gather(plan, G, c64(yv)).cpu().numpy()
     Xs = wp.grid_scatter(plan, G, c64(yv)).cpu().numpy()
+    G.use_blocks = False                   # one lane group per cell instead of the block table
+    Xc = wp.grid_gather(plan, G, c64(yv)).cpu().numpy()
+    G.use_blocks = True
     Go = wproj.build_rows(u, v, w, wl.E, s)
     X_ref = Go.conj().T @ yv
     tol = {"c64": TOL, "bf16": 4e-3, "i16": 1e-4}[taps]
-    assert relerr(Xg, X_ref) < tol and relerr(Xs, X_ref) < tol
-    assert relerr(Xg, Xs) < 1e-5
+    assert relerr(Xg, X_ref) < tol and relerr(Xs, X_ref) < tol and relerr(Xc, X_ref) < tol
+    assert relerr(Xg, Xs) < 1e-5 and relerr(Xg, Xc) < 1e-5
     x = synth.sky(wl.N, 4, 6, synth.rng_for(wl.seed, "sky", 5))
     assert relerr(wp.apply_Phi(plan, G, c64(x)).cpu().numpy(), wproj.phi(Go, x, s)) < tol
+
+
+def gather_table_model(tcp, cells, B=512, CAP=64):
+    """Block table of the transposed copy as the header defines it, from tcolptr."""
+    nnz = int(tcp[-1])
+    nslot = nnz // B + (cells - 1) // CAP + 1
+    c = np.arange(cells)
+    slot = tcp[:cells] // B + c // CAP
+    first = np.ones(cells, dtype=bool)
+    first[1:] = slot[1:] != slot[:-1]
+    t = np.empty((nslot + 1, 2), dtype=np.int64)
+    nb = int(first.sum())
+    t[:nb, 0], t[:nb, 1] = c[first], tcp[:cells][first]
+    t[nb:] = (cells, nnz)
+    return t.ravel()
+
+
+def test_gather_with_crowded_cells():
+    """6000 visibilities within a 3 x 3 cell patch: cells hold up to ~5800 entries (many passes of
+    each lane group) while most of the grid is empty."""
+    N, M = 64, 6000
+    say(f"gather: crowded cells N={N} M={M}")
+    s = Setup(N=N, L=L)
+    rng = np.random.default_rng(3)
+    du = 1 / (2 * L)
+    u = (rng.uniform(-1.5, 1.5, M) + 10.3) * du
+    v = (rng.uniform(-1.5, 1.5, M) - 7.6) * du
+    w = rng.uniform(0, 0.15 * N / (2 * L * L), M)
+    plan = wp.Plan(N, L)
+    G = build(plan, u, v, w, 0.99)
+    tcp = G.tcolptr.cpu().numpy()
+    assert np.diff(tcp).max() > 4096               # single cells span many chunks of a block
+    assert np.array_equal(G.tblk.cpu().numpy(), gather_table_model(tcp, s.Ng ** 2))
+    Go = wproj.build_rows(u, v, w, 0.99, s)
+    assert abs(G.nnz - Go.nnz) <= 1e-6 * Go.nnz
+    yv = synth.random_complex(M, synth.rng_for(1, "y", 9))
+    X_ref = Go.conj().T @ yv
+    Xg = wp.grid_gather(plan, G, c64(yv)).cpu().numpy()
+    Xs = wp.grid_scatter(plan, G, c64(yv)).cpu().numpy()
+    G.use_blocks = False
+    Xc = wp.grid_gather(plan, G, c64(yv)).cpu().numpy()
+    assert relerr(Xg, X_ref) < TOL and relerr(Xs, X_ref) < TOL and relerr(Xc, X_ref) < TOL
+    assert np.all(Xg[X_ref == 0] == 0)             # empty cells are written as zeros
 
 
 def test_transposed_copy_structure():
@@ -200,6 +246,7 @@ def test_transposed_copy_structure():
     assert np.array_equal(col[a], cells_t)
     assert np.array_equal(rows_of[a], trow)
     assert np.array_equal(val[a], tval)
+    assert np.array_equal(G.tblk.cpu().numpy(), gather_table_model(tcp, wl.Ng ** 2))
 
     wl = synth.workload(1)
     say(f"apply: {wl.name} full size, sampled outputs")
