@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", type=int, default=1)
     ap.add_argument("--taps", choices=["c64", "bf16", "i16"], default="c64")
+    ap.add_argument("--phi", choices=["auto", "factors", "stored"], default="auto",
+                    help="exact forms: Phi from the factor records (taps formed in registers), from the stored "
+                         "taps, or whichever degrid times faster before the timed loop")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=384)
     ap.add_argument("--no-solve", action="store_true")
@@ -51,6 +54,12 @@ def parse():
 def degrid_bytes(G, M, Ng, tap_bytes):
     """Algorithmic HBM bytes of one degrid launch: taps + indices once, rowptr, perm, y, one grid read."""
     return G.nnz * (tap_bytes + 4) + (M + 1) * 8 + M * 4 + M * 8 + Ng * Ng * 8
+
+
+def factor_degrid_bytes(G, M, Ng):
+    """Algorithmic HBM bytes of one degrid from factor records: the records once, their offsets,
+    y, one grid read."""
+    return G.fdat.numel() + (M + 1) * 8 + M * 8 + Ng * Ng * 8
 
 
 def scatter_bytes(G, M, Ng, tap_bytes):
@@ -267,7 +276,7 @@ def bench_surrogate(args, wl):
     # ---- exact form
     sync()
     t0 = time.perf_counter()
-    G = wp.build_G(plan, ud, vd, wd, wl.E)
+    G = wp.build_G(plan, ud, vd, wd, wl.E, factors=True)
     sync()
     build_s = time.perf_counter() - t0
     G.order = wp.WP_ORDER_SORTED
@@ -322,7 +331,7 @@ def bench_surrogate(args, wl):
     Gf = None
     if sur.Mf:
         fu, fv, fw = sur.fallback_coords()
-        Gf = wp.build_G(plan, fu, fv, fw, wl.E)
+        Gf = wp.build_G(plan, fu, fv, fw, wl.E, factors=True)
         Gf.order = wp.WP_ORDER_SORTED
         del fu, fv, fw
     sync()
@@ -456,10 +465,11 @@ def main():
     ud, vd, wd = t(u), t(v), t(w)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    G = wp.build_G(plan, ud, vd, wd, wl.E, taps=taps)
+    G = wp.build_G(plan, ud, vd, wd, wl.E, taps=taps, factors=True)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    log(f"bench: G built in {build_s:.3f} s, nnz={G.nnz} ({G.nnz / wl.M:.1f}/vis), work items {G.n_work}")
+    log(f"bench: G built in {build_s:.3f} s, nnz={G.nnz} ({G.nnz / wl.M:.1f}/vis), work items {G.n_work}, "
+        f"factor records {G.fdat.numel() / wl.M:.0f} B/vis")
     xd = t(x.astype(np.complex64).ravel())
     yd = torch.empty(wl.M, dtype=torch.complex64, device=dev)
     xa = torch.empty(wl.N * wl.N, dtype=torch.complex64, device=dev)
@@ -468,6 +478,18 @@ def main():
     # visibility vectors stay in G's sorted row order inside the timed loop (an iterative
     # solver permutes its data vector once); the caller-order cost is reported beside it
     G.order = wp.WP_ORDER_SORTED
+    if args.phi == "auto":
+        # autotune: the faster degrid form on this workload, timed before the timed loop
+        wp.grid_forward(plan, xd, grid)
+        reps = 20 if wl.M < 1 << 20 else 3
+        tf = {}
+        for fac in (True, False, True, False):
+            G.use_factors = fac
+            tf[fac] = min(tf.get(fac, 1e30), time_region(lambda: wp.degrid(plan, G, grid, yd), reps, stream, torch))
+        G.use_factors = tf[True] < tf[False]
+    else:
+        G.use_factors = args.phi == "factors"
+    log(f"bench: Phi from {'factor records' if G.use_factors else 'stored taps'}")
 
     def step():
         wp.apply_Phi(plan, G, xd, yd, grid)
@@ -485,6 +507,10 @@ def main():
     ms_fwd = time_region(lambda: wp.grid_forward(plan, xd, grid), ks, stream, torch)
     wp.grid_forward(plan, xd, grid)
     ms_deg = time_region(lambda: wp.degrid(plan, G, grid, yd), ks, stream, torch)
+    G.use_factors = not G.use_factors          # the other form of the degrid, for comparison
+    ms_deg_alt = time_region(lambda: wp.degrid(plan, G, grid, yd), ks, stream, torch)
+    G.use_factors = not G.use_factors
+    ms_deg_f, ms_deg_s = (ms_deg, ms_deg_alt) if G.use_factors else (ms_deg_alt, ms_deg)
     ms_sc = time_region(lambda: wp.grid_scatter(plan, G, yd, grid), ks, stream, torch)
     ms_ga = time_region(lambda: wp.grid_gather(plan, G, yd, grid), ks, stream, torch)
     G.use_transpose = False
@@ -494,7 +520,9 @@ def main():
     G.order = wp.WP_ORDER_CALLER
     ms_caller = time_region(step, ks, stream, torch)
     G.order = wp.WP_ORDER_SORTED
-    db = degrid_bytes(G, wl.M, plan.Ng, tap_bytes)
+    db_s = degrid_bytes(G, wl.M, plan.Ng, tap_bytes)
+    db_f = factor_degrid_bytes(G, wl.M, plan.Ng)
+    db = db_f if G.use_factors else db_s
     sb = scatter_bytes(G, wl.M, plan.Ng, tap_bytes)
     deg_gbs = db / (ms_deg * 1e-3) / 1e9
     sc_gbs = sb / (ms_sc * 1e-3) / 1e9
@@ -509,15 +537,18 @@ def main():
         f"degrid {ms_deg * 1e3:.1f} us ({deg_gbs:.0f} GB/s), scatter+zero {ms_sc * 1e3:.1f} us ({sc_gbs:.0f} GB/s), "
         f"gather {ms_ga * 1e3:.1f} us ({ga_gbs:.0f} GB/s), Phi^H via scatter {ms_phit_sc * 1e3:.1f} us, "
         f"adj FFT {ms_adj * 1e3:.1f} us")
+    deg_kernel = "k_degrid_sep" if G.use_factors else "k_degrid"
+    deg_label = ("degrid (Phi sparse product, taps formed from factor records)" if G.use_factors
+                 else "degrid (Phi sparse product, stored taps)")
     # the roofline object describes the sparse product that takes longest in a step
     if ms_ga >= ms_deg:
         dominant = {"bound": "hbm", "kernel": ga_label, "achieved": ga_gbs,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ga_gbs / HBM_PEAK_GBS,
                     "traffic": profiled_traffic(wl.name, ga_kernel), "bytes_per_launch": gb, "launch_us": ms_ga * 1e3}
     else:
-        dominant = {"bound": "hbm", "kernel": "degrid (Phi sparse product)", "achieved": deg_gbs,
+        dominant = {"bound": "hbm", "kernel": deg_label, "achieved": deg_gbs,
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": deg_gbs / HBM_PEAK_GBS,
-                    "traffic": profiled_traffic(wl.name, "k_degrid"), "bytes_per_launch": db, "launch_us": ms_deg * 1e3}
+                    "traffic": profiled_traffic(wl.name, deg_kernel), "bytes_per_launch": db, "launch_us": ms_deg * 1e3}
     out = {
         "metric": "visibilities/s for Phi+Phi† (exact vs surrogate kernels) and % HBM roofline",
         "value": wl.M / (ms * 1e-3),
@@ -528,11 +559,17 @@ def main():
                   "i16": "int16x2-block-float-taps/f32-accumulate"}[args.taps],
         "data": "synthetic (seeded sky and baselines; the paper's M31 / 30Dor images are not used)",
         "config": {"workload": wl.name, "N": wl.N, "Ng": plan.Ng, "M": wl.M, "E": wl.E, "kb_W": wl.W,
-                   "uv": f"{wl.uv} sigma={wl.uv_sigma}B", "w_top": wl.w_top, "kernel": "exact (stored G)",
-                   "nnz": G.nnz, "nnz_per_vis": G.nnz / wl.M, "G_bytes": G.nbytes()},
+                   "uv": f"{wl.uv} sigma={wl.uv_sigma}B", "w_top": wl.w_top,
+                   "kernel": ("exact: Phi from factor records, Phi^H from the transposed copy" if G.use_factors
+                              else "exact: stored G, Phi^H from the transposed copy"),
+                   "nnz": G.nnz, "nnz_per_vis": G.nnz / wl.M, "G_bytes": G.nbytes(),
+                   "factor_record_bytes": G.fdat.numel()},
         "roofline": dominant,
-        "degrid_roofline": {"achieved": deg_gbs, "frac": deg_gbs / HBM_PEAK_GBS, "bytes_per_launch": db,
-                            "launch_us": ms_deg * 1e3, "traffic": profiled_traffic(wl.name, "k_degrid")},
+        "degrid_roofline": {"kernel": deg_label, "achieved": deg_gbs, "frac": deg_gbs / HBM_PEAK_GBS,
+                            "bytes_per_launch": db, "launch_us": ms_deg * 1e3,
+                            "traffic": profiled_traffic(wl.name, deg_kernel)},
+        "degrid_forms_us": {"factor_records": ms_deg_f * 1e3, "stored_taps": ms_deg_s * 1e3,
+                            "factor_records_bytes": db_f, "stored_taps_bytes": db_s},
         "stages_us": {"phi": ms_phi * 1e3, "phiT": ms_phit * 1e3, "grid_forward": ms_fwd * 1e3,
                       "degrid": ms_deg * 1e3, "gather": ms_ga * 1e3, "scatter_incl_zero": ms_sc * 1e3,
                       "grid_adjoint": ms_adj * 1e3, "phiT_via_scatter": ms_phit_sc * 1e3,

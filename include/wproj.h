@@ -99,6 +99,18 @@ typedef struct wp_G {
      * wp_gather_table_size; wp_build_G_fill writes the table with the transposed copy. */
     int64_t *tblk;     /* [2*(n_tblk+1)] device                                      */
     int64_t  n_tblk;
+    /* Optional factor records (frec == NULL: the degrid reads the stored taps).  The linear
+     * chirp and the KB window are separable, so row r is g_v(b) g_u(a) on the kept set
+     * {|g_v(b)|^2 |g_u(a)|^2 >= tau_r} (Sections 3.1 and 3.2); with the u candidates ordered by
+     * descending |g_u|^2 and the v candidates by descending |g_v|^2, v candidate i keeps the
+     * first nb[i] u candidates.  Record of sorted row r at fdat + frec[r] (multiple of 8):
+     * uint16 nu, nv; uint16 ua[nu] (u cells), vb[nv] (v cells), nb[nv]; zero padding to 8
+     * bytes; complex float gu[nu], gv[nv].  The kept cells are exactly those of the stored
+     * row; a tap is gv gu rounded to complex float before the product.  fbytes: size of
+     * fdat from wp_build_factor_bytes.  Written by wp_build_G_fill. */
+    int64_t *frec;     /* [M+1] device, byte offsets                                 */
+    void    *fdat;     /* [fbytes] device                                            */
+    int64_t  fbytes;
 } wp_G;
 
 /* Last error message of this thread ("" if none). */
@@ -128,13 +140,21 @@ wp_status wp_plan_destroy(wp_plan *plan);
  * loads in flight per lane: 4, 8 or 16 (not every pair exists: an apply with
  * an unavailable pair returns WP_EINVAL); the gather knobs apply to the form
  * without a block table.  "gather_chunk": entries a wavefront of the blocked
- * gather stages at a time (256, 512 or 1024).  Not thread-safe with concurrent
+ * gather stages at a time (256, 512 or 1024); "degrid_rows": rows per wavefront of
+ * the degrid from factor records (1, 2 or 4).  Not thread-safe with concurrent
  * applies on the same plan.
  */
 wp_status wp_plan_set_tuning(wp_plan *plan, const char *key, int value);
 
 /* Ng and the bytes of the Ng x Ng c64 grid workspace every apply needs. */
 wp_status wp_plan_info(const wp_plan *plan, int64_t *Ng_out, int64_t *grid_bytes_out);
+
+/* Bytes of the factor records of the visibilities counted by the last wp_build_G_count on
+ * this workspace (same plan and M); also lays out the records' offsets in the workspace.
+ * Call between wp_build_G_count and wp_build_G_fill when G->frec / G->fdat are wanted.
+ * Synchronises the stream. */
+wp_status wp_build_factor_bytes(const wp_plan *plan, int64_t M, void *workspace, int64_t *bytes_out,
+                                void *stream);
 
 /* n_tblk of a G with nnz taps: an upper bound on its number of gather blocks (the table
  * has 2*(n_tblk+1) int64 entries). */
@@ -166,7 +186,8 @@ wp_status wp_build_G_count(const wp_plan *plan, int64_t M, const double *u, cons
  * Build G, pass 2 of 2: writes G->rowptr, G->perm, G->col, G->val, G->work,
  * and, when G->tcolptr is not NULL, the transposed copy (tcolptr, trow, tval) and,
  * when G->tblk is not NULL too, its block table (G->n_tblk must then equal
- * wp_gather_table_size's value, else WP_EINVAL).
+ * wp_gather_table_size's value, else WP_EINVAL); when G->frec and G->fdat are set, the
+ * factor records (G->fbytes must equal wp_build_factor_bytes's value, else WP_EINVAL).
  * The caller sets G->M = M, G->nnz and G->n_work from pass 1, G->taps, and
  * points the arrays at buffers of the sizes listed in wp_G.  Same u, v, w, E
  * and workspace as pass 1 (pass 2 also uses part of it as scratch).
@@ -193,7 +214,8 @@ wp_status wp_apply_PhiT(const wp_plan *plan, const wp_G *G, const void *y, void 
 wp_status wp_grid_forward(const wp_plan *plan, const void *x, void *grid, void *stream);
 /* x = A Z^H F^H grid  (grid is used as scratch and overwritten) */
 wp_status wp_grid_adjoint(const wp_plan *plan, void *grid, void *x, void *stream);
-/* y = G grid (degridding sparse matrix-vector product) */
+/* y = G grid (degridding sparse matrix-vector product; from the factor records when
+ * G->frec is set, taps formed in registers) */
 wp_status wp_degrid(const wp_plan *plan, const wp_G *G, const void *grid, void *y, void *stream);
 /* grid = G^H y (gridding: tile-binned scatter, LDS accumulation, atomics at tile borders) */
 wp_status wp_grid_scatter(const wp_plan *plan, const wp_G *G, const void *y, void *grid,

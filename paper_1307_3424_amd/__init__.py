@@ -113,6 +113,9 @@ class GMatrix:
     n_tblk: int = 0
     use_transpose: bool = True
     use_blocks: bool = True          # blocked gather when the table exists
+    frec: object = None              # factor records (separable rows) read by the degrid
+    fdat: object = None
+    use_factors: bool = True         # degrid from the factor records when they exist
     order: int = WP_ORDER_CALLER     # order of the visibility vectors passed with this G
 
     def desc(self, transpose=None) -> _lib.WpG:
@@ -122,6 +125,8 @@ class GMatrix:
         d.perm, d.work = self.perm.data_ptr(), self.work.data_ptr()
         if self.rscale is not None:
             d.rscale = self.rscale.data_ptr()
+        if self.use_factors and self.frec is not None:
+            d.frec, d.fdat, d.fbytes = self.frec.data_ptr(), self.fdat.data_ptr(), self.fdat.numel()
         use = self.use_transpose if transpose is None else transpose
         if use and self.tcolptr is not None:
             d.tcolptr, d.trow, d.tval = self.tcolptr.data_ptr(), self.trow.data_ptr(), self.tval.data_ptr()
@@ -131,15 +136,17 @@ class GMatrix:
 
     def nbytes(self) -> int:
         ts = [self.rowptr, self.col, self.val, self.perm, self.work, self.tcolptr, self.trow, self.tval,
-              self.rscale, self.tblk]
+              self.rscale, self.tblk, self.frec, self.fdat]
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
 def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: bool = True,
-            stream=None) -> GMatrix:
-    """wp_build_workspace_bytes + wp_build_G_count + wp_build_G_fill (u, v, w: float64 CUDA tensors).
+            factors: bool = False, stream=None) -> GMatrix:
+    """wp_build_workspace_bytes + wp_build_G_count (+ wp_build_factor_bytes) + wp_build_G_fill
+    (u, v, w: float64 CUDA tensors).
 
-    transpose: also build the transposed copy used by the gather form of G^H.
+    transpose: also build the transposed copy used by the gather form of G^H (and its block table).
+    factors: also build the factor records the degrid forms its taps from.
     """
     torch = _torch()
     lib = load()
@@ -164,6 +171,11 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: b
                 n_work=nwork.value)
     if taps == WP_TAPS_I16:
         G.rscale = torch.empty(M, dtype=torch.float32, device=dev)
+    if factors:
+        fb = C.c_int64()
+        check(lib.wp_build_factor_bytes(plan.handle, M, _ptr(ws), C.byref(fb), s), "wp_build_factor_bytes")
+        G.frec = torch.empty(M + 1, dtype=torch.int64, device=dev)
+        G.fdat = torch.empty(fb.value, dtype=torch.uint8, device=dev)
     if transpose:
         G.tcolptr = torch.empty(plan.Ng * plan.Ng + 1, dtype=torch.int64, device=dev)
         G.trow = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)

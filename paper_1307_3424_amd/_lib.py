@@ -30,7 +30,7 @@ class WpG(C.Structure):
     _fields_ = [("M", C.c_int64), ("nnz", C.c_int64), ("taps", C.c_int32), ("order", C.c_int32),
                 ("rowptr", _vp), ("col", _vp), ("val", _vp), ("perm", _vp), ("work", _vp),
                 ("n_work", C.c_int64), ("rscale", _vp), ("tcolptr", _vp), ("trow", _vp), ("tval", _vp),
-                ("tblk", _vp), ("n_tblk", C.c_int64)]
+                ("tblk", _vp), ("n_tblk", C.c_int64), ("frec", _vp), ("fdat", _vp), ("fbytes", C.c_int64)]
 
 
 _PG = C.POINTER(WpG)
@@ -43,6 +43,7 @@ SIGNATURES = {
     "wp_plan_info": ([_vp, _pi64, _pi64], _i32),
     "wp_plan_set_tuning": ([_vp, C.c_char_p, _i32], _i32),
     "wp_gather_table_size": ([_vp, _i64, _pi64], _i32),
+    "wp_build_factor_bytes": ([_vp, _i64, _vp, _pi64, _vp], _i32),
     "wp_build_workspace_bytes": ([_vp, _i64, _pi64], _i32),
     "wp_build_G_count": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _pi64, _pi64, _vp], _i32),
     "wp_build_G_fill": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _PG, _vp], _i32),

@@ -55,6 +55,7 @@ wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
     if (G->tcolptr && G->nnz > 0 && (!G->trow || !G->tval))
         return wp_set_error(WP_EINVAL, "G->tcolptr set without trow / tval");
     if (G->tblk && !G->tcolptr) return wp_set_error(WP_EINVAL, "G->tblk set without the transposed copy");
+    if ((G->frec == nullptr) != (G->fdat == nullptr)) return wp_set_error(WP_EINVAL, "G->frec and G->fdat go together");
     if (G->tblk && p) {
         const int64_t want = gather_table_slots(G->nnz, (int64_t)p->Ng * p->Ng);
         if (G->n_tblk != want)
@@ -162,6 +163,12 @@ wp_status wp_plan_set_tuning(wp_plan *p, const char *key, int value) {
         p->tune_gather_chunk = value;
         return WP_OK;
     }
+    if (!std::strcmp(key, "degrid_rows")) {
+        if (value != 0 && value != 1 && value != 2 && value != 4)
+            return wp_set_error(WP_EINVAL, "degrid_rows %d: 0, 1, 2 or 4", value);
+        p->tune_degrid_rows = value;
+        return WP_OK;
+    }
     if (value < 0 || value > 64) return wp_set_error(WP_EINVAL, "tuning value %d out of range", value);
     if (!std::strcmp(key, "degrid_lanes")) p->tune_degrid_lpr = value;
     else if (!std::strcmp(key, "degrid_unroll")) p->tune_degrid_u = value;
@@ -176,6 +183,13 @@ wp_status wp_plan_info(const wp_plan *p, int64_t *Ng_out, int64_t *grid_bytes_ou
     if (Ng_out) *Ng_out = p->Ng;
     if (grid_bytes_out) *grid_bytes_out = (int64_t)p->Ng * p->Ng * 8;
     return WP_OK;
+}
+
+wp_status wp_build_factor_bytes(const wp_plan *p, int64_t M, void *workspace, int64_t *bytes, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!workspace || !bytes) return wp_set_error(WP_EINVAL, "workspace or bytes_out is NULL");
+    if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    return launch_build_factor_bytes(p, M, workspace, bytes, as_stream(stream));
 }
 
 wp_status wp_gather_table_size(const wp_plan *p, int64_t nnz, int64_t *n) {

@@ -176,7 +176,8 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
                                                     double cell, double delta, int W, double beta, int tile,
                                                     int ntile, const double2 *__restrict__ tw64,
                                                     double *__restrict__ tau_out, int *__restrict__ nnz_out,
-                                                    int *__restrict__ key_out, int *__restrict__ err, int64_t r0) {
+                                                    int *__restrict__ key_out, int *__restrict__ fsz_out,
+                                                    int *__restrict__ err, int64_t r0) {
     constexpr int Ng = 1 << LOGNG;
     extern __shared__ __align__(16) unsigned char smem[];
     double2 *h = (double2 *)smem;                 // Ng double2, later PB (Ng+1 doubles)
@@ -197,6 +198,7 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
             tau_out[k] = INFINITY;
             nnz_out[k] = 0;
             key_out[k] = 0;
+            fsz_out[k] = factor_record_bytes(0, 0);
         }
         return;
     }
@@ -279,9 +281,23 @@ __global__ __launch_bounds__(BNTH) void k_row_count(const double *__restrict__ u
     }
     double Kt;
     kept_energy<LOGNG>(A, B, PB, tau, Kt, cnt, redd, redl);
+    // candidates of the factor record, with the fill pass's expressions: u cells with A_a bmax >= tau,
+    // v cells with amax B_b >= tau (B is sorted: B[0] = bmax)
+    double amax = 0.0;
+    for (int a = threadIdx.x; a < Ng; a += BNTH) amax = fmax(amax, A[a]);
+    amax = block_max(amax, redd);
+    const double bmax = B[0];
+    int na = 0, nb = 0;
+    for (int q = threadIdx.x; q < Ng; q += BNTH) {
+        na += (A[q] * bmax >= tau);
+        nb += (amax * B[q] >= tau);
+    }
+    na = block_sum(na, redi);
+    nb = block_sum(nb, redi);
     if (threadIdx.x == 0) {
         tau_out[k] = tau;
         nnz_out[k] = (int)cnt;
+        fsz_out[k] = factor_record_bytes(na, nb);
         // rows are sorted by the Z-order code of their centre cell (tiles of the scatter are then
         // contiguous ranges, and rows close in the uv plane are close in memory)
         const int cu = min(max((int)floor(ut + Ng / 2), 0), Ng - 1);
@@ -302,7 +318,8 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
                                                    const double2 *__restrict__ tw64, const double *__restrict__ tau_in,
                                                    const int *__restrict__ perm, const int64_t *__restrict__ rowptr,
                                                    int *__restrict__ col, void *__restrict__ val,
-                                                   float *__restrict__ rscale, int *__restrict__ err, int64_t r0) {
+                                                   float *__restrict__ rscale, const int64_t *__restrict__ frec,
+                                                   unsigned char *__restrict__ fdat, int *__restrict__ err, int64_t r0) {
     constexpr int Ng = 1 << LOGNG;
     constexpr int PER = (Ng + BNTH - 1) / BNTH;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -320,7 +337,10 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
     const int k = perm[r];
     const double tau = tau_in[k];
     const int64_t beg = rowptr[r], len = rowptr[r + 1] - beg;
-    if (len == 0) return;
+    if (len == 0) {
+        if (fdat && threadIdx.x == 0) *(uint2 *)(fdat + frec[r]) = make_uint2(0u, 0u);   // nu = nv = 0
+        return;
+    }
     const double ut = u[k] / cell, vt = v[k] / cell, wk = w[k];
     const Taps tu = kb_taps(ut, W, beta, Ng, s_wu);
     const Taps tv = kb_taps(vt, W, beta, Ng, s_wv);
@@ -393,6 +413,48 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
         }
         if (threadIdx.x == 0 && total != len) atomicOr(err, 2);
         __syncthreads();
+    }
+    // factor record: candidates ranked by descending energy (ties by ascending cell); a v candidate's
+    // kept u candidates are then the first nb of that order, nb = its tap count
+    if (fdat) {
+        unsigned char *rec = fdat + frec[r];
+        const int nu = nca, nv = ncb;
+        if ((int64_t)factor_record_bytes(nu, nv) != frec[r + 1] - frec[r]) {
+            if (threadIdx.x == 0) atomicOr(err, 4);
+        } else {
+            uint16_t *ua = (uint16_t *)rec + 2, *vb = ua + nu, *nbv = vb + nv;
+            const int vals = (4 + 2 * nu + 4 * nv + 7) & ~7;
+            float2 *gu = (float2 *)(rec + vals), *gv = gu + nu;
+            if (threadIdx.x == 0) {
+                *(uint32_t *)rec = (uint32_t)nu | ((uint32_t)nv << 16);
+                for (int z = 4 + 2 * nu + 4 * nv; z < vals; ++z) rec[z] = 0;
+            }
+            for (int ia = threadIdx.x; ia < nu; ia += BNTH) {
+                const int a = ca[ia];
+                const double Aa = A[a];
+                int rank = 0;
+                for (int j = 0; j < nu; ++j) {
+                    const double Aj = A[ca[j]];
+                    rank += (Aj > Aa) || (Aj == Aa && j < ia);
+                }
+                const double2 g = row_factor(h, tu, W, a, Ng);
+                ua[rank] = (uint16_t)a;
+                gu[rank] = make_float2((float)g.x, (float)g.y);
+            }
+            for (int ib = threadIdx.x; ib < nv; ib += BNTH) {
+                const int b = cb[ib];
+                const double2 g = row_factor(h, tv, W, b, Ng);
+                const double Bb = energy(g);
+                int rank = 0;
+                for (int j = 0; j < nv; ++j) {
+                    const double Bj = energy(row_factor(h, tv, W, cb[j], Ng));
+                    rank += (Bj > Bb) || (Bj == Bb && j < ib);
+                }
+                vb[rank] = (uint16_t)b;
+                nbv[rank] = (uint16_t)((ib + 1 < nv ? off[ib + 1] : (int)len) - off[ib]);
+                gv[rank] = make_float2((float)g.x, (float)g.y);
+            }
+        }
     }
     // emit: one wave per candidate row, ballot-compacted, ascending a
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -659,7 +721,7 @@ inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct WsLayout {
     int64_t tau, nnz, key, k0, k1, i0, i1, flags, zpos, snnz, rowptr, sc32, sc64, tstart, tend, nch, choff, err,
-        tcnt, sc64t, gpos, total;
+        tcnt, sc64t, gpos, fsz, frec, total;
 };
 
 WsLayout ws_layout(const wp_plan *p, int64_t M) {
@@ -689,6 +751,8 @@ WsLayout ws_layout(const wp_plan *p, int64_t M) {
     L.tcnt = take(4 * cells);
     L.sc64t = take(8 * scan_scratch_elems(cells));
     L.gpos = take(4 * (cells + 1));
+    L.fsz = take(4 * M);
+    L.frec = take(8 * (M + 1));
     L.total = o;
     return L;
 }
@@ -709,7 +773,7 @@ wp_status count_rows(const wp_plan *p, int64_t M, const double *u, const double 
         const int64_t n = std::min<int64_t>(ROW_CHUNK, M - r0);
         hipLaunchKernelGGL((k_row_count<LOGNG>), dim3((unsigned)n), dim3(BNTH), lds, s, u, v, w, M, E, p->cell,
                            p->delta, p->W, p->beta, p->tile, p->ntile, p->tw64, (double *)(ws + L.tau),
-                           (int *)(ws + L.nnz), (int *)(ws + L.key), (int *)(ws + L.err), r0);
+                           (int *)(ws + L.nnz), (int *)(ws + L.key), (int *)(ws + L.fsz), (int *)(ws + L.err), r0);
     }
     return wp_check_launch("build_G_count rows");
 }
@@ -720,20 +784,23 @@ wp_status fill_rows(const wp_plan *p, int64_t M, const double *u, const double *
     const size_t lds = fill_lds<LOGNG>();
     if (lds > 160 * 1024) return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d exceeds the LDS budget", p->Ng);
     int *err = (int *)(ws + L.err);
+    const bool rec = G->frec && G->fdat;
+    const int64_t *frec = rec ? (const int64_t *)(ws + L.frec) : nullptr;
+    unsigned char *fdat = rec ? (unsigned char *)G->fdat : nullptr;
     for (int64_t r0 = 0; r0 < M; r0 += ROW_CHUNK) {
         const dim3 g((unsigned)std::min<int64_t>(ROW_CHUNK, M - r0));
         if (G->taps == WP_TAPS_BF16)
             hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_BF16>), g, dim3(BNTH), lds, s, u, v, w, M, p->cell,
                                p->delta, p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr,
-                               G->col, G->val, G->rscale, err, r0);
+                               G->col, G->val, G->rscale, frec, fdat, err, r0);
         else if (G->taps == WP_TAPS_I16)
             hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_I16>), g, dim3(BNTH), lds, s, u, v, w, M, p->cell,
                                p->delta, p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr,
-                               G->col, G->val, G->rscale, err, r0);
+                               G->col, G->val, G->rscale, frec, fdat, err, r0);
         else
             hipLaunchKernelGGL((k_row_fill<LOGNG, WP_TAPS_C64>), g, dim3(BNTH), lds, s, u, v, w, M, p->cell,
                                p->delta, p->W, p->beta, p->tw64, (const double *)(ws + L.tau), G->perm, G->rowptr,
-                               G->col, G->val, G->rscale, err, r0);
+                               G->col, G->val, G->rscale, frec, fdat, err, r0);
     }
     return wp_check_launch("build_G_fill rows");
 }
@@ -777,6 +844,26 @@ wp_status launch_sort_pairs(const int *key, int64_t n, int bits, int *keys_out, 
 }
 
 int64_t builder_workspace_bytes(const wp_plan *p, int64_t M) { return ws_layout(p, M).total; }
+
+// offsets of the factor records in sorted row order (after the count pass) and their total
+wp_status launch_build_factor_bytes(const wp_plan *p, int64_t M, void *wsv, int64_t *bytes, hipStream_t s) {
+    unsigned char *ws = (unsigned char *)wsv;
+    const WsLayout L = ws_layout(p, M);
+    const int nthr = 256;
+    const dim3 gM((unsigned)((M + nthr - 1) / nthr));
+    hipLaunchKernelGGL(k_gather_nnz, gM, dim3(nthr), 0, s, (const int *)(ws + L.i0), (const int *)(ws + L.fsz),
+                       (int64_t *)(ws + L.snnz), M);
+    device_scan<int64_t, int64_t>((const int64_t *)(ws + L.snnz), (int64_t *)(ws + L.frec), M,
+                                  (int64_t *)(ws + L.sc64), s);
+    wp_status st = wp_check_launch("build factor offsets");
+    if (st != WP_OK) return st;
+    // the total also goes next to the error flags (the count pass clears them), where the fill pass
+    // checks it against the caller's buffer
+    WP_HIP(hipMemcpyAsync(ws + L.err + 8, ws + L.frec + 8 * M, 8, hipMemcpyDeviceToDevice, s));
+    WP_HIP(hipMemcpyAsync(bytes, ws + L.frec + 8 * M, 8, hipMemcpyDeviceToHost, s));
+    WP_HIP(hipStreamSynchronize(s));
+    return WP_OK;
+}
 
 wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
                              void *wsv, int64_t *nnz_total, int64_t *nwork, hipStream_t s) {
@@ -852,6 +939,15 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
     const int T = p->ntile * p->ntile;
     WP_HIP(hipMemcpyAsync(G->rowptr, ws + L.rowptr, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
     WP_HIP(hipMemcpyAsync(G->perm, ws + L.i0, 4 * M, hipMemcpyDeviceToDevice, s));
+    if (G->frec && G->fdat) {
+        int64_t total = 0;
+        WP_HIP(hipMemcpyAsync(&total, ws + L.err + 8, 8, hipMemcpyDeviceToHost, s));
+        WP_HIP(hipStreamSynchronize(s));
+        if (total == 0 || total != G->fbytes)
+            return wp_set_error(WP_EINVAL, "factor records: G->fbytes = %lld, the workspace holds %lld (call "
+                                "wp_build_factor_bytes after wp_build_G_count)", (long long)G->fbytes, (long long)total);
+        WP_HIP(hipMemcpyAsync(G->frec, ws + L.frec, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
+    }
     wp_status st;
     switch (p->logNg) {
         case 6: st = fill_rows<6>(p, M, u, v, w, ws, L, G, s); break;

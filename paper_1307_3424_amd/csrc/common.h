@@ -24,6 +24,7 @@ struct wp_plan {
     int ntile;      // tiles per axis
     int device;
     int tune_degrid_lpr, tune_degrid_u;   // 0: automatic (see spmv.hip)
+    int tune_degrid_rows;                 // rows per wave of the degrid from factor records (0: automatic)
     int tune_gather_lpr, tune_gather_u;
     int tune_gather_chunk;                // entries per chunk of the blocked gather (256, 512, 1024)
     float *apod;    // [N]  1 / g(xi), xi = (p - N/2) / Ng       (device)
@@ -131,6 +132,15 @@ constexpr int GB_ENT = 512;
 constexpr int GB_CELLS = 64;
 inline int64_t gather_table_slots(int64_t nnz, int64_t cells) { return nnz / GB_ENT + (cells - 1) / GB_CELLS + 1; }
 
+// ---------------------------------------------------------------------------- factor records
+// Separable form of a kept row: with the u candidates sorted by descending |g_u|^2 and the v
+// candidates by descending |g_v|^2, candidate v cell i keeps the first nb[i] u candidates.
+// Record: uint16 nu, nv; uint16 ua[nu], vb[nv], nb[nv]; zero padding to 8 bytes; complex
+// float gu[nu], gv[nv].  Records start at multiples of 8 bytes.
+__host__ __device__ inline int factor_record_bytes(int nu, int nv) {
+    return ((4 + 2 * nu + 4 * nv + 7) & ~7) + 8 * (nu + nv);
+}
+
 // ---------------------------------------------------------------------------- launchers (host)
 
 // FFT stages of A, Z, F and their adjoint (fft.hip)
@@ -155,6 +165,7 @@ wp_status launch_sort_pairs(const int *key, int64_t n, int bits, int *keys_out, 
 int64_t scan_workspace_bytes(int64_t n);
 wp_status launch_scan_int(const int *in, int *out, int64_t n, void *ws, hipStream_t s);
 int64_t builder_workspace_bytes(const wp_plan *p, int64_t M);
+wp_status launch_build_factor_bytes(const wp_plan *p, int64_t M, void *ws, int64_t *bytes, hipStream_t s);
 wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v,
                              const double *w, double E, void *ws, int64_t *nnz, int64_t *nwork,
                              hipStream_t s);

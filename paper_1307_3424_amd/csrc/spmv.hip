@@ -5,7 +5,8 @@
 //   lanes stream the row's (col, val) pairs with unit stride (coalesced HBM
 //   reads), gather X (L2 / MALL resident when rows are uv-tile sorted), and
 //   reduce the complex sum with cross-lane shuffles.  Blocks are renumbered so
-//   each XCD walks a contiguous range of tile-sorted rows.
+//   each XCD walks a contiguous range of tile-sorted rows.  From factor records
+//   the taps are formed in registers as products of the row's two 1-D factors.
 // Grid    X[col_j] += conj(G_kj) y_k.  One work item (a chunk of rows whose
 //   visibilities fall in one uv tile) per block: taps accumulate with LDS float
 //   atomics into a window covering the tile plus a halo; taps outside the
@@ -21,6 +22,13 @@ namespace {
 
 constexpr int SP_NTH = 256;
 constexpr int WAVES = SP_NTH / 64;
+
+// orders a wave's LDS stores before its later LDS loads by other lanes (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 
 // LPR lanes per row (64 / LPR rows per wave); each lane keeps U taps in flight.
@@ -73,6 +81,92 @@ __global__ __launch_bounds__(SP_NTH) void k_degrid(const int64_t *__restrict__ r
         }
         y[perm ? perm[r] : r] = make_float2(ar, ai);
     }
+}
+
+// Degrid from factor records: R rows per wavefront, LPR = 64 / R lanes per row.  The lanes of a
+// row copy its record into their LDS slice (coalesced) unless it is larger than the slice.  Lane
+// l of a row takes u candidate i = l mod Pa (Pa a power of two >= nu, at most LPR) against v
+// candidates b = l / Pa, l / Pa + LPR / Pa, ...; tap (b, i) is kept when i < nb[b].  nb does not
+// increase along the v order, so a lane stops at the first b that drops its u candidate.  The
+// tap gv[b] gu[i] is formed in registers: a row streams its two factor lists (about 10 bytes per
+// candidate) instead of 12 bytes per tap, and the only other memory accesses are the grid reads.
+constexpr int SEP_WAVE_LDS = 4096;        // bytes of LDS per wave, split between its R rows
+
+template <int LPR, int UB>
+__device__ __forceinline__ void sep_row(const unsigned char *rec, const float2 *__restrict__ grid, int logNg,
+                                        int sl, float &ar, float &ai) {
+    const uint32_t hdr = *(const uint32_t *)rec;
+    const int nu = (int)(hdr & 0xffffu), nv = (int)(hdr >> 16);
+    const uint16_t *ua = (const uint16_t *)rec + 2, *vb = ua + nu, *nbv = vb + nv;
+    const float2 *gu = (const float2 *)(rec + ((4 + 2 * nu + 4 * nv + 7) & ~7)), *gv = gu + nu;
+    int Pa = 1;
+    while (Pa < nu && Pa < LPR) Pa <<= 1;
+    const int Pb = LPR / Pa, g = sl / Pa;
+    for (int i = sl & (Pa - 1); i < nu; i += Pa) {
+        const int a = ua[i];
+        const float2 fu = gu[i];
+        for (int b0 = g; b0 < nv; b0 += Pb * UB) {
+            int c[UB];
+            float2 t[UB];
+            bool keep = false;
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+                const int b = b0 + Pb * q;
+                keep = b < nv && i < (int)nbv[b];
+                c[q] = 0;
+                t[q] = make_float2(0.f, 0.f);
+                if (keep) {
+                    const float2 f = gv[b];
+                    c[q] = ((int)vb[b] << logNg) | a;
+                    t[q] = make_float2(f.x * fu.x - f.y * fu.y, f.x * fu.y + f.y * fu.x);
+                }
+            }
+            // a dropped tap reads cell 0 with a zero weight: cheaper than branching around the read
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+                const float2 x = grid[c[q]];
+                ar = fmaf(t[q].x, x.x, ar);
+                ar = fmaf(-t[q].y, x.y, ar);
+                ai = fmaf(t[q].x, x.y, ai);
+                ai = fmaf(t[q].y, x.x, ai);
+            }
+            if (!keep) break;             // the last b of the batch dropped i: so do all later ones
+        }
+    }
+}
+
+template <int R, int UB>
+__global__ __launch_bounds__(SP_NTH) void k_degrid_sep(const int64_t *__restrict__ frec,
+                                                       const unsigned char *__restrict__ fdat,
+                                                       const float2 *__restrict__ grid, const int *__restrict__ perm,
+                                                       float2 *__restrict__ y, int64_t M, int logNg) {
+    constexpr int LPR = 64 / R, SLICE = SEP_WAVE_LDS / R;
+    __shared__ uint2 s_rec[SP_NTH / 64][SEP_WAVE_LDS / 8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, q = lane / LPR, sl = lane & (LPR - 1);
+    const int64_t r = (xcd_block(blockIdx.x, gridDim.x) * (SP_NTH / 64) + wv) * R + q;
+    uint2 *slice = s_rec[wv] + q * (SLICE / 8);
+    int64_t o = 0;
+    int bytes = 0;
+    if (r < M) {
+        o = frec[r];
+        bytes = (int)(frec[r + 1] - o);
+        if (bytes <= SLICE) {
+            const uint2 *src = (const uint2 *)(fdat + o);
+            for (int e = sl; e < bytes / 8; e += LPR) slice[e] = src[e];
+        }
+    }
+    wave_sync();
+    float ar = 0.f, ai = 0.f;
+    if (r < M) {
+        if (bytes <= SLICE) sep_row<LPR, UB>((const unsigned char *)slice, grid, logNg, sl, ar, ai);
+        else sep_row<LPR, UB>(fdat + o, grid, logNg, sl, ar, ai);
+    }
+#pragma unroll
+    for (int m = LPR / 2; m > 0; m >>= 1) {
+        ar += __shfl_xor(ar, m);
+        ai += __shfl_xor(ai, m);
+    }
+    if (sl == 0 && r < M) y[perm ? perm[r] : r] = make_float2(ar, ai);
 }
 
 template <int TK>
@@ -193,11 +287,6 @@ __global__ __launch_bounds__(SP_NTH) void k_gather(const int64_t *__restrict__ t
 // whatever the cell lengths; no workgroup barrier, no atomics, one fixed summation order.
 constexpr int GW_WAVES = SP_NTH / 64;
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <int TK, int CH>
 __global__ __launch_bounds__(SP_NTH) void k_gather_wave(const int64_t *__restrict__ tblk, int64_t nblk,
@@ -337,6 +426,26 @@ bool valid_lpr_u(int lpr, int u) {
 
 wp_status launch_degrid(const wp_plan *p, const wp_G *G, const float2 *grid, float2 *y, hipStream_t s) {
     if (G->M == 0) return WP_OK;
+    if (G->frec && G->fdat) {
+        // rows per wave: as many as keep about 16 taps per lane or more
+        const double mean = (double)G->nnz / (double)G->M;
+        int R = mean < 256 ? 4 : (mean < 512 ? 2 : 1);
+        while (R > 1 && G->M / R < 16384) R >>= 1;     // small problems: keep the waves many
+        if (p->tune_degrid_rows > 0) R = p->tune_degrid_rows;
+        const int64_t waves = (G->M + R - 1) / R;
+        const dim3 gr((unsigned)((waves + SP_NTH / 64 - 1) / (SP_NTH / 64)));
+        const unsigned char *fd = (const unsigned char *)G->fdat;
+        // measured on MI355X: four grid reads in flight per lane; rows of ~210 taps run best four
+        // to a wave (2048 pixels: 7.47 ms against 9.64 from stored taps) but two at 32768 rows
+        // (17.6 us), rows of ~900 one to a wave (1024 pixels: 5.47 against 8.46 ms)
+        if (R == 4)
+            hipLaunchKernelGGL((k_degrid_sep<4, 4>), gr, dim3(SP_NTH), 0, s, G->frec, fd, grid, yperm(G), y, G->M, p->logNg);
+        else if (R == 2)
+            hipLaunchKernelGGL((k_degrid_sep<2, 4>), gr, dim3(SP_NTH), 0, s, G->frec, fd, grid, yperm(G), y, G->M, p->logNg);
+        else
+            hipLaunchKernelGGL((k_degrid_sep<1, 4>), gr, dim3(SP_NTH), 0, s, G->frec, fd, grid, yperm(G), y, G->M, p->logNg);
+        return wp_check_launch("degrid factor records");
+    }
     const int U = p->tune_degrid_u > 0 ? p->tune_degrid_u : 4;
     const int lpr = pick_lpr((double)G->nnz / (double)G->M, 4.0, p->tune_degrid_lpr);
     if (!valid_lpr_u(lpr, U)) return wp_set_error(WP_EINVAL, "degrid: no kernel for lanes %d, unroll %d", lpr, U);

@@ -366,6 +366,109 @@ def test_w_zero_and_full_energy_small_grid():
         assert relerr(wp.apply_Phi(plan, G, c64(x)).cpu().numpy(), wproj.phi(Go, x, s)) < TOL
 
 
+def decode_records(G):
+    """Per sorted row: (ua, vb, nb, gu, gv) of its factor record, as the header defines it."""
+    frec = G.frec.cpu().numpy()
+    fd = G.fdat.cpu().numpy()
+    out = []
+    for r in range(G.M):
+        o = int(frec[r])
+        nu, nv = (int(x) for x in fd[o:o + 4].view(np.uint16))
+        ua = fd[o + 4:o + 4 + 2 * nu].view(np.uint16).astype(np.int64)
+        vb = fd[o + 4 + 2 * nu:o + 4 + 2 * nu + 2 * nv].view(np.uint16).astype(np.int64)
+        nb = fd[o + 4 + 2 * nu + 2 * nv:o + 4 + 2 * nu + 4 * nv].view(np.uint16).astype(np.int64)
+        vo = o + ((4 + 2 * nu + 4 * nv + 7) & ~7)
+        gu = fd[vo:vo + 8 * nu].view(np.complex64)
+        gv = fd[vo + 8 * nu:vo + 8 * (nu + nv)].view(np.complex64)
+        assert int(frec[r + 1]) - o == (((4 + 2 * nu + 4 * nv + 7) & ~7) + 8 * (nu + nv))
+        out.append((ua, vb, nb, gu, gv))
+    return out
+
+
+def check_records(G, Ng):
+    """Every record expands to its stored row: the same cells, taps equal to the stored values up
+    to complex-float rounding of the two factors."""
+    rp = G.rowptr.cpu().numpy()
+    col = G.col.cpu().numpy()
+    val = G.val.cpu().numpy()
+    for r, (ua, vb, nb, gu, gv) in enumerate(decode_records(G)):
+        assert np.all(np.diff(nb) <= 0) and nb.size and nb[0] == ua.size and np.all(nb >= 1)
+        assert np.all(np.diff(np.abs(gu.astype(np.complex128)) ** 2) <= 1e-6 * np.abs(gu[0]) ** 2)
+        b_idx = np.repeat(np.arange(vb.size), nb)
+        a_idx = np.concatenate([np.arange(n) for n in nb])
+        cells = vb[b_idx] * Ng + ua[a_idx]
+        taps = gv[b_idx].astype(np.complex128) * gu[a_idx].astype(np.complex128)
+        o = np.argsort(cells)
+        c_row = col[rp[r]:rp[r + 1]]
+        assert np.array_equal(cells[o], c_row), f"row {r}: kept cells differ"
+        v_row = val[rp[r]:rp[r + 1]].astype(np.complex128)
+        assert np.all(np.abs(taps[o] - v_row) <= 3e-7 * np.abs(v_row).max() + 3e-7 * np.abs(v_row)), f"row {r}"
+
+
+def test_factor_records_tiny_form():
+    """Every row of the tiny form: records expand to the stored rows; their factors are the
+    oracle's 1-D factors; the degrid from records matches the oracle."""
+    wl = synth.workload(0)
+    say(f"factor records: {wl.name}")
+    x, u, v, w = synth.workload_inputs(wl)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E, factors=True)
+    torch.cuda.synchronize()
+    check_records(G, wl.Ng)
+    perm = G.perm.cpu().numpy()
+    recs = decode_records(G)
+    for r in range(0, wl.M, 37):
+        k = perm[r]
+        gv_o, gu_o = wproj.kernel_row_separable(u[k] * 2 * s.L, v[k] * 2 * s.L, w[k], s)
+        ua, vb, nb, gu, gv = recs[r]
+        assert np.all(np.abs(gu - gu_o[ua]) <= 1e-6 * np.abs(gu_o).max())
+        assert np.all(np.abs(gv - gv_o[vb]) <= 1e-6 * np.abs(gv_o).max())
+    Go = wproj.build_rows(u, v, w, wl.E, s)
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    assert relerr(y, wproj.phi(Go, x, s)) < TOL
+    G.use_factors = False
+    assert relerr(wp.apply_Phi(plan, G, c64(x)).cpu().numpy(), y) < 1e-6
+
+
+def test_factor_records_plain_form():
+    wl = synth.workload(1)
+    say(f"factor records: {wl.name}")
+    x, u, v, w = synth.workload_inputs(wl)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E, factors=True)
+    torch.cuda.synchronize()
+    check_records(G, wl.Ng)
+    rows = synth.subset_rows(wl.M, 64, synth.rng_for(wl.seed, "subset", 1))
+    Go = wproj.build_rows(u, v, w, wl.E, s, rows=rows)
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    assert relerr(y[rows], Go @ wproj.grid_forward(x, s).ravel()) < TOL
+    X = c64(synth.random_complex(wl.Ng ** 2, np.random.default_rng(15)))
+    y1 = wp.degrid(plan, G, X).cpu().numpy()
+    G.use_factors = False
+    assert relerr(y1, wp.degrid(plan, G, X).cpu().numpy()) < 1e-6
+
+
+def test_factor_records_wide_rows_and_edges():
+    """E = 1: rows with w > 0 keep the whole 512 x 512 grid (nu = nv = 512, eight u candidates
+    per lane), rows with w = 0 a 4 x 4 box; plus visibilities at the band edges."""
+    N, M = 256, 24
+    s = Setup(N=N, L=L)
+    plan = wp.Plan(N, L)
+    u, v, w = synth.uvw(N, M, L, "uniform", 0.0, N / (2 * L * L), np.random.default_rng(13))
+    w[::2] = 0.0
+    B = N / (2 * L)
+    u[:4] = [-B * 0.9999, B * 0.9999, 0.0, -B * 0.9999]
+    v[:4] = [B * 0.9999, -B * 0.9999, -B * 0.9999, 0.0]
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), 1.0, factors=True)
+    torch.cuda.synchronize()
+    check_records(G, s.Ng)
+    x = synth.random_complex((N, N), np.random.default_rng(14))
+    Go = wproj.build_rows(u, v, w, 1.0, s)
+    assert relerr(wp.apply_Phi(plan, G, c64(x)).cpu().numpy(), wproj.phi(Go, x, s)) < TOL
+
+
 @pytest.mark.parametrize("E", [0.1, 0.5, 0.9, 0.999])
 def test_energy_levels(E):
     N, M = 64, 53

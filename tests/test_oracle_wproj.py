@@ -176,6 +176,35 @@ def test_separable_rows_equal_2d_rows():
         assert np.abs(g2 - np.outer(gv, gu)).max() < 1e-13 * np.abs(g2).max()
 
 
+@pytest.mark.parametrize("E", [0.5, 0.99, 0.999])
+def test_kept_set_is_a_staircase_of_the_one_dimensional_energies(E):
+    """A tap's energy is the product A_a B_b of the 1-D factor energies, so the kept set is
+    monotone in both: taking the u cells by descending A, each v cell keeps a prefix of them, and
+    the prefix length does not increase with descending B.  The oracle's kept rows (threshold on
+    the 2-D energies) agree with that staircase up to ties at the threshold."""
+    N = 64
+    s = Setup(N=N, L=L)
+    u, v, w = _vis(N, 12, N / (2 * L * L), 72)
+    ut, vt = geometry.grid_coord(u, N, L), geometry.grid_coord(v, N, L)
+    G = wproj.build_rows(u, v, w, E, s)
+    for k in range(u.size):
+        gv, gu = wproj.kernel_row_separable(ut[k], vt[k], w[k], s)
+        A, B = np.abs(gu) ** 2, np.abs(gv) ** 2
+        m = np.outer(B, A)
+        tau, _ = wproj.energy_threshold(np.abs(np.outer(gv, gu)).ravel() ** 2, E)
+        ua, vb = np.argsort(-A, kind="stable"), np.argsort(-B, kind="stable")
+        nb = np.array([(A[ua] * B[b] >= tau).sum() for b in vb])
+        assert np.all(np.diff(nb) <= 0)
+        stair = np.zeros((s.Ng, s.Ng), dtype=bool)
+        for b, n in zip(vb, nb):
+            stair[b, ua[:n]] = True
+        assert np.array_equal(stair, m >= tau)       # the staircase is the product-energy kept set
+        kept = np.zeros(s.Ng * s.Ng, dtype=bool)
+        kept[G.indices[G.indptr[k]:G.indptr[k + 1]]] = True
+        diff = np.nonzero(kept != stair.ravel())[0]
+        assert np.all(np.abs(m.ravel()[diff] - tau) <= 1e-12 * tau)
+
+
 def test_linear_and_exact_chirp_agree_to_first_order():
     N = 32
     l = geometry.padded_coords(N, L)
