@@ -93,7 +93,8 @@ typedef struct wp_G {
     void    *tval;     /* [nnz] device, the entry's G value (not conjugated), same tap type */
     /* Optional block table of the transposed copy (tblk == NULL: the gather runs one lane
      * group per cell).  Blocks are runs of at most 64 consecutive cells whose entries start
-     * within one stretch of 512 entries; block i is (first cell, first entry) at
+     * within one stretch of 512 entries (the plan's gather_block_entries); block i is
+     * (first cell, first entry) at
      * tblk[2i], tblk[2i+1], and the pair after the last block, and every later one up to
      * index n_tblk, is (Ng*Ng, nnz).  One wavefront sums one block.  n_tblk comes from
      * wp_gather_table_size; wp_build_G_fill writes the table with the transposed copy. */
@@ -140,7 +141,10 @@ wp_status wp_plan_destroy(wp_plan *plan);
  * loads in flight per lane: 4, 8 or 16 (not every pair exists: an apply with
  * an unavailable pair returns WP_EINVAL); the gather knobs apply to the form
  * without a block table.  "gather_chunk": entries a wavefront of the blocked
- * gather stages at a time (256, 512 or 1024); "degrid_rows": rows per wavefront of
+ * gather stages at a time (256, 512, 768 or 1024); "gather_block_entries": the entry
+ * stretch of a gather block (256, 384, 512 or 1024; it sets the block table that
+ * wp_gather_table_size sizes and wp_build_G_fill writes, so change it only before
+ * building G); "degrid_rows": rows per wavefront of
  * the degrid from factor records (1, 2 or 4).  Not thread-safe with concurrent
  * applies on the same plan.
  */

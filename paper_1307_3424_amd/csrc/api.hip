@@ -57,7 +57,7 @@ wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
     if (G->tblk && !G->tcolptr) return wp_set_error(WP_EINVAL, "G->tblk set without the transposed copy");
     if ((G->frec == nullptr) != (G->fdat == nullptr)) return wp_set_error(WP_EINVAL, "G->frec and G->fdat go together");
     if (G->tblk && p) {
-        const int64_t want = gather_table_slots(G->nnz, (int64_t)p->Ng * p->Ng);
+        const int64_t want = gather_table_slots(G->nnz, (int64_t)p->Ng * p->Ng, p->gb_ent);
         if (G->n_tblk != want)
             return wp_set_error(WP_EINVAL, "G->n_tblk = %lld, expected %lld", (long long)G->n_tblk, (long long)want);
     }
@@ -98,6 +98,7 @@ wp_status wp_plan_create(wp_plan **out, int N, double fov_L, int kb_W, double kb
     if (!p) return wp_set_error(WP_ENOMEM, "plan allocation");
     p->N = N;
     p->Ng = 2 * N;
+    p->gb_ent = GB_ENT;
     p->logNg = ilog2(p->Ng);
     p->W = kb_W;
     p->chirp = chirp;
@@ -157,9 +158,15 @@ wp_status wp_plan_destroy(wp_plan *p) {
 wp_status wp_plan_set_tuning(wp_plan *p, const char *key, int value) {
     if (wp_status s = check_plan(p)) return s;
     if (!key) return wp_set_error(WP_EINVAL, "key is NULL");
+    if (!std::strcmp(key, "gather_block_entries")) {
+        if (value != 0 && value != 256 && value != 384 && value != 512 && value != 1024)
+            return wp_set_error(WP_EINVAL, "gather_block_entries %d: 0, 256, 384, 512 or 1024", value);
+        p->gb_ent = value > 0 ? value : GB_ENT;
+        return WP_OK;
+    }
     if (!std::strcmp(key, "gather_chunk")) {
-        if (value != 0 && value != 256 && value != 512 && value != 1024)
-            return wp_set_error(WP_EINVAL, "gather_chunk %d: 0, 256, 512 or 1024", value);
+        if (value != 0 && value != 256 && value != 512 && value != 768 && value != 1024)
+            return wp_set_error(WP_EINVAL, "gather_chunk %d: 0, 256, 512, 768 or 1024", value);
         p->tune_gather_chunk = value;
         return WP_OK;
     }
@@ -196,7 +203,7 @@ wp_status wp_gather_table_size(const wp_plan *p, int64_t nnz, int64_t *n) {
     if (wp_status s = check_plan(p)) return s;
     if (!n) return wp_set_error(WP_EINVAL, "n_tblk_out is NULL");
     if (nnz < 0) return wp_set_error(WP_EINVAL, "nnz < 0");
-    *n = gather_table_slots(nnz, (int64_t)p->Ng * p->Ng);
+    *n = gather_table_slots(nnz, (int64_t)p->Ng * p->Ng, p->gb_ent);
     return WP_OK;
 }
 

@@ -690,11 +690,11 @@ __global__ void k_t_sort(const int64_t *__restrict__ tcolptr, int64_t cells, int
 }
 
 // gather blocks: flag the cells that start a block ...
-__global__ void k_gb_flags(const int64_t *__restrict__ tcolptr, int64_t cells, int *__restrict__ flag) {
+__global__ void k_gb_flags(const int64_t *__restrict__ tcolptr, int64_t cells, int ent, int *__restrict__ flag) {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells) return;
-    const int64_t slot = tcolptr[c] / GB_ENT + c / GB_CELLS;
-    flag[c] = (c == 0 || slot != tcolptr[c - 1] / GB_ENT + (c - 1) / GB_CELLS) ? 1 : 0;
+    const int64_t slot = tcolptr[c] / ent + c / GB_CELLS;
+    flag[c] = (c == 0 || slot != tcolptr[c - 1] / ent + (c - 1) / GB_CELLS) ? 1 : 0;
 }
 
 // ... and write (first cell, first entry) of block pos[c] for each of them; the pairs from the
@@ -993,7 +993,7 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
         if ((st = wp_check_launch("build_G_fill transpose")) != WP_OK) return st;
         if (G->tblk) {
             // cnt (free again) holds the block-start flags; their scan gives each block's index
-            hipLaunchKernelGGL(k_gb_flags, gC, dim3(nthr), 0, s, G->tcolptr, cells, cnt);
+            hipLaunchKernelGGL(k_gb_flags, gC, dim3(nthr), 0, s, G->tcolptr, cells, p->gb_ent, cnt);
             int *gpos = (int *)(ws + L.gpos);
             device_scan<int, int>(cnt, gpos, cells, (int *)(ws + L.sc64t), s);
             const int64_t n = cells > G->n_tblk + 1 ? cells : G->n_tblk + 1;

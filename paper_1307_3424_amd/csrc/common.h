@@ -27,6 +27,7 @@ struct wp_plan {
     int tune_degrid_rows;                 // rows per wave of the degrid from factor records (0: automatic)
     int tune_gather_lpr, tune_gather_u;
     int tune_gather_chunk;                // entries per chunk of the blocked gather (256, 512, 1024)
+    int gb_ent;                           // entries stretch of a gather block (see gather_table_slots)
     float *apod;    // [N]  1 / g(xi), xi = (p - N/2) / Ng       (device)
     float2 *tw32;   // [Ng] exp(-2 pi i k / Ng), FP32             (device)
     double2 *tw64;  // [Ng] exp(-2 pi i k / Ng), FP64             (device)
@@ -124,13 +125,13 @@ __host__ __device__ inline void demorton2(int code, int &v, int &u) {
 
 // ---------------------------------------------------------------------------- gather blocks
 // The blocked gather walks the transposed copy in runs of consecutive grid cells: cell c starts
-// a block when slot(c) = floor(tcolptr[c] / GB_ENT) + floor(c / GB_CELLS) differs from
-// slot(c - 1).  Both terms are non-decreasing in c, so a block holds at most GB_CELLS cells
-// whose entries start within one stretch of GB_ENT entries (its last cell may run past it),
-// and there are at most gather_table_slots blocks.
+// a block when slot(c) = floor(tcolptr[c] / ent) + floor(c / GB_CELLS) differs from slot(c - 1)
+// (ent: the plan's gb_ent, GB_ENT unless tuned).  Both terms are non-decreasing in c, so a block
+// holds at most GB_CELLS cells whose entries start within one stretch of ent entries (its last
+// cell may run past it), and there are at most gather_table_slots blocks.
 constexpr int GB_ENT = 512;
 constexpr int GB_CELLS = 64;
-inline int64_t gather_table_slots(int64_t nnz, int64_t cells) { return nnz / GB_ENT + (cells - 1) / GB_CELLS + 1; }
+inline int64_t gather_table_slots(int64_t nnz, int64_t cells, int ent) { return nnz / ent + (cells - 1) / GB_CELLS + 1; }
 
 // ---------------------------------------------------------------------------- factor records
 // Separable form of a kept row: with the u candidates sorted by descending |g_u|^2 and the v

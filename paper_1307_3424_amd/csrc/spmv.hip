@@ -478,6 +478,7 @@ wp_status launch_gather(const wp_plan *p, const wp_G *G, const float2 *y, float2
 #define WP_GW_CH(TKV)                                    \
     do {                                                 \
         if (ch == 256) WP_GW(TKV, 256);                  \
+        else if (ch == 768) WP_GW(TKV, 768);             \
         else if (ch == 1024) WP_GW(TKV, 1024);           \
         else WP_GW(TKV, 512);                            \
     } while (0)

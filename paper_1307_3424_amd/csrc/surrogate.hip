@@ -57,6 +57,7 @@ struct wp_surrogate {
     uint16_t *Bdeg;     // [2H][NOUT] bfloat16: r = Bdeg x box
     uint16_t *Bgrd;     // [NOUT][2H] bfloat16: box contributions = Bgrd x s
     float *b4;          // [NOUT] output bias
+    float *wmax;        // [2] largest |Bgrd| and |b4| (bounds of the gridding's fixed-point window)
     double *fb;         // [3 Mf] fallback u, v, w (slot order)
 };
 
@@ -141,6 +142,14 @@ __device__ inline int64_t deg_index(int n, int kk) {
 }
 __device__ inline int64_t grd_index(int o, int k) {
     return ((int64_t)((o / 32) * (ND / 16) + k / 16) * 64 + (o % 32) + 32 * ((k % 16) / 8)) * 8 + (k % 8);
+}
+
+// largest magnitude of the bfloat16 weights of the gridding product and of the output bias
+// (non-negative floats order like their bit patterns, so an integer maximum serves)
+__global__ void k_weight_max(const uint16_t *__restrict__ Bgrd, const float *__restrict__ b4, float *__restrict__ wmax) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < (int64_t)NOUT * ND) atomicMax((int *)&wmax[0], __float_as_int(fabsf(from_bf16(Bgrd[e]))));
+    if (e < NOUT) atomicMax((int *)&wmax[1], __float_as_int(fabsf(b4[e])));
 }
 
 __global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bdeg, uint16_t *__restrict__ Bgrd) {
@@ -314,12 +323,14 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
                                                      const int *__restrict__ cell_start,
                                                      const uint16_t *__restrict__ h3,
                                                      const uint16_t *__restrict__ Bgrd, const float *__restrict__ b4,
-                                                     float s_out, float2 *__restrict__ grid) {
+                                                     const float *__restrict__ wmax, float s_out,
+                                                     float2 *__restrict__ grid) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint16_t *Sa = (uint16_t *)smem;                               // [AG][SLD]
-    float2 *win = (float2 *)(smem + (size_t)AG * SLD * 2);         // [WV][WU]
+    int2 *win = (int2 *)(smem + (size_t)AG * SLD * 2);             // [WV][WU] fixed point (re, im)
     __shared__ int s_wv[AG], s_wu[AG];
     __shared__ float2 s_Y[AG];
+    __shared__ float s_bnd[AG];                     // bound on |output| / s_out of each cell
     __shared__ float2 s_b4[BOX * BOX];               // output bias (no global loads inside the loop)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < BOX * BOX; i += ANT) s_b4[i] = ((const float2 *)b4)[i];
@@ -333,7 +344,7 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
         s_wv[i] = i < nc ? cv - (o.x + BOX / 2) : 0;
         s_wu[i] = i < nc ? cu - (o.y + BOX / 2) : 0;
     }
-    for (int e = tid; e < WV * WU; e += ANT) win[e] = make_float2(0.f, 0.f);
+    for (int e = tid; e < WV * WU; e += ANT) win[e] = make_int2(0, 0);
     // s of each cell: wave w takes cells w, w + 4, ...; lane l hidden units 4l .. 4l + 3
     for (int i = wave; i < AG; i += ANT / 64) {
         float sr[4] = {0.f, 0.f, 0.f, 0.f}, sm[4] = {0.f, 0.f, 0.f, 0.f};
@@ -369,9 +380,25 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
         pm.y = (uint32_t)to_bf16(sm[2]) | ((uint32_t)to_bf16(sm[3]) << 16);
         *(uint2 *)(Sa + i * SLD + 4 * lane) = pr;
         *(uint2 *)(Sa + i * SLD + H + 4 * lane) = pm;
-        if (lane == 0) s_Y[i] = Y;
+        // |A_i . B_o| <= ||A_i||_1 max|B| and |bias| <= max|b4| (|Y re| + |Y im|): a bound on every
+        // output of the cell (A_i: the bfloat16 values just stored)
+        float l1 = fabsf(from_bf16(pr.x & 0xffffu)) + fabsf(from_bf16(pr.x >> 16)) + fabsf(from_bf16(pr.y & 0xffffu)) +
+                   fabsf(from_bf16(pr.y >> 16)) + fabsf(from_bf16(pm.x & 0xffffu)) + fabsf(from_bf16(pm.x >> 16)) +
+                   fabsf(from_bf16(pm.y & 0xffffu)) + fabsf(from_bf16(pm.y >> 16));
+        for (int o2 = 32; o2 > 0; o2 >>= 1) l1 += __shfl_xor(l1, o2);
+        if (lane == 0) {
+            s_Y[i] = Y;
+            s_bnd[i] = l1 * wmax[0] + wmax[1] * (fabsf(Y.x) + fabsf(Y.y));
+        }
     }
     __syncthreads();
+    // LDS float atomics are slow on this GPU, integer ones fast: the window accumulates in 32-bit
+    // fixed point with a scale from the group's bound (at most AG cells reach one window cell, so
+    // |sum| <= 2^29 < 2^31), and the flush converts back
+    float gmax = 0.f;
+    for (int i = 0; i < nc; ++i) gmax = fmaxf(gmax, s_bnd[i]);
+    const float q = gmax > 0.f ? 536870912.0f / (gmax * s_out * (float)AG) : 1.0f;   // 2^29 / (AG max bound)
+    const float qs = q * s_out;
     // the whole A operand of the group in registers: 32 steps of 16
     constexpr int KS = ND / 16;
     bf16x8 a[KS];
@@ -417,16 +444,18 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
                 if (wb[r] >= 0) {
                     const float2 Y = Yr[r];
                     const float bias = comp == 0 ? br * Y.x + bi * Y.y : br * Y.y - bi * Y.x;
-                    float *dst = (float *)&win[wb[r] + woff] + comp;
-                    atomicAdd(dst, s_out * (acc[h][r] + bias));
+                    int *dst = (int *)&win[wb[r] + woff] + comp;
+                    atomicAdd(dst, __float2int_rn(qs * (acc[h][r] + bias)));
                 }
             }
         }
     }
     __syncthreads();
+    const float iq = 1.0f / q;
     for (int e = tid; e < WV * WU; e += ANT) {
-        const float2 val = win[e];
-        if (val.x != 0.0f || val.y != 0.0f) {
+        const int2 wi = win[e];
+        const float2 val = make_float2((float)wi.x * iq, (float)wi.y * iq);
+        if (wi.x != 0 || wi.y != 0) {
             const int gy = (o.x + e / WU) & (Ng - 1), gx = (o.y + e % WU) & (Ng - 1);
             float *dst = (float *)&grid[(int64_t)gy * Ng + gx];
             atomicAdd(dst, val.x);
@@ -452,16 +481,16 @@ wp_status sur_degrid(const wp_plan *p, const wp_surrogate *S, const float2 *grid
 wp_status sur_grid_add(const wp_plan *p, const wp_surrogate *S, const float2 *y, float2 *grid, hipStream_t s) {
     if (S->Ms == 0) return WP_OK;
     hipLaunchKernelGGL(k_sur_grid, dim3(S->ngrp_a), dim3(ANT), GRD_LDS, s, y, p->logNg, S->grp_a, S->grp_org,
-                       S->ngrp_a, S->cell_key, S->cell_start, S->h3, S->Bgrd, S->b4, S->s_out, grid);
+                       S->ngrp_a, S->cell_key, S->cell_start, S->h3, S->Bgrd, S->b4, S->wmax, S->s_out, grid);
     return wp_check_launch("k_sur_grid");
 }
 
-wp_status check_fallback(const wp_surrogate *S, const wp_G *Gf) {
+wp_status check_fallback(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf) {
     if (S->Mf == 0) return WP_OK;
     if (!Gf) return wp_set_error(WP_EINVAL, "%lld fallback rows need their exact G", (long long)S->Mf);
     if (Gf->M != S->Mf) return wp_set_error(WP_EINVAL, "fallback G has %lld rows, expected %lld", (long long)Gf->M,
                                             (long long)S->Mf);
-    if (Gf->tblk && (!Gf->tcolptr || Gf->n_tblk != gather_table_slots(Gf->nnz, (int64_t)1 << (2 * S->logNg))))
+    if (p && Gf->tblk && (!Gf->tcolptr || Gf->n_tblk != gather_table_slots(Gf->nnz, (int64_t)p->Ng * p->Ng, p->gb_ent)))
         return wp_set_error(WP_EINVAL, "fallback G: block table without the transposed copy or of the wrong size");
     return WP_OK;
 }
@@ -551,6 +580,10 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
     hipLaunchKernelGGL(k_make_B, dim3((unsigned)((NOUT * H + 255) / 256)), dim3(256), 0, s, m->params + OW4, S->Bdeg,
                        S->Bgrd);
     WP_HIP(hipMemcpyAsync(S->b4, m->params + OB4, NOUT * 4, hipMemcpyDeviceToDevice, s));
+    if (hipMalloc((void **)&S->wmax, 8) != hipSuccess) return fail(WP_ENOMEM, "weight bounds");
+    WP_HIP(hipMemsetAsync(S->wmax, 0, 8, s));
+    hipLaunchKernelGGL(k_weight_max, dim3((unsigned)((NOUT * ND + 255) / 256)), dim3(256), 0, s, S->Bgrd, S->b4,
+                       S->wmax);
     if (S->Ms > 0) {
         const int64_t Ms = S->Ms;
         const int gS = (int)((Ms + 255) / 256);
@@ -632,7 +665,7 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
 wp_status wp_surrogate_destroy(wp_surrogate *S) {
     if (!S) return WP_OK;
     void *bufs[] = {S->slot_vis, S->cell_key, S->cell_start, S->grp_d, S->grp_a, S->grp_org, S->h3, S->Bdeg,
-                    S->Bgrd, S->b4, S->fb};
+                    S->Bgrd, S->b4, S->wmax, S->fb};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(S);
@@ -681,7 +714,7 @@ wp_status wp_surrogate_grid_add(const wp_plan *p, const wp_surrogate *S, const v
 wp_status wp_surrogate_apply_Phi(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const void *x, void *y,
                                  void *grid, void *stream) {
     if (wp_status st = check_sur(p, S)) return st;
-    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (wp_status st = check_fallback(p, S, Gf)) return st;
     if (!x || !y || !grid) return wp_set_error(WP_EINVAL, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
     wp_status st = launch_grid_forward(p, (const float2 *)x, (float2 *)grid, s);
@@ -694,7 +727,7 @@ wp_status wp_surrogate_apply_Phi(const wp_plan *p, const wp_surrogate *S, const 
 wp_status wp_surrogate_apply_PhiT(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const void *y, void *x,
                                   void *grid, void *stream) {
     if (wp_status st = check_sur(p, S)) return st;
-    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (wp_status st = check_fallback(p, S, Gf)) return st;
     if (!x || !y || !grid) return wp_set_error(WP_EINVAL, "NULL argument");
     if (S->Mf > 0 && !Gf->tcolptr && (Gf->n_work > 0 && !Gf->work))
         return wp_set_error(WP_EINVAL, "fallback G needs its transposed copy or work items");
@@ -712,7 +745,7 @@ wp_status wp_surrogate_apply_PhiT(const wp_plan *p, const wp_surrogate *S, const
 
 wp_status wp_surrogate_to_slots(const wp_surrogate *S, const wp_G *Gf, const void *in, void *out, void *stream) {
     if (!S) return wp_set_error(WP_EINVAL, "surrogate is NULL");
-    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (wp_status st = check_fallback(nullptr, S, Gf)) return st;
     if (!in || !out || in == out) return wp_set_error(WP_EINVAL, "need distinct input and output vectors");
     const int *fperm = (S->Mf > 0 && Gf->order == WP_ORDER_SORTED) ? Gf->perm : nullptr;
     hipLaunchKernelGGL(k_to_slots, dim3((unsigned)((S->M + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
@@ -730,7 +763,7 @@ wp_status wp_surrogate_solver_workspace_bytes(const wp_plan *p, const wp_surroga
 wp_status wp_surrogate_power_norm2(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const float *x0,
                                    int iters, void *workspace, double *nu_out, void *stream) {
     if (wp_status st = check_sur(p, S)) return st;
-    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (wp_status st = check_fallback(p, S, Gf)) return st;
     if (!x0 || !workspace || !nu_out || iters < 1) return wp_set_error(WP_EINVAL, "bad argument");
     return launch_power_norm2(p, wp_operator{Gf, S, S->M}, x0, iters, nu_out, (unsigned char *)workspace,
                               (hipStream_t)stream);
@@ -739,7 +772,7 @@ wp_status wp_surrogate_power_norm2(const wp_plan *p, const wp_surrogate *S, cons
 wp_status wp_surrogate_solve(const wp_plan *p, const wp_surrogate *S, const wp_G *Gf, const void *y, double eps,
                              double nu, int iters, int levels, float *x, void *workspace, void *stream) {
     if (wp_status st = check_sur(p, S)) return st;
-    if (wp_status st = check_fallback(S, Gf)) return st;
+    if (wp_status st = check_fallback(p, S, Gf)) return st;
     if (!y || !x || !workspace || iters < 0 || !(nu > 0.0) || !(eps >= 0.0))
         return wp_set_error(WP_EINVAL, "bad argument");
     return launch_solve(p, wp_operator{Gf, S, S->M}, (const float2 *)y, eps, nu, iters, levels, x,
