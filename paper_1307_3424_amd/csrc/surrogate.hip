@@ -57,7 +57,7 @@ struct wp_surrogate {
     uint16_t *Bdeg;     // [2H][NOUT] bfloat16: r = Bdeg x box
     uint16_t *Bgrd;     // [NOUT][2H] bfloat16: box contributions = Bgrd x s
     float *b4;          // [NOUT] output bias
-    float *wmax;        // [2] largest |Bgrd| and |b4| (bounds of the gridding's fixed-point window)
+    float *wmax;        // [2] largest output weight norm and |b4| (bounds of the gridding's fixed-point window)
     double *fb;         // [3 Mf] fallback u, v, w (slot order)
 };
 
@@ -144,12 +144,19 @@ __device__ inline int64_t grd_index(int o, int k) {
     return ((int64_t)((o / 32) * (ND / 16) + k / 16) * 64 + (o % 32) + 32 * ((k % 16) / 8)) * 8 + (k % 8);
 }
 
-// largest magnitude of the bfloat16 weights of the gridding product and of the output bias
-// (non-negative floats order like their bit patterns, so an integer maximum serves)
+// largest Euclidean norm of an output's bfloat16 weights in the gridding product (over its 512
+// inputs) and largest |b4| (non-negative floats order like their bit patterns, so an integer
+// maximum serves); one thread per output
 __global__ void k_weight_max(const uint16_t *__restrict__ Bgrd, const float *__restrict__ b4, float *__restrict__ wmax) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < (int64_t)NOUT * ND) atomicMax((int *)&wmax[0], __float_as_int(fabsf(from_bf16(Bgrd[e]))));
-    if (e < NOUT) atomicMax((int *)&wmax[1], __float_as_int(fabsf(b4[e])));
+    const int o = blockIdx.x * 256 + threadIdx.x;
+    if (o >= NOUT) return;
+    float ss = 0.f;
+    for (int k = 0; k < ND; ++k) {
+        const float b = from_bf16(Bgrd[grd_index(o, k)]);
+        ss = fmaf(b, b, ss);
+    }
+    atomicMax((int *)&wmax[0], __float_as_int(sqrtf(ss) * 1.0001f));
+    atomicMax((int *)&wmax[1], __float_as_int(fabsf(b4[o])));
 }
 
 __global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bdeg, uint16_t *__restrict__ Bgrd) {
@@ -380,15 +387,18 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
         pm.y = (uint32_t)to_bf16(sm[2]) | ((uint32_t)to_bf16(sm[3]) << 16);
         *(uint2 *)(Sa + i * SLD + 4 * lane) = pr;
         *(uint2 *)(Sa + i * SLD + H + 4 * lane) = pm;
-        // |A_i . B_o| <= ||A_i||_1 max|B| and |bias| <= max|b4| (|Y re| + |Y im|): a bound on every
-        // output of the cell (A_i: the bfloat16 values just stored)
-        float l1 = fabsf(from_bf16(pr.x & 0xffffu)) + fabsf(from_bf16(pr.x >> 16)) + fabsf(from_bf16(pr.y & 0xffffu)) +
-                   fabsf(from_bf16(pr.y >> 16)) + fabsf(from_bf16(pm.x & 0xffffu)) + fabsf(from_bf16(pm.x >> 16)) +
-                   fabsf(from_bf16(pm.y & 0xffffu)) + fabsf(from_bf16(pm.y >> 16));
-        for (int o2 = 32; o2 > 0; o2 >>= 1) l1 += __shfl_xor(l1, o2);
+        // |A_i . B_o| <= ||A_i||_2 ||B_o||_2 (Cauchy-Schwarz) and |bias| <= max|b4| (|Y re| + |Y im|):
+        // a bound on every output of the cell (A_i: the bfloat16 values just stored)
+        float l2 = 0.f;
+        for (int e2 = 0; e2 < 4; ++e2) {
+            const uint32_t wr = e2 < 2 ? (e2 == 0 ? pr.x : pr.y) : (e2 == 2 ? pm.x : pm.y);
+            const float lo = from_bf16(wr & 0xffffu), hi = from_bf16(wr >> 16);
+            l2 = fmaf(lo, lo, fmaf(hi, hi, l2));
+        }
+        for (int o2 = 32; o2 > 0; o2 >>= 1) l2 += __shfl_xor(l2, o2);
         if (lane == 0) {
             s_Y[i] = Y;
-            s_bnd[i] = l1 * wmax[0] + wmax[1] * (fabsf(Y.x) + fabsf(Y.y));
+            s_bnd[i] = sqrtf(l2) * 1.0001f * wmax[0] + wmax[1] * (fabsf(Y.x) + fabsf(Y.y));
         }
     }
     __syncthreads();
@@ -582,8 +592,7 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
     WP_HIP(hipMemcpyAsync(S->b4, m->params + OB4, NOUT * 4, hipMemcpyDeviceToDevice, s));
     if (hipMalloc((void **)&S->wmax, 8) != hipSuccess) return fail(WP_ENOMEM, "weight bounds");
     WP_HIP(hipMemsetAsync(S->wmax, 0, 8, s));
-    hipLaunchKernelGGL(k_weight_max, dim3((unsigned)((NOUT * ND + 255) / 256)), dim3(256), 0, s, S->Bgrd, S->b4,
-                       S->wmax);
+    hipLaunchKernelGGL(k_weight_max, dim3((unsigned)((NOUT + 255) / 256)), dim3(256), 0, s, S->Bgrd, S->b4, S->wmax);
     if (S->Ms > 0) {
         const int64_t Ms = S->Ms;
         const int gS = (int)((Ms + 255) / 256);
