@@ -17,7 +17,7 @@
 #include <new>
 #include <vector>
 
-#include "common.h"
+#include "gather_block.h"
 
 namespace {
 
@@ -32,6 +32,8 @@ struct ProbDesc {
     const int *trow;
     const void *tval;
     const float *rscale;
+    const int64_t *tblk;   // block table of the transposed copy (nullptr: none)
+    int64_t n_tblk;
     int64_t M;
     int64_t y_off;
 };
@@ -174,6 +176,32 @@ __global__ __launch_bounds__(BT) void k_gather_persist(const ProbDesc *__restric
     }
 }
 
+// Blocked gather over the problems' block tables: an item is (problem, first block) and covers
+// GB_ITEM blocks; each wavefront of the workgroup sums every fourth of them (gather_block).
+constexpr int GB_ITEM = 32;
+
+template <int TK>
+__global__ __launch_bounds__(BT) void k_gather_persist_blk(const ProbDesc *__restrict__ pd,
+                                                           const int2 *__restrict__ items, int n_items,
+                                                           unsigned long long *counter, unsigned long long base,
+                                                           const float2 *__restrict__ y, float2 *__restrict__ grids,
+                                                           int64_t grid_stride) {
+    __shared__ int slot;
+    __shared__ float2 s_p[BT / 64][GB_ENT];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    long long ahead = first_ticket(counter, base);
+    for (;;) {
+        const int it = next_item(counter, base, &slot, ahead);
+        if (it >= n_items) break;
+        const int2 w = items[it];
+        const ProbDesc d = pd[w.x];
+        const int64_t bend = min((int64_t)w.y + GB_ITEM, d.n_tblk);
+        for (int64_t bi = w.y + wv; bi < bend; bi += BT / 64)
+            gather_block<TK, GB_ENT>(d.tblk, bi, d.tcolptr, d.trow, d.tval, d.rscale, y + d.y_off, d.perm,
+                                     grids + (int64_t)w.x * grid_stride, s_p[wv], lane);
+    }
+}
+
 struct Shape {
     int lpr, u, chunk;
 };
@@ -188,8 +216,9 @@ struct wp_batch {
     int64_t M_total;
     std::vector<int64_t> M, y_off;
     ProbDesc *d_desc = nullptr;
-    int2 *d_items_deg = nullptr, *d_items_gat = nullptr;
-    int n_items_deg = 0, n_items_gat = 0;
+    int2 *d_items_deg = nullptr, *d_items_gat = nullptr, *d_items_blk = nullptr;
+    int n_items_deg = 0, n_items_gat = 0, n_items_blk = 0;
+    bool blocks = false;           // every problem has a block table: the gather runs over blocks
     unsigned long long *d_counter = nullptr;
     unsigned long long base = 0;   // next launch's first ticket
     Shape deg{64, 4, 64}, gat{16, 8, 256};
@@ -248,7 +277,22 @@ wp_status run_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s) {
     return launch_deg<WP_TAPS_C64>(b, grids, y, s);
 }
 
+template <int TK>
+wp_status launch_gat_blk(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s) {
+    const int64_t G2 = (int64_t)b->plan->Ng * b->plan->Ng;
+    hipLaunchKernelGGL((k_gather_persist_blk<TK>), dim3(b->nblocks), dim3(BT), 0, s, b->d_desc, b->d_items_blk,
+                       b->n_items_blk, b->d_counter, b->base, y, grids, G2);
+    if (wp_status st = wp_check_launch("batch gather blocks")) return st;
+    b->base += (unsigned long long)b->n_items_blk + 2ull * (unsigned long long)b->nblocks;
+    return WP_OK;
+}
+
 wp_status run_gat(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s) {
+    if (b->blocks) {
+        if (b->taps == WP_TAPS_BF16) return launch_gat_blk<WP_TAPS_BF16>(b, y, grids, s);
+        if (b->taps == WP_TAPS_I16) return launch_gat_blk<WP_TAPS_I16>(b, y, grids, s);
+        return launch_gat_blk<WP_TAPS_C64>(b, y, grids, s);
+    }
     if (b->taps == WP_TAPS_BF16) return launch_gat<WP_TAPS_BF16>(b, y, grids, s);
     if (b->taps == WP_TAPS_I16) return launch_gat<WP_TAPS_I16>(b, y, grids, s);
     return launch_gat<WP_TAPS_C64>(b, y, grids, s);
@@ -294,7 +338,7 @@ wp_status batch_create(wp_batch **out, const wp_plan *p, int P, const wp_G *G) {
         b->M[i] = G[i].M;
         b->y_off[i] = off;
         desc[i] = ProbDesc{G[i].rowptr, G[i].col, G[i].val, G[i].order == WP_ORDER_SORTED ? nullptr : G[i].perm,
-                           G[i].tcolptr, G[i].trow, G[i].tval, G[i].rscale, G[i].M, off};
+                           G[i].tcolptr, G[i].trow, G[i].tval, G[i].rscale, G[i].tblk, G[i].n_tblk, G[i].M, off};
         off += G[i].M;
     }
     b->M_total = off;
@@ -312,6 +356,32 @@ wp_status batch_create(wp_batch **out, const wp_plan *p, int P, const wp_G *G) {
     }
     wp_status st = make_items(b, true);
     if (st == WP_OK && b->transpose) st = make_items(b, false);
+    // blocks when every problem has a block table and cells are short on average (as for one problem)
+    bool tables = b->transpose;
+    int64_t nnz = 0;
+    for (int i = 0; i < P; ++i) {
+        tables = tables && G[i].tblk;
+        nnz += G[i].nnz;
+    }
+    const double mean = (double)nnz / ((double)P * (double)p->Ng * (double)p->Ng);
+    if (st == WP_OK && tables && mean < 512.0) {
+        std::vector<int2> items;
+        int64_t maxn = 0;
+        for (int i = 0; i < P; ++i) {
+            maxn = std::max(maxn, G[i].n_tblk);
+            for (int64_t bi = 0; bi < G[i].n_tblk; bi += GB_ITEM) items.push_back(make_int2(i, (int)bi));
+        }
+        if (items.size() > 0x7fffffff || maxn > 0x7fffffff) {
+            st = wp_set_error(WP_ECAPACITY, "too many batch gather blocks");
+        } else if (!items.empty()) {
+            hipError_t e2 = hipMalloc(&b->d_items_blk, sizeof(int2) * items.size());
+            if (e2 == hipSuccess)
+                e2 = hipMemcpy(b->d_items_blk, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice);
+            if (e2 != hipSuccess) st = wp_set_error(WP_EHIP, "batch block items: %s", hipGetErrorString(e2));
+            b->n_items_blk = (int)items.size();
+            b->blocks = st == WP_OK;
+        }
+    }
     if (st != WP_OK) {
         batch_destroy(b);
         return st;
@@ -325,6 +395,7 @@ void batch_destroy(wp_batch *b) {
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_items_deg) (void)hipFree(b->d_items_deg);
     if (b->d_items_gat) (void)hipFree(b->d_items_gat);
+    if (b->d_items_blk) (void)hipFree(b->d_items_blk);
     if (b->d_counter) (void)hipFree(b->d_counter);
     delete b;
 }

@@ -16,19 +16,13 @@
 // Gather  the same product from the transposed copy, every cell written once: one
 //   wavefront per block of short cells (full-wave loads whatever the cell lengths),
 //   or one lane group per cell when cells are long.
-#include "common.h"
+#include "gather_block.h"
 
 namespace {
 
 constexpr int SP_NTH = 256;
 constexpr int WAVES = SP_NTH / 64;
 
-// orders a wave's LDS stores before its later LDS loads by other lanes (no workgroup barrier)
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 
 // LPR lanes per row (64 / LPR rows per wave); each lane keeps U taps in flight.
@@ -296,66 +290,10 @@ __global__ __launch_bounds__(SP_NTH) void k_gather_wave(const int64_t *__restric
                                                         const float2 *__restrict__ y, const int *__restrict__ perm,
                                                         float2 *__restrict__ grid) {
     __shared__ float2 s_p[GW_WAVES][CH];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t bi = (int64_t)blockIdx.x * GW_WAVES + wv;
-    if (bi >= nblk) return;               // waves leave on their own: nothing below syncs the workgroup
-    const int64_t ca = tblk[2 * bi], ea = tblk[2 * bi + 1], cb = tblk[2 * bi + 2], eb = tblk[2 * bi + 3];
-    const int nc = (int)(cb - ca);
-    if (nc <= 0) return;
-    int L = 64;
-    while (L > 1 && L * nc > 64) L >>= 1;
-    const int q = lane / L, sub = lane & (L - 1);
-    int64_t qb = 0, qe = 0;               // entries of this lane group's cell
-    if (q < nc) {
-        qb = tcolptr[ca + q];
-        qe = tcolptr[ca + q + 1];
-    }
-    float2 *sp = s_p[wv];
-    float ar = 0.f, ai = 0.f;
-    for (int64_t c0 = ea; c0 < eb; c0 += CH) {
-        const int n = (int)min((int64_t)CH, eb - c0);
-        constexpr int PER = CH / 64;
-        int k[PER];
-        float2 v[PER];
-#pragma unroll
-        for (int t = 0; t < PER; ++t) {
-            const int e = t * 64 + lane;
-            if (e < n) {
-                k[t] = trow[c0 + e];
-                v[t] = load_tap_raw<TK>(tval, c0 + e);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < PER; ++t) {
-            const int e = t * 64 + lane;
-            if (e < n) {
-                const int r = k[t];
-                float2 g = v[t];
-                if constexpr (TK == WP_TAPS_I16) {
-                    const float sc = rscale[r];
-                    g.x *= sc;
-                    g.y *= sc;
-                }
-                const float2 yk = y[perm ? perm[r] : r];
-                sp[e] = make_float2(fmaf(g.x, yk.x, g.y * yk.y), fmaf(g.x, yk.y, -g.y * yk.x));   // conj(G) y
-            }
-        }
-        wave_sync();
-        if (q < nc) {
-            const int lo = (int)(max(qb, c0) - c0), hi = (int)(min(qe, c0 + n) - c0);
-            for (int e = lo + sub; e < hi; e += L) {
-                const float2 p = sp[e];
-                ar += p.x;
-                ai += p.y;
-            }
-        }
-        wave_sync();                      // the next chunk overwrites the slice
-    }
-    for (int o = L / 2; o > 0; o >>= 1) {
-        ar += __shfl_xor(ar, o);
-        ai += __shfl_xor(ai, o);
-    }
-    if (sub == 0 && q < nc) grid[ca + q] = make_float2(ar, ai);
+    const int64_t bi = (int64_t)blockIdx.x * GW_WAVES + (threadIdx.x >> 6);
+    if (bi >= nblk) return;               // waves leave on their own: nothing in a block's sum syncs the workgroup
+    gather_block<TK, CH>(tblk, bi, tcolptr, trow, tval, rscale, y, perm, grid, s_p[threadIdx.x >> 6],
+                         threadIdx.x & 63);
 }
 
 __global__ void k_permute(const float2 *__restrict__ in, const int *__restrict__ perm, float2 *__restrict__ out,
