@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import numpy as np
 
-_STREAM = {"sky": 1, "uvw": 2, "noise": 3, "x": 4, "y": 5, "subset": 6, "mlp": 7, "train": 8}
+_STREAM = {"sky": 1, "uvw": 2, "noise": 3, "x": 4, "y": 5, "subset": 6, "mlp": 7, "train": 8, "sweep": 9}
 
 
 def rng_for(seed: int, stream: str, sub: int = 0) -> np.random.Generator:
