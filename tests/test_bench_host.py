@@ -1,0 +1,65 @@
+"""Host logic of bench.py (CPU only): the one-GPU guard and the algorithmic byte counts behind the
+roofline figures."""
+import os
+import subprocess
+import sys
+from types import SimpleNamespace
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in out.stdout
+
+
+class _T:
+    """Stand-in for a 1-D device tensor: numel / cpu().numpy()."""
+
+    def __init__(self, a):
+        self.a = np.asarray(a)
+
+    def numel(self):
+        return self.a.size
+
+    def cpu(self):
+        return self
+
+    def numpy(self):
+        return self.a
+
+
+def test_byte_counts_follow_their_definitions():
+    M, Ng, nnz = 3, 8, 10
+    G = SimpleNamespace(nnz=nnz, n_work=4, tblk=_T(np.zeros(2 * 6)), n_tblk=5, fdat=_T(np.zeros(200)))
+    # degrid from stored taps: taps + 4-byte columns, rowptr, perm, y, one grid read
+    assert bench.degrid_bytes(G, M, Ng, 8) == 10 * 12 + 4 * 8 + 3 * 4 + 3 * 8 + 64 * 8
+    # gather: transposed copy, cell offsets, block table (16 bytes per pair), y, grid written once
+    assert bench.gather_bytes(G, M, Ng, 4) == 10 * 8 + 65 * 8 + 6 * 16 + 3 * 8 + 64 * 8
+    # degrid from factor records: the records, their offsets, y, one grid read
+    assert bench.factor_degrid_bytes(G, M, Ng) == 200 + 4 * 8 + 3 * 8 + 64 * 8
+    G.tblk = None
+    assert bench.gather_bytes(G, M, Ng, 4) == 10 * 8 + 65 * 8 + 3 * 8 + 64 * 8
+
+
+def test_traffic_is_reported_only_for_the_profiled_source(tmp_path, monkeypatch):
+    """profiled_traffic returns a figure only while the sparse-product source hashes as recorded."""
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    src = tmp_path / "paper_1307_3424_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "spmv.hip").write_bytes(b"kernel source")
+    import hashlib
+    h = hashlib.sha256(b"kernel source").hexdigest()[:16]
+    (prof / "spmv_plain-256_traffic.md").write_text(f"spmv_source_sha256_16={h}\ntraffic_bytes.k_degrid=1234\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.profiled_traffic("plain-256-fp32", "k_degrid") == 1234.0
+    assert bench.profiled_traffic("plain-256-fp32", "k_gather_wave") is None
+    (src / "spmv.hip").write_bytes(b"changed source")
+    assert bench.profiled_traffic("plain-256-fp32", "k_degrid") is None
