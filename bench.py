@@ -78,10 +78,22 @@ def gather_bytes(G, M, Ng, tap_bytes):
     return G.nnz * (tap_bytes + 4) + (Ng * Ng + 1) * 8 + table + M * 8 + Ng * Ng * 8
 
 
+def sparse_source_hash():
+    """First 16 hex digits of the SHA-256 of the sparse-product sources (spmv.hip, then gather_block.h
+    when present): traffic counters stay valid while these files are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1307_3424_amd", "csrc")
+    for f in ("spmv.hip", "gather_block.h"):
+        path = os.path.join(csrc, f)
+        if os.path.exists(path):
+            h.update(open(path, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def profiled_traffic(workload_name, kernel):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter summary, or None if the
     summary is missing or the sparse-product source changed since the counters were taken."""
-    import hashlib
     tag = {"plain-256-fp32": "plain-256"}.get(workload_name)
     path = os.path.join(ROOT, "profiles", f"spmv_{tag}_traffic.md")
     if tag is None or not os.path.exists(path):
@@ -91,8 +103,7 @@ def profiled_traffic(workload_name, kernel):
         if "=" in line and not line.startswith(("#", "|", "`")):
             k, v = line.strip().split("=", 1)
             kv[k] = v
-    src = open(os.path.join(ROOT, "paper_1307_3424_amd", "csrc", "spmv.hip"), "rb").read()
-    if kv.get("spmv_source_sha256_16") != hashlib.sha256(src).hexdigest()[:16]:
+    if kv.get("spmv_source_sha256_16") != sparse_source_hash():
         return None
     v = kv.get(f"traffic_bytes.{kernel}")
     return float(v) if v is not None else None
