@@ -22,10 +22,18 @@ s2 = 1 / ||Phi||^2 (so tau (s1 ||Psi||^2 + s2 ||Phi||^2) = 0.98 < 1), zero
 start.  ||Phi||^2 comes from power iteration on Phi^H Phi from a given start
 vector.
 
+levels = 0 takes the Dirac basis Psi = I (Section 4.2), levels >= 1 the
+Daubechies-8 wavelets with that many levels.
+
+Residual image (Section 4.2): the difference of the dirty images of the
+reconstruction and of the original, x_res = Phi^H Phi x_rec - Phi^H Phi x
+(real part, the image domain is real).
+
 Pins (tests/test_oracle_solver.py): noiseless full coverage converges (SNR
-rises past 40 dB), the returned image satisfies the constraint, and a
-Dirac-basis special case against a closed-form projection.  Parity
-unpinned against the paper's printed SNRs (they need its test images).
+rises past 40 dB), the returned image satisfies the constraint, and the
+Dirac basis with Phi = I against its closed form (soft thresholding of y at
+the level where the residual norm equals eps).  Parity unpinned against the
+paper's printed SNRs (they need its test images).
 """
 from __future__ import annotations
 
@@ -74,3 +82,8 @@ def solve(y, apply, apply_adj, shape, eps: float, nu: float, iters: int,
             from .metrics import snr_out
             hist.append(snr_out(x_true, x))
     return (x, hist) if history else x
+
+
+def residual_image(apply, apply_adj, x_rec: np.ndarray, x_true: np.ndarray) -> np.ndarray:
+    """x_res = Re Phi^H Phi x_rec - Re Phi^H Phi x_true (Section 4.2)."""
+    return np.real(apply_adj(apply(x_rec))) - np.real(apply_adj(apply(x_true)))

@@ -19,6 +19,10 @@ a_k = sum_n h_n x_((2k+n) mod n), d_k = sum_n g_n x_((2k+n) mod n), stored
 approximation block.  The transform is orthonormal, so the synthesis is its
 transpose.
 
+Dirac basis: zero levels is the identity, Psi = I (the pixel basis that
+Section 2.3 names as maximally incoherent with the Fourier basis and that
+Section 4.2 uses beside Daubechies 8).
+
 Pins (tests/test_oracle_wavelet.py): sum h = sqrt(2), sum h^2 = 1, even-shift
 orthogonality, 8 vanishing moments of g, perfect reconstruction, db2 against
 its closed form (1 + sqrt 3, 3 + sqrt 3, 3 - sqrt 3, 1 - sqrt 3) / (4 sqrt 2).
@@ -92,6 +96,8 @@ def idwt2(c: np.ndarray, levels: int = 4, p: int = 8) -> np.ndarray:
     h = daubechies_lowpass(p)
     g = highpass(h)
     x = np.array(c, dtype=np.float64, copy=True)
+    if levels == 0:
+        return x
     n = x.shape[0] >> (levels - 1)
     for _ in range(levels):
         blk = x[:n, :n]
