@@ -46,10 +46,14 @@ def parse():
     ap.add_argument("--channels", type=int, default=0, help="batched form: first K channels only (0: all)")
     ap.add_argument("--train-epochs", type=int, default=300, help="surrogate form: training passes")
     ap.add_argument("--tol", type=float, default=1e-3, help="surrogate form: per-row energy error tolerance")
-    ap.add_argument("--sweep", choices=["energy", "coverage"], default=None,
+    ap.add_argument("--sweep", choices=["energy", "coverage", "images"], default=None,
                     help="the paper's experiments on synthetic skies (tiny-form geometry): reconstruction SNR "
-                         "and non-zero fraction against the preserved energy E, or SNR against uv coverage, "
-                         "for w_d = 0, U(0, 1) and 1; one JSON line per point")
+                         "and non-zero fraction against the preserved energy E, SNR against uv coverage "
+                         "(Dirac and Daubechies-8 bases), or the reconstructed, error and residual images at "
+                         "10 %% coverage and E = 0.75; for w_d = 0, U(0, 1) and 1; one JSON line per point")
+    ap.add_argument("--images-out", default=None,
+                    help="--sweep images: also write the sky and every scenario's reconstructed, error and "
+                         "residual images to this .npz file")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for hardware byte counters)")
     return ap.parse_args()
@@ -459,7 +463,10 @@ def bench_sweep(args):
     """Section 4's experiments on synthetic skies with the GPU path (tiny-form geometry, N = 64):
     visibilities uniform in the band with w = w_d w_max (w_max = N / (2 L^2): the chirp spans the
     field's band), data from the E = 1 operator plus 30 dB noise, reconstruction with the operator
-    sparsified at E (200 primal-dual iterations, Daubechies-8 analysis, positivity)."""
+    sparsified at E (200 primal-dual iterations, positivity) in the Daubechies-8 basis, and for the
+    coverage sweep also in the Dirac basis (Section 4.2).  The images sweep (10 % coverage,
+    E = 0.75, Daubechies 8) also reports the error image x - x_rec and the residual image
+    Re Phi^H Phi x_rec - Re Phi^H Phi x, with Phi the operator at E (Section 4.2)."""
     import torch
     import paper_1307_3424_amd as wp
     import synth
@@ -473,10 +480,15 @@ def bench_sweep(args):
     xd = torch.from_numpy(x.astype(np.complex64).ravel()).to(dev)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     w_max = N / (2 * L * L)
+    bases = [("db8", 4)]
     if args.sweep == "energy":
         points = [(0.5, E) for E in (0.1, 0.25, 0.5, 0.75, 0.9, 0.99, 0.999, 1.0)]
-    else:
+    elif args.sweep == "coverage":
         points = [(c, 0.99) for c in (0.1, 0.3, 0.5, 0.7, 0.9)]
+        bases = [("dirac", 0), ("db8", 4)]
+    else:
+        points = [(0.1, 0.75)]
+    images = {"sky": x}
     for wd in ("0", "U(0,1)", "1"):
         for cov, E in points:
             M = int(round(cov * Ng * Ng))
@@ -499,20 +511,34 @@ def bench_sweep(args):
             eps = float(np.sqrt(sig ** 2 * (M + 2 * np.sqrt(M))))
             x0 = torch.from_numpy(synth.rng_for(wl.seed, "x").normal(size=N * N).astype(np.float32)).to(dev)
             nu = wp.power_norm2(plan, G, x0, 50)
-            xr = torch.zeros(N * N, dtype=torch.float32, device=dev)
-            s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            torch.cuda.synchronize()
-            s_ev.record()
-            wp.solve(plan, G, ys, eps, nu, iters, 4, x=xr)
-            e_ev.record()
-            torch.cuda.synchronize()
-            xr_h = xr.cpu().numpy().reshape(N, N).astype(np.float64)
-            snr = float(20 * np.log10(np.std(x) / np.std(x - xr_h)))
-            rec = {"sweep": args.sweep, "w_d": wd, "coverage": cov, "M": M, "E": E,
-                   "nnz_fraction": G.nnz / (M * Ng * Ng), "nnz_fraction_E1": nnz1 / (M * Ng * Ng),
-                   "snr_out_db": snr, "iterations": iters, "solve_ms": s_ev.elapsed_time(e_ev)}
-            print(json.dumps(rec), flush=True)
+            for basis, levels in bases:
+                xr = torch.zeros(N * N, dtype=torch.float32, device=dev)
+                s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                s_ev.record()
+                wp.solve(plan, G, ys, eps, nu, iters, levels, x=xr)
+                e_ev.record()
+                torch.cuda.synchronize()
+                xr_h = xr.cpu().numpy().reshape(N, N).astype(np.float64)
+                snr = float(20 * np.log10(np.std(x) / np.std(x - xr_h)))
+                rec = {"sweep": args.sweep, "w_d": wd, "coverage": cov, "M": M, "E": E, "basis": basis,
+                       "nnz_fraction": G.nnz / (M * Ng * Ng), "nnz_fraction_E1": nnz1 / (M * Ng * Ng),
+                       "snr_out_db": snr, "iterations": iters, "solve_ms": s_ev.elapsed_time(e_ev)}
+                if args.sweep == "images":
+                    # dirty images of the reconstruction and of the sky through the operator at E
+                    dirty = lambda img: wp.apply_PhiT(plan, G, wp.apply_Phi(plan, G, img)).real
+                    res = (dirty(xr.to(torch.complex64)) - dirty(xd)).cpu().numpy().reshape(N, N)
+                    err = x - xr_h
+                    rec.update({"error_rms": float(np.sqrt(np.mean(err ** 2))),
+                                "error_max": float(np.abs(err).max()),
+                                "residual_rms": float(np.sqrt(np.mean(res.astype(np.float64) ** 2))),
+                                "dirty_sky_rms": float(np.sqrt(np.mean(
+                                    dirty(xd).cpu().numpy().astype(np.float64) ** 2)))})
+                    images[f"wd={wd}"] = np.stack([xr_h, err, res.astype(np.float64)])
+                print(json.dumps(rec), flush=True)
             del G
+    if args.sweep == "images" and args.images_out:
+        np.savez_compressed(args.images_out, **images)
 
 
 def main():

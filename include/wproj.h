@@ -402,14 +402,17 @@ wp_status wp_surrogate_solve(const wp_plan *plan, const wp_surrogate *sur, const
 
 /* ----------------------------------------------------------------------------------------
  * Reconstruction (Eq. 7): min ||Psi^T x||_1 s.t. ||y - Phi x||_2 <= eps, x >= 0, with Psi the
- * Daubechies wavelets of 8 vanishing moments (Section 4.2), periodic, `levels` levels.
+ * Daubechies wavelets of 8 vanishing moments (Section 4.2), periodic, `levels` levels, or with
+ * levels = 0 the Dirac (pixel) basis Psi = I, Section 4.2's other dictionary (Section 2.3: maximally
+ * incoherent with the Fourier basis).
  * ------------------------------------------------------------------------------------- */
 
 /* The 16 low-pass taps of Daubechies-8 (spectral factorisation, minimum phase, sum sqrt 2); host. */
 wp_status wp_db8_filter(double *h16);
 
 /* c = Psi^T x (analysis) and x = Psi c (synthesis) of a real N x N float image; x and c may
- * alias; scratch is N*N floats of device memory.  levels >= 1 with N >> (levels-1) >= 8. */
+ * alias; scratch is N*N floats of device memory.  levels = 0 (Dirac basis: a copy) or levels >= 1
+ * with N >> (levels-1) >= 8; other values return WP_EINVAL. */
 wp_status wp_dwt2(const wp_plan *plan, int levels, const float *x, float *c, float *scratch,
                   void *stream);
 wp_status wp_idwt2(const wp_plan *plan, int levels, const float *c, float *x, float *scratch,

@@ -390,7 +390,6 @@ wp_status wp_solve(const wp_plan *p, const wp_G *G, const void *y, double eps, d
     if (!(eps >= 0.0) || !(nu > 0.0) || !std::isfinite(eps) || !std::isfinite(nu))
         return wp_set_error(WP_EINVAL, "eps = %g, nu = %g: need eps >= 0 and nu > 0, finite", eps, nu);
     if (iters < 0) return wp_set_error(WP_EINVAL, "iters = %d", iters);
-    if (levels < 1 || (p->N >> (levels - 1)) < 8) return wp_set_error(WP_EINVAL, "levels = %d", levels);
     return launch_solve(p, wp_operator{G, nullptr, G->M}, (const float2 *)y, eps, nu, iters, levels, x,
                         (unsigned char *)workspace,
                         as_stream(stream));

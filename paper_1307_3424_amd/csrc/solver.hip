@@ -3,7 +3,8 @@
 //   min_x ||Psi^T x||_1  s.t.  ||y - Phi x||_2 <= eps,  x >= 0 (real)
 //
 // Psi: Daubechies wavelets with p = 8 vanishing moments (16 taps), periodic,
-// multi-level, rows then columns per level (Section 4.2 uses Daubechies 8).
+// multi-level, rows then columns per level (Section 4.2 uses Daubechies 8), or
+// with zero levels the Dirac basis Psi = I (Section 4.2's other dictionary).
 // Splitting: primal-dual with one dual variable per term (Condat 2013 / Vu 2013):
 //   x+  = max(0, x - tau (Psi v1 + Re Phi^H v2)) ;  xb = 2 x+ - x ;  x = x+
 //   v1  = clip(v1 + s1 Psi^T xb, -1, 1)
@@ -235,12 +236,20 @@ int64_t solver_workspace_bytes(const wp_plan *p, int64_t M) {
     return al(8 * G2) + 4 * al(4 * N2) + 2 * al(8 * N2) + 2 * al(8 * M) + al(64);
 }
 
+// 0 (Dirac basis) or 1 .. while the coarsest level still has at least 8 samples per line
+static wp_status check_levels(const wp_plan *p, int levels) {
+    if (levels < 0 || levels > 30 || (levels > 0 && (p->N >> (levels - 1)) < 8))
+        return wp_set_error(WP_EINVAL, "levels = %d: need 0 (Dirac) or 1 .. with N >> (levels-1) >= 8, N = %d",
+                            levels, p->N);
+    return WP_OK;
+}
+
 wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s) {
+    if (wp_status st = check_levels(p, levels)) return st;
     bool ok;
     const Filt f = make_filter(ok);
     if (!ok) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
     const int N = p->N;
-    if (levels < 1 || (N >> (levels - 1)) < 8) return wp_set_error(WP_EINVAL, "levels = %d too many for N = %d", levels, N);
     if (c != x) {
         WP_HIP(hipMemcpyAsync(c, x, sizeof(float) * N * N, hipMemcpyDeviceToDevice, s));
     }
@@ -313,15 +322,21 @@ wp_status launch_solve(const wp_plan *p, const wp_operator &op, const float2 *y,
     float2 *v2 = (float2 *)take(8 * M);
     float2 *pv = (float2 *)take(8 * M);
     double *acc = (double *)take(64);
+    if (wp_status st = check_levels(p, levels)) return st;
+    // Dirac basis: Psi v1 = v1 and Psi^T xb = xb are read in place
+    const bool dirac = levels == 0;
+    const float *psi_v1 = dirac ? v1 : t1, *psit_xb = dirac ? xb : t1;
     const float tau = 0.49f, s1 = 1.0f, s2 = (float)(1.0 / nu);
     WP_HIP(hipMemsetAsync(v1, 0, 4 * N2, s));
     WP_HIP(hipMemsetAsync(v2, 0, 8 * M, s));
     for (int it = 0; it < iters; ++it) {
-        if (wp_status st = launch_dwt2(p, levels, v1, t1, tmp, true, s)) return st;           // Psi v1
+        if (!dirac)
+            if (wp_status st = launch_dwt2(p, levels, v1, t1, tmp, true, s)) return st;       // Psi v1
         if (wp_status st = op_phiT(p, op, v2, t2, grid, s)) return st;                        // Phi^H v2
-        hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, t1, t2, xb, xbc, N2, tau, acc);
-        if (wp_status st = launch_dwt2(p, levels, xb, t1, tmp, false, s)) return st;          // Psi^T xb
-        hipLaunchKernelGGL(k_dual1, blocks_for(N2), dim3(NT), 0, s, v1, t1, N2, s1);
+        hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, psi_v1, t2, xb, xbc, N2, tau, acc);
+        if (!dirac)
+            if (wp_status st = launch_dwt2(p, levels, xb, t1, tmp, false, s)) return st;      // Psi^T xb
+        hipLaunchKernelGGL(k_dual1, blocks_for(N2), dim3(NT), 0, s, v1, psit_xb, N2, s1);
         if (wp_status st = op_phi(p, op, xbc, pv, grid, s)) return st;                        // Phi xb
         hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, v2, pv, y, M, s2, acc);
         hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, v2, pv, y, M, s2, eps, acc);

@@ -28,7 +28,7 @@ def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-@pytest.mark.parametrize("N,levels", [(64, 4), (256, 4), (128, 2), (32, 3)])
+@pytest.mark.parametrize("N,levels", [(64, 4), (256, 4), (128, 2), (32, 3), (64, 0)])
 def test_dwt_matches_oracle(N, levels):
     print(f"dwt N={N} levels={levels}", flush=True)
     plan = wp.Plan(N, synth.fov_L())
@@ -86,3 +86,33 @@ def test_solve_tiny_form_matches_oracle(order):
     print(f"SNR_out gpu {snr_g:.3f} dB, oracle {snr_r:.3f} dB", flush=True)
     assert abs(snr_g - snr_r) < 0.1
     assert np.all(xg >= 0)
+
+
+def test_solve_dirac_basis_matches_oracle():
+    """levels = 0: the Dirac (pixel) basis of Section 4.2."""
+    wl, x, u, v, w, s, A, AH, y, eps, x0 = _tiny_problem()
+    print(f"solve dirac: {wl.name} {wl.iters} iterations", flush=True)
+    nu = solver.power_norm2(A, AH, x0, 50)
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E)
+    yd = c64(y)
+    x5 = wp.solve(plan, G, yd, eps, nu, 5, levels=0).cpu().numpy().reshape(wl.N, wl.N)
+    x5_ref = solver.solve(y, A, AH, (wl.N, wl.N), eps, nu, 5, levels=0)
+    assert relerr(x5, x5_ref) < 1e-4
+    xg = wp.solve(plan, G, yd, eps, nu, wl.iters, levels=0).cpu().numpy().reshape(wl.N, wl.N)
+    x_ref = solver.solve(y, A, AH, (wl.N, wl.N), eps, nu, wl.iters, levels=0)
+    snr_g, snr_r = metrics.snr_out(x, xg), metrics.snr_out(x, x_ref)
+    print(f"SNR_out dirac gpu {snr_g:.3f} dB, oracle {snr_r:.3f} dB", flush=True)
+    assert abs(snr_g - snr_r) < 0.1
+    assert np.all(xg >= 0)
+    # the two dictionaries give different estimates
+    xw = wp.solve(plan, G, yd, eps, nu, 5).cpu().numpy().reshape(wl.N, wl.N)
+    assert relerr(xw, x5) > 1e-3
+
+
+def test_levels_rejected():
+    plan = wp.Plan(64, synth.fov_L())
+    x = f32(np.zeros((64, 64)))
+    for bad in (-1, 5):          # 64 >> 4 = 4 < 8 samples per line at the coarsest level
+        with pytest.raises(wp.WprojError):
+            wp.dwt2(plan, x, bad)
