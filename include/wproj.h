@@ -179,8 +179,12 @@ wp_status wp_build_workspace_bytes(const wp_plan *plan, int64_t M, int64_t *byte
  *   E          preserved energy fraction, 0 < E <= 1
  *   workspace  device, wp_build_workspace_bytes(M) bytes, kept until pass 2
  *   nnz_out    host: total taps; n_work_out host: adjoint work items
- * Synchronises the stream (reads back two counts).  The linear chirp only;
- * WP_CHIRP_EXACT returns WP_EUNSUPPORTED.
+ * Synchronises the stream (reads back two counts).
+ * WP_CHIRP_EXACT (Eq. 4, not separable): each row is made whole, a 2-D FP64 FFT of the
+ * chirp on the Ng x Ng padded grid with the window's correlation per axis, in chunks of
+ * rows held in the workspace; needs Ng <= 512 (else WP_EUNSUPPORTED) and 2 L^2 < 1 (the
+ * square root stays real over the padded grid; else WP_EINVAL).  Its tau search splits
+ * the bracket in 16 per pass over the row instead of bisecting.
  */
 wp_status wp_build_G_count(const wp_plan *plan, int64_t M, const double *u, const double *v,
                            const double *w, double E, void *workspace,
@@ -194,7 +198,10 @@ wp_status wp_build_G_count(const wp_plan *plan, int64_t M, const double *u, cons
  * factor records (G->fbytes must equal wp_build_factor_bytes's value, else WP_EINVAL).
  * The caller sets G->M = M, G->nnz and G->n_work from pass 1, G->taps, and
  * points the arrays at buffers of the sizes listed in wp_G.  Same u, v, w, E
- * and workspace as pass 1 (pass 2 also uses part of it as scratch).
+ * and workspace as pass 1 (pass 2 also uses part of it as scratch).  Synchronises the
+ * stream at the end: pass 2 recomputes every row, and a row whose kept count (or factor
+ * record) differs from pass 1's returns WP_EHIP.  Factor records are not made for the
+ * exact chirp (WP_EUNSUPPORTED, also from wp_build_factor_bytes).
  */
 wp_status wp_build_G_fill(const wp_plan *plan, int64_t M, const double *u, const double *v,
                           const double *w, double E, void *workspace, wp_G *G,

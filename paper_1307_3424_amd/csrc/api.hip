@@ -194,6 +194,8 @@ wp_status wp_plan_info(const wp_plan *p, int64_t *Ng_out, int64_t *grid_bytes_ou
 
 wp_status wp_build_factor_bytes(const wp_plan *p, int64_t M, void *workspace, int64_t *bytes, void *stream) {
     if (wp_status s = check_plan(p)) return s;
+    if (p->chirp == WP_CHIRP_EXACT)
+        return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp's rows are not separable (no factor records)");
     if (!workspace || !bytes) return wp_set_error(WP_EINVAL, "workspace or bytes_out is NULL");
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     return launch_build_factor_bytes(p, M, workspace, bytes, as_stream(stream));
@@ -204,6 +206,17 @@ wp_status wp_gather_table_size(const wp_plan *p, int64_t nnz, int64_t *n) {
     if (!n) return wp_set_error(WP_EINVAL, "n_tblk_out is NULL");
     if (nnz < 0) return wp_set_error(WP_EINVAL, "nnz < 0");
     *n = gather_table_slots(nnz, (int64_t)p->Ng * p->Ng, p->gb_ent);
+    return WP_OK;
+}
+
+// the exact chirp: whole 2-D rows (Ng <= EXACT_MAX_NG), and sqrt(1 - l^2 - m^2) real over the
+// padded grid (its corner sits at l = m = -L)
+static wp_status check_exact(const wp_plan *p) {
+    if (p->chirp != WP_CHIRP_EXACT) return WP_OK;
+    if (p->Ng > EXACT_MAX_NG)
+        return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp needs Ng <= %d (Ng = %d)", EXACT_MAX_NG, p->Ng);
+    if (!(2.0 * p->L * p->L < 1.0))
+        return wp_set_error(WP_EINVAL, "build: the exact chirp needs 2 L^2 < 1 (L = %g)", p->L);
     return WP_OK;
 }
 
@@ -221,8 +234,7 @@ wp_status wp_build_G_count(const wp_plan *p, int64_t M, const double *u, const d
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     if (!u || !v || !w || !ws || !nnz_out || !n_work_out) return wp_set_error(WP_EINVAL, "NULL argument");
     if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
-    if (p->chirp != WP_CHIRP_LINEAR)
-        return wp_set_error(WP_EUNSUPPORTED, "build: only the linear chirp (separable rows) is built on the GPU");
+    if (wp_status s = check_exact(p)) return s;
     return launch_build_count(p, M, u, v, w, E, ws, nnz_out, n_work_out, as_stream(stream));
 }
 
@@ -232,9 +244,10 @@ wp_status wp_build_G_fill(const wp_plan *p, int64_t M, const double *u, const do
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     if (!u || !v || !w || !ws) return wp_set_error(WP_EINVAL, "NULL argument");
     if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
-    if (p->chirp != WP_CHIRP_LINEAR)
-        return wp_set_error(WP_EUNSUPPORTED, "build: only the linear chirp (separable rows) is built on the GPU");
+    if (wp_status s = check_exact(p)) return s;
     if (wp_status s = check_G(p, G, true)) return s;
+    if (p->chirp == WP_CHIRP_EXACT && (G->frec || G->fdat))
+        return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp's rows are not separable (no factor records)");
     if (G->M != M) return wp_set_error(WP_EINVAL, "G->M = %lld differs from M = %lld", (long long)G->M, (long long)M);
     return launch_build_fill(p, M, u, v, w, E, ws, G, as_stream(stream));
 }

@@ -28,107 +28,14 @@
 #include <cfloat>
 #include <cstdio>
 
+#include "builder_exact.h"
+#include "builder_util.h"
 #include "fft_lds.h"
 
 namespace {
 
-constexpr int BNTH = 256;      // builder block size
 constexpr int ROWS_PER_ITEM = 32;
 constexpr int64_t ROW_CHUNK = 1 << 22;     // rows per launch of the per-row kernels
-
-// ---------------------------------------------------------------------------- small device helpers
-
-
-__device__ inline double bessel_i0(double x) {
-    // power series sum_k ((x/2)^2)^k / (k!)^2
-    const double q = 0.25 * x * x;
-    double term = 1.0, sum = 1.0;
-    for (int k = 1; k < 200; ++k) {
-        term *= q / ((double)k * (double)k);
-        sum += term;
-        if (term < 1e-17 * sum) break;
-    }
-    return sum;
-}
-
-__device__ inline double kb_weight(double t, int W, double beta) {
-    const double r = 1.0 - (2.0 * t / W) * (2.0 * t / W);
-    return r >= 0.0 ? bessel_i0(beta * sqrt(r)) : 0.0;
-}
-
-struct Taps {
-    int q0;              // grid index (may be < 0 or >= Ng: taken mod Ng) of the first window cell
-    const double *wt;    // W window weights (LDS)
-};
-
-// Window cells and weights of one axis; the weights go to LDS (wt_lds[W]), written by the first W threads.
-__device__ inline Taps kb_taps(double gt, int W, double beta, int Ng, double *wt_lds) {
-    const int base = (int)floor(gt) - W / 2 + 1;     // centred index of the first cell
-    if ((int)threadIdx.x < W) wt_lds[threadIdx.x] = kb_weight(gt - (double)(base + (int)threadIdx.x), W, beta);
-    Taps t;
-    t.q0 = base + Ng / 2;
-    t.wt = wt_lds;
-    return t;
-}
-
-// g(q) = Ng^-1 sum_i wt_i h((q0 + i - q) mod Ng)
-__device__ inline double2 row_factor(const double2 *h, const Taps &t, int W, int q, int Ng) {
-    double2 g = make_double2(0.0, 0.0);
-    for (int i = 0; i < W; ++i) {
-        const double2 hv = h[(t.q0 + i - q) & (Ng - 1)];
-        g.x += t.wt[i] * hv.x;
-        g.y += t.wt[i] * hv.y;
-    }
-    const double s = 1.0 / Ng;
-    return make_double2(g.x * s, g.y * s);
-}
-
-// |g|^2 with one explicit fused multiply-add, so that every kernel that evaluates it
-// (both passes of the builder) gets the same bits
-__device__ inline double energy(double2 g) { return fma(g.x, g.x, g.y * g.y); }
-
-template <typename T>
-__device__ inline T block_sum(T v, T *red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    T s = 0;
-    for (int i = 0; i < BNTH / 64; ++i) s += red[i];
-    return s;
-}
-
-__device__ inline double block_max(double v, double *red) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    double s = red[0];
-    for (int i = 1; i < BNTH / 64; ++i) s = fmax(s, red[i]);
-    return s;
-}
-
-// exclusive scan of one int per thread over the block; returns the total
-__device__ inline int block_excl_scan(int v, int *red, int &total) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o);
-        if (lane >= o) x += y;
-    }
-    __syncthreads();
-    if (lane == 63) red[wid] = x;
-    __syncthreads();
-    int off = 0, tot = 0;
-    for (int i = 0; i < BNTH / 64; ++i) {
-        if (i < wid) off += red[i];
-        tot += red[i];
-    }
-    total = tot;
-    return off + x - v;
-}
 
 // Row setup shared by both passes: chirp, FFT, window taps.  h must hold Ng double2.
 template <int LOGNG>
@@ -721,7 +628,7 @@ inline int64_t align256(int64_t b) { return (b + 255) & ~(int64_t)255; }
 
 struct WsLayout {
     int64_t tau, nnz, key, k0, k1, i0, i1, flags, zpos, snnz, rowptr, sc32, sc64, tstart, tend, nch, choff, err,
-        tcnt, sc64t, gpos, fsz, frec, total;
+        tcnt, sc64t, gpos, fsz, frec, ex, total;
 };
 
 WsLayout ws_layout(const wp_plan *p, int64_t M) {
@@ -753,6 +660,9 @@ WsLayout ws_layout(const wp_plan *p, int64_t M) {
     L.gpos = take(4 * (cells + 1));
     L.fsz = take(4 * M);
     L.frec = take(8 * (M + 1));
+    // the exact chirp's 2-D rows of one chunk (values, or energies in the count pass)
+    L.ex = take(p->chirp == WP_CHIRP_EXACT && p->Ng <= EXACT_MAX_NG
+                    ? EX_ROW_BYTES_PER_CELL * exact_chunk_rows(p->Ng, M) * p->Ng * p->Ng : 0);
     L.total = o;
     return L;
 }
@@ -803,6 +713,53 @@ wp_status fill_rows(const wp_plan *p, int64_t M, const double *u, const double *
                                G->col, G->val, G->rscale, frec, fdat, err, r0);
     }
     return wp_check_launch("build_G_fill rows");
+}
+
+template <int LOGNG>
+wp_status count_rows_exact(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
+                           unsigned char *ws, const WsLayout &L, hipStream_t s) {
+    constexpr int Ng = 1 << LOGNG;
+    const int64_t B = exact_chunk_rows(Ng, M);
+    double2 *rows = (double2 *)(ws + L.ex);
+    double *en = (double *)(rows + B * Ng * Ng);       // energies beside the values
+    for (int64_t k0 = 0; k0 < M; k0 += B) {
+        const unsigned nb = (unsigned)std::min<int64_t>(B, M - k0);
+        hipLaunchKernelGGL((k_exact_rows<LOGNG>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, nullptr, k0,
+                           p->cell, p->delta, p->W, p->beta, p->tw64, rows);
+        hipLaunchKernelGGL((k_exact_cols<LOGNG, true>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, nullptr,
+                           k0, p->cell, p->beta, p->W, p->tw64, rows, en);
+        hipLaunchKernelGGL((k_exact_tau<LOGNG>), dim3(nb), dim3(BNTH), 0, s, u, v, w, k0, p->cell, E,
+                           (const double *)en, (double *)(ws + L.tau), (int *)(ws + L.nnz), (int *)(ws + L.key),
+                           (int *)(ws + L.fsz), (int *)(ws + L.err));
+    }
+    return wp_check_launch("build_G_count exact rows");
+}
+
+template <int LOGNG>
+wp_status fill_rows_exact(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                          const unsigned char *ws, const WsLayout &L, wp_G *G, hipStream_t s) {
+    constexpr int Ng = 1 << LOGNG;
+    const int64_t B = exact_chunk_rows(Ng, M);
+    double2 *rows = (double2 *)(const_cast<unsigned char *>(ws) + L.ex);    // scratch region of the workspace
+    const double *tau = (const double *)(ws + L.tau);
+    int *err = (int *)(const_cast<unsigned char *>(ws) + L.err);
+    for (int64_t r0 = 0; r0 < M; r0 += B) {
+        const unsigned nb = (unsigned)std::min<int64_t>(B, M - r0);
+        hipLaunchKernelGGL((k_exact_rows<LOGNG>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, G->perm, r0,
+                           p->cell, p->delta, p->W, p->beta, p->tw64, rows);
+        hipLaunchKernelGGL((k_exact_cols<LOGNG, false>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, G->perm,
+                           r0, p->cell, p->beta, p->W, p->tw64, rows, nullptr);
+        if (G->taps == WP_TAPS_BF16)
+            hipLaunchKernelGGL((k_exact_fill<LOGNG, WP_TAPS_BF16>), dim3(nb), dim3(BNTH), 0, s, rows, r0, tau,
+                               G->perm, G->rowptr, G->col, G->val, G->rscale, err);
+        else if (G->taps == WP_TAPS_I16)
+            hipLaunchKernelGGL((k_exact_fill<LOGNG, WP_TAPS_I16>), dim3(nb), dim3(BNTH), 0, s, rows, r0, tau,
+                               G->perm, G->rowptr, G->col, G->val, G->rscale, err);
+        else
+            hipLaunchKernelGGL((k_exact_fill<LOGNG, WP_TAPS_C64>), dim3(nb), dim3(BNTH), 0, s, rows, r0, tau,
+                               G->perm, G->rowptr, G->col, G->val, G->rscale, err);
+    }
+    return wp_check_launch("build_G_fill exact rows");
 }
 
 }  // namespace
@@ -872,7 +829,16 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
     const int T = p->ntile * p->ntile;
     WP_HIP(hipMemsetAsync(ws + L.err, 0, 16, s));
     wp_status st;
-    switch (p->logNg) {
+    if (p->chirp == WP_CHIRP_EXACT) {
+        switch (p->logNg) {
+            case 6: st = count_rows_exact<6>(p, M, u, v, w, E, ws, L, s); break;
+            case 7: st = count_rows_exact<7>(p, M, u, v, w, E, ws, L, s); break;
+            case 8: st = count_rows_exact<8>(p, M, u, v, w, E, ws, L, s); break;
+            case 9: st = count_rows_exact<9>(p, M, u, v, w, E, ws, L, s); break;
+            default: return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp needs Ng <= %d (Ng = %d)",
+                                         EXACT_MAX_NG, p->Ng);
+        }
+    } else switch (p->logNg) {
         case 6: st = count_rows<6>(p, M, u, v, w, E, ws, L, s); break;
         case 7: st = count_rows<7>(p, M, u, v, w, E, ws, L, s); break;
         case 8: st = count_rows<8>(p, M, u, v, w, E, ws, L, s); break;
@@ -949,7 +915,16 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
         WP_HIP(hipMemcpyAsync(G->frec, ws + L.frec, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
     }
     wp_status st;
-    switch (p->logNg) {
+    if (p->chirp == WP_CHIRP_EXACT) {
+        switch (p->logNg) {
+            case 6: st = fill_rows_exact<6>(p, M, u, v, w, ws, L, G, s); break;
+            case 7: st = fill_rows_exact<7>(p, M, u, v, w, ws, L, G, s); break;
+            case 8: st = fill_rows_exact<8>(p, M, u, v, w, ws, L, G, s); break;
+            case 9: st = fill_rows_exact<9>(p, M, u, v, w, ws, L, G, s); break;
+            default: return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp needs Ng <= %d (Ng = %d)",
+                                         EXACT_MAX_NG, p->Ng);
+        }
+    } else switch (p->logNg) {
         case 6: st = fill_rows<6>(p, M, u, v, w, ws, L, G, s); break;
         case 7: st = fill_rows<7>(p, M, u, v, w, ws, L, G, s); break;
         case 8: st = fill_rows<8>(p, M, u, v, w, ws, L, G, s); break;
@@ -1004,5 +979,12 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
             if ((st = wp_check_launch("build_G_fill gather blocks")) != WP_OK) return st;
         }
     }
+    // the fill pass recomputes every row: its kept counts must equal the count pass's
+    int host_err = 0;
+    WP_HIP(hipMemcpyAsync(&host_err, ws + L.err, 4, hipMemcpyDeviceToHost, s));
+    WP_HIP(hipStreamSynchronize(s));
+    if (host_err & 6)
+        return wp_set_error(WP_EHIP, "build_G_fill: a row's kept entries or factor record differ from pass 1 (flags %d)",
+                            host_err);
     return WP_OK;
 }

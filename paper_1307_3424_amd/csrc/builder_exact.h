@@ -1,0 +1,290 @@
+// Rows of G for the exact w-term (Eq. 4), which is not separable (Sections 3.1 and 3.2).
+//
+// Row k, for a visibility at grid coordinates (u~, v~) with component w:
+//   1. chirp c(l, m) = exp(-2 pi i w (sqrt(1 - l^2 - m^2) - 1)) on the padded grid,
+//      l = t_u delta, m = t_v delta, t in [-Ng/2, Ng/2) stored at index t mod Ng;
+//      sqrt(1 - r^2) - 1 is evaluated as -r^2 / (1 + sqrt(1 - r^2)) (no cancellation)
+//      and the phase 2 w r^2 / (1 + sqrt(1 - r^2)) goes to sincospi in FP64;
+//   2. H(d) = Ng^-2 sum_t c(t) exp(-2 pi i t.d / Ng): a 2-D FFT in FP64, rows in one
+//      kernel and columns in the next, both in LDS;
+//   3. g(q) = sum_{a,b} KB(u~ - q'_a) KB(v~ - q'_b) H(q' - q) (indices mod Ng).  The
+//      window is separable, so the correlation runs per axis inside the FFT kernels:
+//      along u after the row transform, along v after the column transform (both
+//      are linear and act on different axes, so the order is free);
+//   4. tau = the largest value with K(tau) >= E T, K(tau) = sum of the energies
+//      |g|^2 >= tau, T = K(0).  The search runs on the IEEE-754 bit patterns of the
+//      non-negative doubles (monotone): each pass over the row evaluates K at 15
+//      points splitting the bracket [lo, hi) into 16 (K(lo) >= E T > K(hi)), so 16
+//      passes close a 64-bit bracket.  It ends on an energy of the row, and the kept
+//      set {|g|^2 >= tau} (ties kept) is the sort-defined set; E >= 1 keeps every
+//      non-zero entry.
+// Rows are made in chunks (the 2-D rows of a chunk live in the builder's workspace);
+// the count pass stores each row's energies only, the fill pass its values, and the
+// fill writes the kept entries in ascending flattened column q_v Ng + q_u.
+#pragma once
+
+#include <cfloat>
+
+#include "builder_util.h"
+#include "fft_lds.h"
+
+namespace {
+
+constexpr int EX_LINES = 4;                      // rows / columns per block of the FFT passes
+constexpr int64_t EX_CHUNK_BYTES = 256ll << 20;  // 2-D rows in flight: at most this many bytes
+
+// rows per chunk for a plan: as many Ng x Ng rows (complex FP64 values, then FP64 energies beside
+// them) as EX_CHUNK_BYTES holds, at most 4096
+constexpr int64_t EX_ROW_BYTES_PER_CELL = 24;
+inline int64_t exact_chunk_rows(int Ng, int64_t M) {
+    int64_t b = EX_CHUNK_BYTES / (EX_ROW_BYTES_PER_CELL * Ng * Ng);
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return b < M ? b : M;
+}
+
+__device__ inline bool exact_coords(const double *u, const double *v, const double *w, int64_t k, double cell,
+                                    int Ng, double &ut, double &vt, double &wk) {
+    ut = u[k] / cell;
+    vt = v[k] / cell;
+    wk = w[k];
+    return isfinite(ut) && isfinite(vt) && isfinite(wk) && fabs(ut) < Ng / 2 && fabs(vt) < Ng / 2;
+}
+
+// Pass 1 of a chunk: chirp rows t_v = line, FFT along u, correlation along u with the u window.
+// Block (x, b) handles EX_LINES rows of chunk member b (visibility perm[base + b], or base + b
+// when perm is null).  out[b][t_v][q_u] (double2).
+template <int LOGNG>
+__global__ __launch_bounds__(BNTH) void k_exact_rows(const double *__restrict__ u, const double *__restrict__ v,
+                                                     const double *__restrict__ w, const int *__restrict__ perm,
+                                                     int64_t base, double cell, double delta, int W, double beta,
+                                                     const double2 *__restrict__ tw64, double2 *__restrict__ out) {
+    constexpr int Ng = 1 << LOGNG;
+    __shared__ double2 buf[EX_LINES * Ng];
+    __shared__ double s_wu[16];
+    const int b = blockIdx.y;
+    const int64_t k = perm ? (int64_t)perm[base + b] : base + b;
+    double ut, vt, wk;
+    const bool ok = exact_coords(u, v, w, k, cell, Ng, ut, vt, wk);
+    double2 *dst = out + ((int64_t)b * Ng + (int64_t)blockIdx.x * EX_LINES) * Ng;
+    if (!ok) {
+        for (int e = threadIdx.x; e < EX_LINES * Ng; e += BNTH) dst[e] = make_double2(0.0, 0.0);
+        return;
+    }
+    const Taps tu = kb_taps(ut, W, beta, Ng, s_wu);
+    for (int e = threadIdx.x; e < EX_LINES * Ng; e += BNTH) {
+        const int c = e / Ng, iu = e % Ng, iv = blockIdx.x * EX_LINES + c;
+        const double l = (iu < Ng / 2 ? iu : iu - Ng) * delta, m = (iv < Ng / 2 ? iv : iv - Ng) * delta;
+        const double r2 = l * l + m * m;
+        double sn, cs;
+        sincospi(2.0 * wk * r2 / (1.0 + sqrt(1.0 - r2)), &sn, &cs);
+        buf[e] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    lds_fft<double2, LOGNG, EX_LINES, BNTH, true, Ng>(buf, tw64, false, threadIdx.x);
+    for (int e = threadIdx.x; e < EX_LINES * Ng; e += BNTH) {
+        const int c = e / Ng, q = e % Ng;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < W; ++i) {
+            const double2 h = buf[c * Ng + ((tu.q0 + i - q) & (Ng - 1))];
+            acc.x += tu.wt[i] * h.x;
+            acc.y += tu.wt[i] * h.y;
+        }
+        dst[e] = acc;
+    }
+}
+
+// Pass 2 of a chunk: FFT along v of EX_LINES columns, correlation along v with the v window,
+// scale Ng^-2.  ENERGY: write |g|^2 to energy_out (double, [b][q_v][q_u], a region apart from
+// rows: other blocks still read their columns of rows) instead of g (double2, in place).
+template <int LOGNG, bool ENERGY>
+__global__ __launch_bounds__(BNTH) void k_exact_cols(const double *__restrict__ u, const double *__restrict__ v,
+                                                     const double *__restrict__ w, const int *__restrict__ perm,
+                                                     int64_t base, double cell, double beta, int W,
+                                                     const double2 *__restrict__ tw64, double2 *__restrict__ rows,
+                                                     double *__restrict__ energy_out) {
+    constexpr int Ng = 1 << LOGNG;
+    __shared__ double2 buf[Ng * EX_LINES];
+    __shared__ double s_wv[16];
+    const int b = blockIdx.y;
+    const int64_t k = perm ? (int64_t)perm[base + b] : base + b;
+    double ut, vt, wk;
+    const bool ok = exact_coords(u, v, w, k, cell, Ng, ut, vt, wk);
+    const int qu0 = blockIdx.x * EX_LINES;
+    double2 *src = rows + (int64_t)b * Ng * Ng;
+    const Taps tv = kb_taps(ok ? vt : 0.0, W, beta, Ng, s_wv);
+    for (int e = threadIdx.x; e < Ng * EX_LINES; e += BNTH) {
+        const int iv = e / EX_LINES, c = e % EX_LINES;
+        buf[e] = src[(int64_t)iv * Ng + qu0 + c];
+    }
+    __syncthreads();
+    lds_fft<double2, LOGNG, EX_LINES, BNTH, false, EX_LINES>(buf, tw64, false, threadIdx.x);
+    const double scale = 1.0 / ((double)Ng * (double)Ng);
+    for (int e = threadIdx.x; e < Ng * EX_LINES; e += BNTH) {
+        const int q = e / EX_LINES, c = e % EX_LINES;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int i = 0; i < W; ++i) {
+            const double2 h = buf[((tv.q0 + i - q) & (Ng - 1)) * EX_LINES + c];
+            acc.x += tv.wt[i] * h.x;
+            acc.y += tv.wt[i] * h.y;
+        }
+        const double2 g = ok ? make_double2(acc.x * scale, acc.y * scale) : make_double2(0.0, 0.0);
+        const int64_t at = (int64_t)q * Ng + qu0 + c;
+        if (ENERGY) energy_out[(int64_t)b * Ng * Ng + at] = energy(g);
+        else src[at] = g;
+    }
+}
+
+// Count pass, per row: tau, kept count, sort key.  One block per chunk member (visibility base + b).
+template <int LOGNG>
+__global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u, const double *__restrict__ v,
+                                                    const double *__restrict__ w, int64_t base, double cell,
+                                                    double E, const double *__restrict__ en,
+                                                    double *__restrict__ tau_out, int *__restrict__ nnz_out,
+                                                    int *__restrict__ key_out, int *__restrict__ fsz_out,
+                                                    int *__restrict__ err) {
+    constexpr int Ng = 1 << LOGNG;
+    constexpr int64_t CELLS = (int64_t)Ng * Ng;
+    constexpr int S = 16;                 // sub-brackets per pass
+    __shared__ double redd[BNTH / 64];
+    __shared__ long long redl[BNTH / 64];
+    __shared__ double s_acc[S];
+    const int b = blockIdx.x;
+    const int64_t k = base + b;
+    double ut, vt, wk;
+    if (!exact_coords(u, v, w, k, cell, Ng, ut, vt, wk)) {
+        if (threadIdx.x == 0) {
+            atomicOr(err, 1);
+            tau_out[k] = INFINITY;
+            nnz_out[k] = 0;
+            key_out[k] = 0;
+            fsz_out[k] = 0;
+        }
+        return;
+    }
+    const double *m = en + (int64_t)b * CELLS;
+    double tsum = 0.0, mmax = 0.0;
+    for (int64_t i = threadIdx.x; i < CELLS; i += BNTH) {
+        tsum += m[i];
+        mmax = fmax(mmax, m[i]);
+    }
+    const double T = block_sum(tsum, redd);
+    mmax = block_max(mmax, redd);
+    double tau;
+    if (E >= 1.0) {
+        tau = DBL_TRUE_MIN;                        // every non-zero entry
+    } else {
+        const double target = E * T;
+        unsigned long long lo = 0ull;              // K(lo) = T >= target
+        unsigned long long hi = (unsigned long long)__double_as_longlong(mmax) + 1ull;   // K(hi) = 0
+        while (hi - lo > 1ull) {
+            const unsigned long long span = hi - lo;
+            const int ns = span >= (unsigned long long)S ? S - 1 : (int)span - 1;   // interior points
+            unsigned long long cand[S - 1];
+#pragma unroll
+            for (int s = 0; s < S - 1; ++s) {
+                // lo + span (s + 1) / S without overflow, or lo + s + 1 for a short bracket
+                cand[s] = span >= (unsigned long long)S
+                              ? lo + (span / S) * (s + 1) + ((span % S) * (s + 1)) / S
+                              : lo + (unsigned long long)(s + 1);
+            }
+            double acc[S - 1];
+#pragma unroll
+            for (int s = 0; s < S - 1; ++s) acc[s] = 0.0;
+            for (int64_t i = threadIdx.x; i < CELLS; i += BNTH) {
+                const double mi = m[i];
+                const unsigned long long bits = (unsigned long long)__double_as_longlong(mi);
+#pragma unroll
+                for (int s = 0; s < S - 1; ++s) acc[s] += bits >= cand[s] ? mi : 0.0;
+            }
+            for (int s = 0; s < ns; ++s) {
+                const double K = block_sum(acc[s], redd);
+                if (threadIdx.x == 0) s_acc[s] = K;
+            }
+            __syncthreads();
+            // the largest candidate still holding the target, and the next one above it
+            unsigned long long nlo = lo, nhi = hi;
+            for (int s = 0; s < ns; ++s) {
+                if (s_acc[s] >= target) nlo = cand[s];
+                else { nhi = cand[s]; break; }
+            }
+            __syncthreads();
+            lo = nlo;
+            hi = nhi;
+        }
+        tau = __longlong_as_double((long long)lo);
+    }
+    long long cnt = 0;
+    for (int64_t i = threadIdx.x; i < CELLS; i += BNTH) cnt += m[i] >= tau;
+    cnt = block_sum(cnt, redl);
+    if (threadIdx.x == 0) {
+        tau_out[k] = tau;
+        nnz_out[k] = (int)cnt;
+        fsz_out[k] = 0;                            // no factor records: the rows are not separable
+        const int cu = min(max((int)floor(ut + Ng / 2), 0), Ng - 1);
+        const int cv = min(max((int)floor(vt + Ng / 2), 0), Ng - 1);
+        key_out[k] = morton2(cv, cu);
+    }
+}
+
+// Fill pass, per sorted row r = base + b: the kept entries in ascending flattened column.
+template <int LOGNG, int TK>
+__global__ __launch_bounds__(BNTH) void k_exact_fill(const double2 *__restrict__ rows, int64_t base,
+                                                     const double *__restrict__ tau_in, const int *__restrict__ perm,
+                                                     const int64_t *__restrict__ rowptr, int *__restrict__ col,
+                                                     void *__restrict__ val, float *__restrict__ rscale,
+                                                     int *__restrict__ err) {
+    constexpr int Ng = 1 << LOGNG;
+    constexpr int64_t CELLS = (int64_t)Ng * Ng;
+    constexpr int PER = 4;                          // consecutive entries per thread per tile
+    constexpr int TILE = BNTH * PER;
+    __shared__ double redd[BNTH / 64];
+    __shared__ int redi[BNTH / 64];
+    const int b = blockIdx.x;
+    const int64_t r = base + b;
+    const int k = perm[r];
+    const double tau = tau_in[k];
+    const int64_t beg = rowptr[r], len = rowptr[r + 1] - beg;
+    const double2 *g = rows + (int64_t)b * CELLS;
+    double i16_scale = 1.0;
+    if (TK == WP_TAPS_I16) {
+        // int16 block floating point: every entry |g| <= sqrt(max |g|^2)
+        double mmax = 0.0;
+        for (int64_t i = threadIdx.x; i < CELLS; i += BNTH) mmax = fmax(mmax, energy(g[i]));
+        mmax = block_max(mmax, redd);
+        i16_scale = sqrt(mmax) / 32767.0;
+        if (threadIdx.x == 0) rscale[r] = (float)i16_scale;
+    }
+    if (len == 0) return;
+    int64_t pos = beg;
+    for (int64_t t0 = 0; t0 < CELLS; t0 += TILE) {
+        double2 gv[PER];
+        int c = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int64_t q = t0 + threadIdx.x * PER + i;
+            gv[i] = g[q];
+            c += energy(gv[i]) >= tau;
+        }
+        int total;
+        int64_t p = pos + block_excl_scan(c, redi, total);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int64_t q = t0 + threadIdx.x * PER + i;
+            if (energy(gv[i]) >= tau) {
+                if (p < beg + len) {
+                    col[p] = (int)q;
+                    if (TK == WP_TAPS_BF16) ((uint32_t *)val)[p] = pack_bf16x2((float)gv[i].x, (float)gv[i].y);
+                    else if (TK == WP_TAPS_I16)
+                        ((uint32_t *)val)[p] = pack_i16x2((float)(gv[i].x / i16_scale), (float)(gv[i].y / i16_scale));
+                    else ((float2 *)val)[p] = make_float2((float)gv[i].x, (float)gv[i].y);
+                }
+                ++p;
+            }
+        }
+        pos += total;
+    }
+    if (threadIdx.x == 0 && pos - beg != len) atomicOr(err, 2);
+}
+
+}  // namespace

@@ -8,6 +8,9 @@
 
 // ---------------------------------------------------------------------------- plan
 
+// largest padded grid the exact chirp's builder takes (its 2-D rows are made whole)
+constexpr int EXACT_MAX_NG = 512;
+
 struct wp_plan {
     int N;          // image side
     int Ng;         // padded grid side (2N)

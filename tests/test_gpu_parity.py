@@ -492,8 +492,80 @@ def test_invalid_visibilities_raise():
         wp.build_G(plan, dev(good), dev(good), dev(good), 1.5)
 
 
-def test_exact_chirp_build_is_reported_unsupported():
-    plan = wp.Plan(64, L, chirp=wp.WP_CHIRP_EXACT)
+# --------------------------------------------------------------------------- exact chirp (Eq. 4)
+
+def test_exact_chirp_tiny_form_all_rows_and_operator():
+    wl = synth.workload(0)
+    say(f"build exact chirp: {wl.name} N={wl.N} M={wl.M}")
+    x, u, v, w = synth.workload_inputs(wl)
+    s = Setup(N=wl.N, L=wl.L, kind="exact")
+    plan = wp.Plan(wl.N, wl.L, chirp=wp.WP_CHIRP_EXACT)
+    G = build(plan, u, v, w, wl.E)
+    Go = wproj.build_rows(u, v, w, wl.E, s)
+    assert abs(G.nnz - Go.nnz) <= 1e-6 * Go.nnz
+    check_rows(G, u, v, w, wl.E, s, range(wl.M))
+    G.order = wp.WP_ORDER_CALLER
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    assert relerr(y, wproj.phi(Go, x, s)) < TOL
+    r = synth.random_complex(wl.M, np.random.default_rng(5))
+    xa = wp.apply_PhiT(plan, G, c64(r)).cpu().numpy().reshape(wl.N, wl.N)
+    assert relerr(xa, wproj.phi_adjoint(Go, r, s)) < TOL
+
+
+@pytest.mark.parametrize("E", [0.5, 1.0])
+def test_exact_chirp_wide_field(E):
+    """L = 0.5: the exact and linear chirps differ (O(w r^4)); E = 1 keeps every non-zero entry."""
+    N, M, Lw = 64, 96, 0.5
+    say(f"build exact chirp: wide field N={N} M={M} L={Lw} E={E}")
+    s = Setup(N=N, L=Lw, kind="exact")
+    u, v, w = synth.uvw(N, M, Lw, "uniform", 0.0, N / (2 * Lw * Lw), np.random.default_rng(21))
+    plan = wp.Plan(N, Lw, chirp=wp.WP_CHIRP_EXACT)
+    G = build(plan, u, v, w, E)
+    check_rows(G, u, v, w, E, s, range(M))
+    # the linear chirp's operator differs at this field size
+    plan_lin = wp.Plan(N, Lw)
+    G_lin = build(plan_lin, u, v, w, E)
+    G.order = G_lin.order = wp.WP_ORDER_CALLER
+    x = c64(np.random.default_rng(22).normal(size=(N, N)))
+    y = wp.apply_Phi(plan, G, x).cpu().numpy()
+    assert relerr(wp.apply_Phi(plan_lin, G_lin, x).cpu().numpy(), y) > 1e-3
+
+
+def test_exact_chirp_plain_form_sampled_rows():
+    wl = synth.workload(1)
+    M = 4096
+    say(f"build exact chirp: {wl.name} N={wl.N} first {M} visibilities (sampled rows)")
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    u, v, w = u[:M], v[:M], w[:M]
+    s = Setup(N=wl.N, L=wl.L, kind="exact")
+    plan = wp.Plan(wl.N, wl.L, chirp=wp.WP_CHIRP_EXACT)
+    G = build(plan, u, v, w, wl.E)
+    rows = np.unique(np.concatenate([synth.subset_rows(M, 20, synth.rng_for(wl.seed, "subset")), [0, M - 1]]))
+    check_rows(G, u, v, w, wl.E, s, rows)
+    rp, col, _, perm, _ = gpu_rows(G)
+    assert np.array_equal(np.sort(perm), np.arange(M))
+    assert rp[-1] == G.nnz and np.all(np.diff(rp) > 0) and col.max() < s.Ng ** 2
+
+
+@pytest.mark.parametrize("taps", ["bf16", "i16"])
+def test_exact_chirp_precision_forms(taps):
+    wl = synth.workload(0)
+    x, u, v, w = synth.workload_inputs(wl)
+    plan = wp.Plan(wl.N, wl.L, chirp=wp.WP_CHIRP_EXACT)
+    t = {"bf16": wp.WP_TAPS_BF16, "i16": wp.WP_TAPS_I16}[taps]
+    G = build(plan, u, v, w, wl.E, taps=t)
+    G.order = wp.WP_ORDER_CALLER
+    s = Setup(N=wl.N, L=wl.L, kind="exact")
+    Go = wproj.build_rows(u, v, w, wl.E, s)
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    assert relerr(y, wproj.phi(Go, x, s)) < {"bf16": 4e-3, "i16": 1e-4}[taps]
+
+
+def test_exact_chirp_limits():
     z = np.zeros(3)
-    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):
-        wp.build_G(plan, dev(z), dev(z), dev(z), 0.9)
+    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):      # Ng = 1024 > 512
+        wp.build_G(wp.Plan(512, L, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 0.9)
+    with pytest.raises(wp.WprojError, match="WP_EINVAL"):            # 2 L^2 >= 1
+        wp.build_G(wp.Plan(64, 0.75, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 0.9)
+    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):      # rows are not separable
+        wp.build_G(wp.Plan(64, L, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 0.9, factors=True)
