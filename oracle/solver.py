@@ -63,18 +63,30 @@ def project_ball(z: np.ndarray, y: np.ndarray, eps: float) -> np.ndarray:
 
 
 def solve(y, apply, apply_adj, shape, eps: float, nu: float, iters: int,
-          levels: int = 4, tau: float = 0.49, history: bool = False, x_true=None):
-    """Returns x (and the SNR history against x_true when asked)."""
+          levels: int = 4, tau: float = 0.49, history: bool = False, x_true=None,
+          dictionary=None, weights=None, x0=None):
+    """Returns x (and the SNR history against x_true when asked).
+
+    dictionary: optional (analysis, synthesis) pair replacing the wavelets of `levels`
+    (it must satisfy ||Psi|| <= 1, as a tight frame normalised to 1 does); weights: optional
+    non-negative array shaped like the coefficients, the weighted norm ||W Psi^T x||_1 (the
+    prox of its conjugate clips coefficient i to [-w_i, w_i]); x0: start (zeros by default).
+    """
+    if dictionary is None:
+        analysis, synthesis = (lambda z: dwt2(z, levels)), (lambda c: idwt2(c, levels))
+    else:
+        analysis, synthesis = dictionary
     s1 = 1.0
     s2 = 1.0 / nu
-    x = np.zeros(shape)
-    v1 = np.zeros(shape)
+    x = np.zeros(shape) if x0 is None else np.array(x0, dtype=np.float64)
+    v1 = np.zeros_like(analysis(np.zeros(shape)))
+    bound = 1.0 if weights is None else np.asarray(weights, dtype=np.float64)
     v2 = np.zeros(np.asarray(y).shape, dtype=np.complex128)
     hist = []
     for _ in range(iters):
-        xn = np.maximum(0.0, x - tau * (idwt2(v1, levels) + np.real(apply_adj(v2))))
+        xn = np.maximum(0.0, x - tau * (synthesis(v1) + np.real(apply_adj(v2))))
         xb = 2.0 * xn - x
-        v1 = np.clip(v1 + s1 * dwt2(xb, levels), -1.0, 1.0)
+        v1 = np.clip(v1 + s1 * analysis(xb), -bound, bound)
         u = v2 + s2 * apply(xb)
         v2 = u - s2 * project_ball(u / s2, y, eps)
         x = xn
