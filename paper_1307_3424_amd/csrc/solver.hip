@@ -86,36 +86,133 @@ struct Filt {
 };
 
 // ---------------------------------------------------------------------------- DWT kernels (FP32)
-// One level along lines of length L inside an image of row stride S: line i, element e
-// at in[i * ls + e * es].  Analysis: a_k = sum_n h_n x_(2k+n mod L), d_k = sum_n g_n x_(2k+n mod L),
-// stored [a | d].  Synthesis (the transpose): x_m = sum over n of m's parity of
-// h_n a_((m-n)/2 mod L/2) + g_n d_((m-n)/2 mod L/2).
-__global__ void k_dwt_lines(const float *__restrict__ in, float *__restrict__ out, int L, int lines, int ls,
-                            int es, Filt f, bool synth) {
+// One level along a line of length L (a power of two), H = L / 2.  Analysis:
+// a_k = sum_n h_n x_(2k+n mod L), d_k = sum_n g_n x_(2k+n mod L), stored [a | d].  Synthesis (the
+// transpose): x_m = sum over n of m's parity of h_n a_((m-n)/2 mod H) + g_n d_((m-n)/2 mod H);
+// m - n is even there, so (m - n) >> 1 is exact and & (H - 1) reduces it.  at(j) reads the line.
+template <typename At>
+__device__ __forceinline__ float dwt_tap_sum(At at, int m, int L, const Filt &f, bool synth) {
+    const int H = L >> 1;
+    float acc = 0.f;
+    if (!synth) {
+        const bool lo = m < H;
+        const int k = lo ? m : m - H;
+#pragma unroll
+        for (int n = 0; n < 16; ++n) acc = fmaf(lo ? f.h[n] : f.g[n], at((2 * k + n) & (L - 1)), acc);
+    } else {
+        const int odd = m & 1;
+#pragma unroll
+        for (int n = 0; n < 16; n += 2) {
+            const int nn = n + odd;
+            const int k = ((m - nn) >> 1) & (H - 1);
+            acc = fmaf(odd ? f.h[n + 1] : f.h[n], at(k), acc);
+            acc = fmaf(odd ? f.g[n + 1] : f.g[n], at(H + k), acc);
+        }
+    }
+    return acc;
+}
+
+// One pass of one level over `lines` lines of an image of row stride N: line i, element e at
+// [i * ls + e * es].  Element (i, e) is read from `in` when i < q and e < q, else from `in2`:
+// the synthesis reads the coarser levels' result (in) in the top-left quadrant and the original
+// coefficients (in2) elsewhere, which spares a copy of the coefficients; q = 0 reads in2 only.
+__global__ void k_dwt_lines(const float *__restrict__ in, const float *__restrict__ in2, int q,
+                            float *__restrict__ out, int L, int lines, int ls, int es, Filt f, bool synth) {
     extern __shared__ float line[];
     for (int i = blockIdx.x; i < lines; i += gridDim.x) {
-        for (int e = threadIdx.x; e < L; e += blockDim.x) line[e] = in[(int64_t)i * ls + (int64_t)e * es];
-        __syncthreads();
-        const int H = L / 2;
-        for (int m = threadIdx.x; m < L; m += blockDim.x) {
-            float acc = 0.f;
-            if (!synth) {
-                const int k = m < H ? m : m - H;
-                const float *w = m < H ? f.h : f.g;
-#pragma unroll
-                for (int n = 0; n < 16; ++n) acc = fmaf(w[n], line[(2 * k + n) % L], acc);
-            } else {
-#pragma unroll
-                for (int n = (m & 1); n < 16; n += 2) {
-                    int k = ((m - n) / 2) % H;
-                    if (k < 0) k += H;
-                    acc = fmaf(f.h[n], line[k], acc);
-                    acc = fmaf(f.g[n], line[H + k], acc);
-                }
-            }
-            out[(int64_t)i * ls + (int64_t)m * es] = acc;
+        for (int e = threadIdx.x; e < L; e += blockDim.x) {
+            const int64_t at = (int64_t)i * ls + (int64_t)e * es;
+            line[e] = (i < q && e < q) ? in[at] : in2[at];
         }
         __syncthreads();
+        for (int m = threadIdx.x; m < L; m += blockDim.x)
+            out[(int64_t)i * ls + (int64_t)m * es] = dwt_tap_sum([&](int j) { return line[j]; }, m, L, f, synth);
+        __syncthreads();
+    }
+}
+
+// One whole level (both axes) per kernel, tiled.  A coefficient (r, c) of a level depends on a
+// 16 x 16 window of its input, so a workgroup makes a tile of t x t positions of all four
+// subbands (t = min(DT, H)) from a (2t + 14)^2 window staged in LDS: first the row filters of every
+// window row, then the column filters, in the same order of operations as one pass per axis.
+constexpr int DT = 8;
+constexpr int DWIN = 2 * DT + 14;
+constexpr int DNT = 256;
+
+// Analysis of the top-left L x L block of `in` (row stride N; periodic in L).  The three detail
+// subbands go to det, the approximation (top-left H x H) to ll; both have row stride N.
+__global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, float *__restrict__ det,
+                                                  float *__restrict__ ll, int N, int L, Filt f) {
+    __shared__ float win[DWIN * DWIN];
+    __shared__ float R[DWIN * 2 * DT];
+    const int H = L >> 1, t = H < DT ? H : DT, tiles = H / t, w = 2 * t + 14;
+    const int kr0 = (blockIdx.x / tiles) * t, kc0 = (blockIdx.x % tiles) * t;
+    for (int e = threadIdx.x; e < w * w; e += DNT) {
+        const int i = e / w, j = e % w;
+        win[i * DWIN + j] = in[(int64_t)((2 * kr0 + i) & (L - 1)) * N + ((2 * kc0 + j) & (L - 1))];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < w * 2 * t; e += DNT) {          // rows: R[i][band * t + kc]
+        const int i = e / (2 * t), q = e % (2 * t), band = q / t, kc = q % t;
+        float acc = 0.f;
+#pragma unroll
+        for (int n = 0; n < 16; ++n) acc = fmaf(band ? f.g[n] : f.h[n], win[i * DWIN + 2 * kc + n], acc);
+        R[i * (2 * DT) + q] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * t * t; e += DNT) {          // columns
+        const int q = e % (2 * t), rr = e / (2 * t), band1 = rr / t, kr = rr % t;
+        float acc = 0.f;
+#pragma unroll
+        for (int n = 0; n < 16; ++n) acc = fmaf(band1 ? f.g[n] : f.h[n], R[(2 * kr + n) * (2 * DT) + q], acc);
+        const int band2 = q / t, kc = q % t;
+        const int r = band1 * H + kr0 + kr, c = band2 * H + kc0 + kc;
+        if (band1 == 0 && band2 == 0) ll[(int64_t)r * N + c] = acc;
+        else det[(int64_t)r * N + c] = acc;
+    }
+}
+
+// Synthesis of one level: the L x L result (row stride N) from coefficients whose top-left H x H
+// quadrant (the coarser levels' result) is read from llin and the three detail quadrants from
+// coef.  A tile of 2t x 2t outputs reads t + 8 positions of each band per axis.
+__global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef, const float *__restrict__ llin,
+                                                  float *__restrict__ out, int N, int L, Filt f) {
+    constexpr int CW = 2 * (DT + 8);
+    __shared__ float C[CW * CW];
+    __shared__ float Y[2 * DT * CW];
+    const int H = L >> 1, t = H < DT ? H : DT, tiles = H / t, w = t + 8;
+    const int mr0 = (blockIdx.x / tiles) * 2 * t, mc0 = (blockIdx.x % tiles) * 2 * t;
+    const int kr0 = (mr0 >> 1) - 8, kc0 = (mc0 >> 1) - 8;        // first coefficient of each window
+    for (int e = threadIdx.x; e < 4 * w * w; e += DNT) {
+        const int i = e / (2 * w), j = e % (2 * w);
+        const int r = (i / w) * H + ((kr0 + i % w) & (H - 1)), c = (j / w) * H + ((kc0 + j % w) & (H - 1));
+        C[i * CW + j] = (r < H && c < H) ? llin[(int64_t)r * N + c] : coef[(int64_t)r * N + c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * t * 2 * w; e += DNT) {      // columns: Y[mr][j]
+        const int mr = e / (2 * w), j = e % (2 * w);
+        const int m = mr0 + mr, odd = m & 1;
+        float acc = 0.f;
+#pragma unroll
+        for (int n = 0; n < 16; n += 2) {
+            const int nn = n + odd, i = ((m - nn) >> 1) - kr0;
+            acc = fmaf(odd ? f.h[n + 1] : f.h[n], C[i * CW + j], acc);
+            acc = fmaf(odd ? f.g[n + 1] : f.g[n], C[(w + i) * CW + j], acc);
+        }
+        Y[mr * CW + j] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * t * t; e += DNT) {          // rows
+        const int mr = e / (2 * t), mc = e % (2 * t);
+        const int m = mc0 + mc, odd = m & 1;
+        float acc = 0.f;
+#pragma unroll
+        for (int n = 0; n < 16; n += 2) {
+            const int nn = n + odd, j = ((m - nn) >> 1) - kc0;
+            acc = fmaf(odd ? f.h[n + 1] : f.h[n], Y[mr * CW + j], acc);
+            acc = fmaf(odd ? f.g[n + 1] : f.g[n], Y[mr * CW + w + j], acc);
+        }
+        out[(int64_t)(mr0 + mr) * N + mc0 + mc] = acc;
     }
 }
 
@@ -200,6 +297,11 @@ __global__ void k_normalise_real(const float2 *__restrict__ z, float2 *__restric
     xc[i] = make_float2((float)(z[i].x * s), 0.f);
 }
 
+__global__ void k_copy_f32(const float *__restrict__ x, float *__restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
 __global__ void k_real_to_c64(const float *__restrict__ x, float2 *__restrict__ xc, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) xc[i] = make_float2(x[i], 0.f);
@@ -215,7 +317,7 @@ inline dim3 blocks_reduce(int64_t n) {
     return dim3((unsigned)(b > 1024 ? 1024 : (b < 1 ? 1 : b)));
 }
 
-Filt make_filter(bool &ok) {
+Filt build_filter(bool &ok) {
     double h[16];
     Filt f{};
     ok = daubechies(8, h);
@@ -244,27 +346,53 @@ static wp_status check_levels(const wp_plan *p, int levels) {
     return WP_OK;
 }
 
+// the taps are computed once per process (thread-safe static initialisation)
+static const Filt *db8_filter() {
+    static bool ok = false;
+    static const Filt f = build_filter(ok);
+    return ok ? &f : nullptr;
+}
+
 wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s) {
     if (wp_status st = check_levels(p, levels)) return st;
-    bool ok;
-    const Filt f = make_filter(ok);
-    if (!ok) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
+    const Filt *fp = db8_filter();
+    if (!fp) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
+    const Filt f = *fp;
     const int N = p->N;
-    if (c != x) {
-        WP_HIP(hipMemcpyAsync(c, x, sizeof(float) * N * N, hipMemcpyDeviceToDevice, s));
+    if (levels == 0) {                            // Dirac basis: a copy
+        if (c != x) hipLaunchKernelGGL(k_copy_f32, blocks_for((int64_t)N * N), dim3(NT), 0, s, x, c, (int64_t)N * N);
+        return wp_check_launch(synth ? "idwt2" : "dwt2");
     }
-    // analysis: level by level, rows then columns on the top-left L x L block;
-    // synthesis: coarsest first, columns then rows.
-    for (int lv = 0; lv < levels; ++lv) {
-        const int L = synth ? (N >> (levels - 1 - lv)) : (N >> lv);
-        const size_t lds = sizeof(float) * L;
-        const int th = L < NT ? L : NT;
-        if (!synth) {
-            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, c, tmp, L, L, N, 1, f, false);   // rows
-            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, tmp, c, L, L, 1, N, f, false);   // columns
-        } else {
-            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, c, tmp, L, L, 1, N, f, true);    // columns
-            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, tmp, c, L, L, N, 1, f, true);    // rows
+    if (c == x) {
+        // in place: one pass per axis and level, through tmp
+        for (int lv = 0; lv < levels; ++lv) {
+            const int L = synth ? (N >> (levels - 1 - lv)) : (N >> lv);
+            const size_t lds = sizeof(float) * L;
+            const int th = L < NT ? L : NT;
+            const int ls1 = synth ? 1 : N, es1 = synth ? N : 1;     // first pass: rows (analysis), columns
+            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, nullptr, c, 0, tmp, L, L, ls1, es1, f, synth);
+            hipLaunchKernelGGL(k_dwt_lines, dim3(L), dim3(th), lds, s, nullptr, tmp, 0, c, L, L, es1, ls1, f, synth);
+        }
+        return wp_check_launch(synth ? "idwt2" : "dwt2");
+    }
+    // one tiled kernel per level.  The approximation passed between levels lives in tmp at
+    // disjoint column ranges, so a level never reads the region it writes.
+    auto tiles = [](int L) { const int H = L / 2, t = H < DT ? H : DT; return dim3((unsigned)((H / t) * (H / t))); };
+    if (!synth) {
+        const float *src = x;
+        for (int lv = 0; lv < levels; ++lv) {
+            const int L = N >> lv;
+            float *ll = lv == levels - 1 ? c : tmp + (lv == 0 ? 0 : N - (N >> lv));
+            hipLaunchKernelGGL(k_dwt2_fwd, tiles(L), dim3(DNT), 0, s, src, c, ll, N, L, f);
+            src = ll;
+        }
+    } else {
+        const float *llin = x;                    // the coarsest approximation is in the coefficients
+        for (int st = 0; st < levels; ++st) {
+            const int L = N >> (levels - 1 - st);
+            float *out = st == levels - 1 ? c : tmp + ((levels - 2 - st) % 2 == 0 ? 0 : N / 2);
+            hipLaunchKernelGGL(k_dwt2_inv, tiles(L), dim3(DNT), 0, s, x, llin, out, N, L, f);
+            llin = out;
         }
     }
     return wp_check_launch(synth ? "idwt2" : "dwt2");

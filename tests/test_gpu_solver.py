@@ -28,7 +28,7 @@ def relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
-@pytest.mark.parametrize("N,levels", [(64, 4), (256, 4), (128, 2), (32, 3), (64, 0)])
+@pytest.mark.parametrize("N,levels", [(64, 4), (256, 4), (128, 2), (32, 3), (64, 0), (1024, 4), (512, 5), (256, 1)])
 def test_dwt_matches_oracle(N, levels):
     print(f"dwt N={N} levels={levels}", flush=True)
     plan = wp.Plan(N, synth.fov_L())
