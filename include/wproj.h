@@ -441,6 +441,35 @@ wp_status wp_power_norm2(const wp_plan *plan, const wp_G *G, const float *x0, in
 wp_status wp_solve(const wp_plan *plan, const wp_G *G, const void *y, double eps, double nu,
                    int iters, int levels, float *x, void *workspace, void *stream);
 
+/* ----------------------------------------------------------------------------------------
+ * SARA (Section 4.2's third dictionary; the paper cites Carrillo, McEwen & Wiaux 2012 for it):
+ * Psi = [I, W_1, ..., W_8] / 3, W_p the periodic Daubechies wavelets with p vanishing moments
+ * (`levels` levels, 1 <= levels, N >> (levels-1) >= 8), a tight frame (Psi Psi^T = I), and
+ * reweighted l1 analysis.
+ * ------------------------------------------------------------------------------------- */
+
+/* c = Psi^T x: x is a real N x N float image, c is [9][N][N] floats (Dirac part first); scratch is
+ * 16 N^2 floats of device memory.  x and c must not overlap. */
+wp_status wp_sara_analysis(const wp_plan *plan, int levels, const float *x, float *c, float *scratch,
+                           void *stream);
+/* x = Psi c, same layouts and scratch; c and x must not overlap. */
+wp_status wp_sara_synthesis(const wp_plan *plan, int levels, const float *c, float *x, float *scratch,
+                            void *stream);
+
+/* Device workspace of wp_sara_solve for this plan and G. */
+wp_status wp_sara_workspace_bytes(const wp_plan *plan, const wp_G *G, int64_t *bytes_out);
+
+/* Reweighted analysis solve: `rounds` (>= 1) runs of the wp_solve iteration (same splitting and
+ * step sizes, ||Psi|| = 1) with the weighted norm ||W Psi^T x||_1, the dual step clipping
+ * coefficient i to [-w_i, w_i].  Round 0 has unit weights; before round r >= 1 the weights are
+ * w_i = delta / (delta + |(Psi^T x)_i|) with x the current estimate, delta = the standard
+ * deviation of Psi^T x before round 1 and a tenth of the previous delta afterwards.  x (device,
+ * real N*N floats) holds the start on entry and the estimate on exit and carries over between
+ * rounds; the dual variables restart at zero each round.  Synchronises the stream once per
+ * round from round 1 on (it reads back the coefficients' spread). */
+wp_status wp_sara_solve(const wp_plan *plan, const wp_G *G, const void *y, double eps, double nu,
+                        int iters, int rounds, int levels, float *x, void *workspace, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,8 @@ from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16", "WP_TAPS_I16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
-           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "Batch", "Mlp", "Surrogate"]
+           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "sara_analysis", "sara_synthesis",
+           "sara_solve", "Batch", "Mlp", "Surrogate"]
 
 
 def _torch():
@@ -338,6 +339,47 @@ def solve(plan: Plan, G: GMatrix, y, eps: float, nu: float, iters: int, levels: 
     ws = _solver_ws(plan, G, d) if ws is None else ws
     check(load().wp_solve(plan.handle, C.byref(d), _ptr(y), float(eps), float(nu), int(iters), int(levels),
                           _ptr(x), _ptr(ws), _stream(stream)), "wp_solve")
+    x._wp_ws = ws
+    return x
+
+
+def sara_analysis(plan: Plan, x, levels: int = 4, out=None, stream=None):
+    """wp_sara_analysis: [9, N, N] coefficients (Dirac, then Daubechies 1..8), flattened."""
+    torch = _torch()
+    n2 = plan.N * plan.N
+    _dev_f32(x, n2, "x")
+    out = torch.empty(9 * n2, dtype=torch.float32, device=x.device) if out is None else _dev_f32(out, 9 * n2, "out")
+    scratch = torch.empty(16 * n2, dtype=torch.float32, device=x.device)
+    check(load().wp_sara_analysis(plan.handle, int(levels), _ptr(x), _ptr(out), _ptr(scratch), _stream(stream)),
+          "wp_sara_analysis")
+    return out
+
+
+def sara_synthesis(plan: Plan, c, levels: int = 4, out=None, stream=None):
+    """wp_sara_synthesis: the N*N image of [9, N, N] coefficients."""
+    torch = _torch()
+    n2 = plan.N * plan.N
+    _dev_f32(c, 9 * n2, "c")
+    out = torch.empty(n2, dtype=torch.float32, device=c.device) if out is None else _dev_f32(out, n2, "out")
+    scratch = torch.empty(16 * n2, dtype=torch.float32, device=c.device)
+    check(load().wp_sara_synthesis(plan.handle, int(levels), _ptr(c), _ptr(out), _ptr(scratch), _stream(stream)),
+          "wp_sara_synthesis")
+    return out
+
+
+def sara_solve(plan: Plan, G: GMatrix, y, eps: float, nu: float, iters: int, rounds: int, levels: int = 4, x=None,
+               stream=None):
+    """wp_sara_solve: x (float32 N*N, zeros by default) is updated in place and returned."""
+    torch = _torch()
+    _dev_c64(y, G.M, "y")
+    x = torch.zeros(plan.N * plan.N, dtype=torch.float32, device=y.device) if x is None else \
+        _dev_f32(x, plan.N * plan.N, "x")
+    d = G.desc()
+    b = C.c_int64()
+    check(load().wp_sara_workspace_bytes(plan.handle, C.byref(d), C.byref(b)), "wp_sara_workspace_bytes")
+    ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+    check(load().wp_sara_solve(plan.handle, C.byref(d), _ptr(y), float(eps), float(nu), int(iters), int(rounds),
+                               int(levels), _ptr(x), _ptr(ws), _stream(stream)), "wp_sara_solve")
     x._wp_ws = ws
     return x
 

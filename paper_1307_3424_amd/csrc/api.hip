@@ -408,4 +408,36 @@ wp_status wp_solve(const wp_plan *p, const wp_G *G, const void *y, double eps, d
                         as_stream(stream));
 }
 
+wp_status wp_sara_analysis(const wp_plan *p, int levels, const float *x, float *c, float *scratch, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!x || !c || !scratch) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_sara_analysis(p, levels, x, c, scratch, as_stream(stream));
+}
+
+wp_status wp_sara_synthesis(const wp_plan *p, int levels, const float *c, float *x, float *scratch, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!x || !c || !scratch) return wp_set_error(WP_EINVAL, "NULL argument");
+    return launch_sara_synthesis(p, levels, c, x, scratch, as_stream(stream));
+}
+
+wp_status wp_sara_workspace_bytes(const wp_plan *p, const wp_G *G, int64_t *bytes) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
+    if (!bytes) return wp_set_error(WP_EINVAL, "NULL argument");
+    *bytes = sara_workspace_bytes(p, G->M);
+    return WP_OK;
+}
+
+wp_status wp_sara_solve(const wp_plan *p, const wp_G *G, const void *y, double eps, double nu, int iters, int rounds,
+                        int levels, float *x, void *workspace, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
+    if (!y || !x || !workspace) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (!(eps >= 0.0) || !(nu > 0.0) || !std::isfinite(eps) || !std::isfinite(nu))
+        return wp_set_error(WP_EINVAL, "eps = %g, nu = %g: need eps >= 0 and nu > 0, finite", eps, nu);
+    if (iters < 0 || rounds < 1) return wp_set_error(WP_EINVAL, "iters = %d, rounds = %d", iters, rounds);
+    return launch_sara_solve(p, wp_operator{G, nullptr, G->M}, (const float2 *)y, eps, nu, iters, rounds, levels, x,
+                             (unsigned char *)workspace, as_stream(stream));
+}
+
 }  // extern "C"

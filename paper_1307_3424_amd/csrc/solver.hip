@@ -85,6 +85,12 @@ struct Filt {
     float h[16], g[16];
 };
 
+// Filters of several bases (a batch of transforms takes basis blockIdx.y): Daubechies with p + 1
+// vanishing moments at f[p] for the SARA dictionary, or Daubechies 8 alone at f[0]
+struct FiltSet {
+    Filt f[8];
+};
+
 // ---------------------------------------------------------------------------- DWT kernels (FP32)
 // One level along a line of length L (a power of two), H = L / 2.  Analysis:
 // a_k = sum_n h_n x_(2k+n mod L), d_k = sum_n g_n x_(2k+n mod L), stored [a | d].  Synthesis (the
@@ -140,10 +146,15 @@ constexpr int DWIN = 2 * DT + 14;
 constexpr int DNT = 256;
 
 // Analysis of the top-left L x L block of `in` (row stride N; periodic in L).  The three detail
-// subbands go to det, the approximation (top-left H x H) to ll; both have row stride N.
-__global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, float *__restrict__ det,
-                                                  float *__restrict__ ll, int N, int L, Filt f) {
+// subbands go to det, the approximation (top-left H x H) to ll; both have row stride N.  Basis
+// b = blockIdx.y reads in + b in_zs and writes det + b N^2, ll + b N^2.
+__global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, int64_t in_zs, float *__restrict__ det,
+                                                  float *__restrict__ ll, int N, int L, const FiltSet fs) {
     __shared__ float win[DWIN * DWIN];
+    const Filt &f = fs.f[blockIdx.y];
+    in += blockIdx.y * in_zs;
+    det += (int64_t)blockIdx.y * N * N;
+    ll += (int64_t)blockIdx.y * N * N;
     __shared__ float R[DWIN * 2 * DT];
     const int H = L >> 1, t = H < DT ? H : DT, tiles = H / t, w = 2 * t + 14;
     const int kr0 = (blockIdx.x / tiles) * t, kc0 = (blockIdx.x % tiles) * t;
@@ -174,10 +185,15 @@ __global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, 
 
 // Synthesis of one level: the L x L result (row stride N) from coefficients whose top-left H x H
 // quadrant (the coarser levels' result) is read from llin and the three detail quadrants from
-// coef.  A tile of 2t x 2t outputs reads t + 8 positions of each band per axis.
+// coef.  A tile of 2t x 2t outputs reads t + 8 positions of each band per axis.  Basis
+// b = blockIdx.y offsets all three images by b N^2.
 __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef, const float *__restrict__ llin,
-                                                  float *__restrict__ out, int N, int L, Filt f) {
+                                                  float *__restrict__ out, int N, int L, const FiltSet fs) {
     constexpr int CW = 2 * (DT + 8);
+    const Filt &f = fs.f[blockIdx.y];
+    coef += (int64_t)blockIdx.y * N * N;
+    llin += (int64_t)blockIdx.y * N * N;
+    out += (int64_t)blockIdx.y * N * N;
     __shared__ float C[CW * CW];
     __shared__ float Y[2 * DT * CW];
     const int H = L >> 1, t = H < DT ? H : DT, tiles = H / t, w = t + 8;
@@ -238,6 +254,66 @@ __global__ void k_dual1(float *__restrict__ v1, const float *__restrict__ d, int
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     v1[i] = fminf(1.f, fmaxf(-1.f, v1[i] + s1 * d[i]));
+}
+
+// v1 = clip(v1 + s1 d, -w, w): the dual step of the weighted norm ||W Psi^T x||_1
+__global__ void k_dual1w(float *__restrict__ v1, const float *__restrict__ d, const float *__restrict__ w, int64_t n,
+                         float s1) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    v1[i] = fminf(w[i], fmaxf(-w[i], v1[i] + s1 * d[i]));
+}
+
+// SARA analysis, last step: c_0 = x / 3 (Dirac), c_b = W_b x / 3 (the transforms are in c_1..c_8)
+__global__ void k_sara_scale(const float *__restrict__ x, float *__restrict__ c, int64_t n2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    constexpr float third = 1.0f / 3.0f;
+    c[i] = x[i] * third;
+#pragma unroll
+    for (int b = 1; b < 9; ++b) c[b * n2 + i] *= third;
+}
+
+// SARA synthesis, last step: x = (c_0 + sum_b W_b^T c_b) / 3 (the eight syntheses are in r_0..r_7)
+__global__ void k_sara_sum(const float *__restrict__ c0, const float *__restrict__ r, float *__restrict__ x,
+                           int64_t n2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    float acc = c0[i];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc += r[b * n2 + i];
+    x[i] = acc * (1.0f / 3.0f);
+}
+
+// weights delta / (delta + |alpha|)
+__global__ void k_sara_weights(const float *__restrict__ alpha, float *__restrict__ w, int64_t n, double d) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    w[i] = (float)(d / (d + fabs((double)alpha[i])));
+}
+
+__global__ void k_fill_f32(float *__restrict__ a, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// first pass (second = 0): acc[0] += sum a; second pass: acc[1] += sum (a - mean)^2, mean = acc[0] / n (FP64)
+__global__ void k_sum_dev(const float *__restrict__ a, int64_t n, double *__restrict__ acc, int second) {
+    __shared__ double red[NT / 64];
+    const double mean = second ? acc[0] / (double)n : 0.0;
+    double sum = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)a[i] - mean;
+        sum += second ? v * v : (double)a[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        atomicAdd(acc + second, t);
+    }
 }
 
 // acc += sum |u / s2 - y|^2, u = v2 + s2 p  (FP64)
@@ -317,15 +393,27 @@ inline dim3 blocks_reduce(int64_t n) {
     return dim3((unsigned)(b > 1024 ? 1024 : (b < 1 ? 1 : b)));
 }
 
-Filt build_filter(bool &ok) {
-    double h[16];
+// Daubechies with p vanishing moments: 2p taps, high-pass g_n = (-1)^n h_(2p-1-n), zero-padded to 16
+Filt build_filter(int p, bool &ok) {
+    double h[16] = {0.0};
     Filt f{};
-    ok = daubechies(8, h);
-    for (int n = 0; n < 16; ++n) {
+    ok = daubechies(p, h);
+    for (int n = 0; n < 2 * p; ++n) {
         f.h[n] = (float)h[n];
-        f.g[n] = (float)(((n & 1) ? -1.0 : 1.0) * h[15 - n]);
+        f.g[n] = (float)(((n & 1) ? -1.0 : 1.0) * h[2 * p - 1 - n]);
     }
     return f;
+}
+
+FiltSet build_set(bool sara, bool &ok) {
+    FiltSet fs{};
+    ok = true;
+    for (int b = 0; b < (sara ? 8 : 1); ++b) {
+        bool okb;
+        fs.f[b] = build_filter(sara ? b + 1 : 8, okb);
+        ok = ok && okb;
+    }
+    return fs;
 }
 
 }  // namespace
@@ -347,17 +435,19 @@ static wp_status check_levels(const wp_plan *p, int levels) {
 }
 
 // the taps are computed once per process (thread-safe static initialisation)
-static const Filt *db8_filter() {
-    static bool ok = false;
-    static const Filt f = build_filter(ok);
-    return ok ? &f : nullptr;
+static const FiltSet *filter_set(bool sara) {
+    static bool ok8 = false, oks = false;
+    static const FiltSet db8 = build_set(false, ok8);
+    static const FiltSet all = build_set(true, oks);
+    return sara ? (oks ? &all : nullptr) : (ok8 ? &db8 : nullptr);
 }
 
 wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s) {
     if (wp_status st = check_levels(p, levels)) return st;
-    const Filt *fp = db8_filter();
-    if (!fp) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
-    const Filt f = *fp;
+    const FiltSet *fsp = filter_set(false);
+    if (!fsp) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
+    const FiltSet &fs = *fsp;
+    const Filt &f = fs.f[0];
     const int N = p->N;
     if (levels == 0) {                            // Dirac basis: a copy
         if (c != x) hipLaunchKernelGGL(k_copy_f32, blocks_for((int64_t)N * N), dim3(NT), 0, s, x, c, (int64_t)N * N);
@@ -383,7 +473,7 @@ wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, fl
         for (int lv = 0; lv < levels; ++lv) {
             const int L = N >> lv;
             float *ll = lv == levels - 1 ? c : tmp + (lv == 0 ? 0 : N - (N >> lv));
-            hipLaunchKernelGGL(k_dwt2_fwd, tiles(L), dim3(DNT), 0, s, src, c, ll, N, L, f);
+            hipLaunchKernelGGL(k_dwt2_fwd, tiles(L), dim3(DNT), 0, s, src, (int64_t)0, c, ll, N, L, fs);
             src = ll;
         }
     } else {
@@ -391,7 +481,7 @@ wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, fl
         for (int st = 0; st < levels; ++st) {
             const int L = N >> (levels - 1 - st);
             float *out = st == levels - 1 ? c : tmp + ((levels - 2 - st) % 2 == 0 ? 0 : N / 2);
-            hipLaunchKernelGGL(k_dwt2_inv, tiles(L), dim3(DNT), 0, s, x, llin, out, N, L, f);
+            hipLaunchKernelGGL(k_dwt2_inv, tiles(L), dim3(DNT), 0, s, x, llin, out, N, L, fs);
             llin = out;
         }
     }
@@ -470,6 +560,127 @@ wp_status launch_solve(const wp_plan *p, const wp_operator &op, const float2 *y,
         hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, v2, pv, y, M, s2, eps, acc);
     }
     return wp_check_launch("solve");
+}
+
+// ---------------------------------------------------------------------------- SARA (Section 4.2)
+// Psi = [I, W_1, ..., W_8] / 3 with W_p the Daubechies wavelets of p vanishing moments (`levels`
+// levels, periodic): a tight frame with Psi Psi^T = I.  Coefficients are [9][N][N] (Dirac first);
+// the eight wavelet transforms of a level run in one launch (basis = blockIdx.y).
+
+static wp_status check_sara_levels(const wp_plan *p, int levels) {
+    if (levels < 1 || levels > 30 || (p->N >> (levels - 1)) < 8)
+        return wp_set_error(WP_EINVAL, "levels = %d: SARA needs 1 .. with N >> (levels-1) >= 8, N = %d", levels,
+                            p->N);
+    return WP_OK;
+}
+
+static dim3 sara_tiles(int L) {
+    const int H = L / 2, t = H < DT ? H : DT;
+    return dim3((unsigned)((H / t) * (H / t)), 8);
+}
+
+// c = Psi^T x; tmp holds 8 N^2 floats (the approximations between levels, one image per basis)
+wp_status launch_sara_analysis(const wp_plan *p, int levels, const float *x, float *c, float *tmp, hipStream_t s) {
+    if (wp_status st = check_sara_levels(p, levels)) return st;
+    const FiltSet *fs = filter_set(true);
+    if (!fs) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
+    const int N = p->N;
+    const int64_t N2 = (int64_t)N * N;
+    const float *src = x;
+    int64_t in_zs = 0;                            // every basis reads x at the first level
+    for (int lv = 0; lv < levels; ++lv) {
+        const int L = N >> lv;
+        float *ll = lv == levels - 1 ? c + N2 : tmp + (lv == 0 ? 0 : N - (N >> lv));
+        hipLaunchKernelGGL(k_dwt2_fwd, sara_tiles(L), dim3(DNT), 0, s, src, in_zs, c + N2, ll, N, L, *fs);
+        src = ll;
+        in_zs = N2;
+    }
+    hipLaunchKernelGGL(k_sara_scale, blocks_for(N2), dim3(NT), 0, s, x, c, N2);
+    return wp_check_launch("sara_analysis");
+}
+
+// x = Psi c; tmp holds 16 N^2 floats (per basis: the coarser levels' results, then its synthesis)
+wp_status launch_sara_synthesis(const wp_plan *p, int levels, const float *c, float *x, float *tmp, hipStream_t s) {
+    if (wp_status st = check_sara_levels(p, levels)) return st;
+    const FiltSet *fs = filter_set(true);
+    if (!fs) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
+    const int N = p->N;
+    const int64_t N2 = (int64_t)N * N;
+    const float *coef = c + N2, *llin = c + N2;
+    for (int st = 0; st < levels; ++st) {
+        const int L = N >> (levels - 1 - st);
+        float *out = st == levels - 1 ? tmp + 8 * N2 : tmp + ((levels - 2 - st) % 2 == 0 ? 0 : N / 2);
+        hipLaunchKernelGGL(k_dwt2_inv, sara_tiles(L), dim3(DNT), 0, s, coef, llin, out, N, L, *fs);
+        llin = out;
+    }
+    hipLaunchKernelGGL(k_sara_sum, blocks_for(N2), dim3(NT), 0, s, c, tmp + 8 * N2, x, N2);
+    return wp_check_launch("sara_synthesis");
+}
+
+int64_t sara_workspace_bytes(const wp_plan *p, int64_t M) {
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng;
+    auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    return al(8 * G2) + 3 * al(4 * 9 * N2) + 2 * al(4 * N2) + al(4 * 16 * N2) + 2 * al(8 * N2) + 2 * al(8 * M) +
+           al(64);
+}
+
+// Reweighted analysis over the SARA dictionary: `rounds` primal-dual solves of `iters` iterations
+// with the weighted norm ||W Psi^T x||_1, x carried over, duals restarted at zero; round 0 has
+// unit weights, round r >= 1 w = delta_r / (delta_r + |Psi^T x|), delta_1 = the standard
+// deviation of Psi^T x, delta_(r+1) = delta_r / 10.
+wp_status launch_sara_solve(const wp_plan *p, const wp_operator &op, const float2 *y, double eps, double nu, int iters,
+                            int rounds, int levels, float *x, unsigned char *ws, hipStream_t s) {
+    if (wp_status st = check_sara_levels(p, levels)) return st;
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng, M = op.M, NC = 9 * N2;
+    auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    int64_t o = 0;
+    auto take = [&](int64_t b) { unsigned char *r = ws + o; o += al(b); return r; };
+    float2 *grid = (float2 *)take(8 * G2);
+    float *v1 = (float *)take(4 * NC);
+    float *tc = (float *)take(4 * NC);
+    float *w = (float *)take(4 * NC);
+    float *t1 = (float *)take(4 * N2);
+    float *xb = (float *)take(4 * N2);
+    float *tmp = (float *)take(4 * 16 * N2);
+    float2 *t2 = (float2 *)take(8 * N2);
+    float2 *xbc = (float2 *)take(8 * N2);
+    float2 *v2 = (float2 *)take(8 * M);
+    float2 *pv = (float2 *)take(8 * M);
+    double *acc = (double *)take(64);
+    const float tau = 0.49f, s1 = 1.0f, s2 = (float)(1.0 / nu);
+    double delta = 0.0;
+    for (int r = 0; r < rounds; ++r) {
+        if (r == 0) {
+            hipLaunchKernelGGL(k_fill_f32, blocks_for(NC), dim3(NT), 0, s, w, NC, 1.0f);
+        } else {
+            if (wp_status st = launch_sara_analysis(p, levels, x, tc, tmp, s)) return st;       // alpha
+            if (r == 1) {
+                double h[2] = {0.0, 0.0};
+                hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, acc, 2);
+                hipLaunchKernelGGL(k_sum_dev, blocks_reduce(NC), dim3(NT), 0, s, tc, NC, acc, 0);
+                hipLaunchKernelGGL(k_sum_dev, blocks_reduce(NC), dim3(NT), 0, s, tc, NC, acc, 1);
+                WP_HIP(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+                WP_HIP(hipStreamSynchronize(s));
+                delta = std::sqrt(h[1] / (double)NC);
+            } else {
+                delta /= 10.0;
+            }
+            hipLaunchKernelGGL(k_sara_weights, blocks_for(NC), dim3(NT), 0, s, tc, w, NC, delta);
+        }
+        WP_HIP(hipMemsetAsync(v1, 0, 4 * NC, s));
+        WP_HIP(hipMemsetAsync(v2, 0, 8 * M, s));
+        for (int it = 0; it < iters; ++it) {
+            if (wp_status st = launch_sara_synthesis(p, levels, v1, t1, tmp, s)) return st;     // Psi v1
+            if (wp_status st = op_phiT(p, op, v2, t2, grid, s)) return st;                      // Phi^H v2
+            hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, t1, t2, xb, xbc, N2, tau, acc);
+            if (wp_status st = launch_sara_analysis(p, levels, xb, tc, tmp, s)) return st;      // Psi^T xb
+            hipLaunchKernelGGL(k_dual1w, blocks_for(NC), dim3(NT), 0, s, v1, tc, w, NC, s1);
+            if (wp_status st = op_phi(p, op, xbc, pv, grid, s)) return st;                      // Phi xb
+            hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, v2, pv, y, M, s2, acc);
+            hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, v2, pv, y, M, s2, eps, acc);
+        }
+    }
+    return wp_check_launch("sara_solve");
 }
 
 wp_status filter_db8(double *h) { return daubechies(8, h) ? WP_OK : wp_set_error(WP_EHIP, "filter"); }
