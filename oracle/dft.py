@@ -8,7 +8,8 @@ Eq. 1 / Eq. 3 on the pixel grid, with the primary beam absorbed into the sky
     y_k = sum_p x_p a_phys(p) exp(-2 pi i (u_k l_p + v_k m_p)) C(l_p, m_p; w_k)
 
 where C is the exact w-modulation (Eq. 4) or the linear chirp (Eq. 5), and
-a_phys is 1 or 1/n(l, m).  Cost O(M N^2) (Section 3.2's complexity of the
+a_phys is 1 or 1/n(l, m); with a direction-dependent effect (oracle.dde) C is
+multiplied by the visibility's beam A_k(l, m).  Cost O(M N^2) (Section 3.2's complexity of the
 direct approach).  This is the definition the sparse operator approaches at
 E = 1 as the KB support W grows.
 """
@@ -18,6 +19,7 @@ import numpy as np
 
 from . import geometry as geo
 from .chirp import chirp
+from .dde import gaussian_beam
 
 
 def _phys(l, m, a_phys):
@@ -29,7 +31,8 @@ def _phys(l, m, a_phys):
 
 
 def measure(x, u, v, w, N: int, L: float, kind: str = "linear", a_phys: str = "one",
-            chunk: int = 64) -> np.ndarray:
+            chunk: int = 64, beam=None) -> np.ndarray:
+    """beam: optional [M, 3] per-visibility Gaussian power patterns (l0, m0, sigma), oracle.dde."""
     x = np.asarray(x, dtype=np.complex128)
     lp = geo.image_coords(N, L)
     l = np.broadcast_to(lp[None, :], (N, N)).ravel()
@@ -43,6 +46,8 @@ def measure(x, u, v, w, N: int, L: float, kind: str = "linear", a_phys: str = "o
         e = slice(s, s + chunk)
         ph = np.exp(-2j * np.pi * (u[e, None] * l[None, :] + v[e, None] * m[None, :]))
         C = np.stack([chirp(l, m, wk, kind) for wk in w[e]])
+        if beam is not None:
+            C = C * np.stack([gaussian_beam(l, m, *b) for b in np.asarray(beam)[e]])
         y[e] = (ph * C) @ xa
     return y
 

@@ -49,6 +49,7 @@ import scipy.sparse as sp
 
 from . import geometry as geo
 from .chirp import LINEAR, EXACT, chirp, chirp_1d
+from .dde import gaussian_beam
 from .kb import beatty_beta, kb, kb_ft, kb_taps
 
 
@@ -125,10 +126,15 @@ def chirp_spectrum_1d(w: float, s: Setup) -> np.ndarray:
     return np.fft.fft(np.fft.ifftshift(c)) / s.Ng
 
 
-def chirp_spectrum_2d(w: float, s: Setup) -> np.ndarray:
-    """H[d_v mod Ng, d_u mod Ng] = Ng^-2 sum_t c(l_t, m_t) exp(-2 pi i t.d / Ng)."""
+def chirp_spectrum_2d(w: float, s: Setup, beam=None) -> np.ndarray:
+    """H[d_v mod Ng, d_u mod Ng] = Ng^-2 sum_t c(l_t, m_t) exp(-2 pi i t.d / Ng).
+
+    beam: optional (l0, m0, sigma) of a Gaussian power pattern multiplied into c (oracle.dde).
+    """
     l = geo.padded_coords(s.N, s.L, s.sigma)
     c = chirp(l[None, :], l[:, None], w, s.kind)
+    if beam is not None:
+        c = c * gaussian_beam(l[None, :], l[:, None], *beam)
     return np.fft.fft2(np.fft.ifftshift(c)) / (s.Ng * s.Ng)
 
 
@@ -154,9 +160,9 @@ def kernel_row_separable(ut: float, vt: float, w: float, s: Setup):
     return row_factor_1d(vt, h, s), row_factor_1d(ut, h, s)
 
 
-def kernel_row_2d(ut: float, vt: float, w: float, s: Setup) -> np.ndarray:
-    """Dense Ng x Ng row g_k[q_v, q_u] from the 2-D chirp spectrum."""
-    H = chirp_spectrum_2d(w, s)
+def kernel_row_2d(ut: float, vt: float, w: float, s: Setup, beam=None) -> np.ndarray:
+    """Dense Ng x Ng row g_k[q_v, q_u] from the 2-D chirp spectrum (times the beam, if given)."""
+    H = chirp_spectrum_2d(w, s, beam)
     q = np.arange(s.Ng)
     g = np.zeros((s.Ng, s.Ng), dtype=np.complex128)
     tv, wv = _taps(vt, s)
@@ -169,11 +175,11 @@ def kernel_row_2d(ut: float, vt: float, w: float, s: Setup) -> np.ndarray:
     return g
 
 
-def kernel_row(ut: float, vt: float, w: float, s: Setup) -> np.ndarray:
-    if s.kind == LINEAR:
+def kernel_row(ut: float, vt: float, w: float, s: Setup, beam=None) -> np.ndarray:
+    if s.kind == LINEAR and beam is None:
         gv, gu = kernel_row_separable(ut, vt, w, s)
         return np.outer(gv, gu)
-    return kernel_row_2d(ut, vt, w, s)
+    return kernel_row_2d(ut, vt, w, s, beam)
 
 
 # ----------------------------------------------------------------------------- sparsification
@@ -212,11 +218,12 @@ def sparsify(m: np.ndarray, E: float) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- G
 
-def build_rows(u, v, w, E: float, s: Setup, rows=None, with_info: bool = False):
+def build_rows(u, v, w, E: float, s: Setup, rows=None, with_info: bool = False, beam=None):
     """CSR of the sparsified rows (caller order) as scipy.sparse.csr_matrix.
 
     rows: optional subset of visibility indices; the matrix then has one row
-    per selected visibility in that order.
+    per selected visibility in that order.  beam: optional [M, 3] array of
+    per-visibility Gaussian power patterns (l0, m0, sigma) (oracle.dde).
     """
     u = np.asarray(u, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
@@ -227,7 +234,7 @@ def build_rows(u, v, w, E: float, s: Setup, rows=None, with_info: bool = False):
     indptr = [0]
     cols, vals, info = [], [], []
     for k in idx:
-        g = kernel_row(ut[k], vt[k], w[k], s).ravel()
+        g = kernel_row(ut[k], vt[k], w[k], s, None if beam is None else tuple(beam[k])).ravel()
         m = (g * g.conj()).real
         tau, total = energy_threshold(m, E)
         keep = np.nonzero(m >= tau)[0]
