@@ -221,6 +221,26 @@ wp_status wp_apply_PhiT(const wp_plan *plan, const wp_G *G, const void *y, void 
                         void *stream);
 
 /* Sub-steps of the two applies, exposed for testing and composition. */
+/*
+ * A direction-dependent effect through the same sparsifier (Section 3.2: the per-row energy
+ * threshold assumes nothing about a row, so it applies to every direction-dependent effect, not
+ * only to w).  Each visibility carries a Gaussian antenna power pattern with a pointing offset,
+ * A_k(l, m) = exp(-((l - l0_k)^2 + (m - m0_k)^2) / (2 sigma_k^2)), multiplied into its
+ * w-modulation (the plan's chirp) before the row's Fourier transform; rows are then made whole
+ * in 2-D as for the exact chirp (Ng <= 512, else WP_EUNSUPPORTED).
+ *   beam   [M][3] device float64 (l0, m0, sigma) in direction cosines; finite, sigma > 0
+ * The other arguments, the two passes and their synchronisation are those of wp_build_G_count /
+ * wp_build_G_fill; the workspace is wp_build_dde_workspace_bytes(M) bytes.  Factor records are
+ * not made (WP_EUNSUPPORTED).  A visibility with an unusable beam fails pass 1 with WP_EINVAL.
+ */
+wp_status wp_build_dde_workspace_bytes(const wp_plan *plan, int64_t M, int64_t *bytes_out);
+wp_status wp_build_G_dde_count(const wp_plan *plan, int64_t M, const double *u, const double *v,
+                               const double *w, const double *beam, double E, void *workspace,
+                               int64_t *nnz_out, int64_t *n_work_out, void *stream);
+wp_status wp_build_G_dde_fill(const wp_plan *plan, int64_t M, const double *u, const double *v,
+                              const double *w, const double *beam, double E, void *workspace,
+                              wp_G *G, void *stream);
+
 /* grid = F Z A x */
 wp_status wp_grid_forward(const wp_plan *plan, const void *x, void *grid, void *stream);
 /* x = A Z^H F^H grid  (grid is used as scratch and overwritten) */

@@ -142,25 +142,36 @@ class GMatrix:
 
 
 def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: bool = True,
-            factors: bool = False, stream=None) -> GMatrix:
+            factors: bool = False, stream=None, beam=None) -> GMatrix:
     """wp_build_workspace_bytes + wp_build_G_count (+ wp_build_factor_bytes) + wp_build_G_fill
     (u, v, w: float64 CUDA tensors).
 
     transpose: also build the transposed copy used by the gather form of G^H (and its block table).
     factors: also build the factor records the degrid forms its taps from.
+    beam: optional [M, 3] float64 CUDA tensor of per-visibility Gaussian power patterns
+    (l0, m0, sigma): the rows carry that direction-dependent effect (wp_build_G_dde_*).
     """
     torch = _torch()
     lib = load()
     M = int(u.numel())
     for t, nm in ((u, "u"), (v, "v"), (w, "w")):
         _dev_f64(t, M, nm)
+    if beam is not None:
+        _dev_f64(beam, 3 * M, "beam")
     s = _stream(stream)
     wsb = C.c_int64()
-    check(lib.wp_build_workspace_bytes(plan.handle, M, C.byref(wsb)), "wp_build_workspace_bytes")
+    if beam is None:
+        check(lib.wp_build_workspace_bytes(plan.handle, M, C.byref(wsb)), "wp_build_workspace_bytes")
+    else:
+        check(lib.wp_build_dde_workspace_bytes(plan.handle, M, C.byref(wsb)), "wp_build_dde_workspace_bytes")
     ws = torch.empty(wsb.value, dtype=torch.uint8, device="cuda")
     nnz, nwork = C.c_int64(), C.c_int64()
-    check(lib.wp_build_G_count(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws),
-                               C.byref(nnz), C.byref(nwork), s), "wp_build_G_count")
+    if beam is None:
+        check(lib.wp_build_G_count(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws),
+                                   C.byref(nnz), C.byref(nwork), s), "wp_build_G_count")
+    else:
+        check(lib.wp_build_G_dde_count(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), _ptr(beam), float(E), _ptr(ws),
+                                       C.byref(nnz), C.byref(nwork), s), "wp_build_G_dde_count")
     dev = u.device
     G = GMatrix(M=M, nnz=nnz.value, taps=int(taps),
                 rowptr=torch.empty(M + 1, dtype=torch.int64, device=dev),
@@ -186,8 +197,12 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: b
         G.n_tblk = nt.value
         G.tblk = torch.empty(2 * (nt.value + 1), dtype=torch.int64, device=dev)
     d = G.desc()
-    check(lib.wp_build_G_fill(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws), C.byref(d), s),
-          "wp_build_G_fill")
+    if beam is None:
+        check(lib.wp_build_G_fill(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws), C.byref(d), s),
+              "wp_build_G_fill")
+    else:
+        check(lib.wp_build_G_dde_fill(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), _ptr(beam), float(E), _ptr(ws),
+                                      C.byref(d), s), "wp_build_G_dde_fill")
     G._ws = ws          # keep the workspace alive until the stream has consumed it
     return G
 

@@ -224,7 +224,7 @@ wp_status wp_build_workspace_bytes(const wp_plan *p, int64_t M, int64_t *bytes) 
     if (wp_status s = check_plan(p)) return s;
     if (!bytes) return wp_set_error(WP_EINVAL, "bytes_out is NULL");
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
-    *bytes = builder_workspace_bytes(p, M);
+    *bytes = builder_workspace_bytes(p, M, p->chirp == WP_CHIRP_EXACT);
     return WP_OK;
 }
 
@@ -235,7 +235,7 @@ wp_status wp_build_G_count(const wp_plan *p, int64_t M, const double *u, const d
     if (!u || !v || !w || !ws || !nnz_out || !n_work_out) return wp_set_error(WP_EINVAL, "NULL argument");
     if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
     if (wp_status s = check_exact(p)) return s;
-    return launch_build_count(p, M, u, v, w, E, ws, nnz_out, n_work_out, as_stream(stream));
+    return launch_build_count(p, M, u, v, w, nullptr, E, ws, nnz_out, n_work_out, as_stream(stream));
 }
 
 wp_status wp_build_G_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
@@ -249,7 +249,44 @@ wp_status wp_build_G_fill(const wp_plan *p, int64_t M, const double *u, const do
     if (p->chirp == WP_CHIRP_EXACT && (G->frec || G->fdat))
         return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp's rows are not separable (no factor records)");
     if (G->M != M) return wp_set_error(WP_EINVAL, "G->M = %lld differs from M = %lld", (long long)G->M, (long long)M);
-    return launch_build_fill(p, M, u, v, w, E, ws, G, as_stream(stream));
+    return launch_build_fill(p, M, u, v, w, nullptr, E, ws, G, as_stream(stream));
+}
+
+wp_status wp_build_dde_workspace_bytes(const wp_plan *p, int64_t M, int64_t *bytes) {
+    if (wp_status s = check_plan(p)) return s;
+    if (!bytes) return wp_set_error(WP_EINVAL, "bytes_out is NULL");
+    if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    *bytes = builder_workspace_bytes(p, M, true);
+    return WP_OK;
+}
+
+wp_status wp_build_G_dde_count(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                               const double *beam, double E, void *ws, int64_t *nnz_out, int64_t *n_work_out,
+                               void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    if (!u || !v || !w || !beam || !ws || !nnz_out || !n_work_out) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
+    if (wp_status s = check_exact(p)) return s;
+    if (p->Ng > EXACT_MAX_NG)
+        return wp_set_error(WP_EUNSUPPORTED, "build: 2-D rows need Ng <= %d (Ng = %d)", EXACT_MAX_NG, p->Ng);
+    return launch_build_count(p, M, u, v, w, beam, E, ws, nnz_out, n_work_out, as_stream(stream));
+}
+
+wp_status wp_build_G_dde_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                              const double *beam, double E, void *ws, wp_G *G, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
+    if (!u || !v || !w || !beam || !ws) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
+    if (wp_status s = check_exact(p)) return s;
+    if (p->Ng > EXACT_MAX_NG)
+        return wp_set_error(WP_EUNSUPPORTED, "build: 2-D rows need Ng <= %d (Ng = %d)", EXACT_MAX_NG, p->Ng);
+    if (wp_status s = check_G(p, G, true)) return s;
+    if (G->M != M) return wp_set_error(WP_EINVAL, "G->M = %lld differs from M = %lld", (long long)G->M, (long long)M);
+    if (G->frec || G->fdat)
+        return wp_set_error(WP_EUNSUPPORTED, "build: rows with a beam are made in 2-D (no factor records)");
+    return launch_build_fill(p, M, u, v, w, beam, E, ws, G, as_stream(stream));
 }
 
 wp_status wp_grid_forward(const wp_plan *p, const void *x, void *grid, void *stream) {

@@ -631,7 +631,8 @@ struct WsLayout {
         tcnt, sc64t, gpos, fsz, frec, ex, total;
 };
 
-WsLayout ws_layout(const wp_plan *p, int64_t M) {
+// rows2d: the rows are made whole in 2-D (the exact chirp, or a beam per visibility)
+WsLayout ws_layout(const wp_plan *p, int64_t M, bool rows2d) {
     const int64_t T = (int64_t)p->ntile * p->ntile;
     WsLayout L;
     int64_t o = 0;
@@ -661,8 +662,8 @@ WsLayout ws_layout(const wp_plan *p, int64_t M) {
     L.fsz = take(4 * M);
     L.frec = take(8 * (M + 1));
     // the exact chirp's 2-D rows of one chunk (values, or energies in the count pass)
-    L.ex = take(p->chirp == WP_CHIRP_EXACT && p->Ng <= EXACT_MAX_NG
-                    ? EX_ROW_BYTES_PER_CELL * exact_chunk_rows(p->Ng, M) * p->Ng * p->Ng : 0);
+    L.ex = take(rows2d && p->Ng <= EXACT_MAX_NG ? EX_ROW_BYTES_PER_CELL * exact_chunk_rows(p->Ng, M) * p->Ng * p->Ng
+                                                : 0);
     L.total = o;
     return L;
 }
@@ -716,19 +717,20 @@ wp_status fill_rows(const wp_plan *p, int64_t M, const double *u, const double *
 }
 
 template <int LOGNG>
-wp_status count_rows_exact(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
-                           unsigned char *ws, const WsLayout &L, hipStream_t s) {
+wp_status count_rows_exact(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                           const double *beam, double E, unsigned char *ws, const WsLayout &L, hipStream_t s) {
+    const int exact = p->chirp == WP_CHIRP_EXACT;
     constexpr int Ng = 1 << LOGNG;
     const int64_t B = exact_chunk_rows(Ng, M);
     double2 *rows = (double2 *)(ws + L.ex);
     double *en = (double *)(rows + B * Ng * Ng);       // energies beside the values
     for (int64_t k0 = 0; k0 < M; k0 += B) {
         const unsigned nb = (unsigned)std::min<int64_t>(B, M - k0);
-        hipLaunchKernelGGL((k_exact_rows<LOGNG>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, nullptr, k0,
-                           p->cell, p->delta, p->W, p->beta, p->tw64, rows);
-        hipLaunchKernelGGL((k_exact_cols<LOGNG, true>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, nullptr,
-                           k0, p->cell, p->beta, p->W, p->tw64, rows, en);
-        hipLaunchKernelGGL((k_exact_tau<LOGNG>), dim3(nb), dim3(BNTH), 0, s, u, v, w, k0, p->cell, E,
+        hipLaunchKernelGGL((k_exact_rows<LOGNG>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, beam, exact,
+                           nullptr, k0, p->cell, p->delta, p->W, p->beta, p->tw64, rows);
+        hipLaunchKernelGGL((k_exact_cols<LOGNG, true>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, beam,
+                           nullptr, k0, p->cell, p->beta, p->W, p->tw64, rows, en);
+        hipLaunchKernelGGL((k_exact_tau<LOGNG>), dim3(nb), dim3(BNTH), 0, s, u, v, w, beam, k0, p->cell, E,
                            (const double *)en, (double *)(ws + L.tau), (int *)(ws + L.nnz), (int *)(ws + L.key),
                            (int *)(ws + L.fsz), (int *)(ws + L.err));
     }
@@ -737,7 +739,8 @@ wp_status count_rows_exact(const wp_plan *p, int64_t M, const double *u, const d
 
 template <int LOGNG>
 wp_status fill_rows_exact(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
-                          const unsigned char *ws, const WsLayout &L, wp_G *G, hipStream_t s) {
+                          const double *beam, const unsigned char *ws, const WsLayout &L, wp_G *G, hipStream_t s) {
+    const int exact = p->chirp == WP_CHIRP_EXACT;
     constexpr int Ng = 1 << LOGNG;
     const int64_t B = exact_chunk_rows(Ng, M);
     double2 *rows = (double2 *)(const_cast<unsigned char *>(ws) + L.ex);    // scratch region of the workspace
@@ -745,10 +748,10 @@ wp_status fill_rows_exact(const wp_plan *p, int64_t M, const double *u, const do
     int *err = (int *)(const_cast<unsigned char *>(ws) + L.err);
     for (int64_t r0 = 0; r0 < M; r0 += B) {
         const unsigned nb = (unsigned)std::min<int64_t>(B, M - r0);
-        hipLaunchKernelGGL((k_exact_rows<LOGNG>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, G->perm, r0,
-                           p->cell, p->delta, p->W, p->beta, p->tw64, rows);
-        hipLaunchKernelGGL((k_exact_cols<LOGNG, false>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, G->perm,
-                           r0, p->cell, p->beta, p->W, p->tw64, rows, nullptr);
+        hipLaunchKernelGGL((k_exact_rows<LOGNG>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, beam, exact,
+                           G->perm, r0, p->cell, p->delta, p->W, p->beta, p->tw64, rows);
+        hipLaunchKernelGGL((k_exact_cols<LOGNG, false>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, beam,
+                           G->perm, r0, p->cell, p->beta, p->W, p->tw64, rows, nullptr);
         if (G->taps == WP_TAPS_BF16)
             hipLaunchKernelGGL((k_exact_fill<LOGNG, WP_TAPS_BF16>), dim3(nb), dim3(BNTH), 0, s, rows, r0, tau,
                                G->perm, G->rowptr, G->col, G->val, G->rscale, err);
@@ -800,12 +803,13 @@ wp_status launch_sort_pairs(const int *key, int64_t n, int bits, int *keys_out, 
     return wp_check_launch("sort");
 }
 
-int64_t builder_workspace_bytes(const wp_plan *p, int64_t M) { return ws_layout(p, M).total; }
+// every field sits at the same offset whatever rows2d says: the 2-D rows' region is the last one
+int64_t builder_workspace_bytes(const wp_plan *p, int64_t M, bool rows2d) { return ws_layout(p, M, rows2d).total; }
 
 // offsets of the factor records in sorted row order (after the count pass) and their total
 wp_status launch_build_factor_bytes(const wp_plan *p, int64_t M, void *wsv, int64_t *bytes, hipStream_t s) {
     unsigned char *ws = (unsigned char *)wsv;
-    const WsLayout L = ws_layout(p, M);
+    const WsLayout L = ws_layout(p, M, false);
     const int nthr = 256;
     const dim3 gM((unsigned)((M + nthr - 1) / nthr));
     hipLaunchKernelGGL(k_gather_nnz, gM, dim3(nthr), 0, s, (const int *)(ws + L.i0), (const int *)(ws + L.fsz),
@@ -822,20 +826,22 @@ wp_status launch_build_factor_bytes(const wp_plan *p, int64_t M, void *wsv, int6
     return WP_OK;
 }
 
-wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
-                             void *wsv, int64_t *nnz_total, int64_t *nwork, hipStream_t s) {
+wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                             const double *beam, double E, void *wsv, int64_t *nnz_total, int64_t *nwork,
+                             hipStream_t s) {
     unsigned char *ws = (unsigned char *)wsv;
-    const WsLayout L = ws_layout(p, M);
+    const bool rows2d = p->chirp == WP_CHIRP_EXACT || beam;
+    const WsLayout L = ws_layout(p, M, rows2d);
     const int T = p->ntile * p->ntile;
     WP_HIP(hipMemsetAsync(ws + L.err, 0, 16, s));
     wp_status st;
-    if (p->chirp == WP_CHIRP_EXACT) {
+    if (rows2d) {
         switch (p->logNg) {
-            case 6: st = count_rows_exact<6>(p, M, u, v, w, E, ws, L, s); break;
-            case 7: st = count_rows_exact<7>(p, M, u, v, w, E, ws, L, s); break;
-            case 8: st = count_rows_exact<8>(p, M, u, v, w, E, ws, L, s); break;
-            case 9: st = count_rows_exact<9>(p, M, u, v, w, E, ws, L, s); break;
-            default: return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp needs Ng <= %d (Ng = %d)",
+            case 6: st = count_rows_exact<6>(p, M, u, v, w, beam, E, ws, L, s); break;
+            case 7: st = count_rows_exact<7>(p, M, u, v, w, beam, E, ws, L, s); break;
+            case 8: st = count_rows_exact<8>(p, M, u, v, w, beam, E, ws, L, s); break;
+            case 9: st = count_rows_exact<9>(p, M, u, v, w, beam, E, ws, L, s); break;
+            default: return wp_set_error(WP_EUNSUPPORTED, "build: 2-D rows need Ng <= %d (Ng = %d)",
                                          EXACT_MAX_NG, p->Ng);
         }
     } else switch (p->logNg) {
@@ -891,17 +897,19 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
     WP_HIP(hipMemcpyAsync(&host_err, ws + L.err, 4, hipMemcpyDeviceToHost, s));
     WP_HIP(hipStreamSynchronize(s));
     if (host_err & 1)
-        return wp_set_error(WP_EINVAL, "build_G_count: a visibility has non-finite (u, v, w) or lies outside the band |u|,|v| < N/(2L)");
+        return wp_set_error(WP_EINVAL, "build_G_count: a visibility has non-finite (u, v, w), lies outside the band "
+                            "|u|,|v| < N/(2L)%s", beam ? " or has a beam that is not finite with sigma > 0" : "");
     *nnz_total = host_rowptr_end;
     *nwork = host_items;
     return WP_OK;
 }
 
-wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
-                            const void *wsv, wp_G *G, hipStream_t s) {
+wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                            const double *beam, double E, const void *wsv, wp_G *G, hipStream_t s) {
     (void)E;
     unsigned char *ws = (unsigned char *)const_cast<void *>(wsv);
-    const WsLayout L = ws_layout(p, M);
+    const bool rows2d = p->chirp == WP_CHIRP_EXACT || beam;
+    const WsLayout L = ws_layout(p, M, rows2d);
     const int T = p->ntile * p->ntile;
     WP_HIP(hipMemcpyAsync(G->rowptr, ws + L.rowptr, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
     WP_HIP(hipMemcpyAsync(G->perm, ws + L.i0, 4 * M, hipMemcpyDeviceToDevice, s));
@@ -915,13 +923,13 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
         WP_HIP(hipMemcpyAsync(G->frec, ws + L.frec, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
     }
     wp_status st;
-    if (p->chirp == WP_CHIRP_EXACT) {
+    if (rows2d) {
         switch (p->logNg) {
-            case 6: st = fill_rows_exact<6>(p, M, u, v, w, ws, L, G, s); break;
-            case 7: st = fill_rows_exact<7>(p, M, u, v, w, ws, L, G, s); break;
-            case 8: st = fill_rows_exact<8>(p, M, u, v, w, ws, L, G, s); break;
-            case 9: st = fill_rows_exact<9>(p, M, u, v, w, ws, L, G, s); break;
-            default: return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp needs Ng <= %d (Ng = %d)",
+            case 6: st = fill_rows_exact<6>(p, M, u, v, w, beam, ws, L, G, s); break;
+            case 7: st = fill_rows_exact<7>(p, M, u, v, w, beam, ws, L, G, s); break;
+            case 8: st = fill_rows_exact<8>(p, M, u, v, w, beam, ws, L, G, s); break;
+            case 9: st = fill_rows_exact<9>(p, M, u, v, w, beam, ws, L, G, s); break;
+            default: return wp_set_error(WP_EUNSUPPORTED, "build: 2-D rows need Ng <= %d (Ng = %d)",
                                          EXACT_MAX_NG, p->Ng);
         }
     } else switch (p->logNg) {

@@ -1,10 +1,13 @@
-// Rows of G for the exact w-term (Eq. 4), which is not separable (Sections 3.1 and 3.2).
+// Rows of G made whole in 2-D: the exact w-term (Eq. 4), which is not separable, and any chirp
+// times a per-visibility direction-dependent effect (Sections 3.1 and 3.2).
 //
 // Row k, for a visibility at grid coordinates (u~, v~) with component w:
-//   1. chirp c(l, m) = exp(-2 pi i w (sqrt(1 - l^2 - m^2) - 1)) on the padded grid,
-//      l = t_u delta, m = t_v delta, t in [-Ng/2, Ng/2) stored at index t mod Ng;
-//      sqrt(1 - r^2) - 1 is evaluated as -r^2 / (1 + sqrt(1 - r^2)) (no cancellation)
-//      and the phase 2 w r^2 / (1 + sqrt(1 - r^2)) goes to sincospi in FP64;
+//   1. modulation c(l, m) on the padded grid, l = t_u delta, m = t_v delta, t in
+//      [-Ng/2, Ng/2) stored at index t mod Ng: the exact chirp
+//      exp(-2 pi i w (sqrt(1 - l^2 - m^2) - 1)), with sqrt(1 - r^2) - 1 evaluated as
+//      -r^2 / (1 + sqrt(1 - r^2)) (no cancellation) and the phase 2 w r^2 / (1 + sqrt(1 - r^2))
+//      given to sincospi in FP64, or the linear chirp exp(i pi w r^2); with a beam
+//      (l0, m0, sigma) per visibility, times exp(-((l - l0)^2 + (m - m0)^2) / (2 sigma^2));
 //   2. H(d) = Ng^-2 sum_t c(t) exp(-2 pi i t.d / Ng): a 2-D FFT in FP64, rows in one
 //      kernel and columns in the next, both in LDS;
 //   3. g(q) = sum_{a,b} KB(u~ - q'_a) KB(v~ - q'_b) H(q' - q) (indices mod Ng).  The
@@ -51,12 +54,20 @@ __device__ inline bool exact_coords(const double *u, const double *v, const doub
     return isfinite(ut) && isfinite(vt) && isfinite(wk) && fabs(ut) < Ng / 2 && fabs(vt) < Ng / 2;
 }
 
+// a visibility's beam (l0, m0, sigma) is usable: finite, sigma > 0
+__device__ inline bool beam_ok(const double *beam, int64_t k) {
+    if (!beam) return true;
+    const double l0 = beam[3 * k], m0 = beam[3 * k + 1], sg = beam[3 * k + 2];
+    return isfinite(l0) && isfinite(m0) && isfinite(sg) && sg > 0.0;
+}
+
 // Pass 1 of a chunk: chirp rows t_v = line, FFT along u, correlation along u with the u window.
 // Block (x, b) handles EX_LINES rows of chunk member b (visibility perm[base + b], or base + b
 // when perm is null).  out[b][t_v][q_u] (double2).
 template <int LOGNG>
 __global__ __launch_bounds__(BNTH) void k_exact_rows(const double *__restrict__ u, const double *__restrict__ v,
-                                                     const double *__restrict__ w, const int *__restrict__ perm,
+                                                     const double *__restrict__ w, const double *__restrict__ beam,
+                                                     int exact, const int *__restrict__ perm,
                                                      int64_t base, double cell, double delta, int W, double beta,
                                                      const double2 *__restrict__ tw64, double2 *__restrict__ out) {
     constexpr int Ng = 1 << LOGNG;
@@ -65,7 +76,7 @@ __global__ __launch_bounds__(BNTH) void k_exact_rows(const double *__restrict__ 
     const int b = blockIdx.y;
     const int64_t k = perm ? (int64_t)perm[base + b] : base + b;
     double ut, vt, wk;
-    const bool ok = exact_coords(u, v, w, k, cell, Ng, ut, vt, wk);
+    const bool ok = exact_coords(u, v, w, k, cell, Ng, ut, vt, wk) && beam_ok(beam, k);
     double2 *dst = out + ((int64_t)b * Ng + (int64_t)blockIdx.x * EX_LINES) * Ng;
     if (!ok) {
         for (int e = threadIdx.x; e < EX_LINES * Ng; e += BNTH) dst[e] = make_double2(0.0, 0.0);
@@ -77,7 +88,13 @@ __global__ __launch_bounds__(BNTH) void k_exact_rows(const double *__restrict__ 
         const double l = (iu < Ng / 2 ? iu : iu - Ng) * delta, m = (iv < Ng / 2 ? iv : iv - Ng) * delta;
         const double r2 = l * l + m * m;
         double sn, cs;
-        sincospi(2.0 * wk * r2 / (1.0 + sqrt(1.0 - r2)), &sn, &cs);
+        sincospi(exact ? 2.0 * wk * r2 / (1.0 + sqrt(1.0 - r2)) : wk * r2, &sn, &cs);
+        if (beam) {
+            const double dl = l - beam[3 * k], dm = m - beam[3 * k + 1], sg = beam[3 * k + 2];
+            const double a = exp(-(dl * dl + dm * dm) / (2.0 * sg * sg));
+            cs *= a;
+            sn *= a;
+        }
         buf[e] = make_double2(cs, sn);
     }
     __syncthreads();
@@ -99,7 +116,8 @@ __global__ __launch_bounds__(BNTH) void k_exact_rows(const double *__restrict__ 
 // rows: other blocks still read their columns of rows) instead of g (double2, in place).
 template <int LOGNG, bool ENERGY>
 __global__ __launch_bounds__(BNTH) void k_exact_cols(const double *__restrict__ u, const double *__restrict__ v,
-                                                     const double *__restrict__ w, const int *__restrict__ perm,
+                                                     const double *__restrict__ w, const double *__restrict__ beam,
+                                                     const int *__restrict__ perm,
                                                      int64_t base, double cell, double beta, int W,
                                                      const double2 *__restrict__ tw64, double2 *__restrict__ rows,
                                                      double *__restrict__ energy_out) {
@@ -109,7 +127,7 @@ __global__ __launch_bounds__(BNTH) void k_exact_cols(const double *__restrict__ 
     const int b = blockIdx.y;
     const int64_t k = perm ? (int64_t)perm[base + b] : base + b;
     double ut, vt, wk;
-    const bool ok = exact_coords(u, v, w, k, cell, Ng, ut, vt, wk);
+    const bool ok = exact_coords(u, v, w, k, cell, Ng, ut, vt, wk) && beam_ok(beam, k);
     const int qu0 = blockIdx.x * EX_LINES;
     double2 *src = rows + (int64_t)b * Ng * Ng;
     const Taps tv = kb_taps(ok ? vt : 0.0, W, beta, Ng, s_wv);
@@ -138,8 +156,8 @@ __global__ __launch_bounds__(BNTH) void k_exact_cols(const double *__restrict__ 
 // Count pass, per row: tau, kept count, sort key.  One block per chunk member (visibility base + b).
 template <int LOGNG>
 __global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u, const double *__restrict__ v,
-                                                    const double *__restrict__ w, int64_t base, double cell,
-                                                    double E, const double *__restrict__ en,
+                                                    const double *__restrict__ w, const double *__restrict__ beam,
+                                                    int64_t base, double cell, double E, const double *__restrict__ en,
                                                     double *__restrict__ tau_out, int *__restrict__ nnz_out,
                                                     int *__restrict__ key_out, int *__restrict__ fsz_out,
                                                     int *__restrict__ err) {
@@ -152,7 +170,7 @@ __global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u
     const int b = blockIdx.x;
     const int64_t k = base + b;
     double ut, vt, wk;
-    if (!exact_coords(u, v, w, k, cell, Ng, ut, vt, wk)) {
+    if (!exact_coords(u, v, w, k, cell, Ng, ut, vt, wk) || !beam_ok(beam, k)) {
         if (threadIdx.x == 0) {
             atomicOr(err, 1);
             tau_out[k] = INFINITY;

@@ -168,13 +168,14 @@ wp_status launch_sort_pairs(const int *key, int64_t n, int bits, int *keys_out, 
 // exclusive scan of n ints into out[0..n] (out[n] = total); ws: scan_workspace_bytes(n)
 int64_t scan_workspace_bytes(int64_t n);
 wp_status launch_scan_int(const int *in, int *out, int64_t n, void *ws, hipStream_t s);
-int64_t builder_workspace_bytes(const wp_plan *p, int64_t M);
+int64_t builder_workspace_bytes(const wp_plan *p, int64_t M, bool rows2d);
 wp_status launch_build_factor_bytes(const wp_plan *p, int64_t M, void *ws, int64_t *bytes, hipStream_t s);
-wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v,
-                             const double *w, double E, void *ws, int64_t *nnz, int64_t *nwork,
+// beam: [M][3] (l0, m0, sigma) per visibility, or NULL; with a beam (or the exact chirp) rows are made in 2-D
+wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                             const double *beam, double E, void *ws, int64_t *nnz_total, int64_t *nwork,
                              hipStream_t s);
-wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v,
-                            const double *w, double E, const void *ws, wp_G *G, hipStream_t s);
+wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w,
+                            const double *beam, double E, const void *ws, wp_G *G, hipStream_t s);
 
 
 // solver (solver.hip)

@@ -53,13 +53,13 @@ def gpu_rows(G):
     return rp, col, val, perm, inv
 
 
-def check_rows(G, u, v, w, E, s, rows):
+def check_rows(G, u, v, w, E, s, rows, beam=None):
     """Kept sets and values of the sampled rows against dense oracle rows."""
     rp, col, val, perm, inv = gpu_rows(G)
     ut = u * 2 * s.L          # u / du with du = 1 / (2L)
     vt = v * 2 * s.L
     for k in rows:
-        g = wproj.kernel_row(ut[k], vt[k], w[k], s).ravel()
+        g = wproj.kernel_row(ut[k], vt[k], w[k], s, None if beam is None else tuple(beam[k])).ravel()
         m = (g * g.conj()).real
         tau, _ = wproj.energy_threshold(m, E)
         want = np.nonzero(m >= tau)[0]
@@ -569,3 +569,45 @@ def test_exact_chirp_limits():
         wp.build_G(wp.Plan(64, 0.75, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 0.9)
     with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):      # rows are not separable
         wp.build_G(wp.Plan(64, L, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 0.9, factors=True)
+
+
+# --------------------------------------------------------------------------- direction-dependent effect
+
+def _beams(M, Lf, seed):
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(-0.2, 0.2, M) * Lf, rng.uniform(-0.2, 0.2, M) * Lf,
+                     rng.uniform(0.3, 0.8, M) * Lf], axis=1)
+
+
+@pytest.mark.parametrize("chirp", ["linear", "exact"])
+def test_dde_rows_and_operator_match_oracle(chirp):
+    wl = synth.workload(0)
+    say(f"build with beams: {wl.name} N={wl.N} M={wl.M} chirp={chirp}")
+    x, u, v, w = synth.workload_inputs(wl)
+    beam = _beams(wl.M, wl.L, 51)
+    s = Setup(N=wl.N, L=wl.L, kind=chirp)
+    plan = wp.Plan(wl.N, wl.L, chirp=wp.WP_CHIRP_EXACT if chirp == "exact" else wp.WP_CHIRP_LINEAR)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E, beam=dev(beam))
+    torch.cuda.synchronize()
+    Go = wproj.build_rows(u, v, w, wl.E, s, beam=beam)
+    assert abs(G.nnz - Go.nnz) <= 1e-6 * Go.nnz
+    check_rows(G, u, v, w, wl.E, s, range(0, wl.M, 3), beam=beam)
+    G.order = wp.WP_ORDER_CALLER
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    assert relerr(y, wproj.phi(Go, x, s)) < TOL
+    r = synth.random_complex(wl.M, np.random.default_rng(52))
+    xa = wp.apply_PhiT(plan, G, c64(r)).cpu().numpy().reshape(wl.N, wl.N)
+    assert relerr(xa, wproj.phi_adjoint(Go, r, s)) < TOL
+
+
+def test_dde_invalid_beams_and_limits():
+    N = 64
+    plan = wp.Plan(N, L)
+    z = np.zeros(3)
+    for bad in ([0.0, 0.0, 0.0], [0.0, np.nan, 0.01], [np.inf, 0.0, 0.01]):
+        beam = np.tile([0.0, 0.0, 0.01], (3, 1))
+        beam[1] = bad
+        with pytest.raises(wp.WprojError, match="WP_EINVAL"):
+            wp.build_G(plan, dev(z), dev(z), dev(z), 0.9, beam=dev(beam))
+    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):       # Ng = 1024 > 512
+        wp.build_G(wp.Plan(512, L), dev(z), dev(z), dev(z), 0.9, beam=dev(np.tile([0.0, 0.0, 0.01], (3, 1))))
