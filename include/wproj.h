@@ -248,7 +248,10 @@ wp_status wp_grid_adjoint(const wp_plan *plan, void *grid, void *x, void *stream
 /* y = G grid (degridding sparse matrix-vector product; from the factor records when
  * G->frec is set, taps formed in registers) */
 wp_status wp_degrid(const wp_plan *plan, const wp_G *G, const void *grid, void *y, void *stream);
-/* grid = G^H y (gridding: tile-binned scatter, LDS accumulation, atomics at tile borders) */
+/* grid = G^H y (gridding: tile-binned scatter; each tile's window accumulates in LDS in 64-bit
+ * fixed point scaled by a bound on its partial sums, then float atomics flush it and take the
+ * entries beyond the window).  The bound assumes taps the builder made: |G_kc| <= (W I0(beta))^2
+ * (int16 taps: 46341 times the row scale); larger taps in a hand-made G can overflow the window. */
 wp_status wp_grid_scatter(const wp_plan *plan, const wp_G *G, const void *y, void *grid,
                           void *stream);
 /* grid = G^H y from the transposed copy (no atomics, deterministic); needs G->tcolptr.

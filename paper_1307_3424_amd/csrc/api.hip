@@ -33,6 +33,17 @@ double kb_transform(double xi, int W, double beta) {
     return W;
 }
 
+// I0 by its power series sum_k ((x/2)^2)^k / (k!)^2
+static double bessel_i0_host(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500 && term > 1e-17 * sum; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+    }
+    return sum;
+}
+
 hipStream_t as_stream(void *s) { return (hipStream_t)s; }
 
 wp_status check_plan(const wp_plan *p) {
@@ -107,6 +118,9 @@ wp_status wp_plan_create(wp_plan **out, int N, double fov_L, int kb_W, double kb
     p->beta = kb_beta > 0 ? kb_beta : M_PI * std::sqrt((kb_W / 2.0) * (kb_W / 2.0) * 1.5 * 1.5 - 0.8);
     p->delta = fov_L / N;
     p->cell = 1.0 / (p->Ng * p->delta);
+    // |tap| <= (sum of one axis' W window weights)^2 <= (W I0(beta))^2: each 1-D chirp spectrum value
+    // has modulus at most 1 (and a beam at most 1), the window weights peak at I0(beta)
+    p->tap_bound = (kb_W * bessel_i0_host(p->beta)) * (kb_W * bessel_i0_host(p->beta));
     p->tile = 32;
     p->halo = 16;
     p->ntile = p->Ng / p->tile;

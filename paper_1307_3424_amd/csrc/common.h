@@ -22,6 +22,7 @@ struct wp_plan {
     double beta;    // KB shape
     double delta;   // pixel size L / N
     double cell;    // uv cell 1 / (Ng delta) = 1 / (2L)
+    double tap_bound;   // an upper bound on |G_kc| for every row the builder makes
     int tile;       // adjoint scatter: tile side in cells
     int halo;       // adjoint scatter: LDS window margin per side
     int ntile;      // tiles per axis

@@ -169,8 +169,15 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
                                                     const void *__restrict__ val, const float *__restrict__ rscale,
                                                     const int *__restrict__ perm,
                                                     const float2 *__restrict__ y, float *__restrict__ grid, int logNg,
-                                                    int tile, int halo) {
-    extern __shared__ float win[];                  // [2][WS][WS]: real plane, imaginary plane
+                                                    int tile, int halo, double tap_bound) {
+    // The window accumulates in 64-bit fixed point: LDS integer atomics cost a few clocks per
+    // wavefront instruction where LDS float atomics cost ~200 on this GPU, and integer sums do
+    // not depend on the order of the adds.  Scale: every partial sum of a cell is at most
+    // S = sum over the item's rows of |y_k| max |G_k.| (max |G| <= tap_bound; an int16 tap is at
+    // most 46341 in modulus before its row scale), so q = 2^61 / S keeps it within int64 with a
+    // quantum of S 2^-61, far below float rounding.
+    extern __shared__ unsigned long long win[];     // [2][WS][WS]: real plane, imaginary plane
+    __shared__ double s_red[WAVES];
     const int Ng = 1 << logNg, mask = Ng - 1;
     const int WS = tile + 2 * halo;
     const int WS2 = WS * WS;
@@ -178,9 +185,20 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
     const int tv = work[4 * item + 0], tu = work[4 * item + 1];
     const int rb = work[4 * item + 2], re = work[4 * item + 3];
     const int v0 = (tv * tile - halo) & mask, u0 = (tu * tile - halo) & mask;
-    for (int e = threadIdx.x; e < 2 * WS2; e += SP_NTH) win[e] = 0.f;
-    __syncthreads();
+    for (int e = threadIdx.x; e < 2 * WS2; e += SP_NTH) win[e] = 0ull;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double bsum = 0.0;
+    for (int r = rb + threadIdx.x; r < re; r += SP_NTH) {
+        const float2 yk = y[perm ? perm[r] : r];
+        const double ay = sqrt((double)yk.x * yk.x + (double)yk.y * yk.y);
+        bsum += TK == WP_TAPS_I16 ? 46341.0 * (double)rscale[r] * ay : tap_bound * ay;
+    }
+    for (int o = 32; o > 0; o >>= 1) bsum += __shfl_xor(bsum, o);
+    if (lane == 0) s_red[wid] = bsum;
+    __syncthreads();
+    double S = 0.0;
+    for (int i = 0; i < WAVES; ++i) S += s_red[i];
+    const double q = S > 0.0 ? 2305843009213693952.0 / S : 1.0;     // 2^61 / S
     for (int r = rb + wid; r < re; r += WAVES) {
         float2 yk = y[perm ? perm[r] : r];
         if constexpr (TK == WP_TAPS_I16) {
@@ -196,8 +214,8 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
             const int dv = ((c >> logNg) - v0) & mask;
             const int du = ((c & mask) - u0) & mask;
             if (dv < WS && du < WS) {
-                atomicAdd(&win[dv * WS + du], cr);
-                atomicAdd(&win[WS2 + dv * WS + du], ci);
+                atomicAdd(&win[dv * WS + du], (unsigned long long)__double2ll_rn((double)cr * q));
+                atomicAdd(&win[WS2 + dv * WS + du], (unsigned long long)__double2ll_rn((double)ci * q));
             } else {
                 unsafeAtomicAdd(&grid[2 * (int64_t)c], cr);
                 unsafeAtomicAdd(&grid[2 * (int64_t)c + 1], ci);
@@ -205,14 +223,15 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
         }
     }
     __syncthreads();
+    const double iq = 1.0 / q;
     const int WE = WS < Ng ? WS : Ng;
     for (int e = threadIdx.x; e < WE * WE; e += SP_NTH) {
         const int dv = e / WE, du = e % WE;
-        const float a = win[dv * WS + du], b = win[WS2 + dv * WS + du];
-        if (a != 0.f || b != 0.f) {
+        const long long a = (long long)win[dv * WS + du], b = (long long)win[WS2 + dv * WS + du];
+        if (a != 0 || b != 0) {
             const int64_t g = (int64_t)((v0 + dv) & mask) * Ng + ((u0 + du) & mask);
-            unsafeAtomicAdd(&grid[2 * g], a);
-            unsafeAtomicAdd(&grid[2 * g + 1], b);
+            unsafeAtomicAdd(&grid[2 * g], (float)((double)a * iq));
+            unsafeAtomicAdd(&grid[2 * g + 1], (float)((double)b * iq));
         }
     }
 }
@@ -450,17 +469,20 @@ wp_status launch_scatter(const wp_plan *p, const wp_G *G, const float2 *y, float
     wp_status st = launch_fill_zero((float *)grid, 2 * (int64_t)p->Ng * p->Ng, s);
     if (st != WP_OK || G->n_work == 0) return st;
     const int WS = p->tile + 2 * p->halo;
-    const size_t lds = (size_t)2 * WS * WS * sizeof(float);
+    const size_t lds = (size_t)2 * WS * WS * sizeof(unsigned long long);
     const dim3 gw((unsigned)G->n_work), bw(SP_NTH);
     if (G->taps == WP_TAPS_BF16)
         hipLaunchKernelGGL((k_scatter<WP_TAPS_BF16>), gw, bw, lds, s, G->work, G->n_work, G->rowptr, G->col, G->val,
-                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
+                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo,
+                           p->tap_bound);
     else if (G->taps == WP_TAPS_I16)
         hipLaunchKernelGGL((k_scatter<WP_TAPS_I16>), gw, bw, lds, s, G->work, G->n_work, G->rowptr, G->col, G->val,
-                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
+                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo,
+                           p->tap_bound);
     else
         hipLaunchKernelGGL((k_scatter<WP_TAPS_C64>), gw, bw, lds, s, G->work, G->n_work, G->rowptr, G->col, G->val,
-                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo);
+                           G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo,
+                           p->tap_bound);
     return wp_check_launch("grid_scatter");
 }
 
