@@ -298,3 +298,20 @@ def test_grid_transforms_are_adjoint_and_centred():
     o = geometry.pad_offset(N)
     z[o:o + N, o:o + N] = x * wproj.apodisation(s)
     assert np.abs(Fm @ z @ Fm.T - X).max() < 1e-10 * np.abs(X).max()
+
+
+@pytest.mark.parametrize("kind", ["linear", "exact"])
+def test_taps_are_bounded_by_the_window_peak(kind):
+    """|G_kc| <= (W I0(beta))^2 for every row (the scatter's fixed-point scale relies on it): each
+    axis sums W window weights <= I0(beta) against chirp-spectrum values of modulus <= 1."""
+    from scipy import special
+    N = 32
+    for W in (4, 6):
+        s = Setup(N=N, L=0.3, W=W, kind=kind)
+        bound = (W * special.i0(s.beta)) ** 2
+        u, v, w = synth.uvw(N, 40, 0.3, "uniform", 0.25, N / (2 * 0.3 ** 2), np.random.default_rng(61 + W))
+        w[:8] = 0.0                                    # w = 0 rows concentrate the most energy
+        ut, vt = u * 2 * s.L, v * 2 * s.L
+        peak = max(np.abs(wproj.kernel_row(ut[k], vt[k], w[k], s)).max() for k in range(40))
+        assert peak <= bound
+        assert peak > 1e-3 * bound                     # and the bound is not vacuous
