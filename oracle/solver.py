@@ -64,13 +64,14 @@ def project_ball(z: np.ndarray, y: np.ndarray, eps: float) -> np.ndarray:
 
 def solve(y, apply, apply_adj, shape, eps: float, nu: float, iters: int,
           levels: int = 4, tau: float = 0.49, history: bool = False, x_true=None,
-          dictionary=None, weights=None, x0=None):
+          dictionary=None, weights=None, x0=None, positive: bool = True):
     """Returns x (and the SNR history against x_true when asked).
 
     dictionary: optional (analysis, synthesis) pair replacing the wavelets of `levels`
     (it must satisfy ||Psi|| <= 1, as a tight frame normalised to 1 does); weights: optional
     non-negative array shaped like the coefficients, the weighted norm ||W Psi^T x||_1 (the
-    prox of its conjugate clips coefficient i to [-w_i, w_i]); x0: start (zeros by default).
+    prox of its conjugate clips coefficient i to [-w_i, w_i]); x0: start (zeros by default);
+    positive=False drops the positivity constraint (Eq. 7 as printed).
     """
     if dictionary is None:
         analysis, synthesis = (lambda z: dwt2(z, levels)), (lambda c: idwt2(c, levels))
@@ -84,7 +85,9 @@ def solve(y, apply, apply_adj, shape, eps: float, nu: float, iters: int,
     v2 = np.zeros(np.asarray(y).shape, dtype=np.complex128)
     hist = []
     for _ in range(iters):
-        xn = np.maximum(0.0, x - tau * (synthesis(v1) + np.real(apply_adj(v2))))
+        xn = x - tau * (synthesis(v1) + np.real(apply_adj(v2)))
+        if positive:
+            xn = np.maximum(0.0, xn)
         xb = 2.0 * xn - x
         v1 = np.clip(v1 + s1 * analysis(xb), -bound, bound)
         u = v2 + s2 * apply(xb)
