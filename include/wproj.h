@@ -464,6 +464,19 @@ wp_status wp_power_norm2(const wp_plan *plan, const wp_G *G, const float *x0, in
 wp_status wp_solve(const wp_plan *plan, const wp_G *G, const void *y, double eps, double nu,
                    int iters, int levels, float *x, void *workspace, void *stream);
 
+/* Douglas-Rachford splitting (Section 2.3) for Eq. 7 as printed: min ||Psi^T x||_1 subject to
+ * ||y - Phi x||_2 <= eps, x real, without the positivity wp_solve adds; Psi is Daubechies 8 with
+ * `levels` levels, or the Dirac basis for levels = 0.  From z = 0, each of `iters` iterations sets
+ * x = P_C(z), the projection onto the constraint, then z = z + Psi soft_gamma(Psi^T (2x - z)) - x
+ * (soft threshold gamma >= 0).  Phi is not a tight frame, so P_C runs `inner` (>= 1) steps of
+ * forward-backward on its dual, warm-started from the previous iteration's dual, each one Phi
+ * and one Phi^H with step 1 / nu (nu = ||Phi||^2).  x (device, real N*N floats) receives the last
+ * projection.  Asynchronous. */
+wp_status wp_dr_workspace_bytes(const wp_plan *plan, const wp_G *G, int64_t *bytes_out);
+wp_status wp_dr_solve(const wp_plan *plan, const wp_G *G, const void *y, double eps, double nu,
+                      int iters, int inner, double gamma, int levels, float *x, void *workspace,
+                      void *stream);
+
 /* ----------------------------------------------------------------------------------------
  * SARA (Section 4.2's third dictionary; the paper cites Carrillo, McEwen & Wiaux 2012 for it):
  * Psi = [I, W_1, ..., W_8] / 3, W_p the periodic Daubechies wavelets with p vanishing moments

@@ -21,7 +21,7 @@ from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR
 __all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16", "WP_TAPS_I16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
-           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "sara_analysis", "sara_synthesis",
+           "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "dr_solve", "sara_analysis", "sara_synthesis",
            "sara_solve", "Batch", "Mlp", "Surrogate"]
 
 
@@ -354,6 +354,23 @@ def solve(plan: Plan, G: GMatrix, y, eps: float, nu: float, iters: int, levels: 
     ws = _solver_ws(plan, G, d) if ws is None else ws
     check(load().wp_solve(plan.handle, C.byref(d), _ptr(y), float(eps), float(nu), int(iters), int(levels),
                           _ptr(x), _ptr(ws), _stream(stream)), "wp_solve")
+    x._wp_ws = ws
+    return x
+
+
+def dr_solve(plan: Plan, G: GMatrix, y, eps: float, nu: float, iters: int, inner: int, gamma: float,
+             levels: int = 4, x=None, stream=None):
+    """wp_dr_solve: Douglas-Rachford for Eq. 7 without positivity; returns x (float32 N*N)."""
+    torch = _torch()
+    _dev_c64(y, G.M, "y")
+    x = torch.empty(plan.N * plan.N, dtype=torch.float32, device=y.device) if x is None else \
+        _dev_f32(x, plan.N * plan.N, "x")
+    d = G.desc()
+    b = C.c_int64()
+    check(load().wp_dr_workspace_bytes(plan.handle, C.byref(d), C.byref(b)), "wp_dr_workspace_bytes")
+    ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+    check(load().wp_dr_solve(plan.handle, C.byref(d), _ptr(y), float(eps), float(nu), int(iters), int(inner),
+                             float(gamma), int(levels), _ptr(x), _ptr(ws), _stream(stream)), "wp_dr_solve")
     x._wp_ws = ws
     return x
 

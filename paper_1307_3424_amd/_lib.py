@@ -97,6 +97,8 @@ SIGNATURES = {
     "wp_solver_workspace_bytes": ([_vp, _PG, _pi64], _i32),
     "wp_power_norm2": ([_vp, _PG, _vp, _i32, _vp, C.POINTER(C.c_double), _vp], _i32),
     "wp_solve": ([_vp, _PG, _vp, _d, _d, _i32, _i32, _vp, _vp, _vp], _i32),
+    "wp_dr_workspace_bytes": ([_vp, _PG, _pi64], _i32),
+    "wp_dr_solve": ([_vp, _PG, _vp, _d, _d, _i32, _i32, _d, _i32, _vp, _vp, _vp], _i32),
     "wp_sara_analysis": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_sara_synthesis": ([_vp, _i32, _vp, _vp, _vp, _vp], _i32),
     "wp_sara_workspace_bytes": ([_vp, _PG, _pi64], _i32),

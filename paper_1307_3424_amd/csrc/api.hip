@@ -491,4 +491,25 @@ wp_status wp_sara_solve(const wp_plan *p, const wp_G *G, const void *y, double e
                              (unsigned char *)workspace, as_stream(stream));
 }
 
+wp_status wp_dr_workspace_bytes(const wp_plan *p, const wp_G *G, int64_t *bytes) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
+    if (!bytes) return wp_set_error(WP_EINVAL, "NULL argument");
+    *bytes = dr_workspace_bytes(p, G->M);
+    return WP_OK;
+}
+
+wp_status wp_dr_solve(const wp_plan *p, const wp_G *G, const void *y, double eps, double nu, int iters, int inner,
+                      double gamma, int levels, float *x, void *workspace, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, !G || !G->tcolptr)) return s;
+    if (!y || !x || !workspace) return wp_set_error(WP_EINVAL, "NULL argument");
+    if (!(eps >= 0.0) || !(nu > 0.0) || !std::isfinite(eps) || !std::isfinite(nu))
+        return wp_set_error(WP_EINVAL, "eps = %g, nu = %g: need eps >= 0 and nu > 0, finite", eps, nu);
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return wp_set_error(WP_EINVAL, "gamma = %g", gamma);
+    if (iters < 0 || inner < 1) return wp_set_error(WP_EINVAL, "iters = %d, inner = %d", iters, inner);
+    return launch_dr_solve(p, wp_operator{G, nullptr, G->M}, (const float2 *)y, eps, nu, iters, inner, gamma, levels,
+                           x, (unsigned char *)workspace, as_stream(stream));
+}
+
 }  // extern "C"

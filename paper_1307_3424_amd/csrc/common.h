@@ -191,6 +191,9 @@ wp_status op_phi(const wp_plan *p, const wp_operator &op, const float2 *x, float
 wp_status op_phiT(const wp_plan *p, const wp_operator &op, const float2 *y, float2 *x, float2 *grid, hipStream_t s);
 int64_t solver_workspace_bytes(const wp_plan *p, int64_t M);
 int64_t sara_workspace_bytes(const wp_plan *p, int64_t M);
+int64_t dr_workspace_bytes(const wp_plan *p, int64_t M);
+wp_status launch_dr_solve(const wp_plan *p, const wp_operator &op, const float2 *y, double eps, double nu, int iters,
+                          int inner, double gamma, int levels, float *x, unsigned char *ws, hipStream_t s);
 wp_status launch_sara_analysis(const wp_plan *p, int levels, const float *x, float *c, float *tmp, hipStream_t s);
 wp_status launch_sara_synthesis(const wp_plan *p, int levels, const float *c, float *x, float *tmp, hipStream_t s);
 wp_status launch_sara_solve(const wp_plan *p, const wp_operator &op, const float2 *y, double eps, double nu, int iters,

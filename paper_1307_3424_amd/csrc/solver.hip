@@ -316,6 +316,38 @@ __global__ void k_sum_dev(const float *__restrict__ a, int64_t n, double *__rest
     }
 }
 
+// Douglas-Rachford elementwise steps
+// x = z - Re t (and xc = complex(x) when given)
+__global__ void k_dr_sub(const float *__restrict__ z, const float2 *__restrict__ t, float *__restrict__ x,
+                         float2 *__restrict__ xc, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = z[i] - t[i].x;
+    x[i] = v;
+    if (xc) xc[i] = make_float2(v, 0.f);
+}
+
+// r = 2 x - z
+__global__ void k_dr_reflect(const float *__restrict__ x, const float *__restrict__ z, float *__restrict__ r,
+                             int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = 2.f * x[i] - z[i];
+}
+
+// a = sign(a) max(|a| - g, 0)
+__global__ void k_soft(float *__restrict__ a, int64_t n, float g) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float m = fabsf(a[i]) - g;
+    a[i] = m > 0.f ? copysignf(m, a[i]) : 0.f;
+}
+
+// z = z + q - x
+__global__ void k_dr_update(float *__restrict__ z, const float *__restrict__ q, const float *__restrict__ x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = z[i] + q[i] - x[i];
+}
+
 // acc += sum |u / s2 - y|^2, u = v2 + s2 p  (FP64)
 __global__ void k_ball_norm(const float2 *__restrict__ v2, const float2 *__restrict__ p, const float2 *__restrict__ y,
                             int64_t n, float s2, double *__restrict__ acc) {
@@ -681,6 +713,65 @@ wp_status launch_sara_solve(const wp_plan *p, const wp_operator &op, const float
         }
     }
     return wp_check_launch("sara_solve");
+}
+
+// ---------------------------------------------------------------------------- Douglas-Rachford
+// Eq. 7 as printed (no positivity), the splitting Section 2.3 names:
+//   x = P_C(z);  z = z + Psi soft_gamma(Psi^T (2 x - z)) - x,   z_0 = 0,
+// C = {x : ||y - Phi x|| <= eps}.  P_C by forward-backward on its dual u (carried over between
+// outer iterations, zero at the start): `inner` times p = Phi (z - Re Phi^H u), then the ball step
+// of the primal-dual solver's second dual variable with sigma = 1 / ||Phi||^2; P_C(z) = z - Re Phi^H u.
+
+int64_t dr_workspace_bytes(const wp_plan *p, int64_t M) {
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng;
+    auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    return al(8 * G2) + 5 * al(4 * N2) + 2 * al(8 * N2) + 2 * al(8 * M) + al(64);
+}
+
+wp_status launch_dr_solve(const wp_plan *p, const wp_operator &op, const float2 *y, double eps, double nu, int iters,
+                          int inner, double gamma, int levels, float *x, unsigned char *ws, hipStream_t s) {
+    if (wp_status st = check_levels(p, levels)) return st;
+    const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng, M = op.M;
+    auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
+    int64_t o = 0;
+    auto take = [&](int64_t b) { unsigned char *r = ws + o; o += al(b); return r; };
+    float2 *grid = (float2 *)take(8 * G2);
+    float *z = (float *)take(4 * N2);
+    float *xi = (float *)take(4 * N2);
+    float *r = (float *)take(4 * N2);
+    float *c = (float *)take(4 * N2);
+    float *tmp = (float *)take(4 * N2);
+    float2 *t2 = (float2 *)take(8 * N2);
+    float2 *xc = (float2 *)take(8 * N2);
+    float2 *u = (float2 *)take(8 * M);
+    float2 *pv = (float2 *)take(8 * M);
+    double *acc = (double *)take(64);
+    const float mu = (float)(1.0 / nu), g = (float)gamma;
+    WP_HIP(hipMemsetAsync(z, 0, 4 * N2, s));
+    WP_HIP(hipMemsetAsync(u, 0, 8 * M, s));
+    for (int it = 0; it < iters; ++it) {
+        for (int i = 0; i < inner; ++i) {
+            if (wp_status st = op_phiT(p, op, u, t2, grid, s)) return st;                 // Phi^H u
+            hipLaunchKernelGGL(k_dr_sub, blocks_for(N2), dim3(NT), 0, s, z, t2, xi, xc, N2);
+            if (wp_status st = op_phi(p, op, xc, pv, grid, s)) return st;                 // Phi (z - Re Phi^H u)
+            hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, acc, 1);
+            hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, u, pv, y, M, mu, acc);
+            hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, u, pv, y, M, mu, eps, acc);
+        }
+        if (wp_status st = op_phiT(p, op, u, t2, grid, s)) return st;
+        hipLaunchKernelGGL(k_dr_sub, blocks_for(N2), dim3(NT), 0, s, z, t2, x, nullptr, N2);   // x = P_C(z)
+        hipLaunchKernelGGL(k_dr_reflect, blocks_for(N2), dim3(NT), 0, s, x, z, r, N2);
+        if (levels == 0) {
+            hipLaunchKernelGGL(k_soft, blocks_for(N2), dim3(NT), 0, s, r, N2, g);                // Dirac basis
+            hipLaunchKernelGGL(k_dr_update, blocks_for(N2), dim3(NT), 0, s, z, r, x, N2);
+        } else {
+            if (wp_status st = launch_dwt2(p, levels, r, c, tmp, false, s)) return st;
+            hipLaunchKernelGGL(k_soft, blocks_for(N2), dim3(NT), 0, s, c, N2, g);
+            if (wp_status st = launch_dwt2(p, levels, c, r, tmp, true, s)) return st;
+            hipLaunchKernelGGL(k_dr_update, blocks_for(N2), dim3(NT), 0, s, z, r, x, N2);
+        }
+    }
+    return wp_check_launch("dr_solve");
 }
 
 wp_status filter_db8(double *h) { return daubechies(8, h) ? WP_OK : wp_set_error(WP_EHIP, "filter"); }

@@ -116,3 +116,25 @@ def test_levels_rejected():
     for bad in (-1, 5):          # 64 >> 4 = 4 < 8 samples per line at the coarsest level
         with pytest.raises(wp.WprojError):
             wp.dwt2(plan, x, bad)
+
+
+@pytest.mark.parametrize("levels", [4, 0])
+def test_douglas_rachford_matches_oracle(levels):
+    """Douglas-Rachford for Eq. 7 without positivity (Section 2.3)."""
+    from oracle import dr
+    wl, x, u, v, w, s, A, AH, y, eps, x0 = _tiny_problem()
+    print(f"douglas-rachford: {wl.name} levels={levels}", flush=True)
+    nu = solver.power_norm2(A, AH, x0, 50)
+    gamma = 0.01 * np.abs(wavelet.dwt2(np.real(AH(y)) / nu, levels)).max()
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E)
+    G.order = wp.WP_ORDER_CALLER
+    yd = c64(y)
+    xg = wp.dr_solve(plan, G, yd, eps, nu, 4, 3, gamma, levels).cpu().numpy().reshape(wl.N, wl.N)
+    xr = dr.solve(y, A, AH, (wl.N, wl.N), eps, nu, 4, 3, gamma, levels)
+    assert relerr(xg, xr) < 1e-4
+    xg = wp.dr_solve(plan, G, yd, eps, nu, 60, 3, gamma, levels).cpu().numpy().reshape(wl.N, wl.N)
+    xr = dr.solve(y, A, AH, (wl.N, wl.N), eps, nu, 60, 3, gamma, levels)
+    print(f"DR SNR_out gpu {metrics.snr_out(x, xg):.3f} dB, oracle {metrics.snr_out(x, xr):.3f} dB", flush=True)
+    assert relerr(xg, xr) < 1e-3
+    assert abs(metrics.snr_out(x, xg) - metrics.snr_out(x, xr)) < 0.05
