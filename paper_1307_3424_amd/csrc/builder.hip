@@ -730,7 +730,7 @@ wp_status count_rows_exact(const wp_plan *p, int64_t M, const double *u, const d
                            nullptr, k0, p->cell, p->delta, p->W, p->beta, p->tw64, rows);
         hipLaunchKernelGGL((k_exact_cols<LOGNG, true>), dim3(Ng / EX_LINES, nb), dim3(BNTH), 0, s, u, v, w, beam,
                            nullptr, k0, p->cell, p->beta, p->W, p->tw64, rows, en);
-        hipLaunchKernelGGL((k_exact_tau<LOGNG>), dim3(nb), dim3(BNTH), 0, s, u, v, w, beam, k0, p->cell, E,
+        hipLaunchKernelGGL((k_exact_tau<LOGNG>), dim3(nb), dim3(TNT), 0, s, u, v, w, beam, k0, p->cell, E,
                            (const double *)en, (double *)(ws + L.tau), (int *)(ws + L.nnz), (int *)(ws + L.key),
                            (int *)(ws + L.fsz), (int *)(ws + L.err));
     }

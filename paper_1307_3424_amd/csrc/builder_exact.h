@@ -34,7 +34,29 @@
 namespace {
 
 constexpr int EX_LINES = 4;                      // rows / columns per block of the FFT passes
-constexpr int64_t EX_CHUNK_BYTES = 256ll << 20;  // 2-D rows in flight: at most this many bytes
+constexpr int64_t EX_CHUNK_BYTES = 1ll << 30;    // 2-D rows in flight: at most this many bytes
+constexpr int TNT = 1024;                        // threads of the threshold search (one workgroup per row)
+
+template <typename T>
+__device__ inline T tau_block_sum(T v, T *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T s = 0;
+    for (int i = 0; i < TNT / 64; ++i) s += red[i];
+    return s;
+}
+
+__device__ inline double tau_block_max(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < TNT / 64; ++i) s = fmax(s, red[i]);
+    return s;
+}
 
 // rows per chunk for a plan: as many Ng x Ng rows (complex FP64 values, then FP64 energies beside
 // them) as EX_CHUNK_BYTES holds, at most 4096
@@ -153,9 +175,11 @@ __global__ __launch_bounds__(BNTH) void k_exact_cols(const double *__restrict__ 
     }
 }
 
-// Count pass, per row: tau, kept count, sort key.  One block per chunk member (visibility base + b).
+// Count pass, per row: tau, kept count, sort key.  One workgroup of TNT threads per chunk member
+// (visibility base + b): the 15 sums of a pass are a long dependent stream per lane, so many waves
+// per row keep the CU busy.
 template <int LOGNG>
-__global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u, const double *__restrict__ v,
+__global__ __launch_bounds__(TNT) void k_exact_tau(const double *__restrict__ u, const double *__restrict__ v,
                                                     const double *__restrict__ w, const double *__restrict__ beam,
                                                     int64_t base, double cell, double E, const double *__restrict__ en,
                                                     double *__restrict__ tau_out, int *__restrict__ nnz_out,
@@ -164,8 +188,8 @@ __global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u
     constexpr int Ng = 1 << LOGNG;
     constexpr int64_t CELLS = (int64_t)Ng * Ng;
     constexpr int S = 16;                 // sub-brackets per pass
-    __shared__ double redd[BNTH / 64];
-    __shared__ long long redl[BNTH / 64];
+    __shared__ double redd[TNT / 64];
+    __shared__ long long redl[TNT / 64];
     __shared__ double s_acc[S];
     const int b = blockIdx.x;
     const int64_t k = base + b;
@@ -182,12 +206,12 @@ __global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u
     }
     const double *m = en + (int64_t)b * CELLS;
     double tsum = 0.0, mmax = 0.0;
-    for (int64_t i = threadIdx.x; i < CELLS; i += BNTH) {
+    for (int64_t i = threadIdx.x; i < CELLS; i += TNT) {
         tsum += m[i];
         mmax = fmax(mmax, m[i]);
     }
-    const double T = block_sum(tsum, redd);
-    mmax = block_max(mmax, redd);
+    const double T = tau_block_sum(tsum, redd);
+    mmax = tau_block_max(mmax, redd);
     double tau;
     if (E >= 1.0) {
         tau = DBL_TRUE_MIN;                        // every non-zero entry
@@ -209,14 +233,14 @@ __global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u
             double acc[S - 1];
 #pragma unroll
             for (int s = 0; s < S - 1; ++s) acc[s] = 0.0;
-            for (int64_t i = threadIdx.x; i < CELLS; i += BNTH) {
+            for (int64_t i = threadIdx.x; i < CELLS; i += TNT) {
                 const double mi = m[i];
                 const unsigned long long bits = (unsigned long long)__double_as_longlong(mi);
 #pragma unroll
                 for (int s = 0; s < S - 1; ++s) acc[s] += bits >= cand[s] ? mi : 0.0;
             }
             for (int s = 0; s < ns; ++s) {
-                const double K = block_sum(acc[s], redd);
+                const double K = tau_block_sum(acc[s], redd);
                 if (threadIdx.x == 0) s_acc[s] = K;
             }
             __syncthreads();
@@ -233,8 +257,8 @@ __global__ __launch_bounds__(BNTH) void k_exact_tau(const double *__restrict__ u
         tau = __longlong_as_double((long long)lo);
     }
     long long cnt = 0;
-    for (int64_t i = threadIdx.x; i < CELLS; i += BNTH) cnt += m[i] >= tau;
-    cnt = block_sum(cnt, redl);
+    for (int64_t i = threadIdx.x; i < CELLS; i += TNT) cnt += m[i] >= tau;
+    cnt = tau_block_sum(cnt, redl);
     if (threadIdx.x == 0) {
         tau_out[k] = tau;
         nnz_out[k] = (int)cnt;
