@@ -16,9 +16,10 @@
 //      are linear and act on different axes, so the order is free);
 //   4. tau = the largest value with K(tau) >= E T, K(tau) = sum of the energies
 //      |g|^2 >= tau, T = K(0).  The search runs on the IEEE-754 bit patterns of the
-//      non-negative doubles (monotone): each pass over the row evaluates K at 15
-//      points splitting the bracket [lo, hi) into 16 (K(lo) >= E T > K(hi)), so 16
-//      passes close a 64-bit bracket.  It ends on an energy of the row, and the kept
+//      non-negative doubles (monotone): each pass evaluates K at 15 points splitting
+//      the bracket [lo, hi) into 16 (K(lo) >= E T > K(hi)), so 16 passes close a
+//      64-bit bracket; once the bracket holds few entries, they alone are kept (in
+//      LDS) and K(c) = K(hi) + their sum >= c.  It ends on an energy of the row, and the kept
 //      set {|g|^2 >= tau} (ties kept) is the sort-defined set; E >= 1 keeps every
 //      non-zero entry.
 // Rows are made in chunks (the 2-D rows of a chunk live in the builder's workspace);
@@ -36,6 +37,7 @@ namespace {
 constexpr int EX_LINES = 4;                      // rows / columns per block of the FFT passes
 constexpr int64_t EX_CHUNK_BYTES = 1ll << 30;    // 2-D rows in flight: at most this many bytes
 constexpr int TNT = 1024;                        // threads of the threshold search (one workgroup per row)
+constexpr int TAU_CAP = 8192;                    // entries of a narrowed bracket the search keeps in LDS
 
 template <typename T>
 __device__ inline T tau_block_sum(T v, T *red) {
@@ -46,6 +48,26 @@ __device__ inline T tau_block_sum(T v, T *red) {
     T s = 0;
     for (int i = 0; i < TNT / 64; ++i) s += red[i];
     return s;
+}
+
+// exclusive scan of one int per thread over the TNT threads; returns the total
+__device__ inline int tau_block_excl_scan(int v, int *red, int &total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) red[wid] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int i = 0; i < TNT / 64; ++i) {
+        if (i < wid) off += red[i];
+        tot += red[i];
+    }
+    total = tot;
+    return off + x - v;
 }
 
 __device__ inline double tau_block_max(double v, double *red) {
@@ -190,7 +212,9 @@ __global__ __launch_bounds__(TNT) void k_exact_tau(const double *__restrict__ u,
     constexpr int S = 16;                 // sub-brackets per pass
     __shared__ double redd[TNT / 64];
     __shared__ long long redl[TNT / 64];
+    __shared__ int s_red_i[TNT / 64];
     __shared__ double s_acc[S];
+    __shared__ double s_list[TAU_CAP];
     const int b = blockIdx.x;
     const int64_t k = base + b;
     double ut, vt, wk;
@@ -213,12 +237,23 @@ __global__ __launch_bounds__(TNT) void k_exact_tau(const double *__restrict__ u,
     const double T = tau_block_sum(tsum, redd);
     mmax = tau_block_max(mmax, redd);
     double tau;
+    long long cnt;
     if (E >= 1.0) {
         tau = DBL_TRUE_MIN;                        // every non-zero entry
+        long long c = 0;
+        for (int64_t i = threadIdx.x; i < CELLS; i += TNT) c += m[i] >= tau;
+        cnt = tau_block_sum(c, redl);
     } else {
         const double target = E * T;
-        unsigned long long lo = 0ull;              // K(lo) = T >= target
-        unsigned long long hi = (unsigned long long)__double_as_longlong(mmax) + 1ull;   // K(hi) = 0
+        // bracket [lo, hi) with K(lo) >= target > K(hi), khi = K(hi)
+        unsigned long long lo = 0ull, hi = (unsigned long long)__double_as_longlong(mmax) + 1ull;
+        double khi = 0.0;
+        // once the bracket holds at most TAU_CAP entries they are copied to LDS, and a pass reads
+        // only them: K(c) = base + (sum of the copied entries >= c), base = K(hi) at the copy
+        bool listed = false;
+        int nlist = 0;
+        double base = 0.0;
+        long long base_n = 0;                      // #{m >= hi} at the copy
         while (hi - lo > 1ull) {
             const unsigned long long span = hi - lo;
             const int ns = span >= (unsigned long long)S ? S - 1 : (int)span - 1;   // interior points
@@ -233,32 +268,70 @@ __global__ __launch_bounds__(TNT) void k_exact_tau(const double *__restrict__ u,
             double acc[S - 1];
 #pragma unroll
             for (int s = 0; s < S - 1; ++s) acc[s] = 0.0;
-            for (int64_t i = threadIdx.x; i < CELLS; i += TNT) {
-                const double mi = m[i];
+            // one loop for both sources (a generic pointer: LDS list or the row in global memory)
+            const double *src = listed ? (const double *)s_list : m;
+            const int64_t nsrc = listed ? (int64_t)nlist : CELLS;
+            for (int64_t i = threadIdx.x; i < nsrc; i += TNT) {
+                const double mi = src[i];
                 const unsigned long long bits = (unsigned long long)__double_as_longlong(mi);
 #pragma unroll
                 for (int s = 0; s < S - 1; ++s) acc[s] += bits >= cand[s] ? mi : 0.0;
             }
             for (int s = 0; s < ns; ++s) {
                 const double K = tau_block_sum(acc[s], redd);
-                if (threadIdx.x == 0) s_acc[s] = K;
+                if (threadIdx.x == 0) s_acc[s] = base + K;
             }
             __syncthreads();
             // the largest candidate still holding the target, and the next one above it
             unsigned long long nlo = lo, nhi = hi;
             for (int s = 0; s < ns; ++s) {
-                if (s_acc[s] >= target) nlo = cand[s];
-                else { nhi = cand[s]; break; }
+                if (s_acc[s] >= target) {
+                    nlo = cand[s];
+                } else {
+                    nhi = cand[s];
+                    khi = s_acc[s];
+                    break;
+                }
             }
             __syncthreads();
             lo = nlo;
             hi = nhi;
+            if (!listed && hi - lo > 1ull) {
+                int in = 0, above = 0;
+                for (int64_t i = threadIdx.x; i < CELLS; i += TNT) {
+                    const unsigned long long bits = (unsigned long long)__double_as_longlong(m[i]);
+                    in += bits >= lo && bits < hi;
+                    above += bits >= hi;
+                }
+                int total;
+                const int pos0 = tau_block_excl_scan(in, s_red_i, total);
+                const long long n_above = tau_block_sum((long long)above, redl);
+                if (total <= TAU_CAP) {
+                    // ordered copy of the entries in [lo, hi) (the order fixes the sums' rounding)
+                    int pos = pos0;
+                    for (int64_t i = threadIdx.x; i < CELLS; i += TNT) {
+                        const double mi = m[i];
+                        const unsigned long long bits = (unsigned long long)__double_as_longlong(mi);
+                        if (bits >= lo && bits < hi) s_list[pos++] = mi;
+                    }
+                    __syncthreads();
+                    listed = true;
+                    nlist = total;
+                    base = khi;
+                    base_n = n_above;
+                }
+            }
         }
         tau = __longlong_as_double((long long)lo);
+        // #{m >= tau}
+        long long c = 0;
+        if (listed) {
+            for (int i = threadIdx.x; i < nlist; i += TNT) c += s_list[i] >= tau;
+        } else {
+            for (int64_t i = threadIdx.x; i < CELLS; i += TNT) c += m[i] >= tau;
+        }
+        cnt = (listed ? base_n : 0) + tau_block_sum(c, redl);
     }
-    long long cnt = 0;
-    for (int64_t i = threadIdx.x; i < CELLS; i += TNT) cnt += m[i] >= tau;
-    cnt = tau_block_sum(cnt, redl);
     if (threadIdx.x == 0) {
         tau_out[k] = tau;
         nnz_out[k] = (int)cnt;
