@@ -208,6 +208,23 @@ wp_status wp_build_G_fill(const wp_plan *plan, int64_t M, const double *u, const
                           void *stream);
 
 /*
+ * Both build passes for a batch of P problems (the batched form's channels), problem p with its
+ * own plan[p], M[p], u[p], v[p], w[p] (device float64), E[p] and workspace[p]
+ * (wp_build_workspace_bytes(plan[p], M[p]) bytes).  Pass 1 writes nnz_out[p] and n_work_out[p]
+ * (host arrays of P); pass 2 fills G[p] set up from them as for wp_build_G_fill.  The problems
+ * are built one after another on `stream` (each pass-1 call synchronises it once); the first
+ * failing problem stops the batch and its status is returned.
+ */
+wp_status wp_build_G_count_batch(int P, const wp_plan *const *plan, const int64_t *M,
+                                 const double *const *u, const double *const *v,
+                                 const double *const *w, const double *E, void *const *workspace,
+                                 int64_t *nnz_out, int64_t *n_work_out, void *stream);
+wp_status wp_build_G_fill_batch(int P, const wp_plan *const *plan, const int64_t *M,
+                                const double *const *u, const double *const *v,
+                                const double *const *w, const double *E, void *const *workspace,
+                                wp_G *const *G, void *stream);
+
+/*
  * y = Phi x  (Eq. 8 with the gridding window).
  *   x     [N*N] c64 device          y [M] c64 device (caller order)
  *   grid  device workspace of wp_plan_info's grid_bytes (contents overwritten)

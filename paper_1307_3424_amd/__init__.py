@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR, WP_ORDER_CALLER,
                    WP_ORDER_SORTED, WP_TAPS_BF16, WP_TAPS_C64, WP_TAPS_I16, WprojError, check, load)
 
-__all__ = ["Plan", "GMatrix", "build_G", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
+__all__ = ["Plan", "GMatrix", "build_G", "build_G_batch", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16", "WP_TAPS_I16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
            "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "dr_solve", "sara_analysis", "sara_synthesis",
@@ -141,6 +141,31 @@ class GMatrix:
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
+def _new_G(plan: Plan, M: int, nnz: int, nwork: int, taps: int, transpose: bool, dev) -> GMatrix:
+    """G's arrays for pass 2 of the build, sized from pass 1 (factor records aside)."""
+    torch = _torch()
+    lib = load()
+    G = GMatrix(M=M, nnz=nnz, taps=int(taps),
+                rowptr=torch.empty(M + 1, dtype=torch.int64, device=dev),
+                col=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                val=torch.empty(max(nnz, 1), dtype=(torch.complex64 if taps == WP_TAPS_C64 else torch.int32),
+                                device=dev),
+                perm=torch.empty(M, dtype=torch.int32, device=dev),
+                work=torch.empty(4 * max(nwork, 1), dtype=torch.int32, device=dev),
+                n_work=nwork)
+    if taps == WP_TAPS_I16:
+        G.rscale = torch.empty(M, dtype=torch.float32, device=dev)
+    if transpose:
+        G.tcolptr = torch.empty(plan.Ng * plan.Ng + 1, dtype=torch.int64, device=dev)
+        G.trow = torch.empty(max(nnz, 1), dtype=torch.int32, device=dev)
+        G.tval = torch.empty_like(G.val)
+        nt = C.c_int64()
+        check(lib.wp_gather_table_size(plan.handle, nnz, C.byref(nt)), "wp_gather_table_size")
+        G.n_tblk = nt.value
+        G.tblk = torch.empty(2 * (nt.value + 1), dtype=torch.int64, device=dev)
+    return G
+
+
 def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: bool = True,
             factors: bool = False, stream=None, beam=None) -> GMatrix:
     """wp_build_workspace_bytes + wp_build_G_count (+ wp_build_factor_bytes) + wp_build_G_fill
@@ -173,29 +198,12 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: b
         check(lib.wp_build_G_dde_count(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), _ptr(beam), float(E), _ptr(ws),
                                        C.byref(nnz), C.byref(nwork), s), "wp_build_G_dde_count")
     dev = u.device
-    G = GMatrix(M=M, nnz=nnz.value, taps=int(taps),
-                rowptr=torch.empty(M + 1, dtype=torch.int64, device=dev),
-                col=torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev),
-                val=torch.empty(max(nnz.value, 1), dtype=(torch.complex64 if taps == WP_TAPS_C64 else torch.int32),
-                                device=dev),
-                perm=torch.empty(M, dtype=torch.int32, device=dev),
-                work=torch.empty(4 * max(nwork.value, 1), dtype=torch.int32, device=dev),
-                n_work=nwork.value)
-    if taps == WP_TAPS_I16:
-        G.rscale = torch.empty(M, dtype=torch.float32, device=dev)
+    G = _new_G(plan, M, nnz.value, nwork.value, taps, transpose, dev)
     if factors:
         fb = C.c_int64()
         check(lib.wp_build_factor_bytes(plan.handle, M, _ptr(ws), C.byref(fb), s), "wp_build_factor_bytes")
         G.frec = torch.empty(M + 1, dtype=torch.int64, device=dev)
         G.fdat = torch.empty(fb.value, dtype=torch.uint8, device=dev)
-    if transpose:
-        G.tcolptr = torch.empty(plan.Ng * plan.Ng + 1, dtype=torch.int64, device=dev)
-        G.trow = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
-        G.tval = torch.empty_like(G.val)
-        nt = C.c_int64()
-        check(lib.wp_gather_table_size(plan.handle, nnz.value, C.byref(nt)), "wp_gather_table_size")
-        G.n_tblk = nt.value
-        G.tblk = torch.empty(2 * (nt.value + 1), dtype=torch.int64, device=dev)
     d = G.desc()
     if beam is None:
         check(lib.wp_build_G_fill(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), float(E), _ptr(ws), C.byref(d), s),
@@ -205,6 +213,39 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: b
                                       C.byref(d), s), "wp_build_G_dde_fill")
     G._ws = ws          # keep the workspace alive until the stream has consumed it
     return G
+
+
+def build_G_batch(plans, us, vs, ws_, Es, taps: int = WP_TAPS_C64, transpose: bool = True, stream=None):
+    """wp_build_G_count_batch + wp_build_G_fill_batch: one G per problem (lists of plans and float64
+    CUDA tensors u, v, w, and energies)."""
+    torch = _torch()
+    lib = load()
+    P = len(plans)
+    M = [int(u.numel()) for u in us]
+    for p in range(P):
+        for t, nm in ((us[p], "u"), (vs[p], "v"), (ws_[p], "w")):
+            _dev_f64(t, M[p], f"{nm}[{p}]")
+    s = _stream(stream)
+    work = []
+    for p in range(P):
+        b = C.c_int64()
+        check(lib.wp_build_workspace_bytes(plans[p].handle, M[p], C.byref(b)), "wp_build_workspace_bytes")
+        work.append(torch.empty(b.value, dtype=torch.uint8, device="cuda"))
+    VP = C.c_void_p * P
+    pl = VP(*[q.handle for q in plans])
+    Ma = (C.c_int64 * P)(*M)
+    ua, va, wa = VP(*[_ptr(t) for t in us]), VP(*[_ptr(t) for t in vs]), VP(*[_ptr(t) for t in ws_])
+    Ea = (C.c_double * P)(*[float(e) for e in Es])
+    wsa = VP(*[_ptr(t) for t in work])
+    nnz, nwork = (C.c_int64 * P)(), (C.c_int64 * P)()
+    check(lib.wp_build_G_count_batch(P, pl, Ma, ua, va, wa, Ea, wsa, nnz, nwork, s), "wp_build_G_count_batch")
+    Gs = [_new_G(plans[p], M[p], nnz[p], nwork[p], taps, transpose, us[p].device) for p in range(P)]
+    descs = [G.desc() for G in Gs]
+    Ga = VP(*[C.addressof(d) for d in descs])
+    check(lib.wp_build_G_fill_batch(P, pl, Ma, ua, va, wa, Ea, wsa, Ga, s), "wp_build_G_fill_batch")
+    for G, wk in zip(Gs, work):
+        G._ws = wk
+    return Gs
 
 
 def apply_Phi(plan: Plan, G: GMatrix, x, y=None, grid=None, stream=None):

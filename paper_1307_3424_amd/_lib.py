@@ -48,6 +48,9 @@ SIGNATURES = {
     "wp_build_G_count": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _pi64, _pi64, _vp], _i32),
     "wp_build_G_fill": ([_vp, _i64, _vp, _vp, _vp, _d, _vp, _PG, _vp], _i32),
     "wp_build_dde_workspace_bytes": ([_vp, _i64, _pi64], _i32),
+    "wp_build_G_count_batch": ([_i32, _vp, _pi64, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _pi64, _pi64, _vp],
+                               _i32),
+    "wp_build_G_fill_batch": ([_i32, _vp, _pi64, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _vp, _vp], _i32),
     "wp_build_G_dde_count": ([_vp, _i64, _vp, _vp, _vp, _vp, _d, _vp, _pi64, _pi64, _vp], _i32),
     "wp_build_G_dde_fill": ([_vp, _i64, _vp, _vp, _vp, _vp, _d, _vp, _PG, _vp], _i32),
     "wp_apply_Phi": ([_vp, _PG, _vp, _vp, _vp, _vp], _i32),

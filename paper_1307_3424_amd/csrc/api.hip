@@ -266,6 +266,30 @@ wp_status wp_build_G_fill(const wp_plan *p, int64_t M, const double *u, const do
     return launch_build_fill(p, M, u, v, w, nullptr, E, ws, G, as_stream(stream));
 }
 
+wp_status wp_build_G_count_batch(int P, const wp_plan *const *plan, const int64_t *M, const double *const *u,
+                                 const double *const *v, const double *const *w, const double *E,
+                                 void *const *workspace, int64_t *nnz_out, int64_t *n_work_out, void *stream) {
+    if (P < 1) return wp_set_error(WP_EINVAL, "P = %d", P);
+    if (!plan || !M || !u || !v || !w || !E || !workspace || !nnz_out || !n_work_out)
+        return wp_set_error(WP_EINVAL, "NULL argument");
+    for (int p = 0; p < P; ++p)
+        if (wp_status st = wp_build_G_count(plan[p], M[p], u[p], v[p], w[p], E[p], workspace[p], nnz_out + p,
+                                            n_work_out + p, stream))
+            return st;
+    return WP_OK;
+}
+
+wp_status wp_build_G_fill_batch(int P, const wp_plan *const *plan, const int64_t *M, const double *const *u,
+                                const double *const *v, const double *const *w, const double *E,
+                                void *const *workspace, wp_G *const *G, void *stream) {
+    if (P < 1) return wp_set_error(WP_EINVAL, "P = %d", P);
+    if (!plan || !M || !u || !v || !w || !E || !workspace || !G) return wp_set_error(WP_EINVAL, "NULL argument");
+    for (int p = 0; p < P; ++p)
+        if (wp_status st = wp_build_G_fill(plan[p], M[p], u[p], v[p], w[p], E[p], workspace[p], G[p], stream))
+            return st;
+    return WP_OK;
+}
+
 wp_status wp_build_dde_workspace_bytes(const wp_plan *p, int64_t M, int64_t *bytes) {
     if (wp_status s = check_plan(p)) return s;
     if (!bytes) return wp_set_error(WP_EINVAL, "bytes_out is NULL");

@@ -95,3 +95,18 @@ def test_batch_autotune_keeps_results():
         assert (torch.linalg.norm(y - y_ref) / torch.linalg.norm(y_ref)).item() < 1e-6
         B.apply_PhiT(y, xa, grids)
     B.close()
+
+
+def test_batched_build_equals_single_builds():
+    """wp_build_G_count_batch / wp_build_G_fill_batch: the same G, array for array, as one build per
+    problem (plans of two sizes, uneven counts, one problem of a single visibility)."""
+    plans = [wp.Plan(128, L), wp.Plan(64, L), wp.Plan(128, L)]
+    probs = [_problems(128, [3001], 7)[0], _problems(64, [1], 8)[0], _problems(128, [700], 9)[0]]
+    Es = [0.99, 0.9, 0.999]
+    Gb = wp.build_G_batch(plans, [dev(p[0]) for p in probs], [dev(p[1]) for p in probs],
+                          [dev(p[2]) for p in probs], Es)
+    for plan, (u, v, w), E, G in zip(plans, probs, Es, Gb):
+        Gs = wp.build_G(plan, dev(u), dev(v), dev(w), E)
+        assert G.nnz == Gs.nnz and G.n_work == Gs.n_work
+        for name in ("rowptr", "col", "val", "perm", "work", "tcolptr", "trow", "tval", "tblk"):
+            assert torch.equal(getattr(G, name), getattr(Gs, name)), name
