@@ -305,10 +305,15 @@ wp_status wp_batch_info(const wp_batch *batch, int64_t *M_total, int *shapes6);
 wp_status wp_apply_Phi_batch(wp_batch *batch, const void *x, void *y, void *grids, void *stream);
 wp_status wp_apply_PhiT_batch(wp_batch *batch, const void *y, void *x, void *grids, void *stream);
 /* Autotuner: times the candidate launch shapes of both persistent products on these buffers
- * (HIP events, 5 timed launches each) and keeps the fastest; best_us2[0..1] receive their
- * times (host).  Synchronises; overwrites y and grids. */
+ * (HIP events, 5 timed launches each) and keeps the fastest, then times the kept shape launched
+ * flat (one workgroup per item, no work counter) and keeps that if faster; best_us2[0..1]
+ * receive the kept times (host).  Synchronises; overwrites y and grids. */
 wp_status wp_batch_autotune(wp_batch *batch, const void *x, void *y, void *grids, void *stream,
                             float *best_us2);
+/* Launch mode of the two products: 0 = persistent (the ticket queue; the default), 1 = flat (one
+ * workgroup per item).  *_out (host, may be NULL) receive the modes in force; a value < 0 keeps the
+ * current mode. */
+wp_status wp_batch_mode(wp_batch *batch, int degrid, int gather, int *degrid_out, int *gather_out);
 
 /* ----------------------------------------------------------------------------------------
  * Learned surrogate of the rows of G.  A row (Section 3.1 kernel, Section 3.2 energy rule)

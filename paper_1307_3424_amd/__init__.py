@@ -499,6 +499,12 @@ class Batch:
               "wp_batch_autotune")
         return list(best)
 
+    def mode(self, degrid: int = -1, gather: int = -1):
+        """wp_batch_mode: set (0 persistent, 1 flat, < 0 keep) and return (degrid, gather) modes."""
+        d, g = C.c_int(), C.c_int()
+        check(load().wp_batch_mode(self._h, int(degrid), int(gather), C.byref(d), C.byref(g)), "wp_batch_mode")
+        return d.value, g.value
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().wp_batch_destroy(self._h)

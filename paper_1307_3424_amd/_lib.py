@@ -69,6 +69,7 @@ SIGNATURES = {
     "wp_apply_Phi_batch": ([_vp, _vp, _vp, _vp, _vp], _i32),
     "wp_apply_PhiT_batch": ([_vp, _vp, _vp, _vp, _vp], _i32),
     "wp_batch_autotune": ([_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_float)], _i32),
+    "wp_batch_mode": ([_vp, _i32, _i32, C.POINTER(C.c_int), C.POINTER(C.c_int)], _i32),
     "wp_mlp_param_count": ([], _i64),
     "wp_mlp_create": ([C.POINTER(_vp), _i32], _i32),
     "wp_mlp_destroy": ([_vp], _i32),

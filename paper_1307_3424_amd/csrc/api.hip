@@ -435,6 +435,13 @@ wp_status wp_batch_autotune(wp_batch *b, const void *x, void *y, void *grids, vo
     return batch_autotune(b, (const float2 *)x, (float2 *)y, (float2 *)grids, as_stream(stream), best_us2);
 }
 
+wp_status wp_batch_mode(wp_batch *b, int degrid, int gather, int *degrid_out, int *gather_out) {
+    if (!b) return wp_set_error(WP_EINVAL, "batch is NULL");
+    if (degrid > 1 || gather > 1) return wp_set_error(WP_EINVAL, "mode %d / %d: 0, 1 or < 0", degrid, gather);
+    batch_set_mode(b, degrid, gather, degrid_out, gather_out);
+    return WP_OK;
+}
+
 wp_status wp_db8_filter(double *h16) {
     if (!h16) return wp_set_error(WP_EINVAL, "NULL argument");
     return filter_db8(h16);

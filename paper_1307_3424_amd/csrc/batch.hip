@@ -11,8 +11,10 @@
 // n_items + 2 nblocks tickets: the host knows the next base without reading the
 // counter back and needs no reset launch.
 //
-// Launch shapes (rows or cells per item, lanes per row or cell, loads in flight)
-// are chosen by wp_batch_autotune, which times every candidate with HIP events.
+// The same kernels also run "flat": one workgroup per item (blockIdx.x), the hardware
+// dispatcher balancing the items, no counter.  wp_batch_autotune times both and keeps the
+// faster per product, with the launch shapes (rows or cells per item, lanes per row or cell,
+// loads in flight), every candidate timed with HIP events.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -56,7 +58,15 @@ __device__ __forceinline__ int next_item(unsigned long long *counter, unsigned l
     return it;
 }
 
-template <int TK, int LPR, int U>
+// FLAT: the workgroup's one item is blockIdx.x (pass 0), then it stops; else the ticket queue
+template <bool FLAT>
+__device__ __forceinline__ int take_item(unsigned long long *counter, unsigned long long base, int *slot,
+                                         long long &ahead, int pass) {
+    if (FLAT) return pass == 0 ? (int)blockIdx.x : 0x7fffffff;
+    return next_item(counter, base, slot, ahead);
+}
+
+template <int TK, int LPR, int U, bool FLAT>
 __global__ __launch_bounds__(BT) void k_degrid_persist(const ProbDesc *__restrict__ pd, const int2 *__restrict__ items,
                                                        int n_items, int R, unsigned long long *counter,
                                                        unsigned long long base, const float2 *__restrict__ grids,
@@ -64,9 +74,9 @@ __global__ __launch_bounds__(BT) void k_degrid_persist(const ProbDesc *__restric
     __shared__ int slot;
     const int grp = threadIdx.x / LPR, sub = threadIdx.x & (LPR - 1);
     constexpr int NGRP = BT / LPR;
-    long long ahead = first_ticket(counter, base);
-    for (;;) {
-        const int it = next_item(counter, base, &slot, ahead);
+    long long ahead = FLAT ? 0 : first_ticket(counter, base);
+    for (int pass = 0;; ++pass) {
+        const int it = take_item<FLAT>(counter, base, &slot, ahead, pass);
         if (it >= n_items) break;
         const int2 w = items[it];
         const ProbDesc d = pd[w.x];
@@ -114,7 +124,7 @@ __global__ __launch_bounds__(BT) void k_degrid_persist(const ProbDesc *__restric
     }
 }
 
-template <int TK, int LPR, int U>
+template <int TK, int LPR, int U, bool FLAT>
 __global__ __launch_bounds__(BT) void k_gather_persist(const ProbDesc *__restrict__ pd, const int2 *__restrict__ items,
                                                        int n_items, int C, int64_t cells, unsigned long long *counter,
                                                        unsigned long long base, const float2 *__restrict__ y,
@@ -122,9 +132,9 @@ __global__ __launch_bounds__(BT) void k_gather_persist(const ProbDesc *__restric
     __shared__ int slot;
     const int grp = threadIdx.x / LPR, sub = threadIdx.x & (LPR - 1);
     constexpr int NGRP = BT / LPR;
-    long long ahead = first_ticket(counter, base);
-    for (;;) {
-        const int it = next_item(counter, base, &slot, ahead);
+    long long ahead = FLAT ? 0 : first_ticket(counter, base);
+    for (int pass = 0;; ++pass) {
+        const int it = take_item<FLAT>(counter, base, &slot, ahead, pass);
         if (it >= n_items) break;
         const int2 w = items[it];
         const ProbDesc d = pd[w.x];
@@ -180,7 +190,7 @@ __global__ __launch_bounds__(BT) void k_gather_persist(const ProbDesc *__restric
 // GB_ITEM blocks; each wavefront of the workgroup sums every fourth of them (gather_block).
 constexpr int GB_ITEM = 32;
 
-template <int TK>
+template <int TK, bool FLAT>
 __global__ __launch_bounds__(BT) void k_gather_persist_blk(const ProbDesc *__restrict__ pd,
                                                            const int2 *__restrict__ items, int n_items,
                                                            unsigned long long *counter, unsigned long long base,
@@ -189,9 +199,9 @@ __global__ __launch_bounds__(BT) void k_gather_persist_blk(const ProbDesc *__res
     __shared__ int slot;
     __shared__ float2 s_p[BT / 64][GB_ENT];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    long long ahead = first_ticket(counter, base);
-    for (;;) {
-        const int it = next_item(counter, base, &slot, ahead);
+    long long ahead = FLAT ? 0 : first_ticket(counter, base);
+    for (int pass = 0;; ++pass) {
+        const int it = take_item<FLAT>(counter, base, &slot, ahead, pass);
         if (it >= n_items) break;
         const int2 w = items[it];
         const ProbDesc d = pd[w.x];
@@ -222,6 +232,7 @@ struct wp_batch {
     unsigned long long *d_counter = nullptr;
     unsigned long long base = 0;   // next launch's first ticket
     Shape deg{64, 4, 64}, gat{16, 8, 256};
+    bool flat_deg = false, flat_gat = false;   // one workgroup per item instead of the ticket queue
     int nblocks;                   // persistent grid size
 };
 
@@ -230,10 +241,18 @@ namespace {
 template <int TK>
 wp_status launch_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s) {
     const int64_t G2 = (int64_t)b->plan->Ng * b->plan->Ng;
-    const dim3 g(b->nblocks), t(BT);
+    const bool flat = b->flat_deg;
+    if (flat && b->n_items_deg == 0) return WP_OK;
+    const dim3 g(flat ? b->n_items_deg : b->nblocks), t(BT);
 #define DEG(L, U)                                                                                                   \
-    hipLaunchKernelGGL((k_degrid_persist<TK, L, U>), g, t, 0, s, b->d_desc, b->d_items_deg, b->n_items_deg,      \
-                       b->deg.chunk, b->d_counter, b->base, grids, G2, y)
+    do {                                                                                                            \
+        if (flat)                                                                                                   \
+            hipLaunchKernelGGL((k_degrid_persist<TK, L, U, true>), g, t, 0, s, b->d_desc, b->d_items_deg,         \
+                               b->n_items_deg, b->deg.chunk, b->d_counter, b->base, grids, G2, y);                 \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_degrid_persist<TK, L, U, false>), g, t, 0, s, b->d_desc, b->d_items_deg,        \
+                               b->n_items_deg, b->deg.chunk, b->d_counter, b->base, grids, G2, y);                 \
+    } while (0)
     switch (b->deg.lpr * 100 + b->deg.u) {
         case 1604: DEG(16, 4); break;
         case 1608: DEG(16, 8); break;
@@ -245,17 +264,25 @@ wp_status launch_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s)
     }
 #undef DEG
     if (wp_status st = wp_check_launch("batch degrid")) return st;
-    b->base += (unsigned long long)b->n_items_deg + 2ull * (unsigned long long)b->nblocks;
+    if (!flat) b->base += (unsigned long long)b->n_items_deg + 2ull * (unsigned long long)b->nblocks;
     return WP_OK;
 }
 
 template <int TK>
 wp_status launch_gat(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s) {
     const int64_t G2 = (int64_t)b->plan->Ng * b->plan->Ng;
-    const dim3 g(b->nblocks), t(BT);
+    const bool flat = b->flat_gat;
+    if (flat && b->n_items_gat == 0) return WP_OK;
+    const dim3 g(flat ? b->n_items_gat : b->nblocks), t(BT);
 #define GAT(L, U)                                                                                                   \
-    hipLaunchKernelGGL((k_gather_persist<TK, L, U>), g, t, 0, s, b->d_desc, b->d_items_gat, b->n_items_gat,      \
-                       b->gat.chunk, G2, b->d_counter, b->base, y, grids, G2)
+    do {                                                                                                            \
+        if (flat)                                                                                                   \
+            hipLaunchKernelGGL((k_gather_persist<TK, L, U, true>), g, t, 0, s, b->d_desc, b->d_items_gat,         \
+                               b->n_items_gat, b->gat.chunk, G2, b->d_counter, b->base, y, grids, G2);             \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_gather_persist<TK, L, U, false>), g, t, 0, s, b->d_desc, b->d_items_gat,        \
+                               b->n_items_gat, b->gat.chunk, G2, b->d_counter, b->base, y, grids, G2);             \
+    } while (0)
     switch (b->gat.lpr * 100 + b->gat.u) {
         case 804: GAT(8, 4); break;
         case 808: GAT(8, 8); break;
@@ -267,7 +294,7 @@ wp_status launch_gat(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s)
     }
 #undef GAT
     if (wp_status st = wp_check_launch("batch gather")) return st;
-    b->base += (unsigned long long)b->n_items_gat + 2ull * (unsigned long long)b->nblocks;
+    if (!flat) b->base += (unsigned long long)b->n_items_gat + 2ull * (unsigned long long)b->nblocks;
     return WP_OK;
 }
 
@@ -280,10 +307,15 @@ wp_status run_deg(wp_batch *b, const float2 *grids, float2 *y, hipStream_t s) {
 template <int TK>
 wp_status launch_gat_blk(wp_batch *b, const float2 *y, float2 *grids, hipStream_t s) {
     const int64_t G2 = (int64_t)b->plan->Ng * b->plan->Ng;
-    hipLaunchKernelGGL((k_gather_persist_blk<TK>), dim3(b->nblocks), dim3(BT), 0, s, b->d_desc, b->d_items_blk,
-                       b->n_items_blk, b->d_counter, b->base, y, grids, G2);
+    if (b->flat_gat && b->n_items_blk == 0) return WP_OK;
+    if (b->flat_gat)
+        hipLaunchKernelGGL((k_gather_persist_blk<TK, true>), dim3(b->n_items_blk), dim3(BT), 0, s, b->d_desc,
+                           b->d_items_blk, b->n_items_blk, b->d_counter, b->base, y, grids, G2);
+    else
+        hipLaunchKernelGGL((k_gather_persist_blk<TK, false>), dim3(b->nblocks), dim3(BT), 0, s, b->d_desc,
+                           b->d_items_blk, b->n_items_blk, b->d_counter, b->base, y, grids, G2);
     if (wp_status st = wp_check_launch("batch gather blocks")) return st;
-    b->base += (unsigned long long)b->n_items_blk + 2ull * (unsigned long long)b->nblocks;
+    if (!b->flat_gat) b->base += (unsigned long long)b->n_items_blk + 2ull * (unsigned long long)b->nblocks;
     return WP_OK;
 }
 
@@ -449,6 +481,13 @@ wp_status batch_autotune(wp_batch *b, const float2 *x, float2 *y, float2 *grids,
     }
     b->deg = keep;
     if (wp_status st = make_items(b, true)) return st;
+    {   // one workgroup per item against the ticket queue, for the kept shape
+        b->flat_deg = true;
+        float us;
+        if (wp_status st = time_it(true, us)) return st;
+        if (us < best) best = us;
+        else b->flat_deg = false;
+    }
     best_us[0] = best;
     if (b->transpose) {
         best = 1e30f;
@@ -462,11 +501,23 @@ wp_status batch_autotune(wp_batch *b, const float2 *x, float2 *y, float2 *grids,
         }
         b->gat = keep;
         if (wp_status st = make_items(b, false)) return st;
+        b->flat_gat = true;
+        float us;
+        if (wp_status st = time_it(false, us)) return st;
+        if (us < best) best = us;
+        else b->flat_gat = false;
         best_us[1] = best;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return WP_OK;
+}
+
+void batch_set_mode(wp_batch *b, int deg, int gat, int *deg_out, int *gat_out) {
+    if (deg >= 0) b->flat_deg = deg == 1;
+    if (gat >= 0) b->flat_gat = gat == 1;
+    if (deg_out) *deg_out = b->flat_deg ? 1 : 0;
+    if (gat_out) *gat_out = b->flat_gat ? 1 : 0;
 }
 
 void batch_shapes(const wp_batch *b, int *out6) {

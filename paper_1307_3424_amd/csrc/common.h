@@ -212,4 +212,5 @@ int64_t batch_total_vis(const wp_batch *b);
 wp_status batch_phi(wp_batch *b, const float2 *x, float2 *y, float2 *grids, hipStream_t s);
 wp_status batch_phiT(wp_batch *b, const float2 *y, float2 *x, float2 *grids, hipStream_t s);
 wp_status batch_autotune(wp_batch *b, const float2 *x, float2 *y, float2 *grids, hipStream_t s, float *best_us);
+void batch_set_mode(wp_batch *b, int deg, int gat, int *deg_out, int *gat_out);
 void batch_shapes(const wp_batch *b, int *out6);

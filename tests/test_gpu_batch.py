@@ -97,6 +97,33 @@ def test_batch_autotune_keeps_results():
     B.close()
 
 
+@pytest.mark.parametrize("taps", [wp.WP_TAPS_C64, wp.WP_TAPS_BF16])
+def test_flat_and_persistent_launches_agree(taps):
+    """Both launch modes of both products give the same results (flat: one workgroup per item),
+    interleaved, so the persistent launches' work counter stays consistent across flat ones."""
+    N, counts = 128, [5000, 1, 200, 9000]
+    plan = wp.Plan(N, L)
+    Gs = [wp.build_G(plan, dev(u), dev(v), dev(w), 0.99, taps=taps) for u, v, w in _problems(N, counts, 11)]
+    B = wp.Batch(plan, Gs)
+    x, y, grids = B.new_buffers()
+    x.copy_(dev(synth.random_complex(len(counts) * N * N, np.random.default_rng(4)).astype(np.complex64)))
+    xa = torch.empty_like(x)
+    res = {}
+    for rep in range(2):
+        for mode in (0, 1, 0):
+            assert B.mode(mode, mode) == (mode, mode)
+            B.apply_Phi(x, y, grids)
+            B.apply_PhiT(y, xa, grids)
+            res.setdefault(mode, []).append((y.clone(), xa.clone()))
+    y0, x0 = res[0][0]
+    for yy, xx in res[0] + res[1]:
+        assert torch.equal(yy, y0)                                     # degrid: one summation order
+        assert (torch.linalg.norm(xx - x0) / torch.linalg.norm(x0)).item() < 1e-6
+    with pytest.raises(wp.WprojError):
+        B.mode(2, 0)
+    B.close()
+
+
 def test_batched_build_equals_single_builds():
     """wp_build_G_count_batch / wp_build_G_fill_batch: the same G, array for array, as one build per
     problem (plans of two sizes, uneven counts, one problem of a single visibility)."""
