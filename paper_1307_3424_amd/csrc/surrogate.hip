@@ -352,53 +352,69 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
         s_wu[i] = i < nc ? cu - (o.y + BOX / 2) : 0;
     }
     for (int e = tid; e < WV * WU; e += ANT) win[e] = make_int2(0, 0);
-    // s of each cell: wave w takes cells w, w + 4, ...; lane l hidden units 4l .. 4l + 3
-    for (int i = wave; i < AG; i += ANT / 64) {
-        float sr[4] = {0.f, 0.f, 0.f, 0.f}, sm[4] = {0.f, 0.f, 0.f, 0.f};
-        float2 Y = make_float2(0.f, 0.f);
-        if (i < nc) {
-            const int jb = cell_start[c0 + i], je = cell_start[c0 + i + 1];
-            for (int k0 = jb; k0 < je; k0 += 4) {
-                uint2 hv[4];
-                float2 yk[4];
+    // s of each cell: wave w takes the cell pairs (w + 8j, w + 8j + 4); lane l hidden units 4l .. 4l + 3.
+    // The two cells' loads are issued together (cells hold few visibilities: one round trip each).
+    constexpr int NW = ANT / 64;
+    for (int i0 = wave; i0 < AG; i0 += 2 * NW) {
+        float sr[2][4] = {}, sm[2][4] = {};
+        float2 Y[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        int jb[2], je[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = i0 + h * NW;
+            jb[h] = i < nc ? cell_start[c0 + i] : 0;
+            je[h] = i < nc ? cell_start[c0 + i + 1] : 0;
+        }
+        for (int k0 = 0; jb[0] + k0 < je[0] || jb[1] + k0 < je[1]; k0 += 4) {
+            uint2 hv[2][4];
+            float2 yk[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const bool ok = k0 + q < je;
-                    hv[q] = ok ? nt_load_u2(h3 + (int64_t)(k0 + q) * H + 4 * lane) : make_uint2(0u, 0u);
-                    yk[q] = ok ? nt_load_f2(y + k0 + q) : make_float2(0.f, 0.f);
+                    const int k = jb[h] + k0 + q;
+                    const bool ok = k < je[h];
+                    hv[h][q] = ok ? nt_load_u2(h3 + (int64_t)k * H + 4 * lane) : make_uint2(0u, 0u);
+                    yk[h][q] = ok ? nt_load_f2(y + k) : make_float2(0.f, 0.f);
                 }
 #pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const float h0 = __uint_as_float(hv[q].x << 16), h1 = __uint_as_float(hv[q].x & 0xffff0000u);
-                    const float h2 = __uint_as_float(hv[q].y << 16), h3v = __uint_as_float(hv[q].y & 0xffff0000u);
-                    sr[0] += h0 * yk[q].x; sm[0] += h0 * yk[q].y;
-                    sr[1] += h1 * yk[q].x; sm[1] += h1 * yk[q].y;
-                    sr[2] += h2 * yk[q].x; sm[2] += h2 * yk[q].y;
-                    sr[3] += h3v * yk[q].x; sm[3] += h3v * yk[q].y;
-                    Y.x += yk[q].x;
-                    Y.y += yk[q].y;
+                    const float h0 = __uint_as_float(hv[h][q].x << 16), h1 = __uint_as_float(hv[h][q].x & 0xffff0000u);
+                    const float h2 = __uint_as_float(hv[h][q].y << 16), h3v = __uint_as_float(hv[h][q].y & 0xffff0000u);
+                    sr[h][0] += h0 * yk[h][q].x; sm[h][0] += h0 * yk[h][q].y;
+                    sr[h][1] += h1 * yk[h][q].x; sm[h][1] += h1 * yk[h][q].y;
+                    sr[h][2] += h2 * yk[h][q].x; sm[h][2] += h2 * yk[h][q].y;
+                    sr[h][3] += h3v * yk[h][q].x; sm[h][3] += h3v * yk[h][q].y;
+                    Y[h].x += yk[h][q].x;
+                    Y[h].y += yk[h][q].y;
                 }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int i = i0 + h * NW;
+            if (i >= AG) continue;                 // wave-uniform
+            uint2 pr, pm;
+            pr.x = (uint32_t)to_bf16(sr[h][0]) | ((uint32_t)to_bf16(sr[h][1]) << 16);
+            pr.y = (uint32_t)to_bf16(sr[h][2]) | ((uint32_t)to_bf16(sr[h][3]) << 16);
+            pm.x = (uint32_t)to_bf16(sm[h][0]) | ((uint32_t)to_bf16(sm[h][1]) << 16);
+            pm.y = (uint32_t)to_bf16(sm[h][2]) | ((uint32_t)to_bf16(sm[h][3]) << 16);
+            *(uint2 *)(Sa + i * SLD + 4 * lane) = pr;
+            *(uint2 *)(Sa + i * SLD + H + 4 * lane) = pm;
+            // |A_i . B_o| <= ||A_i||_2 ||B_o||_2 (Cauchy-Schwarz) and |bias| <= max|b4| (|Y re| + |Y im|):
+            // a bound on every output of the cell (A_i: the bfloat16 values just stored)
+            float l2 = 0.f;
+            for (int e2 = 0; e2 < 4; ++e2) {
+                const uint32_t wr = e2 < 2 ? (e2 == 0 ? pr.x : pr.y) : (e2 == 2 ? pm.x : pm.y);
+                const float lo = from_bf16(wr & 0xffffu), hi = from_bf16(wr >> 16);
+                l2 = fmaf(lo, lo, fmaf(hi, hi, l2));
             }
-        }
-        uint2 pr, pm;
-        pr.x = (uint32_t)to_bf16(sr[0]) | ((uint32_t)to_bf16(sr[1]) << 16);
-        pr.y = (uint32_t)to_bf16(sr[2]) | ((uint32_t)to_bf16(sr[3]) << 16);
-        pm.x = (uint32_t)to_bf16(sm[0]) | ((uint32_t)to_bf16(sm[1]) << 16);
-        pm.y = (uint32_t)to_bf16(sm[2]) | ((uint32_t)to_bf16(sm[3]) << 16);
-        *(uint2 *)(Sa + i * SLD + 4 * lane) = pr;
-        *(uint2 *)(Sa + i * SLD + H + 4 * lane) = pm;
-        // |A_i . B_o| <= ||A_i||_2 ||B_o||_2 (Cauchy-Schwarz) and |bias| <= max|b4| (|Y re| + |Y im|):
-        // a bound on every output of the cell (A_i: the bfloat16 values just stored)
-        float l2 = 0.f;
-        for (int e2 = 0; e2 < 4; ++e2) {
-            const uint32_t wr = e2 < 2 ? (e2 == 0 ? pr.x : pr.y) : (e2 == 2 ? pm.x : pm.y);
-            const float lo = from_bf16(wr & 0xffffu), hi = from_bf16(wr >> 16);
-            l2 = fmaf(lo, lo, fmaf(hi, hi, l2));
-        }
-        for (int o2 = 32; o2 > 0; o2 >>= 1) l2 += __shfl_xor(l2, o2);
-        if (lane == 0) {
-            s_Y[i] = Y;
-            s_bnd[i] = sqrtf(l2) * 1.0001f * wmax[0] + wmax[1] * (fabsf(Y.x) + fabsf(Y.y));
+            for (int o2 = 32; o2 > 0; o2 >>= 1) l2 += __shfl_xor(l2, o2);
+            if (lane == 0) {
+                s_Y[i] = Y[h];
+                s_bnd[i] = sqrtf(l2) * 1.0001f * wmax[0] + wmax[1] * (fabsf(Y[h].x) + fabsf(Y[h].y));
+            }
         }
     }
     __syncthreads();
