@@ -352,24 +352,27 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
         s_wu[i] = i < nc ? cu - (o.y + BOX / 2) : 0;
     }
     for (int e = tid; e < WV * WU; e += ANT) win[e] = make_int2(0, 0);
-    // s of each cell: wave w takes the cell pairs (w + 8j, w + 8j + 4); lane l hidden units 4l .. 4l + 3.
-    // The two cells' loads are issued together (cells hold few visibilities: one round trip each).
-    constexpr int NW = ANT / 64;
-    for (int i0 = wave; i0 < AG; i0 += 2 * NW) {
-        float sr[2][4] = {}, sm[2][4] = {};
-        float2 Y[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-        int jb[2], je[2];
+    // s of each cell: wave w takes the cells w + 4h + 16j (h < CP) together; lane l hidden units
+    // 4l .. 4l + 3.  The CP cells' loads are issued together (cells hold few visibilities).
+    constexpr int NW = ANT / 64, CP = 4;
+    for (int i0 = wave; i0 < AG; i0 += CP * NW) {
+        float sr[CP][4] = {}, sm[CP][4] = {};
+        float2 Y[CP] = {};
+        int jb[CP], je[CP];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < CP; ++h) {
             const int i = i0 + h * NW;
             jb[h] = i < nc ? cell_start[c0 + i] : 0;
             je[h] = i < nc ? cell_start[c0 + i + 1] : 0;
         }
-        for (int k0 = 0; jb[0] + k0 < je[0] || jb[1] + k0 < je[1]; k0 += 4) {
-            uint2 hv[2][4];
-            float2 yk[2][4];
+        int kmax = 0;
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < CP; ++h) kmax = max(kmax, je[h] - jb[h]);
+        for (int k0 = 0; k0 < kmax; k0 += 4) {
+            uint2 hv[CP][4];
+            float2 yk[CP][4];
+#pragma unroll
+            for (int h = 0; h < CP; ++h)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int k = jb[h] + k0 + q;
@@ -378,7 +381,7 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
                     yk[h][q] = ok ? nt_load_f2(y + k) : make_float2(0.f, 0.f);
                 }
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < CP; ++h)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const float h0 = __uint_as_float(hv[h][q].x << 16), h1 = __uint_as_float(hv[h][q].x & 0xffff0000u);
@@ -392,7 +395,7 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
                 }
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < CP; ++h) {
             const int i = i0 + h * NW;
             if (i >= AG) continue;                 // wave-uniform
             uint2 pr, pm;
