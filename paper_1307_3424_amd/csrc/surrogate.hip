@@ -352,9 +352,9 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
         s_wu[i] = i < nc ? cu - (o.y + BOX / 2) : 0;
     }
     for (int e = tid; e < WV * WU; e += ANT) win[e] = make_int2(0, 0);
-    // s of each cell: wave w takes the cells w + 4h + 16j (h < CP) together; lane l hidden units
+    // s of each cell: wave w takes the cells w + 4h (h < CP = 8: all eight of its cells) together; lane l hidden units
     // 4l .. 4l + 3.  The CP cells' loads are issued together (cells hold few visibilities).
-    constexpr int NW = ANT / 64, CP = 4;
+    constexpr int NW = ANT / 64, CP = 8;
     for (int i0 = wave; i0 < AG; i0 += CP * NW) {
         float sr[CP][4] = {}, sm[CP][4] = {};
         float2 Y[CP] = {};
