@@ -25,11 +25,13 @@ template <> struct Shape<10> { static constexpr int CR = 1, TR = 128, CC = 4, TC
 template <> struct Shape<11> { static constexpr int CR = 1, TR = 256, CC = 4, TC = 512; };
 template <> struct Shape<12> { static constexpr int CR = 1, TR = 512, CC = 2, TC = 512; };
 
-__device__ inline float apod_at(const float *__restrict__ apod, int N, int aphys, float delta, int im,
-                                int iu) {
+// INVN: the physical apodisation carries the 1/n(l, m) factor.  A template parameter rather than
+// a runtime test, so that a kernel's loads are not split by a branch.
+template <bool INVN>
+__device__ inline float apod_at(const float *__restrict__ apod, int N, float delta, int im, int iu) {
     float a = apod[im] * apod[iu];
-    if (aphys == WP_APHYS_INV_N) {
-        float l = (iu - N / 2) * delta, m = (im - N / 2) * delta;
+    if constexpr (INVN) {
+        const float l = (iu - N / 2) * delta, m = (im - N / 2) * delta;
         a *= rsqrtf(1.0f - l * l - m * m);
     }
     return a;
@@ -37,106 +39,150 @@ __device__ inline float apod_at(const float *__restrict__ apod, int N, int aphys
 
 __device__ inline float sgn(int k) { return (k & 1) ? -1.0f : 1.0f; }
 
+// Every kernel loads all of a thread's elements (and the apodisation factors) into registers
+// before it writes any of them to LDS, so the loads are in flight together instead of one
+// round trip per element.
+
 // Forward, pass 1: rows.  Block handles C image rows (padded rows jv = im + N/2).
-template <int LOGNG, int C, int NTH>
+template <int LOGNG, int C, int NTH, bool INVN>
 __global__ __launch_bounds__(NTH) void k_fwd_rows(const float2 *__restrict__ x, float2 *__restrict__ grid,
                                                       const float *__restrict__ apod, const float2 *__restrict__ tw,
-                                                      int aphys, float delta) {
-    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+                                                      float delta) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2, PE = C * Ng / NTH, PZ = C * N / NTH;
+    static_assert(C * N % NTH == 0, "shape");
     __shared__ float2 buf[C * Ng];
     const int tid = threadIdx.x;
     const int im0 = blockIdx.x * C;
     x += (int64_t)blockIdx.y * N * N;
     grid += (int64_t)blockIdx.y * Ng * Ng;
-    for (int e = tid; e < C * Ng; e += NTH) {
-        const int c = e / Ng, j = e % Ng, im = im0 + c;
-        float2 v = make_float2(0.f, 0.f);
-        if (j >= N / 2 && j < N / 2 + N) {
-            const int iu = j - N / 2;
-            const float s = apod_at(apod, N, aphys, delta, im, iu) * sgn(j + im + N / 2);
-            v = x[(int64_t)im * N + iu];
-            v.x *= s;
-            v.y *= s;
-        }
-        buf[c * Ng + j] = v;
+    FftTwiddles<float2, LOGNG, C, NTH, true> twp;
+    twp.load(tw, false, tid);
+    // the padded row is non-zero only at j in [N/2, 3N/2): load those, write zeros elsewhere
+    float2 v[PZ];
+    float a[PZ];
+#pragma unroll
+    for (int i = 0; i < PZ; ++i) {
+        const int e = tid + i * NTH, c = e / N, iu = e % N, im = im0 + c;
+        v[i] = x[(int64_t)im * N + iu];
+        a[i] = apod_at<INVN>(apod, N, delta, im, iu) * sgn(iu + N / 2 + im + N / 2);
+    }
+#pragma unroll
+    for (int i = 0; i < PZ; ++i) {
+        const int e = tid + i * NTH, c = e / N, iu = e % N;
+        buf[c * Ng + iu + N / 2] = make_float2(v[i].x * a[i], v[i].y * a[i]);
+        buf[c * Ng + (iu < N / 2 ? iu : iu + N)] = make_float2(0.f, 0.f);
     }
     __syncthreads();
-    lds_fft<float2, LOGNG, C, NTH, true, Ng>(buf, tw, false, tid);
-    for (int e = tid; e < C * Ng; e += NTH) {
-        const int c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
-        grid[(int64_t)jv * Ng + q] = buf[c * Ng + q];
+    lds_fft<float2, LOGNG, C, NTH, true, Ng>(buf, tw, &twp, false, tid);
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+        const int e = tid + i * NTH, c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
+        grid[(int64_t)jv * Ng + q] = buf[e];
     }
 }
 
 // Forward, pass 2: columns (block handles C adjacent columns), in place.
 template <int LOGNG, int C, int NTH>
 __global__ __launch_bounds__(NTH) void k_fwd_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
-    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2, PE = Ng * C / NTH, PZ = N * C / NTH;
+    static_assert(N * C % NTH == 0, "shape");
     __shared__ float2 buf[Ng * C];
     const int tid = threadIdx.x;
     const int qu0 = xcd_block(blockIdx.x, gridDim.x) * C;
     grid += (int64_t)blockIdx.y * Ng * Ng;
-    for (int e = tid; e < Ng * C; e += NTH) {
-        const int jv = e / C, c = e % C;
-        float2 v = make_float2(0.f, 0.f);
-        if (jv >= N / 2 && jv < N / 2 + N) v = grid[(int64_t)jv * Ng + qu0 + c];
-        buf[jv * C + c] = v;
+    FftTwiddles<float2, LOGNG, C, NTH, false> twp;
+    twp.load(tw, false, tid);
+    // only rows jv in [N/2, 3N/2) are non-zero: load those, write zeros elsewhere
+    float2 v[PZ];
+#pragma unroll
+    for (int i = 0; i < PZ; ++i) {
+        const int e = tid + i * NTH, jv = N / 2 + e / C, c = e % C;
+        v[i] = grid[(int64_t)jv * Ng + qu0 + c];
+    }
+#pragma unroll
+    for (int i = 0; i < PZ; ++i) {
+        const int e = tid + i * NTH, r = e / C, c = e % C;
+        buf[(N / 2 + r) * C + c] = v[i];
+        buf[(r < N / 2 ? r : r + N) * C + c] = make_float2(0.f, 0.f);
     }
     __syncthreads();
-    lds_fft<float2, LOGNG, C, NTH, false, C>(buf, tw, false, tid);
-    for (int e = tid; e < Ng * C; e += NTH) {
-        const int qv = e / C, c = e % C;
-        float2 v = buf[qv * C + c];
+    lds_fft<float2, LOGNG, C, NTH, false, C>(buf, tw, &twp, false, tid);
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+        const int e = tid + i * NTH, qv = e / C, c = e % C;
+        const float2 w = buf[e];
         const float s = sgn(qv + qu0 + c);
-        grid[(int64_t)qv * Ng + qu0 + c] = make_float2(v.x * s, v.y * s);
+        grid[(int64_t)qv * Ng + qu0 + c] = make_float2(w.x * s, w.y * s);
     }
 }
 
 // Adjoint, pass 1: columns, inverse, keep the central N rows, in place.
 template <int LOGNG, int C, int NTH>
 __global__ __launch_bounds__(NTH) void k_adj_cols(float2 *__restrict__ grid, const float2 *__restrict__ tw) {
-    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2, PE = Ng * C / NTH, PO = N * C / NTH;
+    static_assert(Ng * C % NTH == 0 && N * C % NTH == 0, "shape");
     __shared__ float2 buf[Ng * C];
     const int tid = threadIdx.x;
     const int qu0 = xcd_block(blockIdx.x, gridDim.x) * C;
     grid += (int64_t)blockIdx.y * Ng * Ng;
-    for (int e = tid; e < Ng * C; e += NTH) {
-        const int qv = e / C, c = e % C;
-        float2 v = grid[(int64_t)qv * Ng + qu0 + c];
+    FftTwiddles<float2, LOGNG, C, NTH, false> twp;
+    twp.load(tw, true, tid);
+    float2 v[PE];
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+        const int e = tid + i * NTH, qv = e / C, c = e % C;
+        v[i] = grid[(int64_t)qv * Ng + qu0 + c];
+    }
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+        const int e = tid + i * NTH, qv = e / C, c = e % C;
         const float s = sgn(qv + qu0 + c);
-        buf[qv * C + c] = make_float2(v.x * s, v.y * s);
+        buf[e] = make_float2(v[i].x * s, v[i].y * s);          // e = qv C + c
     }
     __syncthreads();
-    lds_fft<float2, LOGNG, C, NTH, false, C>(buf, tw, true, tid);
-    for (int e = tid; e < N * C; e += NTH) {
-        const int jv = N / 2 + e / C, c = e % C;
+    lds_fft<float2, LOGNG, C, NTH, false, C>(buf, tw, &twp, true, tid);
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+        const int e = tid + i * NTH, jv = N / 2 + e / C, c = e % C;
         grid[(int64_t)jv * Ng + qu0 + c] = buf[jv * C + c];
     }
 }
 
 // Adjoint, pass 2: rows, inverse, crop the central N, apodise, write the image.
-template <int LOGNG, int C, int NTH>
+template <int LOGNG, int C, int NTH, bool INVN>
 __global__ __launch_bounds__(NTH) void k_adj_rows(const float2 *__restrict__ grid, float2 *__restrict__ x,
                                                       const float *__restrict__ apod, const float2 *__restrict__ tw,
-                                                      int aphys, float delta) {
-    constexpr int Ng = 1 << LOGNG, N = Ng / 2;
+                                                      float delta) {
+    constexpr int Ng = 1 << LOGNG, N = Ng / 2, PE = C * Ng / NTH, PO = C * N / NTH;
+    static_assert(C * Ng % NTH == 0 && C * N % NTH == 0, "shape");
     __shared__ float2 buf[C * Ng];
     const int tid = threadIdx.x;
     const int im0 = blockIdx.x * C;
     grid += (int64_t)blockIdx.y * Ng * Ng;
     x += (int64_t)blockIdx.y * N * N;
-    for (int e = tid; e < C * Ng; e += NTH) {
-        const int c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
-        buf[c * Ng + q] = grid[(int64_t)jv * Ng + q];
+    FftTwiddles<float2, LOGNG, C, NTH, true> twp;
+    twp.load(tw, true, tid);
+    float a[PO];                                                // output factors, needed after the transform
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+        const int e = tid + i * NTH, c = e / N, iu = e % N, im = im0 + c;
+        a[i] = apod_at<INVN>(apod, N, delta, im, iu) * sgn(iu + N / 2 + im + N / 2);
     }
+    float2 v[PE];
+#pragma unroll
+    for (int i = 0; i < PE; ++i) {
+        const int e = tid + i * NTH, c = e / Ng, q = e % Ng, jv = im0 + c + N / 2;
+        v[i] = grid[(int64_t)jv * Ng + q];
+    }
+#pragma unroll
+    for (int i = 0; i < PE; ++i) buf[tid + i * NTH] = v[i];   // e = c Ng + q
     __syncthreads();
-    lds_fft<float2, LOGNG, C, NTH, true, Ng>(buf, tw, true, tid);
-    for (int e = tid; e < C * N; e += NTH) {
-        const int c = e / N, iu = e % N, im = im0 + c;
-        const int ju = iu + N / 2, jv = im + N / 2;
-        const float s = apod_at(apod, N, aphys, delta, im, iu) * sgn(ju + jv);
-        float2 v = buf[c * Ng + ju];
-        x[(int64_t)im * N + iu] = make_float2(v.x * s, v.y * s);
+    lds_fft<float2, LOGNG, C, NTH, true, Ng>(buf, tw, &twp, true, tid);
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+        const int e = tid + i * NTH, c = e / N, iu = e % N, im = im0 + c;
+        const float2 w = buf[c * Ng + iu + N / 2];
+        x[(int64_t)im * N + iu] = make_float2(w.x * a[i], w.y * a[i]);
     }
 }
 
@@ -145,8 +191,12 @@ wp_status fwd(const wp_plan *p, const float2 *x, float2 *grid, int batch, hipStr
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     using S = Shape<LOGNG>;
     static_assert(N % S::CR == 0 && Ng % S::CC == 0, "shape");
-    hipLaunchKernelGGL((k_fwd_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, x, grid,
-                       p->apod, p->tw32, p->aphys, (float)p->delta);
+    if (p->aphys == WP_APHYS_INV_N)
+        hipLaunchKernelGGL((k_fwd_rows<LOGNG, S::CR, S::TR, true>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, x,
+                           grid, p->apod, p->tw32, (float)p->delta);
+    else
+        hipLaunchKernelGGL((k_fwd_rows<LOGNG, S::CR, S::TR, false>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, x,
+                           grid, p->apod, p->tw32, (float)p->delta);
     hipLaunchKernelGGL((k_fwd_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC, batch), dim3(S::TC), 0, s, grid, p->tw32);
     return wp_check_launch("grid_forward");
 }
@@ -156,8 +206,12 @@ wp_status adj(const wp_plan *p, float2 *grid, float2 *x, int batch, hipStream_t 
     constexpr int Ng = 1 << LOGNG, N = Ng / 2;
     using S = Shape<LOGNG>;
     hipLaunchKernelGGL((k_adj_cols<LOGNG, S::CC, S::TC>), dim3(Ng / S::CC, batch), dim3(S::TC), 0, s, grid, p->tw32);
-    hipLaunchKernelGGL((k_adj_rows<LOGNG, S::CR, S::TR>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, grid, x,
-                       p->apod, p->tw32, p->aphys, (float)p->delta);
+    if (p->aphys == WP_APHYS_INV_N)
+        hipLaunchKernelGGL((k_adj_rows<LOGNG, S::CR, S::TR, true>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, grid,
+                           x, p->apod, p->tw32, (float)p->delta);
+    else
+        hipLaunchKernelGGL((k_adj_rows<LOGNG, S::CR, S::TR, false>), dim3(N / S::CR, batch), dim3(S::TR), 0, s, grid,
+                           x, p->apod, p->tw32, (float)p->delta);
     return wp_check_launch("grid_adjoint");
 }
 

@@ -60,8 +60,11 @@ __device__ __forceinline__ void dft8(T2 *a, bool inverse) {
     }
 }
 
+// pre (or null): this stage's twiddles, already conjugated for the inverse, pre[i][r - 1] for the
+// thread's i-th butterfly
 template <typename T2, int R, int LOGN, int BATCH, int NTH, bool ROWS, int LD>
-__device__ __forceinline__ void fft_stage(T2 *buf, const T2 *__restrict__ tw, bool inverse, int tid, int Ns) {
+__device__ __forceinline__ void fft_stage(T2 *buf, const T2 *__restrict__ tw, const T2 (*pre)[7], bool inverse,
+                                          int tid, int Ns) {
     constexpr int n = 1 << LOGN;
     constexpr int nq = n / R;
     constexpr int nb = BATCH * nq;
@@ -91,8 +94,13 @@ __device__ __forceinline__ void fft_stage(T2 *buf, const T2 *__restrict__ tw, bo
             if (Ns > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    T2 t = tw[r * k * step];
-                    if (inverse) t.y = -t.y;
+                    T2 t;
+                    if (pre) {
+                        t = pre[i][r - 1];
+                    } else {
+                        t = tw[r * k * step];
+                        if (inverse) t.y = -t.y;
+                    }
                     a[r] = cmul(a[r], t);
                 }
             }
@@ -117,16 +125,79 @@ __device__ __forceinline__ void fft_stage(T2 *buf, const T2 *__restrict__ tw, bo
     __syncthreads();
 }
 
+// Stage s of an n-point transform: radix 8 for s < LOGN / 3, then radix 4 or 2; the sub-transform
+// length before stage s is 8^s; per(s) is the number of butterflies per thread.
+template <int LOGN>
+struct FftStages {
+    static constexpr int n = 1 << LOGN, N8 = LOGN / 3, REM = LOGN % 3, count = N8 + (REM ? 1 : 0);
+    static constexpr int radix(int s) { return s < N8 ? 8 : (REM == 2 ? 4 : 2); }
+    static constexpr int ns(int s) { return 1 << (3 * s); }
+    static constexpr int per(int s, int batch, int nth) { return (batch * (n / radix(s)) + nth - 1) / nth; }
+    static constexpr int per_max(int batch, int nth) {
+        int m = 1;
+        for (int s = 1; s < count; ++s) m = per(s, batch, nth) > m ? per(s, batch, nth) : m;
+        return m;
+    }
+};
+
+// The twiddles of every stage after the first, for all of a thread's butterflies.  Loaded before
+// the caller stages its data, their latency overlaps those loads instead of stalling each stage.
+// Only where they fit a modest register budget (enabled); otherwise the stages load their own.
+template <typename T2, int LOGN, int BATCH, int NTH, bool ROWS>
+struct FftTwiddles {
+    using St = FftStages<LOGN>;
+    static constexpr int NT = St::count > 1 ? St::count - 1 : 1, PM = St::per_max(BATCH, NTH);
+    static constexpr bool enabled = St::count > 1 && NT * PM * 7 <= 14;
+    T2 t[enabled ? NT : 1][enabled ? PM : 1][7];
+
+    __device__ __forceinline__ void load(const T2 *__restrict__ tw, bool inverse, int tid) {
+        if constexpr (enabled) load_stage<1>(tw, inverse, tid);
+    }
+    template <int S>
+    __device__ __forceinline__ void load_stage(const T2 *__restrict__ tw, bool inverse, int tid) {
+        if constexpr (S < St::count) {
+            constexpr int R = St::radix(S), Ns = St::ns(S), nq = St::n / R, nb = BATCH * nq;
+            constexpr int PER = St::per(S, BATCH, NTH), step = St::n / (R * Ns);
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int b = tid + i * NTH;
+                const int j = ROWS ? (b % nq) : (b / BATCH);
+                const int k = j & (Ns - 1);                     // k < Ns, so r k step < n
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    T2 v = tw[r * k * step];
+                    if (inverse) v.y = -v.y;
+                    t[S - 1][i][r - 1] = (nb % NTH == 0 || b < nb) ? v : T2{};
+                }
+            }
+            load_stage<S + 1>(tw, inverse, tid);
+        }
+    }
+};
+
+// pre (or null): twiddles loaded by FftTwiddles::load with the same inverse flag
 template <typename T2, int LOGN, int BATCH, int NTH, bool ROWS, int LD>
-__device__ __forceinline__ void lds_fft(T2 *buf, const T2 *__restrict__ tw, bool inverse, int tid) {
+__device__ __forceinline__ void lds_fft(T2 *buf, const T2 *__restrict__ tw,
+                                        const FftTwiddles<T2, LOGN, BATCH, NTH, ROWS> *pre, bool inverse, int tid) {
+    using Pre = FftTwiddles<T2, LOGN, BATCH, NTH, ROWS>;
     constexpr int N8 = LOGN / 3;
     constexpr int REM = LOGN % 3;
     int Ns = 1;
 #pragma unroll
     for (int s = 0; s < N8; ++s) {
-        fft_stage<T2, 8, LOGN, BATCH, NTH, ROWS, LD>(buf, tw, inverse, tid, Ns);
+        const T2(*ps)[7] = nullptr;
+        if constexpr (Pre::enabled) ps = (pre && s > 0) ? pre->t[s - 1] : nullptr;
+        fft_stage<T2, 8, LOGN, BATCH, NTH, ROWS, LD>(buf, tw, ps, inverse, tid, Ns);
         Ns *= 8;
     }
-    if constexpr (REM == 2) fft_stage<T2, 4, LOGN, BATCH, NTH, ROWS, LD>(buf, tw, inverse, tid, Ns);
-    if constexpr (REM == 1) fft_stage<T2, 2, LOGN, BATCH, NTH, ROWS, LD>(buf, tw, inverse, tid, Ns);
+    const T2(*pl)[7] = nullptr;
+    if constexpr (Pre::enabled && REM != 0) pl = pre ? pre->t[N8 - 1] : nullptr;
+    if constexpr (REM == 2) fft_stage<T2, 4, LOGN, BATCH, NTH, ROWS, LD>(buf, tw, pl, inverse, tid, Ns);
+    if constexpr (REM == 1) fft_stage<T2, 2, LOGN, BATCH, NTH, ROWS, LD>(buf, tw, pl, inverse, tid, Ns);
+}
+
+template <typename T2, int LOGN, int BATCH, int NTH, bool ROWS, int LD>
+__device__ __forceinline__ void lds_fft(T2 *buf, const T2 *__restrict__ tw, bool inverse, int tid) {
+    lds_fft<T2, LOGN, BATCH, NTH, ROWS, LD>(buf, tw, (const FftTwiddles<T2, LOGN, BATCH, NTH, ROWS> *)nullptr,
+                                            inverse, tid);
 }
