@@ -151,16 +151,26 @@ constexpr int DNT = 256;
 __global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, int64_t in_zs, float *__restrict__ det,
                                                   float *__restrict__ ll, int N, int L, const FiltSet fs) {
     __shared__ float win[DWIN * DWIN];
-    const Filt &f = fs.f[blockIdx.y];
+    const Filt f = fs.f[blockIdx.y];                              // taps in registers, read once
     in += blockIdx.y * in_zs;
     det += (int64_t)blockIdx.y * N * N;
     ll += (int64_t)blockIdx.y * N * N;
     __shared__ float R[DWIN * 2 * DT];
     const int H = L >> 1, t = H < DT ? H : DT, tiles = H / t, w = 2 * t + 14;
     const int kr0 = (blockIdx.x / tiles) * t, kc0 = (blockIdx.x % tiles) * t;
-    for (int e = threadIdx.x; e < w * w; e += DNT) {
-        const int i = e / w, j = e % w;
-        win[i * DWIN + j] = in[(int64_t)((2 * kr0 + i) & (L - 1)) * N + ((2 * kc0 + j) & (L - 1))];
+    // stage the window: all of a thread's loads in flight before the first LDS write (positions
+    // past the window load a clamped in-window address and are not stored)
+    constexpr int PW = (DWIN * DWIN + DNT - 1) / DNT;
+    float v[PW];
+#pragma unroll
+    for (int k = 0; k < PW; ++k) {
+        const int e = min((int)threadIdx.x + k * DNT, w * w - 1), i = e / w, j = e % w;
+        v[k] = in[(int64_t)((2 * kr0 + i) & (L - 1)) * N + ((2 * kc0 + j) & (L - 1))];
+    }
+#pragma unroll
+    for (int k = 0; k < PW; ++k) {
+        const int e = threadIdx.x + k * DNT;
+        if (e < w * w) win[(e / w) * DWIN + e % w] = v[k];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < w * 2 * t; e += DNT) {          // rows: R[i][band * t + kc]
@@ -190,7 +200,15 @@ __global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, 
 __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef, const float *__restrict__ llin,
                                                   float *__restrict__ out, int N, int L, const FiltSet fs) {
     constexpr int CW = 2 * (DT + 8);
-    const Filt &f = fs.f[blockIdx.y];
+    // taps in registers, read once, split by parity: an output at parity o uses h_(n+o), g_(n+o)
+    float he[8], ho[8], ge[8], go[8];
+#pragma unroll
+    for (int n = 0; n < 8; ++n) {
+        he[n] = fs.f[blockIdx.y].h[2 * n];
+        ho[n] = fs.f[blockIdx.y].h[2 * n + 1];
+        ge[n] = fs.f[blockIdx.y].g[2 * n];
+        go[n] = fs.f[blockIdx.y].g[2 * n + 1];
+    }
     coef += (int64_t)blockIdx.y * N * N;
     llin += (int64_t)blockIdx.y * N * N;
     out += (int64_t)blockIdx.y * N * N;
@@ -199,10 +217,21 @@ __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef
     const int H = L >> 1, t = H < DT ? H : DT, tiles = H / t, w = t + 8;
     const int mr0 = (blockIdx.x / tiles) * 2 * t, mc0 = (blockIdx.x % tiles) * 2 * t;
     const int kr0 = (mr0 >> 1) - 8, kc0 = (mc0 >> 1) - 8;        // first coefficient of each window
-    for (int e = threadIdx.x; e < 4 * w * w; e += DNT) {
-        const int i = e / (2 * w), j = e % (2 * w);
+    // stage the four band windows, every load in flight before the first LDS write; the source
+    // (coarser result or detail coefficients) is a pointer select, not a branch
+    constexpr int PC = (CW * CW + DNT - 1) / DNT;
+    float v[PC];
+#pragma unroll
+    for (int k = 0; k < PC; ++k) {
+        const int e = min((int)threadIdx.x + k * DNT, 4 * w * w - 1), i = e / (2 * w), j = e % (2 * w);
         const int r = (i / w) * H + ((kr0 + i % w) & (H - 1)), c = (j / w) * H + ((kc0 + j % w) & (H - 1));
-        C[i * CW + j] = (r < H && c < H) ? llin[(int64_t)r * N + c] : coef[(int64_t)r * N + c];
+        const float *src = (r < H && c < H) ? llin : coef;
+        v[k] = src[(int64_t)r * N + c];
+    }
+#pragma unroll
+    for (int k = 0; k < PC; ++k) {
+        const int e = threadIdx.x + k * DNT;
+        if (e < 4 * w * w) C[(e / (2 * w)) * CW + e % (2 * w)] = v[k];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 2 * t * 2 * w; e += DNT) {      // columns: Y[mr][j]
@@ -212,8 +241,8 @@ __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef
 #pragma unroll
         for (int n = 0; n < 16; n += 2) {
             const int nn = n + odd, i = ((m - nn) >> 1) - kr0;
-            acc = fmaf(odd ? f.h[n + 1] : f.h[n], C[i * CW + j], acc);
-            acc = fmaf(odd ? f.g[n + 1] : f.g[n], C[(w + i) * CW + j], acc);
+            acc = fmaf(odd ? ho[n / 2] : he[n / 2], C[i * CW + j], acc);
+            acc = fmaf(odd ? go[n / 2] : ge[n / 2], C[(w + i) * CW + j], acc);
         }
         Y[mr * CW + j] = acc;
     }
@@ -225,8 +254,8 @@ __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef
 #pragma unroll
         for (int n = 0; n < 16; n += 2) {
             const int nn = n + odd, j = ((m - nn) >> 1) - kc0;
-            acc = fmaf(odd ? f.h[n + 1] : f.h[n], Y[mr * CW + j], acc);
-            acc = fmaf(odd ? f.g[n + 1] : f.g[n], Y[mr * CW + w + j], acc);
+            acc = fmaf(odd ? ho[n / 2] : he[n / 2], Y[mr * CW + j], acc);
+            acc = fmaf(odd ? go[n / 2] : ge[n / 2], Y[mr * CW + w + j], acc);
         }
         out[(int64_t)(mr0 + mr) * N + mc0 + mc] = acc;
     }
