@@ -41,27 +41,44 @@ __device__ __forceinline__ void gather_block(const int64_t *__restrict__ tblk, i
         constexpr int PER = CH / 64;
         int k[PER];
         float2 v[PER];
+        // Each phase issues all of a lane's loads before the next phase waits on them: entries, then
+        // the permutation (one wave-uniform test, outside the loop), then y and the row scales.
+        // Lanes past the chunk's end take row 0 (a valid row: there are entries) and store nothing.
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
             const int e = t * 64 + lane;
+            k[t] = 0;
+            v[t] = make_float2(0.f, 0.f);
             if (e < n) {
                 k[t] = trow[c0 + e];
                 v[t] = load_tap_raw<TK>(tval, c0 + e);
             }
         }
+        int yi[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) yi[t] = k[t];
+        if (perm) {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) yi[t] = perm[yi[t]];
+        }
+        float2 yk[PER];
+        float sc[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            yk[t] = y[yi[t]];
+            sc[t] = 1.f;
+            if constexpr (TK == WP_TAPS_I16) sc[t] = rscale[k[t]];
+        }
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
             const int e = t * 64 + lane;
             if (e < n) {
-                const int r = k[t];
                 float2 g = v[t];
                 if constexpr (TK == WP_TAPS_I16) {
-                    const float sc = rscale[r];
-                    g.x *= sc;
-                    g.y *= sc;
+                    g.x *= sc[t];
+                    g.y *= sc[t];
                 }
-                const float2 yk = y[perm ? perm[r] : r];
-                sp[e] = make_float2(fmaf(g.x, yk.x, g.y * yk.y), fmaf(g.x, yk.y, -g.y * yk.x));   // conj(G) y
+                sp[e] = make_float2(fmaf(g.x, yk[t].x, g.y * yk[t].y), fmaf(g.x, yk[t].y, -g.y * yk[t].x));   // conj(G) y
             }
         }
         wave_sync();
