@@ -78,11 +78,14 @@ def check_rows(G, u, v, w, E, s, rows, beam=None):
 
 # --------------------------------------------------------------------------- A, Z, F
 
-@pytest.mark.parametrize("N", [32, 64, 256, 1024])
-def test_grid_forward_and_adjoint(N):
-    say(f"grid transforms N={N}")
-    s = Setup(N=N, L=L)
-    plan = wp.Plan(N, L)
+@pytest.mark.parametrize("aphys", ["one", "inv_n"])
+@pytest.mark.parametrize("N", [32, 64, 128, 256, 512, 1024, 2048])
+def test_grid_forward_and_adjoint(N, aphys):
+    """A, Z, F and their adjoint at every supported grid size (Ng = 64 .. 4096), with the plain
+    apodisation and with the 1/n factor of Eq. 1 folded in."""
+    say(f"grid transforms N={N} aphys={aphys}")
+    s = Setup(N=N, L=L, a_phys=aphys)
+    plan = wp.Plan(N, L, aphys=wp.WP_APHYS_INV_N if aphys == "inv_n" else wp.WP_APHYS_ONE)
     rng = np.random.default_rng(N)
     x = synth.random_complex((N, N), rng)
     X = wp.grid_forward(plan, c64(x)).cpu().numpy().reshape(s.Ng, s.Ng)
