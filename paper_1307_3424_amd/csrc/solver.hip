@@ -137,6 +137,24 @@ __global__ void k_dwt_lines(const float *__restrict__ in, const float *__restric
     }
 }
 
+// Optional store epilogues of the tiled level kernels, used by the primal-dual loop to fold its
+// elementwise steps into the transforms (null pointers: plain stores).
+// Dual: in place of storing coefficient c_i, v1_i = clip(v1_i + s1 c_i, -1, 1) (the l1 dual step).
+struct DualEpi {
+    float *v1;
+    float s1;
+};
+// Primal: in place of storing the synthesis x_i = (Psi v1)_i, the primal step with it:
+// x+ = max(0, x - tau (Psi v1 + Re(Phi^H v2))); xb = 2 x+ - x; x = x+; xbc = complex(xb).
+struct PrimalEpi {
+    float *x;
+    const float2 *phit;
+    float *xb;
+    float2 *xbc;
+    float tau;
+    double *acc_zero;                     // set to zero (the next ball norm's accumulator)
+};
+
 // One whole level (both axes) per kernel, tiled.  A coefficient (r, c) of a level depends on a
 // 16 x 16 window of its input, so a workgroup makes a tile of t x t positions of all four
 // subbands (t = min(DT, H)) from a (2t + 14)^2 window staged in LDS: first the row filters of every
@@ -149,7 +167,8 @@ constexpr int DNT = 256;
 // subbands go to det, the approximation (top-left H x H) to ll; both have row stride N.  Basis
 // b = blockIdx.y reads in + b in_zs and writes det + b N^2, ll + b N^2.
 __global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, int64_t in_zs, float *__restrict__ det,
-                                                  float *__restrict__ ll, int N, int L, const FiltSet fs) {
+                                                  float *__restrict__ ll, int N, int L, const FiltSet fs,
+                                                  DualEpi de = {nullptr, 0.f}, int ll_final = 0) {
     __shared__ float win[DWIN * DWIN];
     const Filt f = fs.f[blockIdx.y];                              // taps in registers, read once
     in += blockIdx.y * in_zs;
@@ -188,8 +207,15 @@ __global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, 
         for (int n = 0; n < 16; ++n) acc = fmaf(band1 ? f.g[n] : f.h[n], R[(2 * kr + n) * (2 * DT) + q], acc);
         const int band2 = q / t, kc = q % t;
         const int r = band1 * H + kr0 + kr, c = band2 * H + kc0 + kc;
-        if (band1 == 0 && band2 == 0) ll[(int64_t)r * N + c] = acc;
-        else det[(int64_t)r * N + c] = acc;
+        const bool is_ll = band1 == 0 && band2 == 0;
+        if (de.v1 && (!is_ll || ll_final)) {        // a final coefficient: the dual step instead
+            float *v = de.v1 + (int64_t)r * N + c;
+            *v = fminf(1.f, fmaxf(-1.f, *v + de.s1 * acc));
+        } else if (is_ll) {
+            ll[(int64_t)r * N + c] = acc;
+        } else {
+            det[(int64_t)r * N + c] = acc;
+        }
     }
 }
 
@@ -198,7 +224,8 @@ __global__ __launch_bounds__(DNT) void k_dwt2_fwd(const float *__restrict__ in, 
 // coef.  A tile of 2t x 2t outputs reads t + 8 positions of each band per axis.  Basis
 // b = blockIdx.y offsets all three images by b N^2.
 __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef, const float *__restrict__ llin,
-                                                  float *__restrict__ out, int N, int L, const FiltSet fs) {
+                                                  float *__restrict__ out, int N, int L, const FiltSet fs,
+                                                  PrimalEpi pe = {nullptr, nullptr, nullptr, nullptr, 0.f, nullptr}) {
     constexpr int CW = 2 * (DT + 8);
     // taps in registers, read once, split by parity: an output at parity o uses h_(n+o), g_(n+o)
     float he[8], ho[8], ge[8], go[8];
@@ -257,8 +284,19 @@ __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef
             acc = fmaf(odd ? ho[n / 2] : he[n / 2], Y[mr * CW + j], acc);
             acc = fmaf(odd ? go[n / 2] : ge[n / 2], Y[mr * CW + w + j], acc);
         }
-        out[(int64_t)(mr0 + mr) * N + mc0 + mc] = acc;
+        const int64_t i = (int64_t)(mr0 + mr) * N + mc0 + mc;
+        if (pe.x) {                               // the primal step with (Psi v1)_i = acc
+            const float xo = pe.x[i];
+            const float xn = fmaxf(0.f, xo - pe.tau * (acc + pe.phit[i].x));
+            const float b = 2.f * xn - xo;
+            pe.x[i] = xn;
+            pe.xb[i] = b;
+            pe.xbc[i] = make_float2(b, 0.f);
+        } else {
+            out[i] = acc;
+        }
     }
+    if (pe.x && blockIdx.x == 0 && threadIdx.x == 0) *pe.acc_zero = 0.0;
 }
 
 // ---------------------------------------------------------------------------- iteration kernels
@@ -503,13 +541,18 @@ static const FiltSet *filter_set(bool sara) {
     return sara ? (oks ? &all : nullptr) : (ok8 ? &db8 : nullptr);
 }
 
-wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s) {
+// de (analysis) / pe (synthesis), when given, replace the stores of the final coefficients / of the
+// final synthesis (the tiled path only: c != x and levels > 0)
+static wp_status launch_dwt2_epi(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth,
+                                 hipStream_t s, const DualEpi *de, const PrimalEpi *pe) {
     if (wp_status st = check_levels(p, levels)) return st;
     const FiltSet *fsp = filter_set(false);
     if (!fsp) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
     const FiltSet &fs = *fsp;
     const Filt &f = fs.f[0];
     const int N = p->N;
+    if ((de || pe) && (levels == 0 || c == x))
+        return wp_set_error(WP_EINVAL, "dwt2: store epilogues need the tiled path (levels > 0, c != x)");
     if (levels == 0) {                            // Dirac basis: a copy
         if (c != x) hipLaunchKernelGGL(k_copy_f32, blocks_for((int64_t)N * N), dim3(NT), 0, s, x, c, (int64_t)N * N);
         return wp_check_launch(synth ? "idwt2" : "dwt2");
@@ -534,7 +577,8 @@ wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, fl
         for (int lv = 0; lv < levels; ++lv) {
             const int L = N >> lv;
             float *ll = lv == levels - 1 ? c : tmp + (lv == 0 ? 0 : N - (N >> lv));
-            hipLaunchKernelGGL(k_dwt2_fwd, tiles(L), dim3(DNT), 0, s, src, (int64_t)0, c, ll, N, L, fs);
+            hipLaunchKernelGGL(k_dwt2_fwd, tiles(L), dim3(DNT), 0, s, src, (int64_t)0, c, ll, N, L, fs,
+                               de ? *de : DualEpi{nullptr, 0.f}, (int)(lv == levels - 1));
             src = ll;
         }
     } else {
@@ -542,11 +586,17 @@ wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, fl
         for (int st = 0; st < levels; ++st) {
             const int L = N >> (levels - 1 - st);
             float *out = st == levels - 1 ? c : tmp + ((levels - 2 - st) % 2 == 0 ? 0 : N / 2);
-            hipLaunchKernelGGL(k_dwt2_inv, tiles(L), dim3(DNT), 0, s, x, llin, out, N, L, fs);
+            const PrimalEpi none{nullptr, nullptr, nullptr, nullptr, 0.f, nullptr};
+            hipLaunchKernelGGL(k_dwt2_inv, tiles(L), dim3(DNT), 0, s, x, llin, out, N, L, fs,
+                               pe && st == levels - 1 ? *pe : none);
             llin = out;
         }
     }
     return wp_check_launch(synth ? "idwt2" : "dwt2");
+}
+
+wp_status launch_dwt2(const wp_plan *p, int levels, const float *x, float *c, float *tmp, bool synth, hipStream_t s) {
+    return launch_dwt2_epi(p, levels, x, c, tmp, synth, s, nullptr, nullptr);
 }
 
 wp_status op_phi(const wp_plan *p, const wp_operator &op, const float2 *x, float2 *y, float2 *grid, hipStream_t s) {
@@ -608,14 +658,21 @@ wp_status launch_solve(const wp_plan *p, const wp_operator &op, const float2 *y,
     const float tau = 0.49f, s1 = 1.0f, s2 = (float)(1.0 / nu);
     WP_HIP(hipMemsetAsync(v1, 0, 4 * N2, s));
     WP_HIP(hipMemsetAsync(v2, 0, 8 * M, s));
+    // With wavelets, the primal step is the last synthesis level's store epilogue and the l1 dual
+    // step the analysis's (the same arithmetic as k_primal and k_dual1, two launches fewer).
+    const PrimalEpi pe{x, t2, xb, xbc, tau, acc};
+    const DualEpi de{v1, s1};
     for (int it = 0; it < iters; ++it) {
-        if (!dirac)
-            if (wp_status st = launch_dwt2(p, levels, v1, t1, tmp, true, s)) return st;       // Psi v1
         if (wp_status st = op_phiT(p, op, v2, t2, grid, s)) return st;                        // Phi^H v2
-        hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, psi_v1, t2, xb, xbc, N2, tau, acc);
-        if (!dirac)
-            if (wp_status st = launch_dwt2(p, levels, xb, t1, tmp, false, s)) return st;      // Psi^T xb
-        hipLaunchKernelGGL(k_dual1, blocks_for(N2), dim3(NT), 0, s, v1, psit_xb, N2, s1);
+        if (!dirac) {
+            if (wp_status st = launch_dwt2_epi(p, levels, v1, t1, tmp, true, s, nullptr, &pe))  // Psi v1, primal
+                return st;
+            if (wp_status st = launch_dwt2_epi(p, levels, xb, t1, tmp, false, s, &de, nullptr)) // Psi^T xb, dual
+                return st;
+        } else {
+            hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, psi_v1, t2, xb, xbc, N2, tau, acc);
+            hipLaunchKernelGGL(k_dual1, blocks_for(N2), dim3(NT), 0, s, v1, psit_xb, N2, s1);
+        }
         if (wp_status st = op_phi(p, op, xbc, pv, grid, s)) return st;                        // Phi xb
         hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, v2, pv, y, M, s2, acc);
         hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, v2, pv, y, M, s2, eps, acc);
