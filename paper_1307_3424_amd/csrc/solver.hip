@@ -301,34 +301,22 @@ __global__ __launch_bounds__(DNT) void k_dwt2_inv(const float *__restrict__ coef
 
 // ---------------------------------------------------------------------------- iteration kernels
 
-// x+ = max(0, x - tau (psi_v1 + Re(phit_v2))); xb = 2 x+ - x; x = x+; xbc = complex(xb)
-__global__ void k_primal(float *__restrict__ x, const float *__restrict__ psi_v1, const float2 *__restrict__ phit_v2,
-                         float *__restrict__ xb, float2 *__restrict__ xbc, int64_t n, float tau,
-                         double *__restrict__ acc_zero) {
+// Dirac basis (Psi = I), pixel by pixel: the primal step x+ = max(0, x - tau (v1 + Re(phit_v2))),
+// xb = 2 x+ - x, x = x+, xbc = complex(xb); then the l1 dual step v1 = clip(v1 + s1 xb, -1, 1)
+// (v1 is read for the primal step before its update)
+__global__ void k_primal_dual1_dirac(float *__restrict__ x, float *__restrict__ v1, const float2 *__restrict__ phit_v2,
+                                     float *__restrict__ xb, float2 *__restrict__ xbc, int64_t n, float tau, float s1,
+                                     double *__restrict__ acc_zero) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *acc_zero = 0.0;
     if (i >= n) return;
-    const float xo = x[i];
-    const float xn = fmaxf(0.f, xo - tau * (psi_v1[i] + phit_v2[i].x));
+    const float xo = x[i], vo = v1[i];
+    const float xn = fmaxf(0.f, xo - tau * (vo + phit_v2[i].x));
     const float b = 2.f * xn - xo;
     x[i] = xn;
     xb[i] = b;
     xbc[i] = make_float2(b, 0.f);
-}
-
-// v1 = clip(v1 + s1 d, -1, 1)
-__global__ void k_dual1(float *__restrict__ v1, const float *__restrict__ d, int64_t n, float s1) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    v1[i] = fminf(1.f, fmaxf(-1.f, v1[i] + s1 * d[i]));
-}
-
-// v1 = clip(v1 + s1 d, -w, w): the dual step of the weighted norm ||W Psi^T x||_1
-__global__ void k_dual1w(float *__restrict__ v1, const float *__restrict__ d, const float *__restrict__ w, int64_t n,
-                         float s1) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    v1[i] = fminf(w[i], fmaxf(-w[i], v1[i] + s1 * d[i]));
+    v1[i] = fminf(1.f, fmaxf(-1.f, vo + s1 * b));
 }
 
 // SARA analysis, last step: c_0 = x / 3 (Dirac), c_b = W_b x / 3 (the transforms are in c_1..c_8)
@@ -350,6 +338,40 @@ __global__ void k_sara_sum(const float *__restrict__ c0, const float *__restrict
 #pragma unroll
     for (int b = 0; b < 8; ++b) acc += r[b * n2 + i];
     x[i] = acc * (1.0f / 3.0f);
+}
+
+// SARA loop: k_sara_scale, then the dual step of the weighted norm ||W Psi^T x||_1,
+// v1 = clip(v1 + s1 c, -w, w), over the nine bases, per pixel, in one pass (c is not stored)
+__global__ void k_sara_scale_dual(const float *__restrict__ x, const float *__restrict__ c, float *__restrict__ v1,
+                                  const float *__restrict__ w, int64_t n2, float s1) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n2) return;
+    constexpr float third = 1.0f / 3.0f;
+#pragma unroll
+    for (int b = 0; b < 9; ++b) {
+        const int64_t j = b * n2 + i;
+        const float cb = b == 0 ? x[i] * third : c[j] * third;
+        v1[j] = fminf(w[j], fmaxf(-w[j], v1[j] + s1 * cb));
+    }
+}
+
+// SARA loop: k_sara_sum, then the primal step (as in k_primal_dual1_dirac) with Psi v1 = that sum
+__global__ void k_sara_sum_primal(const float *__restrict__ c0, const float *__restrict__ r, float *__restrict__ x,
+                                  const float2 *__restrict__ phit_v2, float *__restrict__ xb,
+                                  float2 *__restrict__ xbc, int64_t n2, float tau, double *__restrict__ acc_zero) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *acc_zero = 0.0;
+    if (i >= n2) return;
+    float acc = c0[i];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc += r[b * n2 + i];
+    const float psi = acc * (1.0f / 3.0f);
+    const float xo = x[i];
+    const float xn = fmaxf(0.f, xo - tau * (psi + phit_v2[i].x));
+    const float b2 = 2.f * xn - xo;
+    x[i] = xn;
+    xb[i] = b2;
+    xbc[i] = make_float2(b2, 0.f);
 }
 
 // weights delta / (delta + |alpha|)
@@ -652,14 +674,13 @@ wp_status launch_solve(const wp_plan *p, const wp_operator &op, const float2 *y,
     float2 *pv = (float2 *)take(8 * M);
     double *acc = (double *)take(64);
     if (wp_status st = check_levels(p, levels)) return st;
-    // Dirac basis: Psi v1 = v1 and Psi^T xb = xb are read in place
+    // Dirac basis (levels 0, Psi = I): the primal and dual steps in one elementwise pass
     const bool dirac = levels == 0;
-    const float *psi_v1 = dirac ? v1 : t1, *psit_xb = dirac ? xb : t1;
     const float tau = 0.49f, s1 = 1.0f, s2 = (float)(1.0 / nu);
     WP_HIP(hipMemsetAsync(v1, 0, 4 * N2, s));
     WP_HIP(hipMemsetAsync(v2, 0, 8 * M, s));
     // With wavelets, the primal step is the last synthesis level's store epilogue and the l1 dual
-    // step the analysis's (the same arithmetic as k_primal and k_dual1, two launches fewer).
+    // step the analysis's (the same arithmetic as the elementwise kernels, two launches fewer).
     const PrimalEpi pe{x, t2, xb, xbc, tau, acc};
     const DualEpi de{v1, s1};
     for (int it = 0; it < iters; ++it) {
@@ -670,8 +691,8 @@ wp_status launch_solve(const wp_plan *p, const wp_operator &op, const float2 *y,
             if (wp_status st = launch_dwt2_epi(p, levels, xb, t1, tmp, false, s, &de, nullptr)) // Psi^T xb, dual
                 return st;
         } else {
-            hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, psi_v1, t2, xb, xbc, N2, tau, acc);
-            hipLaunchKernelGGL(k_dual1, blocks_for(N2), dim3(NT), 0, s, v1, psit_xb, N2, s1);
+            hipLaunchKernelGGL(k_primal_dual1_dirac, blocks_for(N2), dim3(NT), 0, s, x, v1, t2, xb, xbc, N2, tau, s1,
+                               acc);
         }
         if (wp_status st = op_phi(p, op, xbc, pv, grid, s)) return st;                        // Phi xb
         hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, v2, pv, y, M, s2, acc);
@@ -697,8 +718,9 @@ static dim3 sara_tiles(int L) {
     return dim3((unsigned)((H / t) * (H / t)), 8);
 }
 
-// c = Psi^T x; tmp holds 8 N^2 floats (the approximations between levels, one image per basis)
-wp_status launch_sara_analysis(const wp_plan *p, int levels, const float *x, float *c, float *tmp, hipStream_t s) {
+// the eight wavelet analyses of x into c_1 .. c_8 (unscaled); tmp holds 8 N^2 floats
+static wp_status sara_analysis_levels(const wp_plan *p, int levels, const float *x, float *c, float *tmp,
+                                      hipStream_t s) {
     if (wp_status st = check_sara_levels(p, levels)) return st;
     const FiltSet *fs = filter_set(true);
     if (!fs) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
@@ -713,12 +735,20 @@ wp_status launch_sara_analysis(const wp_plan *p, int levels, const float *x, flo
         src = ll;
         in_zs = N2;
     }
+    return WP_OK;
+}
+
+// c = Psi^T x; tmp holds 8 N^2 floats (the approximations between levels, one image per basis)
+wp_status launch_sara_analysis(const wp_plan *p, int levels, const float *x, float *c, float *tmp, hipStream_t s) {
+    if (wp_status st = sara_analysis_levels(p, levels, x, c, tmp, s)) return st;
+    const int64_t N2 = (int64_t)p->N * p->N;
     hipLaunchKernelGGL(k_sara_scale, blocks_for(N2), dim3(NT), 0, s, x, c, N2);
     return wp_check_launch("sara_analysis");
 }
 
-// x = Psi c; tmp holds 16 N^2 floats (per basis: the coarser levels' results, then its synthesis)
-wp_status launch_sara_synthesis(const wp_plan *p, int levels, const float *c, float *x, float *tmp, hipStream_t s) {
+// the eight wavelet syntheses of c_1 .. c_8 into tmp + 8 N^2 (one image per basis); tmp holds 16 N^2
+// floats (per basis: the coarser levels' results, then its synthesis)
+static wp_status sara_synthesis_levels(const wp_plan *p, int levels, const float *c, float *tmp, hipStream_t s) {
     if (wp_status st = check_sara_levels(p, levels)) return st;
     const FiltSet *fs = filter_set(true);
     if (!fs) return wp_set_error(WP_EHIP, "Daubechies filter construction failed");
@@ -731,6 +761,13 @@ wp_status launch_sara_synthesis(const wp_plan *p, int levels, const float *c, fl
         hipLaunchKernelGGL(k_dwt2_inv, sara_tiles(L), dim3(DNT), 0, s, coef, llin, out, N, L, *fs);
         llin = out;
     }
+    return WP_OK;
+}
+
+// x = Psi c; tmp holds 16 N^2 floats
+wp_status launch_sara_synthesis(const wp_plan *p, int levels, const float *c, float *x, float *tmp, hipStream_t s) {
+    if (wp_status st = sara_synthesis_levels(p, levels, c, tmp, s)) return st;
+    const int64_t N2 = (int64_t)p->N * p->N;
     hipLaunchKernelGGL(k_sara_sum, blocks_for(N2), dim3(NT), 0, s, c, tmp + 8 * N2, x, N2);
     return wp_check_launch("sara_synthesis");
 }
@@ -738,8 +775,7 @@ wp_status launch_sara_synthesis(const wp_plan *p, int levels, const float *c, fl
 int64_t sara_workspace_bytes(const wp_plan *p, int64_t M) {
     const int64_t N2 = (int64_t)p->N * p->N, G2 = (int64_t)p->Ng * p->Ng;
     auto al = [](int64_t b) { return (b + 255) & ~(int64_t)255; };
-    return al(8 * G2) + 3 * al(4 * 9 * N2) + 2 * al(4 * N2) + al(4 * 16 * N2) + 2 * al(8 * N2) + 2 * al(8 * M) +
-           al(64);
+    return al(8 * G2) + 3 * al(4 * 9 * N2) + al(4 * N2) + al(4 * 16 * N2) + 2 * al(8 * N2) + 2 * al(8 * M) + al(64);
 }
 
 // Reweighted analysis over the SARA dictionary: `rounds` primal-dual solves of `iters` iterations
@@ -757,7 +793,6 @@ wp_status launch_sara_solve(const wp_plan *p, const wp_operator &op, const float
     float *v1 = (float *)take(4 * NC);
     float *tc = (float *)take(4 * NC);
     float *w = (float *)take(4 * NC);
-    float *t1 = (float *)take(4 * N2);
     float *xb = (float *)take(4 * N2);
     float *tmp = (float *)take(4 * 16 * N2);
     float2 *t2 = (float2 *)take(8 * N2);
@@ -787,12 +822,15 @@ wp_status launch_sara_solve(const wp_plan *p, const wp_operator &op, const float
         }
         WP_HIP(hipMemsetAsync(v1, 0, 4 * NC, s));
         WP_HIP(hipMemsetAsync(v2, 0, 8 * M, s));
+        // the primal step joins the synthesis's final sum and the dual step the analysis's final
+        // scaling (the same arithmetic as the separate kernels); Phi^H v2 goes first (independent)
         for (int it = 0; it < iters; ++it) {
-            if (wp_status st = launch_sara_synthesis(p, levels, v1, t1, tmp, s)) return st;     // Psi v1
             if (wp_status st = op_phiT(p, op, v2, t2, grid, s)) return st;                      // Phi^H v2
-            hipLaunchKernelGGL(k_primal, blocks_for(N2), dim3(NT), 0, s, x, t1, t2, xb, xbc, N2, tau, acc);
-            if (wp_status st = launch_sara_analysis(p, levels, xb, tc, tmp, s)) return st;      // Psi^T xb
-            hipLaunchKernelGGL(k_dual1w, blocks_for(NC), dim3(NT), 0, s, v1, tc, w, NC, s1);
+            if (wp_status st = sara_synthesis_levels(p, levels, v1, tmp, s)) return st;         // Psi v1
+            hipLaunchKernelGGL(k_sara_sum_primal, blocks_for(N2), dim3(NT), 0, s, v1, tmp + 8 * N2, x, t2, xb, xbc,
+                               N2, tau, acc);
+            if (wp_status st = sara_analysis_levels(p, levels, xb, tc, tmp, s)) return st;      // Psi^T xb
+            hipLaunchKernelGGL(k_sara_scale_dual, blocks_for(N2), dim3(NT), 0, s, xb, tc, v1, w, N2, s1);
             if (wp_status st = op_phi(p, op, xbc, pv, grid, s)) return st;                      // Phi xb
             hipLaunchKernelGGL(k_ball_norm, blocks_reduce(M), dim3(NT), 0, s, v2, pv, y, M, s2, acc);
             hipLaunchKernelGGL(k_dual2, blocks_for(M), dim3(NT), 0, s, v2, pv, y, M, s2, eps, acc);
