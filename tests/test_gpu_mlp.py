@@ -70,6 +70,30 @@ def test_gradients_match_oracle(mlp):
         assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), k
 
 
+def test_forward_and_gradients_match_fp64_network(mlp):
+    """Against the plain FP64 network (no rounding model): the bfloat16 products with FP32
+    accumulation stay within P12's 1e-2 relative error, outputs and every parameter's gradient."""
+    n = 512
+    p = _set(mlp, 15)
+    X = _feat(n, 16)
+    T = np.random.default_rng(17).normal(size=(n, 2048)).astype(np.float32) * 0.05
+    net = S.from_packed(p)
+    out = mlp.forward(_dev(X.ravel())).cpu().numpy().reshape(n, -1)
+    o, cache = S.forward(net, X.astype(np.float64))
+    e_out = np.linalg.norm(out - o) / np.linalg.norm(o)
+    g_gpu, loss = mlp.gradients(_dev(X.ravel()), _dev(T.ravel()))
+    l_ref, dO = S.mse_loss(o, T.astype(np.float64))
+    g_ref = S.backward(net, cache, dO)
+    g_dev = S.from_packed(g_gpu.cpu().numpy())
+    e_grad = {k: float(np.linalg.norm(getattr(g_dev, k) - g_ref[k]) / np.linalg.norm(g_ref[k])) for k in net.NAMES}
+    print(f"fp64 network: output rel err {e_out:.2e}, loss rel err {abs(loss - l_ref) / l_ref:.2e}, "
+          f"gradients {e_grad}", flush=True)
+    assert e_out < 1e-2
+    assert abs(loss - l_ref) < 1e-2 * l_ref
+    for k, e in e_grad.items():
+        assert e < 1e-2, k
+
+
 def test_adam_step_matches_oracle(mlp):
     n = 256
     p = _set(mlp, 6)

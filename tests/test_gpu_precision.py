@@ -1,23 +1,31 @@
-"""Precision form (N = 1024, M = 4 194 304): complex64 taps vs 4-byte taps (bfloat16 pairs, and int16
-pairs with one FP32 scale per row) with FP32 accumulation; operator error against the FP64 oracle on a
-seeded 4096-visibility subset at full size.
+"""Precision form (N = 1024, M = 4 194 304) at full size, in the launch forms the benchmark times:
+complex64 taps against 4-byte taps (bfloat16 pairs, and int16 pairs with one FP32 scale per row),
+FP32 accumulation, operator error against the FP64 oracle on a seeded 4096-visibility subset.
 
-Tolerances: complex64 1e-5 and 4-byte taps 1e-3 (the precision form's targets).  bfloat16 keeps 8
-significant bits, so its unit roundoff 2^-9 bounds the relative error of every stored tap; its Phi
-meets 1e-3 but its adjoint, driven by random visibilities, lands at about 1.05e-3, so the bfloat16
-adjoint is held to 2^-9 and the int16 block-floating-point taps carry the 1e-3 target.
+G is built with its transposed copy and its factor records, as the benchmark builds it, so Phi is
+checked from the stored taps and from the factor records, and Phi^H through the transposed-copy
+gather (the per-cell form at this density: cells average about 900 entries, and the 3.8e9 entries
+put most offsets past 2^31) and through the tiled scatter.
+
+Tolerances:
+* complex64 taps: 1e-5 (the FP32 target of the precision form);
+* int16 block floating point: 1e-3 (the target for 4-byte taps), both directions;
+* bfloat16 taps: the rounding model of tests/helpers.py bounds the expected relative error of the
+  rounded taps from the oracle's own rows and vector (1.5 x that bound, plus 1e-5 for the FP32
+  arithmetic).  Against the 1e-3 target, Phi meets it; Phi^H (random visibilities, incoherent sums
+  per cell) lands at about 1.05e-3 and misses it, a stated result: that check is an expected failure.
 """
 import json
-import multiprocessing as mp
 import os
 
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 import synth
 from oracle import wproj
 from oracle.wproj import Setup
+
+from helpers import bf16_rms_bound, oracle_rows, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -25,56 +33,105 @@ torch = pytest.importorskip("torch")
 import paper_1307_3424_amd as wp  # noqa: E402
 
 ROWS = 4096
+TAPS = {"c64": wp.WP_TAPS_C64, "bf16": wp.WP_TAPS_BF16, "i16": wp.WP_TAPS_I16}
+_ref = {}
+_res = {}
 
 
-def relerr(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
-
-
-def oracle_rows(u, v, w, E, s, rows, workers):
-    chunks = np.array_split(rows, workers * 4)
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        parts = pool.map(wproj.build_rows_csr_parts, [(u[c], v[c], w[c], E, s, None) for c in chunks if c.size])
-    return sp.vstack([sp.csr_matrix((d, i, p), shape=(n, s.Ng * s.Ng)) for p, i, d, n in parts]).tocsr()
-
-
-def test_precision_form_operator_error():
+def reference():
+    """Oracle rows of the subset, y = G X on them, x = Phi^H of a y that is non-zero on them only,
+    and the bfloat16 rounding-model bounds (computed once per module)."""
+    if _ref:
+        return _ref
     wl = synth.workload(2)
     x, u, v, w = synth.workload_inputs(wl)
     s = Setup(N=wl.N, L=wl.L)
     rows = synth.subset_rows(wl.M, ROWS, synth.rng_for(wl.seed, "subset"))
-    workers = max(1, min(16, os.cpu_count() or 1))
-    print(f"precision: oracle rows {ROWS} on {workers} processes", flush=True)
-    Go = oracle_rows(u, v, w, wl.E, s, rows, workers)
+    print(f"precision: oracle rows {ROWS}", flush=True)
+    Go = oracle_rows(u, v, w, wl.E, s, rows)
     X = wproj.grid_forward(x, s).ravel()
     y_ref = Go @ X
     ys = synth.random_complex(ROWS, synth.rng_for(wl.seed, "y", 4))
     x_ref = wproj.phi_adjoint(Go, ys, s)
-    print("precision: oracle done, building G on the GPU", flush=True)
+    a = wproj.apodisation(s)
+    # Phi^H: the cells' rounding errors are independent, so after the unnormalised inverse FFT each
+    # image pixel carries their summed variance, times its apodisation factor squared
+    b_grid = bf16_rms_bound(Go, ys, True, np.ones(1))
+    b_phiT = b_grid * float(np.linalg.norm(a)) / float(np.linalg.norm(x_ref))
+    b_phi = bf16_rms_bound(Go, X, False, y_ref)
+    _ref.update(wl=wl, x=x, u=u, v=v, w=w, rows=rows, y_ref=y_ref, ys=ys, x_ref=x_ref,
+                bound={"phi": b_phi, "phiT": b_phiT})
+    print(f"precision: bfloat16 rounding-model bounds {_ref['bound']}", flush=True)
+    return _ref
+
+
+def results(name):
+    """Operator errors of one tap type, every launch form (computed once per module)."""
+    if name in _res:
+        return _res[name]
+    r = reference()
+    wl = r["wl"]
     plan = wp.Plan(wl.N, wl.L)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
-    ud, vd, wd = t(u), t(v), t(w)
-    xd = t(x.astype(np.complex64).ravel())
+    ud, vd, wd = t(r["u"]), t(r["v"]), t(r["w"])
+    xd = t(r["x"].astype(np.complex64).ravel())
     yfull = np.zeros(wl.M, dtype=np.complex64)
-    yfull[rows] = ys
+    yfull[r["rows"]] = r["ys"]
     yfd = t(yfull)
-    res = {}
-    for name, taps in (("c64", wp.WP_TAPS_C64), ("bf16", wp.WP_TAPS_BF16), ("i16", wp.WP_TAPS_I16)):
-        G = wp.build_G(plan, ud, vd, wd, wl.E, taps=taps, transpose=False)
-        G.use_transpose = False
-        y = wp.apply_Phi(plan, G, xd).cpu().numpy()
+    print(f"precision {name}: building G (transposed copy, factor records)", flush=True)
+    G = wp.build_G(plan, ud, vd, wd, wl.E, taps=TAPS[name], transpose=True, factors=True)
+    torch.cuda.synchronize()
+    res = {"nnz": G.nnz, "G_bytes": G.nbytes(), "max_offset": int(G.tcolptr[-1].item())}
+    rows = r["rows"]
+    for form, fac in (("factors", True), ("stored", False)):
+        G.use_factors = fac
+        y = wp.apply_Phi(plan, G, xd).cpu().numpy()[rows]
+        res[f"phi_{form}"] = relerr(y, r["y_ref"])
+    G.use_factors = True
+    for form, tr in (("gather", True), ("scatter", False)):
+        G.use_transpose = tr
         xa = wp.apply_PhiT(plan, G, yfd).cpu().numpy().reshape(wl.N, wl.N)
-        per = np.abs(y[rows] - y_ref) / np.abs(y_ref)
-        res[name] = {"phi_rel_err": relerr(y[rows], y_ref), "phiT_rel_err": relerr(xa, x_ref),
-                     "per_vis_median": float(np.median(per)), "per_vis_p99": float(np.quantile(per, 0.99)),
-                     "nnz": G.nnz, "G_bytes": G.nbytes()}
-        print(f"precision {name}: {res[name]}", flush=True)
-        del G
-        torch.cuda.empty_cache()
+        res[f"phiT_{form}"] = relerr(xa, r["x_ref"])
+    print(f"precision {name}: {res}", flush=True)
+    del G
+    torch.cuda.empty_cache()
+    plan.close()
+    _res[name] = res
     os.makedirs("gpurun_out", exist_ok=True)
     with open("gpurun_out/precision_form.json", "w") as f:
-        json.dump({"workload": wl.name, "rows": ROWS, **res}, f)
-    assert res["c64"]["phi_rel_err"] < 1e-5 and res["c64"]["phiT_rel_err"] < 1e-5
-    assert res["i16"]["phi_rel_err"] < 1e-3 and res["i16"]["phiT_rel_err"] < 1e-3
-    assert res["bf16"]["phi_rel_err"] < 1e-3 and res["bf16"]["phiT_rel_err"] < 2.0 ** -9
+        json.dump({"workload": wl.name, "rows": ROWS, "bf16_model_bound": r["bound"], **_res}, f)
+    return res
+
+
+def test_precision_form_complex64():
+    res = results("c64")
+    assert res["max_offset"] > 2 ** 31                 # entries past the int32 range are read
+    for k in ("phi_factors", "phi_stored", "phiT_gather", "phiT_scatter"):
+        assert res[k] < 1e-5, k
+
+
+def test_precision_form_int16_block_float():
+    res = results("i16")
+    for k in ("phi_factors", "phi_stored", "phiT_gather", "phiT_scatter"):
+        assert res[k] < 1e-3, k
+
+
+def test_precision_form_bfloat16_within_rounding_model():
+    res = results("bf16")
+    bound = reference()["bound"]
+    # the factor records hold complex float factors: that form of Phi is not rounded to bfloat16
+    assert res["phi_factors"] < 1e-5
+    assert res["phi_stored"] < 1.5 * bound["phi"] + 1e-5
+    for k in ("phiT_gather", "phiT_scatter"):
+        assert res[k] < 1.5 * bound["phiT"] + 1e-5, k
+
+
+def test_precision_form_bfloat16_phi_meets_target():
+    assert results("bf16")["phi_stored"] < 1e-3
+
+
+@pytest.mark.xfail(reason="bfloat16 taps: Phi^H measures about 1.05e-3 against the 1e-3 target (a stated miss; "
+                          "the int16 block-floating-point taps meet it)", strict=False)
+def test_precision_form_bfloat16_adjoint_target():
+    res = results("bf16")
+    assert res["phiT_gather"] < 1e-3 and res["phiT_scatter"] < 1e-3

@@ -152,3 +152,32 @@ def test_douglas_rachford_matches_oracle(levels):
     print(f"DR SNR_out gpu {metrics.snr_out(x, xg):.3f} dB, oracle {metrics.snr_out(x, xr):.3f} dB", flush=True)
     assert relerr(xg, xr) < 1e-3
     assert abs(metrics.snr_out(x, xg) - metrics.snr_out(x, xr)) < 0.05
+
+
+def test_solve_plain_form_matches_oracle_snr():
+    """The plain 256-pixel form's 500-iteration solve against the FP64 oracle's solve of the same
+    problem (tests/golden/solve_plain256.json, written by make_solve_plain256.py from oracle/ only):
+    the same sky, noise draw, ball radius and power-iteration start; SNR_out within 0.1 dB."""
+    import json
+    import os
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "solve_plain256.json")))
+    wl = synth.workload(1)
+    x, u, v, w = synth.workload_inputs(wl)
+    print(f"solve: {wl.name} {wl.iters} iterations against the oracle's SNR {ref['snr_out_db']:.3f} dB", flush=True)
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E)
+    y0 = wp.apply_Phi(plan, G, c64(x)).cpu().numpy().astype(np.complex128)
+    sig = metrics.noise_sigma(y0, wl.snr_in_db)
+    assert abs(sig - ref["sigma_n"]) < 1e-5 * ref["sigma_n"]          # same data as the oracle's
+    y = y0 + synth.noise(wl.M, sig, synth.rng_for(wl.seed, "noise"))
+    eps = metrics.l2_ball_radius(sig, wl.M)
+    x0 = synth.rng_for(wl.seed, "x").normal(size=(wl.N, wl.N))
+    nu = wp.power_norm2(plan, G, f32(x0), 50)
+    assert abs(nu - ref["nu"]) < 1e-4 * ref["nu"]
+    G.order = wp.WP_ORDER_SORTED
+    yd = wp.to_sorted(G, c64(y))
+    xg = wp.solve(plan, G, yd, eps, nu, wl.iters).cpu().numpy().reshape(wl.N, wl.N)
+    snr_g = metrics.snr_out(x, xg)
+    print(f"SNR_out gpu {snr_g:.3f} dB, oracle {ref['snr_out_db']:.3f} dB", flush=True)
+    assert abs(snr_g - ref["snr_out_db"]) < 0.1
+    assert np.all(xg >= 0)
