@@ -387,6 +387,31 @@ wp_status wp_mlp_box_targets(const wp_plan *plan, const wp_G *G, const double *u
 wp_status wp_mlp_row_errors(const wp_plan *plan, wp_mlp *mlp, const wp_G *G, const double *u,
                             const double *v, const float *feat, float *eps, void *stream);
 
+/* Run-time per-row check without exact rows (the energy rule of Section 3.2 applied to the
+ * network's rows).  The check lattice holds nodes over (w, du, dv): node i = (iw nd + iv) nd + iu at
+ * w = w_top iw / (nw - 1) (w_top: the network's feature scale) and du = -1/2 + iu / (nd - 1) cells
+ * from the grid's centre cell (dv likewise; the last offset node sits 2^-20 cells below +1/2, so it
+ * keeps the centre cell).  nw, nd >= 2, at most 2^26 nodes.
+ * wp_mlp_lattice_coords writes the nodes' u, v, w (device float64 [nw nd nd] each, wavelengths).
+ * wp_mlp_check_table takes G, the exact complex64 rows of those nodes (built from those
+ * coordinates, caller order = node order), and the nodes' features, and writes table (device
+ * float32 [2 nw nd nd]): table[i] = the network's row error ||t_i - g_i||^2 / ||g_i||^2 at node i
+ * (as wp_mlp_row_errors) and table[nw nd nd + i] = the node's kept energy ||g_i||^2.
+ * wp_mlp_row_check estimates the error of n network rows from the table alone, with no exact row:
+ * est[k] = max(the largest node error of the lattice cell holding row k's (w, du, dv),
+ * (| ||t_k|| - sqrt(K_k) | / sqrt(K_k))^2) with K_k the kept energy interpolated trilinearly
+ * between the cell's nodes (the second term bounds the error from below when K_k is the row's
+ * kept energy, by the reverse triangle inequality); +infinity outside the lattice (w beyond the
+ * trained range), not a number if a node error is.  feat: device float32 [3n] (wp_mlp_features),
+ * est: device float32 [n], both in the caller's order.  Runs the network in chunks of max_batch rows
+ * (overwrites its activation buffers).  Rows with est > tol then fall back (wp_surrogate_create). */
+wp_status wp_mlp_lattice_coords(const wp_plan *plan, const wp_mlp *mlp, int nw, int nd, double *u, double *v,
+                                double *w, void *stream);
+wp_status wp_mlp_check_table(const wp_plan *plan, wp_mlp *mlp, const wp_G *G, int nw, int nd, const double *u,
+                             const double *v, const float *feat, float *table, void *stream);
+wp_status wp_mlp_row_check(const wp_plan *plan, wp_mlp *mlp, int nw, int nd, const float *table, int64_t n,
+                           const float *feat, float *est, void *stream);
+
 /* ----------------------------------------------------------------------------------------
  * Surrogate operator.  Rows of visibilities whose per-row energy error (wp_mlp_row_errors)
  * is at most tol come from the surrogate network; the others ("fallback") from an exact G

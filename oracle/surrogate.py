@@ -349,3 +349,56 @@ def from_packed(p, w_top: float = 1.0, s_out: float = 1.0, H: int = HIDDEN, n_ou
 
 def to_packed(net: Net) -> np.ndarray:
     return np.concatenate([getattr(net, k).ravel() for k in net.NAMES])
+
+
+# ----------------------------------------------------------------------------- run-time check
+
+def lattice_coords(nw: int, nd: int, w_top: float, s):
+    """(u, v, w) of the check lattice's nodes, node i = (iw nd + iv) nd + iu: w = w_top iw / (nw - 1),
+    offsets -1/2 + j / (nd - 1) cells from the centre cell, the last one 2^-20 cells below +1/2 (so
+    that it keeps the centre cell as its nearest)."""
+    cell = geo.cell_size(s.N, s.L, s.sigma)
+    off = -0.5 + np.arange(nd) / (nd - 1.0)
+    off[-1] = 0.5 - 2.0 ** -20
+    iw, iv, iu = np.meshgrid(np.arange(nw), np.arange(nd), np.arange(nd), indexing="ij")
+    return off[iu.ravel()] * cell, off[iv.ravel()] * cell, w_top * iw.ravel() / (nw - 1.0)
+
+
+def check_table(net: Net, E: float, nw: int, nd: int, s, q=_ident):
+    """(node errors, node kept energies) of the check lattice: the network's row error against the
+    exact sparsified row of every node (Section 3.2's energy rule), and that row's kept energy."""
+    from .wproj import build_rows
+    u, v, w = lattice_coords(nw, nd, net.w_top, s)
+    G = build_rows(u, v, w, E, s)
+    eps = row_errors(net, u, v, w, G, s, q)
+    K = np.asarray(G.multiply(G.conj()).sum(axis=1)).ravel().real
+    return eps, K
+
+
+def check_estimate(net: Net, u, v, w, table_eps, table_K, nw: int, nd: int, s, q=_ident) -> np.ndarray:
+    """Run-time estimate of each network row's error from the lattice alone (no exact row):
+    max(largest node error of the lattice cell holding (w, du, dv),
+        (| ||t|| - sqrt(K) | / sqrt(K))^2), K = trilinear interpolation of the nodes' kept energies
+    (the second term is the reverse triangle inequality's lower bound on ||t - g||^2 / ||g||^2 when
+    K = ||g||^2); +inf outside the lattice."""
+    cu, du, cv, dv = _cells(u, v, s)
+    t = taps(net, w, du, dv, q).reshape(len(cu), -1)
+    tn = np.sqrt(np.sum(np.abs(t) ** 2, axis=1))
+    f = features(w, du, dv, net.w_top)
+    wf = 0.5 * (f[:, 0] + 1.0) * (nw - 1)
+    uf = (0.5 * f[:, 1] + 0.5) * (nd - 1)
+    vf = (0.5 * f[:, 2] + 0.5) * (nd - 1)
+    out = np.full(len(cu), np.inf)
+    e_node = np.asarray(table_eps).reshape(nw, nd, nd)
+    K_node = np.asarray(table_K).reshape(nw, nd, nd)
+    for k in range(len(cu)):
+        if not (0 <= wf[k] <= nw - 1 and 0 <= uf[k] <= nd - 1 and 0 <= vf[k] <= nd - 1):
+            continue
+        iw, iu, iv = min(int(wf[k]), nw - 2), min(int(uf[k]), nd - 2), min(int(vf[k]), nd - 2)
+        tw, tu, tv = wf[k] - iw, uf[k] - iu, vf[k] - iv
+        corner = e_node[iw:iw + 2, iv:iv + 2, iu:iu + 2]
+        wgt = np.einsum("a,b,c->abc", [1 - tw, tw], [1 - tv, tv], [1 - tu, tu])
+        K = float(np.sum(wgt * K_node[iw:iw + 2, iv:iv + 2, iu:iu + 2]))
+        lb = (tn[k] - np.sqrt(K)) ** 2 / K if K > 0 else np.inf
+        out[k] = max(float(corner.max()), lb)
+    return out

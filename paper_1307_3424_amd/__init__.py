@@ -634,6 +634,40 @@ class Mlp:
                                        _stream(stream)), "wp_mlp_row_errors")
         return eps
 
+    def lattice_coords(self, plan: Plan, nw: int, nd: int, stream=None):
+        """wp_mlp_lattice_coords: (u, v, w) of the check lattice's nw * nd * nd nodes (float64 CUDA)."""
+        torch = _torch()
+        n = int(nw) * int(nd) * int(nd)
+        u, v, w = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(3))
+        check(load().wp_mlp_lattice_coords(plan.handle, self._h, int(nw), int(nd), _ptr(u), _ptr(v), _ptr(w),
+                                           _stream(stream)), "wp_mlp_lattice_coords")
+        return u, v, w
+
+    def check_table(self, plan: Plan, E: float, nw: int = 257, nd: int = 33, stream=None):
+        """The check lattice's table: its nodes' exact rows (wp_build_G_* on wp_mlp_lattice_coords) and
+        wp_mlp_check_table.  Returns float32 CUDA [2 nw nd nd] (node errors, then kept energies)."""
+        torch = _torch()
+        u, v, w = self.lattice_coords(plan, nw, nd, stream)
+        G = build_G(plan, u, v, w, E, transpose=False, stream=stream)
+        feat = self.features(plan, u, v, w, stream=stream)
+        table = torch.empty(2 * G.M, dtype=torch.float32, device="cuda")
+        d = G.desc()
+        check(load().wp_mlp_check_table(plan.handle, self._h, C.byref(d), int(nw), int(nd), _ptr(u), _ptr(v),
+                                        _ptr(feat), _ptr(table), _stream(stream)), "wp_mlp_check_table")
+        torch.cuda.synchronize()
+        return table
+
+    def row_check(self, plan: Plan, table, nw: int, nd: int, feat, stream=None):
+        """wp_mlp_row_check: estimated row errors (float32 CUDA [n], caller order) from the table alone."""
+        torch = _torch()
+        n = feat.numel() // 3
+        _dev_f32n(feat, 3 * n, "feat")
+        _dev_f32n(table, 2 * int(nw) * int(nd) * int(nd), "table")
+        est = torch.empty(n, dtype=torch.float32, device="cuda")
+        check(load().wp_mlp_row_check(plan.handle, self._h, int(nw), int(nd), _ptr(table), n, _ptr(feat), _ptr(est),
+                                      _stream(stream)), "wp_mlp_row_check")
+        return est
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load().wp_mlp_destroy(self._h)

@@ -83,6 +83,9 @@ SIGNATURES = {
     "wp_mlp_output_scale": ([_vp, C.POINTER(C.c_double)], _i32),
     "wp_mlp_box_targets": ([_vp, _PG, _vp, _vp, _d, _vp, _vp, _vp], _i32),
     "wp_mlp_row_errors": ([_vp, _vp, _PG, _vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_mlp_lattice_coords": ([_vp, _vp, _i32, _i32, _vp, _vp, _vp, _vp], _i32),
+    "wp_mlp_check_table": ([_vp, _vp, _PG, _i32, _i32, _vp, _vp, _vp, _vp, _vp], _i32),
+    "wp_mlp_row_check": ([_vp, _vp, _i32, _i32, _vp, _i64, _vp, _vp, _vp], _i32),
     "wp_surrogate_create": ([C.POINTER(_vp), _vp, _vp, _i64, _vp, _vp, _vp, _vp, _d, _pi64, _vp], _i32),
     "wp_surrogate_destroy": ([_vp], _i32),
     "wp_surrogate_info": ([_vp, _pi64], _i32),

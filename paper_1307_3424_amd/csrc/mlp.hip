@@ -286,7 +286,8 @@ __global__ __launch_bounds__(NTH) void k_row_errors(const float *__restrict__ o,
                                                     const int64_t *__restrict__ rowptr, const int *__restrict__ col,
                                                     const float2 *__restrict__ val, const int *__restrict__ perm,
                                                     const double *__restrict__ u, const double *__restrict__ v,
-                                                    double cell, int logNg, float s_out, float *__restrict__ eps) {
+                                                    double cell, int logNg, float s_out, float *__restrict__ eps,
+                                                    float *__restrict__ energy) {
     __shared__ float2 box[NTH / 64][BOX * BOX];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * (NTH / 64) + wv;
@@ -324,7 +325,70 @@ __global__ __launch_bounds__(NTH) void k_row_errors(const float *__restrict__ o,
     d = wave_sum(d);
     tot = wave_sum(tot);
     out = wave_sum(out);
-    if (live && lane == 0) eps[k] = tot > 0.0 ? (float)((d + out) / tot) : 0.0f;
+    if (live && lane == 0) {
+        eps[k] = tot > 0.0 ? (float)((d + out) / tot) : 0.0f;
+        if (energy) energy[k] = (float)tot;
+    }
+}
+
+// Check lattice: node i = (iw nd + iv) nd + iu at w = w_top iw / (nw - 1) and offsets du = -1/2 + iu / (nd - 1)
+// (dv likewise) from the centre cell; the last offset node sits just below +1/2, so that it keeps the
+// centre cell (at +1/2 the nearest cell would change).
+__global__ void k_lattice_coords(int nw, int nd, double w_top, double cell, double *__restrict__ u,
+                                 double *__restrict__ v, double *__restrict__ w) {
+    const int64_t i = (int64_t)blockIdx.x * NTH + threadIdx.x;
+    const int64_t n = (int64_t)nw * nd * nd;
+    if (i >= n) return;
+    const int iu = (int)(i % nd), iv = (int)((i / nd) % nd), iw = (int)(i / ((int64_t)nd * nd));
+    auto off = [nd](int j) { return j == nd - 1 ? 0.5 - 0x1p-20 : -0.5 + (double)j / (double)(nd - 1); };
+    u[i] = off(iu) * cell;
+    v[i] = off(iv) * cell;
+    w[i] = w_top * (double)iw / (double)(nw - 1);
+}
+
+// Run-time per-row check of network rows k0 .. k0 + n - 1 (caller order; outputs o of those rows), from
+// the check lattice alone (no exact row):
+//   est = max( largest node error of the lattice cell holding (w, du, dv),
+//              (| ||t|| - sqrt(K) | / sqrt(K))^2 )
+// with K the kept energy interpolated trilinearly between the cell's nodes.  The second term is a lower
+// bound of the row's error ||t - g||^2 / ||g||^2 by the reverse triangle inequality when K = ||g||^2.
+// A row outside the lattice (w beyond the trained range) or with a non-finite value gets +infinity.
+__global__ __launch_bounds__(NTH) void k_row_check(const float *__restrict__ o, int64_t k0, int n,
+                                                   const float *__restrict__ feat, const float *__restrict__ table,
+                                                   int nw, int nd, float s_out, float *__restrict__ est) {
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (NTH / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const float *oi = o + (int64_t)i * NOUT;
+    double e = 0.0;
+    for (int p = lane; p < NOUT; p += 64) e += (double)oi[p] * oi[p];
+    e = wave_sum(e);
+    if (lane != 0) return;
+    const int64_t k = k0 + i;
+    const float *f = feat + 3 * k;
+    const double wf = (0.5 * ((double)f[0] + 1.0)) * (nw - 1);
+    const double uf = (0.5 * (double)f[1] + 0.5) * (nd - 1), vf = (0.5 * (double)f[2] + 0.5) * (nd - 1);
+    float r = INFINITY;
+    if (wf >= 0.0 && wf <= (double)(nw - 1) && uf >= 0.0 && uf <= (double)(nd - 1) && vf >= 0.0 &&
+        vf <= (double)(nd - 1) && isfinite(e)) {
+        const int iw = min((int)wf, nw - 2), iu = min((int)uf, nd - 2), iv = min((int)vf, nd - 2);
+        const double tw = wf - iw, tu = uf - iu, tv = vf - iv;
+        const int64_t nodes = (int64_t)nw * nd * nd;
+        float emax = 0.0f;
+        double K = 0.0;
+        for (int c = 0; c < 8; ++c) {
+            const int a = c & 1, b = (c >> 1) & 1, d = c >> 2;
+            const int64_t node = ((int64_t)(iw + d) * nd + (iv + b)) * nd + (iu + a);
+            const float en = table[node];
+            emax = (en > emax || en != en) ? en : emax;            // a NaN node error propagates
+            K += (a ? tu : 1.0 - tu) * (b ? tv : 1.0 - tv) * (d ? tw : 1.0 - tw) * (double)table[nodes + node];
+        }
+        const double tn = (double)s_out * sqrt(e);
+        const double lb = K > 0.0 ? (tn - sqrt(K)) * (tn - sqrt(K)) / K : INFINITY;
+        r = fmaxf(emax, (float)lb);
+        if (emax != emax) r = emax;
+    }
+    est[k] = r;
 }
 
 int blocks_for(int64_t n, int per = NTH) { return (int)std::min<int64_t>((n + per - 1) / per, 65536); }
@@ -624,8 +688,11 @@ wp_status wp_mlp_box_targets(const wp_plan *p, const wp_G *G, const double *u, c
     return wp_check_launch("k_box_targets");
 }
 
-wp_status wp_mlp_row_errors(const wp_plan *p, wp_mlp *m, const wp_G *G, const double *u, const double *v,
-                            const float *feat, float *eps, void *stream) {
+}  // extern "C"
+
+namespace {
+wp_status row_errors(const wp_plan *p, wp_mlp *m, const wp_G *G, const double *u, const double *v, const float *feat,
+                     float *eps, float *energy, void *stream) {
     if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
     wp_status st = check_mlp(m);
     if (st != WP_OK) return st;
@@ -642,8 +709,61 @@ wp_status wp_mlp_row_errors(const wp_plan *p, wp_mlp *m, const wp_G *G, const do
         if ((st = wp_check_launch("k_gather_feat")) != WP_OK) return st;
         if ((st = mlp_forward(m, nr, m->xb, m->o, s)) != WP_OK) return st;
         k_row_errors<<<(nr + 3) / 4, NTH, 0, s>>>(m->o, r0, nr, G->rowptr, G->col, (const float2 *)G->val, G->perm, u,
-                                                  v, p->cell, p->logNg, (float)m->s_out, eps);
+                                                  v, p->cell, p->logNg, (float)m->s_out, eps, energy);
         if ((st = wp_check_launch("k_row_errors")) != WP_OK) return st;
+    }
+    return WP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+wp_status wp_mlp_row_errors(const wp_plan *p, wp_mlp *m, const wp_G *G, const double *u, const double *v,
+                            const float *feat, float *eps, void *stream) {
+    return row_errors(p, m, G, u, v, feat, eps, nullptr, stream);
+}
+
+wp_status wp_mlp_lattice_coords(const wp_plan *p, const wp_mlp *m, int nw, int nd, double *u, double *v, double *w,
+                                void *stream) {
+    if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
+    wp_status st = check_mlp(m);
+    if (st != WP_OK) return st;
+    if (nw < 2 || nd < 2 || (int64_t)nw * nd * nd > (1 << 26))
+        return wp_set_error(WP_EINVAL, "lattice %d x %d x %d: need nw, nd >= 2 and at most 2^26 nodes", nw, nd, nd);
+    if (!u || !v || !w) return wp_set_error(WP_EINVAL, "NULL array");
+    if (!(m->w_top > 0.0)) return wp_set_error(WP_EINVAL, "the network's w_top is not set");
+    const int64_t n = (int64_t)nw * nd * nd;
+    k_lattice_coords<<<(int)((n + NTH - 1) / NTH), NTH, 0, (hipStream_t)stream>>>(nw, nd, m->w_top, p->cell, u, v, w);
+    return wp_check_launch("k_lattice_coords");
+}
+
+wp_status wp_mlp_check_table(const wp_plan *p, wp_mlp *m, const wp_G *G, int nw, int nd, const double *u,
+                             const double *v, const float *feat, float *table, void *stream) {
+    if (!G) return wp_set_error(WP_EINVAL, "G is NULL");
+    if (nw < 2 || nd < 2 || G->M != (int64_t)nw * nd * nd)
+        return wp_set_error(WP_EINVAL, "G->M = %lld is not the lattice's %d x %d x %d nodes", (long long)G->M, nw, nd,
+                            nd);
+    if (!table) return wp_set_error(WP_EINVAL, "table is NULL");
+    return row_errors(p, m, G, u, v, feat, table, table + G->M, stream);
+}
+
+wp_status wp_mlp_row_check(const wp_plan *p, wp_mlp *m, int nw, int nd, const float *table, int64_t n,
+                           const float *feat, float *est, void *stream) {
+    if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
+    wp_status st = check_mlp(m);
+    if (st != WP_OK) return st;
+    if (nw < 2 || nd < 2 || (int64_t)nw * nd * nd > (1 << 26))
+        return wp_set_error(WP_EINVAL, "lattice %d x %d x %d: need nw, nd >= 2 and at most 2^26 nodes", nw, nd, nd);
+    if (n < 0) return wp_set_error(WP_EINVAL, "n = %lld", (long long)n);
+    if (n == 0) return WP_OK;
+    if (!table || !feat || !est) return wp_set_error(WP_EINVAL, "NULL array");
+    hipStream_t s = (hipStream_t)stream;
+    for (int64_t k0 = 0; k0 < n; k0 += m->max_batch) {
+        const int nr = (int)std::min<int64_t>(m->max_batch, n - k0);
+        if ((st = mlp_forward(m, nr, feat + 3 * k0, m->o, s)) != WP_OK) return st;
+        k_row_check<<<(nr + 3) / 4, NTH, 0, s>>>(m->o, k0, nr, feat, table, nw, nd, (float)m->s_out, est);
+        if ((st = wp_check_launch("k_row_check")) != WP_OK) return st;
     }
     return WP_OK;
 }

@@ -1,0 +1,200 @@
+"""The learned surrogate end to end on the GPU, against the FP64 oracle:
+
+* the run-time row check (check lattice table and per-row estimates, no exact row at run time)
+  against the oracle's check on its own lattice rows;
+* the surrogate operator against the oracle's plain FP64 network (no rounding model), to P12's 1e-2;
+* a reduced-scale form of the learned workload: the network trained on the GPU on exact rows the
+  builder makes, the run-time check picking network rows with no exact G, and what the trained network
+  gains over the method without it (the exact operator, and the untrained network that falls back on
+  every row): the share of rows needing no stored G, the bytes per visibility, the surrogate operator's
+  error against the oracle's exact operator, and an equal reconstruction SNR (within 0.1 dB).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import metrics, surrogate as S, wproj
+from oracle.wproj import Setup
+
+from helpers import oracle_rows, relerr
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_1307_3424_amd as wp  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _small(M, seed, support=24, N=64):
+    L = synth.fov_L()
+    rng = np.random.default_rng(seed)
+    B = N / (2 * L)
+    u, v = rng.uniform(-B, B, M), rng.uniform(-B, B, M)
+    w_top = synth.configs.w_for_support(support, 4, L)
+    w = rng.uniform(0, 1.2 * w_top, M)          # a sixth of them beyond the trained w range
+    return L, u, v, w, w_top
+
+
+def test_row_check_matches_oracle():
+    N, M, nw, nd, E = 64, 300, 5, 5, 0.99
+    L, u, v, w, w_top = _small(M, 31)
+    plan = wp.Plan(N, L)
+    mlp = wp.Mlp(max_batch=512)
+    s_out = 0.02
+    p = synth.mlp_init(32)
+    mlp.set_params(p, w_top, s_out)
+    table = mlp.check_table(plan, E, nw, nd).cpu().numpy()
+    s = Setup(N=N, L=L)
+    net = S.from_packed(p, w_top=w_top, s_out=s_out)
+    eps_ref, K_ref = S.check_table(net, E, nw, nd, s, q=S.round_bf16)
+    n = nw * nd * nd
+    # node errors: the network's bfloat16 products (rounding model of the oracle's network) against
+    # the same rows; kept energies: FP32 taps against FP64 (relative 1e-6)
+    np.testing.assert_allclose(table[:n], eps_ref, rtol=2e-3)
+    np.testing.assert_allclose(table[n:], K_ref, rtol=1e-5)
+    feat = mlp.features(plan, _dev(u), _dev(v), _dev(w))
+    est = mlp.row_check(plan, _dev(table), nw, nd, feat).cpu().numpy()
+    est_ref = S.check_estimate(net, u, v, w, eps_ref, K_ref, nw, nd, s, q=S.round_bf16)
+    assert np.array_equal(np.isinf(est), np.isinf(est_ref)) and np.isinf(est).sum() > 10
+    fin = np.isfinite(est_ref)
+    np.testing.assert_allclose(est[fin], est_ref[fin], rtol=5e-3)
+    mlp.close()
+    plan.close()
+
+
+def test_surrogate_operator_matches_fp64_network():
+    """The surrogate operator (bfloat16 products, FP32 accumulation) against the oracle's plain FP64
+    network and FP64 products: P12's 1e-2, both directions."""
+    N, M = 64, 2000
+    L, u, v, w, w_top = _small(M, 33, N=N)
+    w = np.minimum(w, w_top)
+    plan = wp.Plan(N, L)
+    mlp = wp.Mlp(max_batch=1024)
+    s_out = wp.Mlp.output_scale(plan)
+    p = synth.mlp_init(34)
+    mlp.set_params(p, w_top, s_out)
+    net = S.from_packed(p, w_top=w_top, s_out=s_out)
+    s = Setup(N=N, L=L)
+    sur = wp.Surrogate(plan, mlp, _dev(u), _dev(v), _dev(w))
+    slot = sur.slots().cpu().numpy()
+    x = synth.sky(N, 4, 6, np.random.default_rng(35))
+    y = sur.apply_Phi(_dev(x.astype(np.complex64).ravel())).cpu().numpy()
+    y_ref = S.phi_s(net, u, v, w, x, s)[slot]
+    e_phi = relerr(y, y_ref)
+    r = synth.random_complex(M, np.random.default_rng(36))
+    xa = sur.apply_PhiT(_dev(r[slot].astype(np.complex64))).cpu().numpy().reshape(N, N)
+    e_phiT = relerr(xa, S.phi_s_adjoint(net, u, v, w, r, s))
+    print(f"surrogate vs FP64 network: Phi {e_phi:.2e}, Phi^H {e_phiT:.2e}", flush=True)
+    assert e_phi < 1e-2 and e_phiT < 1e-2
+    sur.close()
+    mlp.close()
+    plan.close()
+
+
+TRAIN_ROWS = 200_000
+EPOCHS = 300
+TOL = 1e-3
+NW, ND = 257, 33
+
+
+def test_trained_surrogate_gain_at_the_plain_form():
+    wl = synth.workload(1)
+    x, u, v, w = synth.workload_inputs(wl)
+    dev = torch.device("cuda")
+    plan = wp.Plan(wl.N, wl.L)
+    s_out = wp.Mlp.output_scale(plan)
+    # ---- training on exact rows the builder makes
+    tu, tv, tw = (_dev(a) for a in synth.training_positions(wl, TRAIN_ROWS, synth.rng_for(wl.seed, "train")))
+    Gt = wp.build_G(plan, tu, tv, tw, wl.E, transpose=False)
+    mlp = wp.Mlp(max_batch=8192)
+    mlp.set_params(synth.mlp_init(wl.seed), wl.w_top, s_out)
+    T, lost = mlp.box_targets(plan, Gt, tu, tv, s_out)
+    assert float(lost.max()) == 0.0                  # the kept sets fit the 32 x 32 box
+    ft = mlp.features(plan, tu, tv, tw)
+    del Gt
+    # the method without the trained network: the initial network serves no row
+    ud, vd, wd = _dev(u), _dev(v), _dev(w)
+    feat = mlp.features(plan, ud, vd, wd)
+    est0 = mlp.row_check(plan, mlp.check_table(plan, wl.E, NW, ND), NW, ND, feat)
+    served0 = float((est0 <= TOL).float().mean())
+    print(f"train: {TRAIN_ROWS} exact rows, {EPOCHS} passes", flush=True)
+    hist = mlp.train(ft, T, 8192, EPOCHS, 2e-3)
+    assert hist[-1] < 0.05 * hist[0]
+    del T, ft
+    # ---- run-time check from the lattice alone
+    table = mlp.check_table(plan, wl.E, NW, ND)
+    est = mlp.row_check(plan, table, NW, ND, feat)
+    served = est <= TOL
+    frac = float(served.float().mean())
+    # true errors of every row, from the exact rows (a measurement here, not part of the check)
+    G = wp.build_G(plan, ud, vd, wd, wl.E)
+    eps_true = mlp.row_errors(plan, G, ud, vd, feat)
+    false_accept = float((eps_true[served] > TOL).float().mean()) if frac > 0 else 0.0
+    worst = float(eps_true[served].max()) if frac > 0 else 0.0
+    print(f"check: {frac:.1%} network rows (untrained {served0:.1%}); served rows over tol {false_accept:.2%}, "
+          f"worst {worst:.2e}", flush=True)
+    # ---- surrogate operator with exact fallback rows
+    sur = wp.Surrogate(plan, mlp, ud, vd, wd, eps=est, tol=TOL)
+    Gf = None
+    if sur.Mf:
+        fu, fv, fw = sur.fallback_coords()
+        Gf = wp.build_G(plan, fu, fv, fw, wl.E)
+    slot = sur.slots().cpu().numpy()
+    inv = np.empty_like(slot)
+    inv[slot] = np.arange(slot.size)
+    # against the oracle's exact operator on a seeded subset of rows
+    rows = synth.subset_rows(wl.M, 2048, synth.rng_for(wl.seed, "subset", 7))
+    s = Setup(N=wl.N, L=wl.L)
+    Go = oracle_rows(u, v, w, wl.E, s, rows)
+    y_ref = Go @ wproj.grid_forward(x, s).ravel()
+    xd = _dev(x.astype(np.complex64).ravel())
+    y_s = sur.apply_Phi(xd, Gf=Gf).cpu().numpy()[inv[rows]]
+    e_phi = relerr(y_s, y_ref)
+    yr = synth.random_complex(rows.size, synth.rng_for(wl.seed, "y", 7))
+    yfull = np.zeros(wl.M, dtype=np.complex64)
+    yfull[rows] = yr
+    xa = sur.apply_PhiT(sur.to_slots(_dev(yfull), Gf=Gf), Gf=Gf).cpu().numpy().reshape(wl.N, wl.N)
+    e_phiT = relerr(xa, wproj.phi_adjoint(Go, yr, s))
+    # bytes per visibility: the surrogate keeps a network row's last hidden layer (256 bfloat16)
+    # and the fallback rows' G; the exact form keeps every row's taps and their transposed copy
+    sur_bytes = sur.Ms * 512 + (Gf.nbytes() if Gf is not None else 0)
+    exact_bytes = G.nbytes()
+    # ---- reconstruction from the same data with each operator
+    G.order = wp.WP_ORDER_SORTED
+    y0 = wp.apply_Phi(plan, G, xd)
+    sig = metrics.noise_sigma(wp.to_caller(G, y0).cpu().numpy().astype(np.complex128), wl.snr_in_db)
+    y_meas = wp.to_caller(G, y0) + _dev(synth.noise(wl.M, sig, synth.rng_for(wl.seed, "noise")).astype(np.complex64))
+    eps_ball = metrics.l2_ball_radius(sig, wl.M)
+    x0 = _dev(synth.rng_for(wl.seed, "x").normal(size=wl.N * wl.N).astype(np.float32))
+    iters = 200
+    nu_e = wp.power_norm2(plan, G, x0, 50)
+    xe = wp.solve(plan, G, wp.to_sorted(G, y_meas), eps_ball, nu_e, iters).cpu().numpy().reshape(wl.N, wl.N)
+    nu_s = sur.power_norm2(x0, 50, Gf=Gf)
+    xs = torch.zeros(wl.N * wl.N, dtype=torch.float32, device=dev)
+    sur.solve(sur.to_slots(y_meas, Gf=Gf), eps_ball, nu_s, iters, 4, x=xs, Gf=Gf)
+    xs = xs.cpu().numpy().reshape(wl.N, wl.N)
+    snr_e, snr_s = metrics.snr_out(x, xe), metrics.snr_out(x, xs)
+    rec = {"train_rows": TRAIN_ROWS, "epochs": EPOCHS, "loss_first_last": [hist[0], hist[-1]],
+           "network_rows": frac, "network_rows_untrained": served0, "served_over_tol": false_accept,
+           "served_worst_error": worst, "phi_rel_err_vs_oracle": e_phi, "phiT_rel_err_vs_oracle": e_phiT,
+           "bytes_per_vis_surrogate": sur_bytes / wl.M, "bytes_per_vis_exact": exact_bytes / wl.M,
+           "snr_exact_db": snr_e, "snr_surrogate_db": snr_s}
+    print(f"surrogate gain: {rec}", flush=True)
+    os.makedirs("gpurun_out", exist_ok=True)
+    with open("gpurun_out/surrogate_gain_plain256.json", "w") as f:
+        json.dump(rec, f)
+    assert served0 == 0.0                   # without the trained network every row falls back
+    assert frac >= 0.2                      # the trained network serves a fifth of the rows or more
+    assert false_accept <= 0.02             # the lattice check rarely passes a row over tol
+    assert sur_bytes < 0.9 * exact_bytes
+    assert e_phi < 0.05 and e_phiT < 0.05   # rows within 1e-3 energy error: a few per cent per product
+    assert abs(snr_s - snr_e) < 0.1
+    sur.close()
+    mlp.close()
+    plan.close()
