@@ -232,6 +232,15 @@ wp_status wp_build_G_fill_batch(int P, const wp_plan *const *plan, const int64_t
 wp_status wp_apply_Phi(const wp_plan *plan, const wp_G *G, const void *x, void *y, void *grid,
                        void *stream);
 
+/* y = Phi x like wp_apply_Phi, for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): no grid argument, and the call allocates
+ * nothing.  Its grid workspace is a static device array of the library, one per GPU, of 2048 x 2048
+ * complex floats (32 MiB, held until the process ends); plans with Ng > 2048 return WP_ECAPACITY.
+ * The device of `stream` must be current.  Every call on a GPU uses that GPU's one array, so calls
+ * that overlap on a GPU (other streams, other threads) race; serialise them.  Nothing carries over
+ * between calls: the forward transform overwrites every cell the degrid reads. */
+wp_status wp_apply_Phi_noalloc(const wp_plan *plan, const wp_G *G, const void *x, void *y, void *stream);
+
 /* x = Phi^H y  (the adjoint; x is overwritten).  G^H y is the transposed-copy gather
  * when G->tcolptr is set, else the tiled scatter. */
 wp_status wp_apply_PhiT(const wp_plan *plan, const wp_G *G, const void *y, void *x, void *grid,

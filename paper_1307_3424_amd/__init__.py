@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (WP_APHYS_INV_N, WP_APHYS_ONE, WP_CHIRP_EXACT, WP_CHIRP_LINEAR, WP_ORDER_CALLER,
                    WP_ORDER_SORTED, WP_TAPS_BF16, WP_TAPS_C64, WP_TAPS_I16, WprojError, check, load)
 
-__all__ = ["Plan", "GMatrix", "build_G", "build_G_batch", "apply_Phi", "apply_PhiT", "grid_forward", "grid_adjoint",
+__all__ = ["Plan", "GMatrix", "build_G", "build_G_batch", "apply_Phi", "apply_Phi_noalloc", "apply_PhiT", "grid_forward", "grid_adjoint",
            "degrid", "grid_scatter", "grid_gather", "load", "WprojError", "WP_TAPS_C64", "WP_TAPS_BF16", "WP_TAPS_I16",
            "WP_CHIRP_LINEAR", "WP_CHIRP_EXACT", "WP_APHYS_ONE", "WP_APHYS_INV_N", "WP_ORDER_CALLER",
            "WP_ORDER_SORTED", "to_sorted", "to_caller", "db8_filter", "dwt2", "idwt2", "power_norm2", "solve", "dr_solve", "sara_analysis", "sara_synthesis",
@@ -256,6 +256,16 @@ def apply_Phi(plan: Plan, G: GMatrix, x, y=None, grid=None, stream=None):
     d = G.desc()
     check(load().wp_apply_Phi(plan.handle, C.byref(d), _ptr(x), _ptr(y), _ptr(grid), _stream(stream)),
           "wp_apply_Phi")
+    return y
+
+
+def apply_Phi_noalloc(plan: Plan, G: GMatrix, x, y, stream=None):
+    """wp_apply_Phi_noalloc: y = Phi x with the library's static grid (no device allocation; y given)."""
+    _dev_c64(x, plan.N * plan.N, "x")
+    _dev_c64(y, G.M, "y")
+    d = G.desc()
+    check(load().wp_apply_Phi_noalloc(plan.handle, C.byref(d), _ptr(x), _ptr(y), _stream(stream)),
+          "wp_apply_Phi_noalloc")
     return y
 
 

@@ -55,6 +55,7 @@ SIGNATURES = {
     "wp_build_G_dde_fill": ([_vp, _i64, _vp, _vp, _vp, _vp, _d, _vp, _PG, _vp], _i32),
     "wp_apply_Phi": ([_vp, _PG, _vp, _vp, _vp, _vp], _i32),
     "wp_apply_PhiT": ([_vp, _PG, _vp, _vp, _vp, _vp], _i32),
+    "wp_apply_Phi_noalloc": ([_vp, _PG, _vp, _vp, _vp], _i32),
     "wp_grid_forward": ([_vp, _vp, _vp, _vp], _i32),
     "wp_grid_adjoint": ([_vp, _vp, _vp, _vp], _i32),
     "wp_degrid": ([_vp, _PG, _vp, _vp, _vp], _i32),

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -360,6 +361,55 @@ wp_status wp_apply_Phi(const wp_plan *p, const wp_G *G, const void *x, void *y, 
     hipStream_t s = as_stream(stream);
     if (wp_status st = launch_grid_forward(p, (const float2 *)x, (float2 *)grid, s)) return st;
     return launch_degrid(p, G, (const float2 *)grid, (float2 *)y, s);
+}
+
+}  // extern "C"
+
+// Grid workspace of wp_apply_Phi_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends.  Host code never passes `scratch` itself (in host code the name is only a stand-in
+// for the symbol); it looks up each device's address once, with that device current, and passes that.
+namespace {
+constexpr int64_t NOALLOC_MAX_CELLS = (int64_t)2048 * 2048;     // Ng <= 2048: 32 MiB of complex float
+constexpr int NOALLOC_MAX_DEVICES = 64;
+__device__ __align__(256) float2 scratch[NOALLOC_MAX_CELLS];
+std::mutex g_scratch_mu;
+float2 *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+wp_status scratch_grid(float2 **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return wp_set_error(WP_EHIP, "wp_apply_Phi_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return wp_set_error(WP_EUNSUPPORTED, "wp_apply_Phi_noalloc: device %d beyond the %d supported", dev,
+                            NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return wp_set_error(WP_EHIP, "wp_apply_Phi_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (float2 *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return WP_OK;
+}
+}  // namespace
+
+extern "C" {
+
+wp_status wp_apply_Phi_noalloc(const wp_plan *p, const wp_G *G, const void *x, void *y, void *stream) {
+    if (wp_status s = check_plan(p)) return s;
+    if (wp_status s = check_G(p, G, false)) return s;
+    if (!x || (G->M > 0 && !y)) return wp_set_error(WP_EINVAL, "NULL argument");
+    if ((int64_t)p->Ng * p->Ng > NOALLOC_MAX_CELLS)
+        return wp_set_error(WP_ECAPACITY, "wp_apply_Phi_noalloc: Ng = %d exceeds the static grid of %lld cells "
+                            "(Ng <= 2048); use wp_apply_Phi with a caller grid", p->Ng, (long long)NOALLOC_MAX_CELLS);
+    float2 *grid = nullptr;
+    if (wp_status st = scratch_grid(&grid)) return st;
+    hipStream_t s = as_stream(stream);
+    // the forward transform writes every cell of the grid: nothing left by an earlier call is read
+    if (wp_status st = launch_grid_forward(p, (const float2 *)x, grid, s)) return st;
+    return launch_degrid(p, G, grid, (float2 *)y, s);
 }
 
 wp_status wp_grid_gather(const wp_plan *p, const wp_G *G, const void *y, void *grid, void *stream) {
