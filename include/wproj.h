@@ -80,7 +80,10 @@ typedef struct wp_G {
     int32_t  order;    /* WP_ORDER_CALLER: y in caller order; WP_ORDER_SORTED: y[r] is row r */
     int64_t *rowptr;   /* [M+1] device, sorted-row order, rowptr[0] = 0              */
     int32_t *col;      /* [nnz] device, flattened grid index, ascending in a row    */
-    void    *val;      /* [nnz] device, c64 or bf16 pairs                            */
+    void    *val;      /* [nnz] device, c64 or bf16 pairs.  col and val may both be NULL when the
+                          factor records below are set (the factor-record form: no stored taps and
+                          no transposed copy; Phi forms its taps from the records, the scatter
+                          form of G^H too, and wp_build_G_fill then writes only the records) */
     int32_t *perm;     /* [M]   device, sorted row r is visibility perm[r]           */
     int32_t *work;     /* [4*n_work] device, adjoint work items (tile_v, tile_u, row_begin, row_end) */
     int64_t  n_work;
@@ -276,7 +279,9 @@ wp_status wp_grid_adjoint(const wp_plan *plan, void *grid, void *x, void *stream
 wp_status wp_degrid(const wp_plan *plan, const wp_G *G, const void *grid, void *y, void *stream);
 /* grid = G^H y (gridding: tile-binned scatter; each tile's window accumulates in LDS in 64-bit
  * fixed point scaled by a bound on its partial sums, then float atomics flush it and take the
- * entries beyond the window).  The bound assumes taps the builder made: |G_kc| <= (W I0(beta))^2
+ * entries beyond the window).  Without stored taps (G->val NULL) the taps come from the factor
+ * records, each formed as the complex float product gv gu that the degrid forms (Section 3.1: the
+ * separable kernel of the linear chirp, regenerated in registers).  The bound assumes taps the builder made: |G_kc| <= (W I0(beta))^2
  * (int16 taps: 46341 times the row scale); larger taps in a hand-made G can overflow the window. */
 wp_status wp_grid_scatter(const wp_plan *plan, const wp_G *G, const void *y, void *grid,
                           void *stream);

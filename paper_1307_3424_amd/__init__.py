@@ -122,7 +122,9 @@ class GMatrix:
     def desc(self, transpose=None) -> _lib.WpG:
         d = _lib.WpG()
         d.M, d.nnz, d.taps, d.n_work, d.order = self.M, self.nnz, self.taps, self.n_work, self.order
-        d.rowptr, d.col, d.val = self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr()
+        d.rowptr = self.rowptr.data_ptr()
+        d.col = self.col.data_ptr() if self.col is not None else None
+        d.val = self.val.data_ptr() if self.val is not None else None
         d.perm, d.work = self.perm.data_ptr(), self.work.data_ptr()
         if self.rscale is not None:
             d.rscale = self.rscale.data_ptr()
@@ -141,15 +143,16 @@ class GMatrix:
         return sum(t.numel() * t.element_size() for t in ts if t is not None)
 
 
-def _new_G(plan: Plan, M: int, nnz: int, nwork: int, taps: int, transpose: bool, dev) -> GMatrix:
-    """G's arrays for pass 2 of the build, sized from pass 1 (factor records aside)."""
+def _new_G(plan: Plan, M: int, nnz: int, nwork: int, taps: int, transpose: bool, dev, stored: bool = True) -> GMatrix:
+    """G's arrays for pass 2 of the build, sized from pass 1 (factor records aside); stored=False leaves
+    out the taps and their columns (the factor-record form)."""
     torch = _torch()
     lib = load()
     G = GMatrix(M=M, nnz=nnz, taps=int(taps),
                 rowptr=torch.empty(M + 1, dtype=torch.int64, device=dev),
-                col=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
-                val=torch.empty(max(nnz, 1), dtype=(torch.complex64 if taps == WP_TAPS_C64 else torch.int32),
-                                device=dev),
+                col=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev) if stored else None,
+                val=(torch.empty(max(nnz, 1), dtype=(torch.complex64 if taps == WP_TAPS_C64 else torch.int32),
+                                 device=dev) if stored else None),
                 perm=torch.empty(M, dtype=torch.int32, device=dev),
                 work=torch.empty(4 * max(nwork, 1), dtype=torch.int32, device=dev),
                 n_work=nwork)
@@ -167,12 +170,14 @@ def _new_G(plan: Plan, M: int, nnz: int, nwork: int, taps: int, transpose: bool,
 
 
 def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: bool = True,
-            factors: bool = False, stream=None, beam=None) -> GMatrix:
+            factors: bool = False, stream=None, beam=None, stored: bool = True) -> GMatrix:
     """wp_build_workspace_bytes + wp_build_G_count (+ wp_build_factor_bytes) + wp_build_G_fill
     (u, v, w: float64 CUDA tensors).
 
     transpose: also build the transposed copy used by the gather form of G^H (and its block table).
     factors: also build the factor records the degrid forms its taps from.
+    stored: False keeps only the factor records (needs factors=True, transpose=False): no taps, no
+    columns, no transposed copy; Phi forms its taps from the records and Phi^H scatters from them.
     beam: optional [M, 3] float64 CUDA tensor of per-visibility Gaussian power patterns
     (l0, m0, sigma): the rows carry that direction-dependent effect (wp_build_G_dde_*).
     """
@@ -198,7 +203,9 @@ def build_G(plan: Plan, u, v, w, E: float, taps: int = WP_TAPS_C64, transpose: b
         check(lib.wp_build_G_dde_count(plan.handle, M, _ptr(u), _ptr(v), _ptr(w), _ptr(beam), float(E), _ptr(ws),
                                        C.byref(nnz), C.byref(nwork), s), "wp_build_G_dde_count")
     dev = u.device
-    G = _new_G(plan, M, nnz.value, nwork.value, taps, transpose, dev)
+    if not stored and (not factors or transpose or beam is not None):
+        raise ValueError("stored=False needs factors=True, transpose=False and no beam")
+    G = _new_G(plan, M, nnz.value, nwork.value, taps, transpose, dev, stored)
     if factors:
         fb = C.c_int64()
         check(lib.wp_build_factor_bytes(plan.handle, M, _ptr(ws), C.byref(fb), s), "wp_build_factor_bytes")

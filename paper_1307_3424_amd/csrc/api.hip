@@ -60,8 +60,11 @@ wp_status check_G(const wp_plan *p, const wp_G *G, bool need_work) {
         return wp_set_error(WP_EINVAL, "G->taps = %d", G->taps);
     if (G->taps == WP_TAPS_I16 && G->M > 0 && !G->rscale) return wp_set_error(WP_EINVAL, "WP_TAPS_I16 needs G->rscale");
     if (G->order != WP_ORDER_CALLER && G->order != WP_ORDER_SORTED) return wp_set_error(WP_EINVAL, "G->order = %d", G->order);
-    if (G->M > 0 && (!G->rowptr || !G->perm || (G->nnz > 0 && (!G->col || !G->val))))
-        return wp_set_error(WP_EINVAL, "G has a NULL array");
+    if (G->M > 0 && (!G->rowptr || !G->perm)) return wp_set_error(WP_EINVAL, "G has a NULL array");
+    // no stored taps (col and val both NULL) is the factor-record form: it needs the records
+    if (G->nnz > 0 && (!G->col || !G->val) && !(!G->col && !G->val && G->frec && G->fdat))
+        return wp_set_error(WP_EINVAL, "G has a NULL array (col / val may be NULL together only with factor records)");
+    if (!G->val && G->tcolptr) return wp_set_error(WP_EINVAL, "the transposed copy needs the stored taps");
     if (need_work && G->n_work > 0 && !G->work) return wp_set_error(WP_EINVAL, "G->work is NULL");
     if (need_work && G->n_work > 0x7fffffff) return wp_set_error(WP_ECAPACITY, "G->n_work too large");
     if (G->tcolptr && G->nnz > 0 && (!G->trow || !G->tval))

@@ -366,6 +366,10 @@ wp_status batch_create(wp_batch **out, const wp_plan *p, int P, const wp_G *G) {
             delete b;
             return wp_set_error(WP_EINVAL, "batch: problem %d has a different tap type", i);
         }
+        if (G[i].nnz > 0 && (!G[i].col || !G[i].val)) {
+            delete b;
+            return wp_set_error(WP_EINVAL, "batch: problem %d has no stored taps (factor-record form)", i);
+        }
         if (!G[i].tcolptr) b->transpose = false;
         b->M[i] = G[i].M;
         b->y_off[i] = off;

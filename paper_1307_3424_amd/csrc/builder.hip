@@ -363,6 +363,7 @@ __global__ __launch_bounds__(BNTH) void k_row_fill(const double *__restrict__ u,
             }
         }
     }
+    if (!col) return;                                  // factor-record form: no stored taps
     // emit: one wave per candidate row, ballot-compacted, ascending a
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int ib = wid; ib < ncb; ib += BNTH / 64) {

@@ -675,7 +675,8 @@ wp_status wp_mlp_box_targets(const wp_plan *p, const wp_G *G, const double *u, c
                              float *target, float *lost, void *stream) {
     if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
     if (!G) return wp_set_error(WP_EINVAL, "G is NULL");
-    if (G->taps != WP_TAPS_C64) return wp_set_error(WP_EINVAL, "box targets need complex64 taps");
+    if (G->taps != WP_TAPS_C64 || (G->nnz > 0 && (!G->col || !G->val)))
+        return wp_set_error(WP_EINVAL, "box targets need stored complex64 taps");
     if (!(s_out > 0.0)) return wp_set_error(WP_EINVAL, "s_out must be > 0");
     if (p->Ng < 2 * BOX) return wp_set_error(WP_EINVAL, "Ng = %d < %d", p->Ng, 2 * BOX);
     if (G->M == 0) return WP_OK;
@@ -697,7 +698,8 @@ wp_status row_errors(const wp_plan *p, wp_mlp *m, const wp_G *G, const double *u
     wp_status st = check_mlp(m);
     if (st != WP_OK) return st;
     if (!G) return wp_set_error(WP_EINVAL, "G is NULL");
-    if (G->taps != WP_TAPS_C64) return wp_set_error(WP_EINVAL, "the energy check needs complex64 taps");
+    if (G->taps != WP_TAPS_C64 || (G->nnz > 0 && (!G->col || !G->val)))
+        return wp_set_error(WP_EINVAL, "the energy check needs stored complex64 taps");
     if (p->Ng < 2 * BOX) return wp_set_error(WP_EINVAL, "Ng = %d < %d", p->Ng, 2 * BOX);
     if (G->M == 0) return WP_OK;
     if (!u || !v || !feat || !eps || !G->rowptr || !G->perm) return wp_set_error(WP_EINVAL, "NULL array");

@@ -236,6 +236,87 @@ __global__ __launch_bounds__(SP_NTH) void k_scatter(const int *__restrict__ work
     }
 }
 
+// Scatter form of G^H from the factor records alone (no stored taps, no transposed copy): the work
+// items and the fixed-point window of k_scatter; a wave takes one row at a time and its lanes walk
+// the row's kept taps through the record's staircase as k_degrid_sep does (lane l: u candidate
+// l mod Pa against v candidates l / Pa, l / Pa + 64 / Pa, ..., stopping at the first v candidate
+// that drops it), forming each tap gv gu in registers.  The taps equal the degrid's, so the two
+// products stay adjoint to FP32 rounding.
+__global__ __launch_bounds__(SP_NTH) void k_scatter_sep(const int *__restrict__ work, int64_t n_work,
+                                                        const int64_t *__restrict__ frec,
+                                                        const unsigned char *__restrict__ fdat,
+                                                        const int *__restrict__ perm, const float2 *__restrict__ y,
+                                                        float *__restrict__ grid, int logNg, int tile, int halo,
+                                                        double tap_bound) {
+    extern __shared__ unsigned long long win[];     // [2][WS][WS]: real plane, imaginary plane
+    __shared__ double s_red[WAVES];
+    const int Ng = 1 << logNg, mask = Ng - 1;
+    const int WS = tile + 2 * halo;
+    const int WS2 = WS * WS;
+    const int64_t item = blockIdx.x;
+    const int tv = work[4 * item + 0], tu = work[4 * item + 1];
+    const int rb = work[4 * item + 2], re = work[4 * item + 3];
+    const int v0 = (tv * tile - halo) & mask, u0 = (tu * tile - halo) & mask;
+    for (int e = threadIdx.x; e < 2 * WS2; e += SP_NTH) win[e] = 0ull;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double bsum = 0.0;
+    for (int r = rb + threadIdx.x; r < re; r += SP_NTH) {
+        const float2 yk = y[perm ? perm[r] : r];
+        bsum += tap_bound * sqrt((double)yk.x * yk.x + (double)yk.y * yk.y);
+    }
+    for (int o = 32; o > 0; o >>= 1) bsum += __shfl_xor(bsum, o);
+    if (lane == 0) s_red[wid] = bsum;
+    __syncthreads();
+    double S = 0.0;
+    for (int i = 0; i < WAVES; ++i) S += s_red[i];
+    const double q = S > 0.0 ? 2305843009213693952.0 / S : 1.0;     // 2^61 / S, as in k_scatter
+    for (int r = rb + wid; r < re; r += WAVES) {
+        const float2 yk = y[perm ? perm[r] : r];
+        const unsigned char *rec = fdat + frec[r];
+        const uint32_t hdr = *(const uint32_t *)rec;
+        const int nu = (int)(hdr & 0xffffu), nv = (int)(hdr >> 16);
+        const uint16_t *ua = (const uint16_t *)rec + 2, *vb = ua + nu, *nbv = vb + nv;
+        const float2 *gu = (const float2 *)(rec + ((4 + 2 * nu + 4 * nv + 7) & ~7)), *gv = gu + nu;
+        int Pa = 1;
+        while (Pa < nu && Pa < 64) Pa <<= 1;
+        const int Pb = 64 / Pa;
+        for (int i = lane & (Pa - 1); i < nu; i += Pa) {
+            const int a = ua[i];
+            const float2 fu = gu[i];
+            for (int b = lane / Pa; b < nv; b += Pb) {
+                if (i >= (int)nbv[b]) break;          // nb falls along the v order: later b drop i too
+                const float2 f = gv[b];
+                const float tr = f.x * fu.x - f.y * fu.y, ti = f.x * fu.y + f.y * fu.x;
+                const float cr = tr * yk.x + ti * yk.y;          // conj(t) * y
+                const float ci = tr * yk.y - ti * yk.x;
+                const int cv = vb[b];
+                const int dv = (cv - v0) & mask;
+                const int du = (a - u0) & mask;
+                if (dv < WS && du < WS) {
+                    atomicAdd(&win[dv * WS + du], (unsigned long long)__double2ll_rn((double)cr * q));
+                    atomicAdd(&win[WS2 + dv * WS + du], (unsigned long long)__double2ll_rn((double)ci * q));
+                } else {
+                    const int64_t c = ((int64_t)cv << logNg) | a;
+                    unsafeAtomicAdd(&grid[2 * c], cr);
+                    unsafeAtomicAdd(&grid[2 * c + 1], ci);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const double iq = 1.0 / q;
+    const int WE = WS < Ng ? WS : Ng;
+    for (int e = threadIdx.x; e < WE * WE; e += SP_NTH) {
+        const int dv = e / WE, du = e % WE;
+        const long long a = (long long)win[dv * WS + du], b = (long long)win[WS2 + dv * WS + du];
+        if (a != 0 || b != 0) {
+            const int64_t g = (int64_t)((v0 + dv) & mask) * Ng + ((u0 + du) & mask);
+            unsafeAtomicAdd(&grid[2 * g], (float)((double)a * iq));
+            unsafeAtomicAdd(&grid[2 * g + 1], (float)((double)b * iq));
+        }
+    }
+}
+
 // Gather form of G^H: grid cell c sums conj(G_kc) y_k over its entries of the
 // transposed copy.  LPR lanes per cell (64 / LPR cells per wave), U entries in
 // flight per lane, cells in order, every cell written once (no atomics).
@@ -471,6 +552,12 @@ wp_status launch_scatter(const wp_plan *p, const wp_G *G, const float2 *y, float
     const int WS = p->tile + 2 * p->halo;
     const size_t lds = (size_t)2 * WS * WS * sizeof(unsigned long long);
     const dim3 gw((unsigned)G->n_work), bw(SP_NTH);
+    if (!G->val) {                 // no stored taps: form them from the factor records
+        hipLaunchKernelGGL(k_scatter_sep, gw, bw, lds, s, G->work, G->n_work, G->frec,
+                           (const unsigned char *)G->fdat, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo,
+                           p->tap_bound);
+        return wp_check_launch("grid_scatter from factor records");
+    }
     if (G->taps == WP_TAPS_BF16)
         hipLaunchKernelGGL((k_scatter<WP_TAPS_BF16>), gw, bw, lds, s, G->work, G->n_work, G->rowptr, G->col, G->val,
                            G->rscale, yperm(G), y, (float *)grid, p->logNg, p->tile, p->halo,

@@ -2,7 +2,8 @@
 cells) at full size, in the launch forms the benchmark times, against the FP64 oracle on a seeded
 4096-visibility subset: Phi from the factor records and from the stored taps, Phi^H through the
 blocked gather over the transposed copy (cells average about 210 entries) and through the
-per-cell gather.  G holds about 3.5e9 taps, so row and cell offsets run past 2^31.
+per-cell gather; then the factor-record form (no stored taps, no transposed copy: Phi from the
+records, Phi^H scattered from them).  G holds about 3.5e9 taps, so row and cell offsets run past 2^31.
 
 Tolerance: 1e-5 (the FP32 target), against the oracle's rows with the same (W, beta, E, chirp).
 """
@@ -62,6 +63,20 @@ def test_surrogate_form_exact_operator_full_size():
         e = relerr(xa, x_ref)
         print(f"full size: Phi^H ({'blocked' if blocks else 'per-cell'} gather) rel err {e:.3e}", flush=True)
         assert e < 1e-5, blocks
+    stored_bytes = G.nbytes()
+    del G
+    torch.cuda.empty_cache()
+    # the factor-record form: no stored taps, no transposed copy; Phi^H scattered from the records
+    print(f"full size {wl.name}: factor-record form", flush=True)
+    G = wp.build_G(plan, t(u), t(v), t(w), wl.E, transpose=False, factors=True, stored=False)
+    torch.cuda.synchronize()
+    assert G.nbytes() < 0.1 * stored_bytes
+    e = relerr(wp.apply_Phi(plan, G, xd).cpu().numpy()[rows], y_ref)
+    xa = wp.apply_PhiT(plan, G, yfd).cpu().numpy().reshape(wl.N, wl.N)
+    e2 = relerr(xa, x_ref)
+    print(f"full size: record form Phi rel err {e:.3e}, Phi^H (scatter from records) rel err {e2:.3e}, "
+          f"{G.nbytes() / 1e9:.1f} GB against {stored_bytes / 1e9:.1f} GB", flush=True)
+    assert e < 1e-5 and e2 < 1e-5
     del G
     torch.cuda.empty_cache()
     plan.close()

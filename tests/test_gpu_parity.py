@@ -469,6 +469,42 @@ def test_factor_records_plain_form():
     assert relerr(y1, wp.degrid(plan, G, X).cpu().numpy()) < 1e-6
 
 
+@pytest.mark.parametrize("workload", [0, 1])
+def test_factor_record_form_without_stored_taps(workload):
+    """G kept as factor records only (no taps, no columns, no transposed copy): Phi from the records
+    and Phi^H scattered from them, against the oracle (every row of the tiny form; 4096 sampled rows of
+    the plain form), and adjoint to each other; a fraction of the stored form's bytes."""
+    wl = synth.workload(workload)
+    say(f"factor-record form: {wl.name}")
+    x, u, v, w = synth.workload_inputs(wl)
+    s = Setup(N=wl.N, L=wl.L)
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E, factors=True, transpose=False, stored=False)
+    torch.cuda.synchronize()
+    assert G.col is None and G.val is None and G.tcolptr is None
+    rows = np.arange(wl.M) if workload == 0 else synth.subset_rows(wl.M, 4096, synth.rng_for(wl.seed, "subset", 3))
+    Go = oracle_rows(u, v, w, wl.E, s, rows)
+    y = wp.apply_Phi(plan, G, c64(x)).cpu().numpy()
+    assert relerr(y[rows], Go @ wproj.grid_forward(x, s).ravel()) < TOL
+    yv = np.zeros(wl.M, dtype=np.complex128)
+    yv[rows] = synth.random_complex(rows.size, synth.rng_for(wl.seed, "y", 3))
+    xa = wp.apply_PhiT(plan, G, c64(yv)).cpu().numpy().reshape(wl.N, wl.N)
+    assert relerr(xa, wproj.phi_adjoint(Go, yv[rows], s)) < TOL
+    # the two products of the record form are adjoint (random x and y over every row)
+    rng = np.random.default_rng(17)
+    xr = c64(synth.random_complex(wl.N * wl.N, rng))
+    yr = c64(synth.random_complex(wl.M, rng))
+    Px = wp.apply_Phi(plan, G, xr).to(torch.complex128)
+    Py = wp.apply_PhiT(plan, G, yr).to(torch.complex128)
+    lhs = torch.vdot(Px, yr.to(torch.complex128)).item()
+    rhs = torch.vdot(xr.to(torch.complex128), Py).item()
+    assert abs(lhs - rhs) <= 1e-5 * (torch.linalg.norm(Px) * torch.linalg.norm(yr.to(torch.complex128))).item()
+    Gs = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E, factors=True)
+    assert G.nbytes() < 0.25 * Gs.nbytes()
+    with pytest.raises(ValueError):
+        wp.build_G(plan, dev(u), dev(v), dev(w), wl.E, factors=False, transpose=False, stored=False)
+
+
 def test_factor_records_wide_rows_and_edges():
     """E = 1: rows with w > 0 keep the whole 512 x 512 grid (nu = nv = 512, eight u candidates
     per lane), rows with w = 0 a 4 x 4 box; plus visibilities at the band edges."""
