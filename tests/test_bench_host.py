@@ -57,9 +57,15 @@ def test_traffic_is_reported_only_for_the_profiled_source(tmp_path, monkeypatch)
     (src / "spmv.hip").write_bytes(b"kernel source")
     import hashlib
     h = hashlib.sha256(b"kernel source").hexdigest()[:16]
-    (prof / "spmv_plain-256_traffic.md").write_text(f"spmv_source_sha256_16={h}\ntraffic_bytes.k_degrid=1234\n")
+    (prof / "traffic_plain-256-fp32.md").write_text(f"spmv_source_sha256_16={h}\ntraffic_bytes.k_degrid=1234\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     assert bench.profiled_traffic("plain-256-fp32", "k_degrid") == 1234.0
     assert bench.profiled_traffic("plain-256-fp32", "k_gather_wave") is None
     (src / "spmv.hip").write_bytes(b"changed source")
     assert bench.profiled_traffic("plain-256-fp32", "k_degrid") is None
+    # the surrogate's kernels are keyed to their own source
+    (src / "surrogate.hip").write_bytes(b"network kernels")
+    hs = hashlib.sha256(b"network kernels").hexdigest()[:16]
+    (prof / "traffic_surrogate-2048.md").write_text(f"surrogate_source_sha256_16={hs}\ntraffic_bytes.k_sur_grid=99\n")
+    assert bench.profiled_traffic("surrogate-2048", "k_sur_grid", "surrogate") == 99.0
+    assert bench.profiled_traffic("surrogate-2048", "k_sur_grid") is None
