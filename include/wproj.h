@@ -143,7 +143,10 @@ wp_status wp_plan_destroy(wp_plan *plan);
  * restores the automatic choice.  Lanes per row / cell: 4, 8, 16, 32 or 64;
  * loads in flight per lane: 4, 8 or 16 (not every pair exists: an apply with
  * an unavailable pair returns WP_EINVAL); the gather knobs apply to the form
- * without a block table.  "gather_chunk": entries a wavefront of the blocked
+ * without a block table.  "solve_graph": 1 replays the primal-dual loop of wp_solve from a captured
+ * HIP graph, 0 (automatic) or 2 launches its kernels one by one.  "exact_rows": how the exact chirp's
+ * rows are made: 1 from the separable expansion at any Ng, 2 whole in 2-D (Ng <= 512), 0 automatic
+ * (whole up to Ng = 512, the expansion above).  "gather_chunk": entries a wavefront of the blocked
  * gather stages at a time (256, 512, 768 or 1024); "gather_block_entries": the entry
  * stretch of a gather block (256, 384, 512 or 1024; it sets the block table that
  * wp_gather_table_size sizes and wp_build_G_fill writes, so change it only before
@@ -183,11 +186,17 @@ wp_status wp_build_workspace_bytes(const wp_plan *plan, int64_t M, int64_t *byte
  *   workspace  device, wp_build_workspace_bytes(M) bytes, kept until pass 2
  *   nnz_out    host: total taps; n_work_out host: adjoint work items
  * Synchronises the stream (reads back two counts).
- * WP_CHIRP_EXACT (Eq. 4, not separable): each row is made whole, a 2-D FP64 FFT of the
- * chirp on the Ng x Ng padded grid with the window's correlation per axis, in chunks of
- * rows held in the workspace; needs Ng <= 512 (else WP_EUNSUPPORTED) and 2 L^2 < 1 (the
- * square root stays real over the padded grid; else WP_EINVAL).  Its tau search splits
- * the bracket in 16 per pass over the row instead of bisecting.
+ * WP_CHIRP_EXACT (Eq. 4, not separable) needs 2 L^2 < 1 (the square root stays real over the
+ * padded grid; else WP_EINVAL).  Up to Ng = 512 each row is made whole, a 2-D FP64 FFT of the
+ * chirp on the Ng x Ng padded grid with the window's correlation per axis, in chunks of rows
+ * held in the workspace (its tau search splits the bracket in 16 per pass over the row).  Above
+ * Ng = 512 the chirp is the linear chirp times exp(i pi w s^2 / (1 + sqrt(1 - s))^2),
+ * s = l^2 + m^2, whose interpolation at 8 Chebyshev points of l^2 makes each row a sum of 8 outer
+ * products of 1-D rows (16 one-dimensional FP64 FFTs; expansion error below 1e-10 over the padded
+ * grid); the row is formed on a window of at most 88 x 88 cells around its cell and thresholded
+ * there, after checking that a bound on every entry outside the window lies below tau.  That form
+ * needs E < 1 and rows spreading over at most 67 cells, 4 w L^2 / sqrt(1 - 2 L^2) <= 67 (else
+ * WP_EUNSUPPORTED); a row whose outside bound reaches tau fails with WP_EHIP.
  */
 wp_status wp_build_G_count(const wp_plan *plan, int64_t M, const double *u, const double *v,
                            const double *w, double E, void *workspace,
@@ -521,7 +530,10 @@ wp_status wp_power_norm2(const wp_plan *plan, const wp_G *G, const float *x0, in
  * l2 ball): tau = 0.49, sigma_1 = 1, sigma_2 = 1 / nu.  x (device, real N*N floats) holds
  * the start on entry and the estimate on exit; y is c64 [M] in G's visibility order
  * (G->order); eps is the ball radius, nu = ||Phi||^2.  Dual variables start at zero.
- * Asynchronous: iters iterations are enqueued with no host synchronisation. */
+ * Asynchronous: the iterations' kernels are enqueued one by one.  With the plan's tuning key
+ * "solve_graph" = 1 and 20 iterations or more, chunks of 10 iterations are instead captured once into
+ * a HIP graph (on a private stream) and replayed on `stream`, and the call then synchronises the
+ * stream before it returns (the graph is released). */
 wp_status wp_solve(const wp_plan *plan, const wp_G *G, const void *y, double eps, double nu,
                    int iters, int levels, float *x, void *workspace, void *stream);
 

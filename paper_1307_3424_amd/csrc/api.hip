@@ -188,6 +188,16 @@ wp_status wp_plan_set_tuning(wp_plan *p, const char *key, int value) {
         p->tune_gather_chunk = value;
         return WP_OK;
     }
+    if (!std::strcmp(key, "exact_rows")) {
+        if (value < 0 || value > 2) return wp_set_error(WP_EINVAL, "exact_rows %d: 0, 1 or 2", value);
+        p->exact_rows = value;
+        return WP_OK;
+    }
+    if (!std::strcmp(key, "solve_graph")) {
+        if (value < 0 || value > 2) return wp_set_error(WP_EINVAL, "solve_graph %d: 0, 1 or 2", value);
+        p->solve_graph = value;
+        return WP_OK;
+    }
     if (!std::strcmp(key, "degrid_rows")) {
         if (value != 0 && value != 1 && value != 2 && value != 4)
             return wp_set_error(WP_EINVAL, "degrid_rows %d: 0, 1, 2 or 4", value);
@@ -227,12 +237,18 @@ wp_status wp_gather_table_size(const wp_plan *p, int64_t nnz, int64_t *n) {
     return WP_OK;
 }
 
-// the exact chirp: whole 2-D rows (Ng <= EXACT_MAX_NG), and sqrt(1 - l^2 - m^2) real over the
-// padded grid (its corner sits at l = m = -L)
-static wp_status check_exact(const wp_plan *p) {
+// the exact chirp: whole 2-D rows up to Ng = EXACT_MAX_NG, the separable expansion above (or when the
+// plan asks for it; never with a beam), which keeps a window of the row and so needs E < 1; and
+// sqrt(1 - l^2 - m^2) real over the padded grid (its corner sits at l = m = -L)
+static wp_status check_exact(const wp_plan *p, double E, bool beam = false) {
     if (p->chirp != WP_CHIRP_EXACT) return WP_OK;
-    if (p->Ng > EXACT_MAX_NG)
-        return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp needs Ng <= %d (Ng = %d)", EXACT_MAX_NG, p->Ng);
+    const bool lowrank = !beam && (p->exact_rows == 1 || (p->exact_rows == 0 && p->Ng > EXACT_MAX_NG));
+    if (!lowrank && p->Ng > EXACT_MAX_NG)
+        return wp_set_error(WP_EUNSUPPORTED, "build: whole 2-D rows of the exact chirp need Ng <= %d (Ng = %d)",
+                            EXACT_MAX_NG, p->Ng);
+    if (lowrank && !(E < 1.0))
+        return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp's separable expansion keeps a window of each "
+                            "row and needs E < 1 (E = %g)", E);
     if (!(2.0 * p->L * p->L < 1.0))
         return wp_set_error(WP_EINVAL, "build: the exact chirp needs 2 L^2 < 1 (L = %g)", p->L);
     return WP_OK;
@@ -252,7 +268,7 @@ wp_status wp_build_G_count(const wp_plan *p, int64_t M, const double *u, const d
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     if (!u || !v || !w || !ws || !nnz_out || !n_work_out) return wp_set_error(WP_EINVAL, "NULL argument");
     if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
-    if (wp_status s = check_exact(p)) return s;
+    if (wp_status s = check_exact(p, E)) return s;
     return launch_build_count(p, M, u, v, w, nullptr, E, ws, nnz_out, n_work_out, as_stream(stream));
 }
 
@@ -262,7 +278,7 @@ wp_status wp_build_G_fill(const wp_plan *p, int64_t M, const double *u, const do
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     if (!u || !v || !w || !ws) return wp_set_error(WP_EINVAL, "NULL argument");
     if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
-    if (wp_status s = check_exact(p)) return s;
+    if (wp_status s = check_exact(p, E)) return s;
     if (wp_status s = check_G(p, G, true)) return s;
     if (p->chirp == WP_CHIRP_EXACT && (G->frec || G->fdat))
         return wp_set_error(WP_EUNSUPPORTED, "build: the exact chirp's rows are not separable (no factor records)");
@@ -309,7 +325,7 @@ wp_status wp_build_G_dde_count(const wp_plan *p, int64_t M, const double *u, con
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     if (!u || !v || !w || !beam || !ws || !nnz_out || !n_work_out) return wp_set_error(WP_EINVAL, "NULL argument");
     if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
-    if (wp_status s = check_exact(p)) return s;
+    if (wp_status s = check_exact(p, E, true)) return s;
     if (p->Ng > EXACT_MAX_NG)
         return wp_set_error(WP_EUNSUPPORTED, "build: 2-D rows need Ng <= %d (Ng = %d)", EXACT_MAX_NG, p->Ng);
     return launch_build_count(p, M, u, v, w, beam, E, ws, nnz_out, n_work_out, as_stream(stream));
@@ -321,7 +337,7 @@ wp_status wp_build_G_dde_fill(const wp_plan *p, int64_t M, const double *u, cons
     if (M < 1 || M > 0x7fffffff) return wp_set_error(WP_EINVAL, "M = %lld out of range", (long long)M);
     if (!u || !v || !w || !beam || !ws) return wp_set_error(WP_EINVAL, "NULL argument");
     if (!(E > 0.0 && E <= 1.0)) return wp_set_error(WP_EINVAL, "E = %g: need 0 < E <= 1", E);
-    if (wp_status s = check_exact(p)) return s;
+    if (wp_status s = check_exact(p, E, true)) return s;
     if (p->Ng > EXACT_MAX_NG)
         return wp_set_error(WP_EUNSUPPORTED, "build: 2-D rows need Ng <= %d (Ng = %d)", EXACT_MAX_NG, p->Ng);
     if (wp_status s = check_G(p, G, true)) return s;

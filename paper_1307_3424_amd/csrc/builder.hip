@@ -29,6 +29,7 @@
 #include <cstdio>
 
 #include "builder_exact.h"
+#include "builder_lowrank.h"
 #include "builder_util.h"
 #include "fft_lds.h"
 
@@ -669,6 +670,13 @@ WsLayout ws_layout(const wp_plan *p, int64_t M, bool rows2d) {
     return L;
 }
 
+// the exact chirp's rows come from the separable expansion above Ng = 512, or when the plan asks for it
+// (no beam: a beam's rows stay whole in 2-D)
+inline bool exact_lowrank(const wp_plan *p, const double *beam) {
+    if (beam || p->chirp != WP_CHIRP_EXACT) return false;
+    return p->exact_rows == 1 || (p->exact_rows == 0 && p->Ng > EXACT_MAX_NG);
+}
+
 template <int LOGNG>
 size_t count_lds() { return (size_t)32 << LOGNG; }
 template <int LOGNG>
@@ -736,6 +744,36 @@ wp_status count_rows_exact(const wp_plan *p, int64_t M, const double *u, const d
                            (int *)(ws + L.fsz), (int *)(ws + L.err));
     }
     return wp_check_launch("build_G_count exact rows");
+}
+
+// the exact chirp's rows from the separable expansion (builder_lowrank.h): one workgroup per row
+template <int LOGNG>
+wp_status lowrank_rows(const wp_plan *p, int64_t M, const double *u, const double *v, const double *w, double E,
+                       unsigned char *ws, const WsLayout &L, const wp_G *G, hipStream_t s) {
+    constexpr size_t lds = lowrank_lds<LOGNG>();
+    static_assert(lds <= 160 * 1024, "LDS budget");
+    const double L2 = p->L * p->L;
+    for (int64_t r0 = 0; r0 < M; r0 += ROW_CHUNK) {
+        const dim3 g((unsigned)std::min<int64_t>(ROW_CHUNK, M - r0));
+        if (!G)
+            hipLaunchKernelGGL((k_lowrank_rows<LOGNG, false, WP_TAPS_C64>), g, dim3(BNTH), lds, s, u, v, w, E, p->cell,
+                               p->delta, p->W, p->beta, L2, p->tw64, r0, nullptr, (double *)(ws + L.tau),
+                               (int *)(ws + L.nnz), (int *)(ws + L.key), (int *)(ws + L.fsz), nullptr, nullptr,
+                               nullptr, nullptr, (int *)(ws + L.err));
+        else if (G->taps == WP_TAPS_BF16)
+            hipLaunchKernelGGL((k_lowrank_rows<LOGNG, true, WP_TAPS_BF16>), g, dim3(BNTH), lds, s, u, v, w, E, p->cell,
+                               p->delta, p->W, p->beta, L2, p->tw64, r0, G->perm, (double *)(ws + L.tau), nullptr,
+                               nullptr, nullptr, G->rowptr, G->col, G->val, G->rscale, (int *)(ws + L.err));
+        else if (G->taps == WP_TAPS_I16)
+            hipLaunchKernelGGL((k_lowrank_rows<LOGNG, true, WP_TAPS_I16>), g, dim3(BNTH), lds, s, u, v, w, E, p->cell,
+                               p->delta, p->W, p->beta, L2, p->tw64, r0, G->perm, (double *)(ws + L.tau), nullptr,
+                               nullptr, nullptr, G->rowptr, G->col, G->val, G->rscale, (int *)(ws + L.err));
+        else
+            hipLaunchKernelGGL((k_lowrank_rows<LOGNG, true, WP_TAPS_C64>), g, dim3(BNTH), lds, s, u, v, w, E, p->cell,
+                               p->delta, p->W, p->beta, L2, p->tw64, r0, G->perm, (double *)(ws + L.tau), nullptr,
+                               nullptr, nullptr, G->rowptr, G->col, G->val, G->rscale, (int *)(ws + L.err));
+    }
+    return wp_check_launch(G ? "build_G_fill exact rows (separable expansion)" : "build_G_count exact rows (separable expansion)");
 }
 
 template <int LOGNG>
@@ -836,7 +874,18 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
     const int T = p->ntile * p->ntile;
     WP_HIP(hipMemsetAsync(ws + L.err, 0, 16, s));
     wp_status st;
-    if (rows2d) {
+    if (rows2d && exact_lowrank(p, beam)) {
+        switch (p->logNg) {
+            case 6: st = lowrank_rows<6>(p, M, u, v, w, E, ws, L, nullptr, s); break;
+            case 7: st = lowrank_rows<7>(p, M, u, v, w, E, ws, L, nullptr, s); break;
+            case 8: st = lowrank_rows<8>(p, M, u, v, w, E, ws, L, nullptr, s); break;
+            case 9: st = lowrank_rows<9>(p, M, u, v, w, E, ws, L, nullptr, s); break;
+            case 10: st = lowrank_rows<10>(p, M, u, v, w, E, ws, L, nullptr, s); break;
+            case 11: st = lowrank_rows<11>(p, M, u, v, w, E, ws, L, nullptr, s); break;
+            case 12: st = lowrank_rows<12>(p, M, u, v, w, E, ws, L, nullptr, s); break;
+            default: return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d", p->Ng);
+        }
+    } else if (rows2d) {
         switch (p->logNg) {
             case 6: st = count_rows_exact<6>(p, M, u, v, w, beam, E, ws, L, s); break;
             case 7: st = count_rows_exact<7>(p, M, u, v, w, beam, E, ws, L, s); break;
@@ -900,6 +949,11 @@ wp_status launch_build_count(const wp_plan *p, int64_t M, const double *u, const
     if (host_err & 1)
         return wp_set_error(WP_EINVAL, "build_G_count: a visibility has non-finite (u, v, w), lies outside the band "
                             "|u|,|v| < N/(2L)%s", beam ? " or has a beam that is not finite with sigma > 0" : "");
+    if (host_err & 16)
+        return wp_set_error(WP_EUNSUPPORTED, "build_G_count: an exact-chirp row spreads over more than %d cells "
+                            "(the separable expansion's window); reduce w", LR_WMAX - 2 * LR_MARGIN);
+    if (host_err & 8)
+        return wp_set_error(WP_EHIP, "build_G_count: an exact-chirp row keeps entries outside its window");
     *nnz_total = host_rowptr_end;
     *nwork = host_items;
     return WP_OK;
@@ -924,7 +978,18 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
         WP_HIP(hipMemcpyAsync(G->frec, ws + L.frec, 8 * (M + 1), hipMemcpyDeviceToDevice, s));
     }
     wp_status st;
-    if (rows2d) {
+    if (rows2d && exact_lowrank(p, beam)) {
+        switch (p->logNg) {
+            case 6: st = lowrank_rows<6>(p, M, u, v, w, E, ws, L, G, s); break;
+            case 7: st = lowrank_rows<7>(p, M, u, v, w, E, ws, L, G, s); break;
+            case 8: st = lowrank_rows<8>(p, M, u, v, w, E, ws, L, G, s); break;
+            case 9: st = lowrank_rows<9>(p, M, u, v, w, E, ws, L, G, s); break;
+            case 10: st = lowrank_rows<10>(p, M, u, v, w, E, ws, L, G, s); break;
+            case 11: st = lowrank_rows<11>(p, M, u, v, w, E, ws, L, G, s); break;
+            case 12: st = lowrank_rows<12>(p, M, u, v, w, E, ws, L, G, s); break;
+            default: return wp_set_error(WP_EUNSUPPORTED, "build: Ng = %d", p->Ng);
+        }
+    } else if (rows2d) {
         switch (p->logNg) {
             case 6: st = fill_rows_exact<6>(p, M, u, v, w, beam, ws, L, G, s); break;
             case 7: st = fill_rows_exact<7>(p, M, u, v, w, beam, ws, L, G, s); break;

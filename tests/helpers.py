@@ -47,3 +47,22 @@ def bf16_rms_bound(G, vec, adjoint: bool, ref) -> float:
     p2 = np.abs(np.asarray(vec)) ** 2
     tot = float((A2.T @ p2).sum()) if adjoint else float((A2 @ p2).sum())
     return BF16_U / np.sqrt(3.0) * np.sqrt(tot) / float(np.linalg.norm(ref))
+
+
+def oracle_row_window(args):
+    """One oracle row (the literal construction: the whole Ng x Ng row) around its visibility's cell:
+    (first v cell, first u cell, energies and values on a (2 half) x (2 half) window of cells,
+    tau, number of kept cells outside the window).  Worker form for process pools."""
+    ut, vt, w, E, s, half = args
+    g = wproj.kernel_row(ut, vt, w, s)
+    m = (g * g.conj()).real
+    tau, _ = wproj.energy_threshold(m, E)
+    Ng = s.Ng
+    cv = int(np.floor(vt + 0.5)) + Ng // 2 - half
+    cu = int(np.floor(ut + 0.5)) + Ng // 2 - half
+    rv = (cv + np.arange(2 * half)) % Ng
+    ru = (cu + np.arange(2 * half)) % Ng
+    mw = m[np.ix_(rv, ru)]
+    gw = g[np.ix_(rv, ru)]
+    outside = int((m >= tau).sum() - (mw >= tau).sum())
+    return cv, cu, mw, gw, tau, outside

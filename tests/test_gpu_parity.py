@@ -621,8 +621,12 @@ def test_exact_chirp_precision_forms(taps):
 
 def test_exact_chirp_limits():
     z = np.zeros(3)
-    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):      # Ng = 1024 > 512
-        wp.build_G(wp.Plan(512, L, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 0.9)
+    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):      # Ng = 1024 > 512: a window of each row, E < 1
+        wp.build_G(wp.Plan(512, L, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 1.0)
+    big = wp.Plan(512, L, chirp=wp.WP_CHIRP_EXACT)
+    big.set_tuning("exact_rows", 2)                                  # whole 2-D rows asked for at Ng = 1024
+    with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):
+        wp.build_G(big, dev(z), dev(z), dev(z), 0.9)
     with pytest.raises(wp.WprojError, match="WP_EINVAL"):            # 2 L^2 >= 1
         wp.build_G(wp.Plan(64, 0.75, chirp=wp.WP_CHIRP_EXACT), dev(z), dev(z), dev(z), 0.9)
     with pytest.raises(wp.WprojError, match="WP_EUNSUPPORTED"):      # rows are not separable

@@ -181,3 +181,25 @@ def test_solve_plain_form_matches_oracle_snr():
     print(f"SNR_out gpu {snr_g:.3f} dB, oracle {ref['snr_out_db']:.3f} dB", flush=True)
     assert abs(snr_g - ref["snr_out_db"]) < 0.1
     assert np.all(xg >= 0)
+
+
+@pytest.mark.parametrize("levels", [4, 0])
+def test_solve_graph_replays_match_direct_launches(levels):
+    """The solver loop replayed from a captured HIP graph (chunks of 10 iterations) against the same
+    iterations launched one by one: identical iterates, for 35 iterations (three replays and five
+    direct ones) and again after eager work on the same stream in between."""
+    wl, x, u, v, w, s, A, AH, y, eps, x0 = _tiny_problem()
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E)
+    yd = c64(y)
+    nu = solver.power_norm2(A, AH, x0, 50)
+    plan.set_tuning("solve_graph", 2)
+    ref = wp.solve(plan, G, yd, eps, nu, 35, levels=levels).cpu().numpy()
+    plan.set_tuning("solve_graph", 1)
+    for rep in range(3):
+        got = wp.solve(plan, G, yd, eps, nu, 35, levels=levels).cpu().numpy()
+        assert np.array_equal(got, ref), rep
+        wp.apply_Phi(plan, G, c64(x))                 # eager work between the replays
+        torch.cuda.synchronize()
+    x_ref = solver.solve(y, A, AH, (wl.N, wl.N), eps, nu, 35, levels=levels)
+    assert relerr(ref.reshape(wl.N, wl.N), x_ref) < 1e-4
