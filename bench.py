@@ -66,6 +66,12 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-3, help="surrogate form: per-row energy error tolerance")
     ap.add_argument("--check-nw", type=int, default=257, help="surrogate form: check lattice nodes along w")
     ap.add_argument("--check-nd", type=int, default=33, help="surrogate form: check lattice nodes per offset axis")
+    ap.add_argument("--save-params", default=None,
+                    help="surrogate form: write the trained network's parameters to this .npy file")
+    ap.add_argument("--load-params", default=None,
+                    help="surrogate form: take the network's parameters from this .npy file (written by "
+                         "--save-params) instead of training; for counter runs, whose profiler slows the training's "
+                         "many small launches")
     ap.add_argument("--sweep", choices=["energy", "coverage", "images"], default=None,
                     help="the paper's experiments on synthetic skies (tiny-form geometry): reconstruction SNR "
                          "and non-zero fraction against the preserved energy E, SNR against uv coverage "
@@ -609,15 +615,22 @@ def bench_surrogate(args, wl):
     del Gt, lost
     sync()
     data_s = time.perf_counter() - t0
-    log(f"bench: {wl.train_samples} exact training rows in {data_s:.1f} s (largest energy outside the box "
-        f"{lost_max:.2e}); training {args.train_epochs} passes")
     t0 = time.perf_counter()
-    hist = mlp.train(ft, T, 8192, args.train_epochs, 2e-3)
+    if args.load_params:
+        mlp.set_params(np.load(args.load_params), wl.w_top, s_out)
+        hist = [float("nan"), float("nan")]
+        log(f"bench: network parameters from {args.load_params} (no training)")
+    else:
+        log(f"bench: {wl.train_samples} exact training rows in {data_s:.1f} s (largest energy outside the box "
+            f"{lost_max:.2e}); training {args.train_epochs} passes")
+        hist = mlp.train(ft, T, 8192, args.train_epochs, 2e-3)
     sync()
     train_s = time.perf_counter() - t0
     del T, ft
     torch.cuda.empty_cache()
     log(f"bench: trained in {train_s:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    if args.save_params:
+        np.save(args.save_params, mlp.get_params()[0])
     # ---- run-time check from the lattice (no exact row), surrogate set-up, fallback G
     t0 = time.perf_counter()
     table = mlp.check_table(plan, wl.E, args.check_nw, args.check_nd)
