@@ -82,7 +82,24 @@ def parse():
                          "residual images to this .npz file")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one 256 MiB device copy (reference for hardware byte counters)")
-    return ap.parse_args()
+    ap.add_argument("--tune", action="append", default=[], metavar="KEY=VALUE",
+                    help="wp_plan_set_tuning on the benchmark's plans (repeatable), e.g. sur_degrid=1")
+    args = ap.parse_args()
+    tune = []
+    for kv in args.tune:
+        k, _, v = kv.partition("=")
+        if not k or not v.lstrip("-").isdigit():
+            ap.error(f"--tune {kv!r}: expected KEY=INTEGER")
+        tune.append((k, int(v)))
+    args.tune = tune
+    return args
+
+
+def tuned(plan, args):
+    """Apply the --tune settings to a plan."""
+    for k, v in args.tune:
+        plan.set_tuning(k, v)
+    return plan
 
 
 def degrid_bytes(G, M, Ng, tap_bytes):
@@ -298,7 +315,7 @@ def bench_plain(args, wl, with_cpu=True, with_solve=True):
     log(f"bench: workload {wl.name} N={wl.N} M={wl.M} E={wl.E} taps={args.taps}")
     x, u, v, w = synth.workload_inputs(wl)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    plan = wp.Plan(wl.N, wl.L, kb_W=wl.W)
+    plan = tuned(wp.Plan(wl.N, wl.L, kb_W=wl.W), args)
     taps = {"c64": wp.WP_TAPS_C64, "bf16": wp.WP_TAPS_BF16, "i16": wp.WP_TAPS_I16}[args.taps]
     tap_bytes = 8 if taps == wp.WP_TAPS_C64 else 4
     ud, vd, wd = t(u), t(v), t(w)
@@ -436,7 +453,7 @@ def bench_batched(args, wl):
     torch.cuda.set_device(dev)
     P = len(wl.channels) if args.channels <= 0 else min(args.channels, len(wl.channels))
     log(f"bench: workload {wl.name} N={wl.N} channels={P} M_total={sum(wl.channels[:P])}")
-    plan = wp.Plan(wl.N, wl.L, kb_W=wl.W)
+    plan = tuned(wp.Plan(wl.N, wl.L, kb_W=wl.W), args)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     Gs, skies = [], []
     t0 = time.perf_counter()
@@ -552,7 +569,7 @@ def bench_surrogate(args, wl):
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     log(f"bench: workload {wl.name} N={wl.N} M={wl.M} E={wl.E}: exact and surrogate forms")
     x, u, v, w = synth.workload_inputs(wl)
-    plan = wp.Plan(wl.N, wl.L, kb_W=wl.W)
+    plan = tuned(wp.Plan(wl.N, wl.L, kb_W=wl.W), args)
     ud, vd, wd = t(u), t(v), t(w)
     xd = t(x.astype(np.complex64).ravel())
     stream = torch.cuda.current_stream()
@@ -903,6 +920,8 @@ def main():
                                                      "cpu_baseline", "phi_vis_per_s", "phiT_vis_per_s")}
     else:
         out = bench_plain(args, wl)
+    if args.tune:
+        out["config"]["tuning"] = dict(args.tune)
     out["extra_keys"] = sorted(k for k in out if k not in (
         "metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
         "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"))

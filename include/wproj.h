@@ -151,8 +151,11 @@ wp_status wp_plan_destroy(wp_plan *plan);
  * stretch of a gather block (256, 384, 512 or 1024; it sets the block table that
  * wp_gather_table_size sizes and wp_build_G_fill writes, so change it only before
  * building G); "degrid_rows": rows per wavefront of
- * the degrid from factor records (1, 2 or 4).  Not thread-safe with concurrent
- * applies on the same plan.
+ * the degrid from factor records (1, 2 or 4).  "sur_degrid": the surrogate's
+ * degridding (wp_surrogate_degrid and the apply calls): 1 stages each cell's box
+ * through registers from the FP32 grid, 2 (the automatic choice) streams a
+ * bfloat16 copy of the grid and the weights straight into a three-stage LDS
+ * ring.  Not thread-safe with concurrent applies on the same plan.
  */
 wp_status wp_plan_set_tuning(wp_plan *plan, const char *key, int value);
 

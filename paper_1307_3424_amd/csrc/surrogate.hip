@@ -21,6 +21,7 @@
 // is the order of the coordinates wp_surrogate_fallback_coords returns (build the fallback
 // G from those, in caller order, or keep its sorted order consistently).
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "mlp_core.h"
@@ -34,6 +35,17 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint2 nt_load_u2(const uint16_t *p) {
     const u32x2 v = __builtin_nontemporal_load((const u32x2 *)p);
     return make_uint2(v.x, v.y);
+}
+__device__ __forceinline__ u32x4 nt_load_u4(const uint16_t *p) {
+    return __builtin_nontemporal_load((const u32x4 *)p);
+}
+// sum over each row of 16 lanes, left in every lane of the row (quad swaps, then half-row and row mirrors)
+__device__ __forceinline__ float dpp_sum16(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));  // half-row mirror
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));  // row mirror
+    return x;
 }
 __device__ __forceinline__ float2 nt_load_f2(const float2 *p) {
     typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -59,6 +71,7 @@ struct wp_surrogate {
     float *b4;          // [NOUT] output bias
     float *wmax;        // [2] largest output weight norm and |b4| (bounds of the gridding's fixed-point window)
     double *fb;         // [3 Mf] fallback u, v, w (slot order)
+    uint32_t *gbf;      // [Ng][Ng + 2 PADC] the degridding's grid in bfloat16 pairs, columns wrapped by PADC
 };
 
 namespace {
@@ -317,6 +330,234 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid(const float2 *__restrict_
     }
 }
 
+// ---------------------------------------------------------------------------- degridding, LDS ring
+
+// The degridding's A operand (each cell's 32 x 32 box) read straight into LDS: the grid is first
+// rounded to bfloat16 (re, im) pairs, 4 bytes per cell, with PADC wrapped columns on each side, so a
+// box row's 32 cells are one contiguous run whatever the cell (the box never wraps along u), and each
+// product step's 16 cells are 64 bytes.  Workgroups stream both operands with direct global-to-LDS
+// loads (16 bytes per lane, no registers) through a ring of three stages, each issued two steps before
+// its product; the step loop is unrolled by three, so every LDS access names its stage at compile time.
+// LDS rows are 64 bytes with their four 16-byte chunks permuted (chunk c of row r at slot
+// c ^ ((r >> 1) & 3)): the product's fragment reads, 32 rows of one chunk, spread over all banks.
+constexpr int PADC = 16;
+constexpr int RA = DG * 64, RB = DBN * 64;              // bytes of a stage: A rows, B rows
+constexpr int STG = RA + RB;
+constexpr int RPASS2 = 64;                              // cells per epilogue pass
+static_assert((size_t)RPASS2 * RLD * 4 + (2 * DG + 1) * 4 <= 3 * (size_t)STG, "epilogue must fit the ring");
+static_assert((KDEP / BK) % 3 == 1, "the step loop runs in threes plus one");
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+__device__ __forceinline__ int swz(int r, int c) { return c ^ ((r >> 1) & 3); }
+
+// acc[fm][fn] += A rows [arow0 + 32 fm, +32) times B rows [brow0 + 32 fn, +32), one 32-deep step, from
+// a stage's permuted 64-byte rows
+template <int FM, int FN>
+__device__ __forceinline__ void mma_ring(f32x16 (&acc)[FM][FN], const unsigned char *As, const unsigned char *Bs,
+                                         int arow0, int brow0, int lane) {
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+        const int c = kk / 8 + (lane >> 5), ro = lane & 31;
+        bf16x8 a[FM], b[FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) {
+            const int r = arow0 + 32 * fm + ro;
+            a[fm] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(As + r * 64 + swz(r, c) * 16));
+        }
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            const int r = brow0 + 32 * fn + ro;
+            b[fn] = __builtin_bit_cast(bf16x8, *(const u32x4 *)(Bs + r * 64 + swz(r, c) * 16));
+        }
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+                acc[fm][fn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[fm], b[fn], acc[fm][fn], 0, 0, 0);
+    }
+}
+
+// gbf[gy][pc] = the cell (gy, (pc - PADC) mod Ng) of the grid as a bfloat16 pair (re low, im high)
+__global__ void k_grid_bf16_pad(const float2 *__restrict__ grid, int logNg, uint32_t *__restrict__ gbf) {
+    const int Ng = 1 << logNg, RS = Ng + 2 * PADC;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)Ng * RS) return;
+    const int gy = (int)(e / RS), pc = (int)(e % RS);
+    const float2 g = grid[(int64_t)gy * Ng + ((pc - PADC) & (Ng - 1))];
+    gbf[e] = (uint32_t)to_bf16(g.x) | ((uint32_t)to_bf16(g.y) << 16);
+}
+
+// s_waitcnt: vector memory count <= N (N < 16), LDS count 0, export count unconstrained
+template <int N>
+__device__ __forceinline__ void wait_vm_lgkm0() {
+    static_assert(N >= 0 && N < 16, "vmcnt");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | (0x7 << 4));
+}
+
+template <int V>
+using ic = std::integral_constant<int, V>;
+
+// Same work and outputs as k_sur_degrid (two workgroups per group of <= DG cells, part 0 / 1 form
+// r re / r im), operands through the LDS ring.  Per step each wave loads one 16-row piece of A (1 KB)
+// and two of B: three loads, the only vector memory operations of the loop, so "this wave's stage t
+// has landed" is "at most the three loads of stage t + 1 are outstanding".  Epilogue: r of 64 cells at
+// a time in the ring (FP32), then one visibility per 16 lanes, two per group of lanes in flight: the
+// hidden layer read in two 16-byte pieces per lane, the dot product summed across the row of lanes.
+__global__ __launch_bounds__(DNT, 4) void k_sur_degrid_ring(const uint32_t *__restrict__ gbf, int logNg,
+                                                            const int *__restrict__ grp, int ngrp,
+                                                            const int *__restrict__ cell_key,
+                                                            const int *__restrict__ cell_start,
+                                                            const uint16_t *__restrict__ h3,
+                                                            const uint16_t *__restrict__ Bdeg,
+                                                            const float *__restrict__ b4, float s_out,
+                                                            float2 *__restrict__ y) {
+    __shared__ __align__(16) unsigned char ring[3 * STG];
+    __shared__ float2 s_b4[BOX * BOX];               // output bias
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 2, wn = wave & 3;
+    const int part = blockIdx.y;
+    for (int i = tid; i < BOX * BOX; i += DNT) s_b4[i] = ((const float2 *)b4)[i];
+    const int g = (int)xcd_block(blockIdx.x, ngrp);
+    const int c0 = grp[g], nc = grp[g + 1] - c0;
+    const int Ng = 1 << logNg, RS = Ng + 2 * PADC;
+    // this lane's pieces: A row ra (its grid cell), B rows rb0, rb1; the permuted chunk it carries
+    const int ra = 16 * wave + (lane >> 2), rb0 = 32 * wave + (lane >> 2), rb1 = rb0 + 16;
+    const int ca = swz(ra, lane & 3), cb0 = swz(rb0, lane & 3), cb1 = swz(rb1, lane & 3);
+    int acv = 0, acu = 0;                            // rows past the group read cell (0, 0): in bounds, unused
+    if (ra < nc) demorton2(cell_key[c0 + ra], acv, acu);
+    // byte offsets: a uniform base plus a 32-bit per-lane part (the padded grid is < 4 GiB)
+    const char *gA = (const char *)gbf;
+    const char *gB = (const char *)(Bdeg + (int64_t)part * DBN * KDEP);   // [step][256][32]
+    const uint32_t a_col = 4u * (uint32_t)(acu + 4 * ca), a_row = 4u * (uint32_t)RS;
+    const uint32_t b_off0 = 2u * (uint32_t)(rb0 * 32 + 8 * cb0), b_off1 = 2u * (uint32_t)(rb1 * 32 + 8 * cb1);
+    auto stage = [&](auto sc) -> unsigned char * {
+        constexpr int S = decltype(sc)::value;
+        return ring + S * STG;
+    };
+    // the loads' LDS destinations as wave-uniform 32-bit addresses: the ring's waits are the explicit ones
+    // of each step, not ones derived from the destinations
+    auto lds_dst = [&](const unsigned char *p) {
+        const uint32_t a = (uint32_t)(uintptr_t)(const lds_void_t *)p;
+        return (lds_void_t *)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)a);
+    };
+    auto issue = [&](int t, auto sc) {
+        unsigned char *st = stage(sc);
+        const uint32_t gy = (uint32_t)((acv + (t >> 1) - BOX / 2) & (Ng - 1));
+        __builtin_amdgcn_global_load_lds((const void *)(gA + (gy * a_row + a_col + 64u * (t & 1))),
+                                         lds_dst(st + 16 * wave * 64), 16, 0, 0);
+        const char *gBt = gB + (size_t)t * DBN * 64;
+        __builtin_amdgcn_global_load_lds((const void *)(gBt + b_off0), lds_dst(st + RA + 32 * wave * 64), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(gBt + b_off1), lds_dst(st + RA + (32 * wave + 16) * 64), 16,
+                                         0, 0);
+    };
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    // bias term of each cell: thread -> cell si, one 16-byte chunk (4 box cells) of the step's 16
+    const int si = tid >> 2, sq = tid & 3;
+    float bacc = 0.0f;
+    constexpr int NSTEP = KDEP / BK;
+    __syncthreads();                                 // s_b4
+    auto step = [&](int t, auto sc) {
+        constexpr int S = decltype(sc)::value;
+        if (t + 1 < NSTEP) wait_vm_lgkm0<3>(); else wait_vm_lgkm0<0>();
+        __builtin_amdgcn_s_barrier();                // every wave's stage t is in; every wave is past step t - 1
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (t + 2 < NSTEP) issue(t + 2, ic<(S + 2) % 3>{});
+        const unsigned char *st = stage(sc);
+        {
+            const u32x4 a = *(const u32x4 *)(st + si * 64 + swz(si, sq) * 16);
+            const int p0 = 16 * t + 4 * sq;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float xr = __uint_as_float(a[e] << 16), xi = __uint_as_float(a[e] & 0xffff0000u);
+                const float2 bb = s_b4[p0 + e];
+                bacc += part == 0 ? bb.x * xr - bb.y * xi : bb.x * xi + bb.y * xr;
+            }
+        }
+        mma_ring<2, 2>(acc, st, st + RA, 64 * wm, 64 * wn, lane);
+    };
+    issue(0, ic<0>{});
+    issue(1, ic<1>{});
+    for (int t = 0; t < NSTEP - 1; t += 3) {
+        step(t, ic<0>{});
+        step(t + 1, ic<1>{});
+        step(t + 2, ic<2>{});
+    }
+    step(NSTEP - 1, ic<0>{});
+    __syncthreads();                                 // the ring becomes the epilogue's r, starts and biases
+    float *Rl = (float *)ring;                       // [RPASS2][RLD] FP32
+    int *s_cs = (int *)(ring + RPASS2 * RLD * 4);
+    float *s_beta = (float *)(s_cs + DG + 1);
+    for (int i = tid; i <= nc; i += DNT) s_cs[i] = cell_start[c0 + i];
+    bacc += __shfl_xor(bacc, 1);
+    bacc += __shfl_xor(bacc, 2);
+    if (sq == 0) s_beta[si] = bacc;
+    const int lg = wave * 4 + (lane >> 4), lj = lane & 15;   // 32 groups of 16 lanes; lane lj of its group
+    for (int pass = 0; pass < DG / RPASS2; ++pass) {
+        const int c_lo = RPASS2 * pass;
+        if (c_lo >= nc) break;                       // uniform over the workgroup
+        const int c_hi = min(c_lo + RPASS2, nc);
+        if (wm == pass) {                            // cells [64 pass, +64): the accumulators of the waves of row pass
+#pragma unroll
+            for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < 2; ++fn)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        Rl[(32 * fm + acc_row(r, lane)) * RLD + 64 * wn + 32 * fn + (lane & 31)] = acc[fm][fn][r];
+        }
+        __syncthreads();
+        const int vb = s_cs[c_lo], ve = s_cs[c_hi];
+        // visibilities v0 = vb + lg + 64 i and v0 + 32: hidden units 8 lj .. 8 lj + 7 and 128 + 8 lj .. + 7
+        for (int v0 = vb + lg; v0 < ve; v0 += 64) {
+            const int v1 = v0 + 32;
+            const bool ok1 = v1 < ve;
+            const uint16_t *h0 = h3 + (int64_t)v0 * H + 8 * lj, *h1 = h3 + (int64_t)(ok1 ? v1 : v0) * H + 8 * lj;
+            const u32x4 a0 = nt_load_u4(h0), b0 = nt_load_u4(h0 + H / 2);
+            const u32x4 a1 = nt_load_u4(h1), b1 = nt_load_u4(h1 + H / 2);
+            int cl[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int v = q == 0 ? v0 : (ok1 ? v1 : v0);
+                int lo = c_lo, hi = c_hi - 1;        // cell of visibility v
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_cs[mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                cl[q] = lo;
+            }
+            float sum[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const u32x4 ha = q == 0 ? a0 : a1, hb = q == 0 ? b0 : b1;
+                const float *rr = Rl + (cl[q] - c_lo) * RLD + 8 * lj;
+                const float4 r0 = *(const float4 *)rr, r1 = *(const float4 *)(rr + 4);
+                const float4 r2 = *(const float4 *)(rr + H / 2), r3 = *(const float4 *)(rr + H / 2 + 4);
+                float acc_s = __uint_as_float(ha[0] << 16) * r0.x + __uint_as_float(ha[0] & 0xffff0000u) * r0.y;
+                acc_s += __uint_as_float(ha[1] << 16) * r0.z + __uint_as_float(ha[1] & 0xffff0000u) * r0.w;
+                acc_s += __uint_as_float(ha[2] << 16) * r1.x + __uint_as_float(ha[2] & 0xffff0000u) * r1.y;
+                acc_s += __uint_as_float(ha[3] << 16) * r1.z + __uint_as_float(ha[3] & 0xffff0000u) * r1.w;
+                acc_s += __uint_as_float(hb[0] << 16) * r2.x + __uint_as_float(hb[0] & 0xffff0000u) * r2.y;
+                acc_s += __uint_as_float(hb[1] << 16) * r2.z + __uint_as_float(hb[1] & 0xffff0000u) * r2.w;
+                acc_s += __uint_as_float(hb[2] << 16) * r3.x + __uint_as_float(hb[2] & 0xffff0000u) * r3.y;
+                acc_s += __uint_as_float(hb[3] << 16) * r3.z + __uint_as_float(hb[3] & 0xffff0000u) * r3.w;
+                sum[q] = dpp_sum16(acc_s);
+            }
+            if (lj == 0) {
+                ((float *)&y[v0])[part] = s_out * (sum[0] + s_beta[cl[0]]);
+                if (ok1) ((float *)&y[v1])[part] = s_out * (sum[1] + s_beta[cl[1]]);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------- gridding
 
 // One workgroup per group of <= AG consecutive occupied cells whose boxes fit the LDS window:
@@ -502,6 +743,14 @@ wp_status check_sur(const wp_plan *p, const wp_surrogate *s) {
 
 wp_status sur_degrid(const wp_plan *p, const wp_surrogate *S, const float2 *grid, float2 *y, hipStream_t s) {
     if (S->Ms == 0) return WP_OK;
+    const int form = p->sur_degrid > 0 ? p->sur_degrid : 2;
+    if (form == 2) {
+        const int64_t n = (int64_t)p->Ng * (p->Ng + 2 * PADC);
+        hipLaunchKernelGGL(k_grid_bf16_pad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, grid, p->logNg, S->gbf);
+        hipLaunchKernelGGL(k_sur_degrid_ring, dim3(S->ngrp_d, 2), dim3(DNT), 0, s, S->gbf, p->logNg, S->grp_d,
+                           S->ngrp_d, S->cell_key, S->cell_start, S->h3, S->Bdeg, S->b4, S->s_out, y);
+        return wp_check_launch("k_sur_degrid_ring");
+    }
     hipLaunchKernelGGL(k_sur_degrid, dim3(S->ngrp_d, 2), dim3(DNT), DEG_LDS, s, grid, p->logNg, S->grp_d, S->ngrp_d,
                        S->cell_key, S->cell_start, S->h3, S->Bdeg, S->b4, S->s_out, y);
     return wp_check_launch("k_sur_degrid");
@@ -669,6 +918,9 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
         WP_HIP(hipStreamSynchronize(s));
         // last hidden layer of every surrogate row, in slot order
         if (hipMalloc((void **)&S->h3, (size_t)Ms * H * 2) != hipSuccess) return fail(WP_ENOMEM, "hidden features");
+        // the degridding's bfloat16 copy of the grid, with wrapped columns
+        if (hipMalloc((void **)&S->gbf, (size_t)p->Ng * (p->Ng + 2 * PADC) * 4) != hipSuccess)
+            return fail(WP_ENOMEM, "bfloat16 grid");
         for (int64_t j0 = 0; j0 < Ms; j0 += m->max_batch) {
             const int n = (int)std::min<int64_t>(m->max_batch, Ms - j0);
             hipLaunchKernelGGL(k_feat_slots, dim3((3 * n + 255) / 256), dim3(256), 0, s, (const float *)feat.p,
@@ -693,7 +945,7 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
 wp_status wp_surrogate_destroy(wp_surrogate *S) {
     if (!S) return WP_OK;
     void *bufs[] = {S->slot_vis, S->cell_key, S->cell_start, S->grp_d, S->grp_a, S->grp_org, S->h3, S->Bdeg,
-                    S->Bgrd, S->b4, S->wmax, S->fb};
+                    S->Bgrd, S->b4, S->wmax, S->fb, S->gbf};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(S);

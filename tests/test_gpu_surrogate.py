@@ -76,6 +76,39 @@ def test_degrid_matches_oracle_on_bf16_exact_grids(setup):
     sur.close()
 
 
+def test_degrid_forms_agree(setup):
+    """The LDS-ring degridding (form 2, the default) reads the grid rounded to bfloat16, which is also
+    what the register-staged form (1) feeds its products, and runs the same products in the same order;
+    it sums the bias term b4 . box from the rounded grid and each visibility's dot product h . r in
+    another order.  So on grids exact in bfloat16 the two differ by FP32 rounding only, and on general
+    grids by at most 2^-9 of sum |b4| |X| per row and component more (the bias from the FP32 grid in
+    form 1)."""
+    d = setup
+    plan = d["plan"]
+    sur = W.Surrogate(plan, d["mlp"], _dev(d["u"]), _dev(d["v"]), _dev(d["w"]))
+    Ng = d["s"].Ng
+    rng = np.random.default_rng(29)
+    X = (_bf16_exact(Ng * Ng, rng) + 1j * _bf16_exact(Ng * Ng, rng)).astype(np.complex64)
+    Xg = (rng.normal(size=Ng * Ng) + 1j * rng.normal(size=Ng * Ng)).astype(np.complex64)
+    out = {}
+    try:
+        for form in (1, 2):
+            plan.set_tuning("sur_degrid", form)
+            out[form] = (sur.degrid(_dev(X)).cpu().numpy(), sur.degrid(_dev(Xg)).cpu().numpy())
+    finally:
+        plan.set_tuning("sur_degrid", 0)
+    slot = sur.slots().cpu().numpy()
+    cols, _ = S.surrogate_rows(d["net"], d["u"], d["v"], d["w"], d["s"], q=S.round_bf16)
+    b4 = d["net"].b4.reshape(-1, 2)
+    bmag = np.abs(b4[:, 0] + 1j * b4[:, 1]) * d["net"].s_out
+    for k, (Xk, bf16_exact) in enumerate(((X, True), (Xg, False))):
+        bsum = np.sum(bmag[None, :] * np.abs(Xk[cols]), axis=1)[slot]
+        y1, y2 = out[1][k], out[2][k]
+        bound = 2e-6 * np.abs(y1).max() + (1e-5 if bf16_exact else 2.0 ** -9 * np.sqrt(2.0) + 1e-5) * bsum
+        assert np.all(np.abs(y1 - y2) <= bound), k
+    sur.close()
+
+
 def test_grid_add_matches_oracle_with_exact_cell_sums(setup):
     d = setup
     sur = W.Surrogate(d["plan"], d["mlp"], _dev(d["u"]), _dev(d["v"]), _dev(d["w"]))
