@@ -155,7 +155,11 @@ wp_status wp_plan_destroy(wp_plan *plan);
  * degridding (wp_surrogate_degrid and the apply calls): 1 stages each cell's box
  * through registers from the FP32 grid, 2 (the automatic choice) streams a
  * bfloat16 copy of the grid and the weights straight into a three-stage LDS
- * ring.  Not thread-safe with concurrent applies on the same plan.
+ * ring.  "sur_grid": the surrogate's gridding (wp_surrogate_grid_add and the
+ * adjoint apply): 1 streams the weights from L2 into registers for groups of
+ * <= 32 cells, 2 (the automatic choice) forms each cell's s once, then runs
+ * groups of <= 128 cells in slices of 256 outputs through the LDS ring.  Not
+ * thread-safe with concurrent applies on the same plan.
  */
 wp_status wp_plan_set_tuning(wp_plan *plan, const char *key, int value);
 

@@ -188,6 +188,11 @@ wp_status wp_plan_set_tuning(wp_plan *p, const char *key, int value) {
         p->tune_gather_chunk = value;
         return WP_OK;
     }
+    if (!std::strcmp(key, "sur_grid")) {
+        if (value < 0 || value > 2) return wp_set_error(WP_EINVAL, "sur_grid %d: 0, 1 or 2", value);
+        p->sur_grid = value;
+        return WP_OK;
+    }
     if (!std::strcmp(key, "sur_degrid")) {
         if (value < 0 || value > 2) return wp_set_error(WP_EINVAL, "sur_degrid %d: 0, 1 or 2", value);
         p->sur_degrid = value;

@@ -35,6 +35,7 @@ struct wp_plan {
     int solve_graph;                      // solver loop: 0 automatic (direct launches), 1 HIP graph, 2 direct
     int exact_rows;                       // exact chirp rows: 0 automatic, 1 separable expansion, 2 whole 2-D
     int sur_degrid;                       // surrogate degridding: 0 automatic (2), 1 register-staged, 2 LDS ring
+    int sur_grid;                         // surrogate gridding: 0 automatic (2), 1 register-staged, 2 LDS ring
     float *apod;    // [N]  1 / g(xi), xi = (p - N/2) / Ng       (device)
     float2 *tw32;   // [Ng] exp(-2 pi i k / Ng), FP32             (device)
     double2 *tw64;  // [Ng] exp(-2 pi i k / Ng), FP64             (device)

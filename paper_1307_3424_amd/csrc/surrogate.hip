@@ -72,6 +72,13 @@ struct wp_surrogate {
     float *wmax;        // [2] largest output weight norm and |b4| (bounds of the gridding's fixed-point window)
     double *fb;         // [3 Mf] fallback u, v, w (slot order)
     uint32_t *gbf;      // [Ng][Ng + 2 PADC] the degridding's grid in bfloat16 pairs, columns wrapped by PADC
+    // the gridding through the LDS ring
+    uint16_t *Bgrd2;    // [NSL][ND / 32][256][32] weights of each slice of 256 outputs, step-major
+    uint16_t *Sg;       // [ncell][ND] s of each cell in bfloat16, rewritten by every gridding
+    float4 *cY;         // [ncell] (sum of y re, sum of y im, bound on the cell's outputs / s_out, 0)
+    int *grp_g;         // [ngrp_g + 1] first cell of each ring-gridding group
+    int2 *grp_gorg;     // [ngrp_g] smallest (v, u) of each ring-gridding group's cells
+    int ngrp_g;
 };
 
 namespace {
@@ -91,6 +98,9 @@ constexpr int ANT = 256;            // threads of a gridding workgroup (4 waves)
 constexpr int WV = 64, WU = 64;     // LDS window (cells); a group's cells span at most WV - BOX + 1 rows
 constexpr int SLD = ND + 8;         // row stride of the staged A operand (s, 512 values)
 constexpr size_t GRD_LDS = (size_t)AG * SLD * 2 + (size_t)WV * WU * 8;
+constexpr int NSL = NOUT / 256;      // slices of 256 outputs (4 box rows) of the ring gridding
+constexpr int GSPAN = 64;            // a ring-gridding group's cells span at most GSPAN rows and GSPAN columns
+constexpr int GWR = GSPAN + 4, GWC = GSPAN + BOX;   // its LDS window per slice (cells)
 
 __device__ inline int cell_index(double gt, int Ng) {
     const long long c = (long long)floor(gt + 0.5) + Ng / 2;
@@ -156,6 +166,10 @@ __device__ inline int64_t deg_index(int n, int kk) {
 __device__ inline int64_t grd_index(int o, int k) {
     return ((int64_t)((o / 32) * (ND / 16) + k / 16) * 64 + (o % 32) + 32 * ((k % 16) / 8)) * 8 + (k % 8);
 }
+//   Bgrd2[o][k], the same weights for the ring gridding: [slice o / 256][step k / 32][o % 256][k % 32]
+__device__ inline int64_t grd2_index(int o, int k) {
+    return ((int64_t)((o / 256) * (ND / 32) + k / 32) * 256 + (o % 256)) * 32 + (k % 32);
+}
 
 // largest Euclidean norm of an output's bfloat16 weights in the gridding product (over its 512
 // inputs) and largest |b4| (non-negative floats order like their bit patterns, so an integer
@@ -172,7 +186,8 @@ __global__ void k_weight_max(const uint16_t *__restrict__ Bgrd, const float *__r
     atomicMax((int *)&wmax[1], __float_as_int(fabsf(b4[o])));
 }
 
-__global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bdeg, uint16_t *__restrict__ Bgrd) {
+__global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bdeg, uint16_t *__restrict__ Bgrd,
+                         uint16_t *__restrict__ Bgrd2) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)NOUT * H) return;
     const int p = (int)(e / H), j = (int)(e % H);      // box cell p, hidden j
@@ -187,6 +202,10 @@ __global__ void k_make_B(const float *__restrict__ W4, uint16_t *__restrict__ Bd
     Bgrd[grd_index(2 * p, H + j)] = bi;
     Bgrd[grd_index(2 * p + 1, j)] = nbi;
     Bgrd[grd_index(2 * p + 1, H + j)] = br;
+    Bgrd2[grd2_index(2 * p, j)] = br;
+    Bgrd2[grd2_index(2 * p, H + j)] = bi;
+    Bgrd2[grd2_index(2 * p + 1, j)] = nbi;
+    Bgrd2[grd2_index(2 * p + 1, H + j)] = br;
 }
 
 // ---------------------------------------------------------------------------- degridding
@@ -734,6 +753,214 @@ __global__ __launch_bounds__(ANT, 2) void k_sur_grid(const float2 *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------------------- gridding, LDS ring
+
+// s of every cell, the A operand of the ring gridding: s_c = sum over the cell's visibilities of
+// h_k y_k (k < 256: with Re y, k >= 256: with Im y) in bfloat16, with the cell's sum of y and a bound
+// on its outputs / s_out (as the register-staged gridding bounds them).  One cell per 16 lanes: lane j
+// holds hidden units 8 j .. 8 j + 7 and 128 + 8 j .. + 7; two visibilities' loads in flight.
+__global__ __launch_bounds__(256) void k_sur_cell_s(const float2 *__restrict__ y, const int *__restrict__ cell_start,
+                                                    int ncell, const uint16_t *__restrict__ h3,
+                                                    const float *__restrict__ wmax, uint16_t *__restrict__ Sg,
+                                                    float4 *__restrict__ cY) {
+    const int c = blockIdx.x * 16 + (threadIdx.x >> 4), j = threadIdx.x & 15;
+    if (c >= ncell) return;                          // whole rows of 16 lanes
+    const int vb = cell_start[c], ve = cell_start[c + 1];
+    float sr[16], si[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sr[e] = si[e] = 0.0f;
+    float2 Y = make_float2(0.f, 0.f);
+    for (int v = vb; v < ve; v += 2) {
+        const bool two = v + 1 < ve;
+        const uint16_t *h0 = h3 + (int64_t)v * H + 8 * j, *h1 = h3 + (int64_t)(two ? v + 1 : v) * H + 8 * j;
+        const u32x4 a0 = nt_load_u4(h0), b0 = nt_load_u4(h0 + H / 2);
+        const u32x4 a1 = nt_load_u4(h1), b1 = nt_load_u4(h1 + H / 2);
+        const float2 y0 = y[v], y1 = two ? y[v + 1] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const u32x4 ha = q == 0 ? a0 : a1, hb = q == 0 ? b0 : b1;
+            const float2 yk = q == 0 ? y0 : y1;      // zero for the absent second visibility
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float l0 = __uint_as_float(ha[e] << 16), l1 = __uint_as_float(ha[e] & 0xffff0000u);
+                const float m0 = __uint_as_float(hb[e] << 16), m1 = __uint_as_float(hb[e] & 0xffff0000u);
+                sr[2 * e] += l0 * yk.x; si[2 * e] += l0 * yk.y;
+                sr[2 * e + 1] += l1 * yk.x; si[2 * e + 1] += l1 * yk.y;
+                sr[8 + 2 * e] += m0 * yk.x; si[8 + 2 * e] += m0 * yk.y;
+                sr[8 + 2 * e + 1] += m1 * yk.x; si[8 + 2 * e + 1] += m1 * yk.y;
+            }
+            Y.x += yk.x;
+            Y.y += yk.y;
+        }
+    }
+    u32x4 o[4];                                      // re lo, re hi, im lo, im hi pieces
+    float l2 = 0.0f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint16_t r0 = to_bf16(sr[2 * e]), r1 = to_bf16(sr[2 * e + 1]);
+        const uint16_t r2 = to_bf16(sr[8 + 2 * e]), r3 = to_bf16(sr[8 + 2 * e + 1]);
+        const uint16_t i0 = to_bf16(si[2 * e]), i1 = to_bf16(si[2 * e + 1]);
+        const uint16_t i2 = to_bf16(si[8 + 2 * e]), i3 = to_bf16(si[8 + 2 * e + 1]);
+        o[0][e] = (uint32_t)r0 | ((uint32_t)r1 << 16);
+        o[1][e] = (uint32_t)r2 | ((uint32_t)r3 << 16);
+        o[2][e] = (uint32_t)i0 | ((uint32_t)i1 << 16);
+        o[3][e] = (uint32_t)i2 | ((uint32_t)i3 << 16);
+        const uint16_t vals[8] = {r0, r1, r2, r3, i0, i1, i2, i3};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float f = from_bf16(vals[q]);
+            l2 = fmaf(f, f, l2);
+        }
+    }
+    uint16_t *row = Sg + (int64_t)c * ND + 8 * j;
+    *(u32x4 *)row = o[0];
+    *(u32x4 *)(row + H / 2) = o[1];
+    *(u32x4 *)(row + H) = o[2];
+    *(u32x4 *)(row + H + H / 2) = o[3];
+    l2 = dpp_sum16(l2);
+    // |A_c . B_o| <= ||A_c||_2 ||B_o||_2 (Cauchy-Schwarz) and |bias| <= max|b4| (|Y re| + |Y im|)
+    if (j == 0) cY[c] = make_float4(Y.x, Y.y, sqrtf(l2) * 1.0001f * wmax[0] + wmax[1] * (fabsf(Y.x) + fabsf(Y.y)), 0.f);
+}
+
+// The box contributions s_out (W4 s_c + conj(b4) Y_c) of a group of <= DG cells spanning at most GSPAN
+// rows and columns, for one slice of 256 outputs (box rows 4 sl .. 4 sl + 3): the product of the cells'
+// s [DG x 512] and the slice's weights [256 x 512] through the same three-stage ring of direct loads as
+// the degridding (16 steps of 32), then added in 32-bit fixed point into an LDS window over the ring
+// (the slice's box rows of every cell: (span + 4) x (span + 32) cells) and flushed to the grid with
+// atomics.  The eight slices of a group are consecutive blocks on one XCD, so they share its s in L2.
+__global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__restrict__ Sg,
+                                                          const float4 *__restrict__ cY, int logNg,
+                                                          const int *__restrict__ grp, const int2 *__restrict__ org,
+                                                          int ngrp, const int *__restrict__ cell_key,
+                                                          const uint16_t *__restrict__ Bgrd2,
+                                                          const float *__restrict__ b4, float s_out,
+                                                          float2 *__restrict__ grid) {
+    __shared__ __align__(16) unsigned char ring[3 * STG];
+    __shared__ int s_woff[DG];
+    __shared__ float2 s_Y[DG];
+    __shared__ int s_gmax;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 2, wn = wave & 3;
+    const int lb = (int)xcd_block(blockIdx.x, (int64_t)ngrp * NSL);
+    const int g = lb / NSL, sl = lb % NSL;
+    const int c0 = grp[g], nc = grp[g + 1] - c0;
+    const int2 o0 = org[g];                          // smallest (v, u) of the group's cells
+    const int Ng = 1 << logNg;
+    if (tid == 0) s_gmax = 0;
+    __syncthreads();
+    for (int i = tid; i < DG; i += DNT) {
+        int woff = 0;
+        float2 Yi = make_float2(0.f, 0.f);
+        if (i < nc) {
+            int cv, cu;
+            demorton2(cell_key[c0 + i], cv, cu);
+            woff = (cv - o0.x) * GWC + (cu - o0.y);
+            const float4 cy = cY[c0 + i];
+            Yi = make_float2(cy.x, cy.y);
+            atomicMax(&s_gmax, __float_as_int(cy.z));    // non-negative floats order like their bit patterns
+        }
+        s_woff[i] = woff;
+        s_Y[i] = Yi;
+    }
+    // this lane's pieces: A row ra (a cell of the group; rows past it repeat the last cell, unused), B rows rb0, rb1
+    const int ra = 16 * wave + (lane >> 2), rb0 = 32 * wave + (lane >> 2), rb1 = rb0 + 16;
+    const int ca = swz(ra, lane & 3), cb0 = swz(rb0, lane & 3), cb1 = swz(rb1, lane & 3);
+    const char *arow = (const char *)(Sg + (int64_t)(c0 + min(ra, nc - 1)) * ND) + 16 * ca;
+    const char *gB = (const char *)(Bgrd2 + (int64_t)sl * 256 * ND);     // [step][256][32]
+    const uint32_t b_off0 = 2u * (uint32_t)(rb0 * 32 + 8 * cb0), b_off1 = 2u * (uint32_t)(rb1 * 32 + 8 * cb1);
+    auto stage = [&](auto sc) -> unsigned char * {
+        constexpr int S = decltype(sc)::value;
+        return ring + S * STG;
+    };
+    auto lds_dst = [&](const unsigned char *p) {
+        const uint32_t a = (uint32_t)(uintptr_t)(const lds_void_t *)p;
+        return (lds_void_t *)(uintptr_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)a);
+    };
+    auto issue = [&](int t, auto sc) {
+        unsigned char *st = stage(sc);
+        __builtin_amdgcn_global_load_lds((const void *)(arow + 64 * t), lds_dst(st + 16 * wave * 64), 16, 0, 0);
+        const char *gBt = gB + (size_t)t * 256 * 64;
+        __builtin_amdgcn_global_load_lds((const void *)(gBt + b_off0), lds_dst(st + RA + 32 * wave * 64), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void *)(gBt + b_off1), lds_dst(st + RA + (32 * wave + 16) * 64), 16,
+                                         0, 0);
+    };
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    constexpr int NSTEP = ND / BK;
+    static_assert(NSTEP % 3 == 1, "the step loop runs in threes plus one");
+    auto step = [&](int t, auto sc) {
+        constexpr int S = decltype(sc)::value;
+        if (t + 1 < NSTEP) wait_vm_lgkm0<3>(); else wait_vm_lgkm0<0>();
+        __builtin_amdgcn_s_barrier();                // every wave's stage t is in; every wave is past step t - 1
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (t + 2 < NSTEP) issue(t + 2, ic<(S + 2) % 3>{});
+        const unsigned char *st = stage(sc);
+        mma_ring<2, 2>(acc, st, st + RA, 64 * wm, 64 * wn, lane);
+    };
+    issue(0, ic<0>{});
+    issue(1, ic<1>{});
+    for (int t = 0; t < NSTEP - 1; t += 3) {
+        step(t, ic<0>{});
+        step(t + 1, ic<1>{});
+        step(t + 2, ic<2>{});
+    }
+    step(NSTEP - 1, ic<0>{});
+    __syncthreads();                                 // the ring becomes the window
+    int2 *win = (int2 *)ring;                        // [GWR][GWC] fixed point (re, im)
+    static_assert((size_t)GWR * GWC * 8 <= 3 * (size_t)STG, "window must fit the ring");
+    for (int e = tid; e < GWR * GWC; e += DNT) win[e] = make_int2(0, 0);
+    // the scale: at most DG cells reach one window cell, each by at most the group's largest bound, so
+    // every sum stays within 2^29 < 2^31
+    const float gmax = __int_as_float(s_gmax);
+    const float q = gmax > 0.f ? 536870912.0f / (gmax * s_out * (float)DG) : 1.0f;
+    const float qs = q * s_out;
+    // this lane's two outputs (one per fn): window offset within a cell's box rows, component, bias weights
+    int wo[2], comp[2];
+    float br[2], bi[2];
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn) {
+        const int oo = 256 * sl + 64 * wn + 32 * fn + (lane & 31);
+        const int p = oo >> 1;
+        comp[fn] = oo & 1;
+        wo[fn] = ((p >> 5) - 4 * sl) * GWC + (p & (BOX - 1));
+        br[fn] = b4[2 * p];
+        bi[fn] = b4[2 * p + 1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int fm = 0; fm < 2; ++fm)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = 64 * wm + 32 * fm + acc_row(r, lane);
+            if (i < nc) {
+                const int wc = s_woff[i];
+                const float2 Y = s_Y[i];
+#pragma unroll
+                for (int fn = 0; fn < 2; ++fn) {
+                    const float bias = comp[fn] == 0 ? br[fn] * Y.x + bi[fn] * Y.y : br[fn] * Y.y - bi[fn] * Y.x;
+                    atomicAdd((int *)&win[wc + wo[fn]] + comp[fn], __float2int_rn(qs * (acc[fm][fn][r] + bias)));
+                }
+            }
+        }
+    __syncthreads();
+    const float iq = 1.0f / q;
+    const int gv0 = o0.x - BOX / 2 + 4 * sl, gu0 = o0.y - BOX / 2;
+    for (int e = tid; e < GWR * GWC; e += DNT) {
+        const int2 wi = win[e];
+        if (wi.x != 0 || wi.y != 0) {
+            const int gy = (gv0 + e / GWC) & (Ng - 1), gx = (gu0 + e % GWC) & (Ng - 1);
+            float *dst = (float *)&grid[(int64_t)gy * Ng + gx];
+            atomicAdd(dst, (float)wi.x * iq);
+            atomicAdd(dst + 1, (float)wi.y * iq);
+        }
+    }
+}
+
 wp_status check_sur(const wp_plan *p, const wp_surrogate *s) {
     if (!p) return wp_set_error(WP_EINVAL, "plan is NULL");
     if (!s) return wp_set_error(WP_EINVAL, "surrogate is NULL");
@@ -758,6 +985,16 @@ wp_status sur_degrid(const wp_plan *p, const wp_surrogate *S, const float2 *grid
 
 wp_status sur_grid_add(const wp_plan *p, const wp_surrogate *S, const float2 *y, float2 *grid, hipStream_t s) {
     if (S->Ms == 0) return WP_OK;
+    const int form = p->sur_grid > 0 ? p->sur_grid : 2;
+    if (form == 2) {
+        hipLaunchKernelGGL(k_sur_cell_s, dim3((unsigned)((S->ncell + 15) / 16)), dim3(256), 0, s, y, S->cell_start,
+                           (int)S->ncell, S->h3, S->wmax, S->Sg, S->cY);
+        wp_status st = wp_check_launch("k_sur_cell_s");
+        if (st != WP_OK) return st;
+        hipLaunchKernelGGL(k_sur_grid_ring, dim3((unsigned)((int64_t)S->ngrp_g * NSL)), dim3(DNT), 0, s, S->Sg, S->cY,
+                           p->logNg, S->grp_g, S->grp_gorg, S->ngrp_g, S->cell_key, S->Bgrd2, S->b4, S->s_out, grid);
+        return wp_check_launch("k_sur_grid_ring");
+    }
     hipLaunchKernelGGL(k_sur_grid, dim3(S->ngrp_a), dim3(ANT), GRD_LDS, s, y, p->logNg, S->grp_a, S->grp_org,
                        S->ngrp_a, S->cell_key, S->cell_start, S->h3, S->Bgrd, S->b4, S->wmax, S->s_out, grid);
     return wp_check_launch("k_sur_grid");
@@ -853,10 +1090,11 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
     }
     if (hipMalloc((void **)&S->Bdeg, (size_t)ND * KDEP * 2) != hipSuccess ||
         hipMalloc((void **)&S->Bgrd, (size_t)NOUT * ND * 2) != hipSuccess ||
+        hipMalloc((void **)&S->Bgrd2, (size_t)NOUT * ND * 2) != hipSuccess ||
         hipMalloc((void **)&S->b4, (size_t)NOUT * 4) != hipSuccess)
         return fail(WP_ENOMEM, "weights");
     hipLaunchKernelGGL(k_make_B, dim3((unsigned)((NOUT * H + 255) / 256)), dim3(256), 0, s, m->params + OW4, S->Bdeg,
-                       S->Bgrd);
+                       S->Bgrd, S->Bgrd2);
     WP_HIP(hipMemcpyAsync(S->b4, m->params + OB4, NOUT * 4, hipMemcpyDeviceToDevice, s));
     if (hipMalloc((void **)&S->wmax, 8) != hipSuccess) return fail(WP_ENOMEM, "weight bounds");
     WP_HIP(hipMemsetAsync(S->wmax, 0, 8, s));
@@ -884,13 +1122,27 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
         WP_HIP(hipMemcpyAsync(ckey.data(), S->cell_key, 4 * (size_t)h_nc, hipMemcpyDeviceToHost, s));
         WP_HIP(hipMemcpyAsync(cstart.data(), S->cell_start, 4 * (size_t)(h_nc + 1), hipMemcpyDeviceToHost, s));
         WP_HIP(hipStreamSynchronize(s));
-        std::vector<int> gd, ga;
-        std::vector<int2> go;
+        std::vector<int> gd, ga, gg;
+        std::vector<int2> go, ggo;
         int vmin = 0, vmax = 0, umin = 0, umax = 0;
+        int gvmin = 0, gvmax = 0, gumin = 0, gumax = 0;
         for (int c = 0; c < h_nc; ++c) {
             if (c % DG == 0) gd.push_back(c);
             int cv, cu;
             demorton2(ckey[c], cv, cu);
+            // ring gridding: <= DG consecutive cells spanning at most GSPAN rows and GSPAN columns
+            const bool gfits = !gg.empty() && c - gg.back() < DG &&
+                               std::max(gvmax, cv) - std::min(gvmin, cv) < GSPAN &&
+                               std::max(gumax, cu) - std::min(gumin, cu) < GSPAN;
+            if (gfits) {
+                gvmin = std::min(gvmin, cv); gvmax = std::max(gvmax, cv);
+                gumin = std::min(gumin, cu); gumax = std::max(gumax, cu);
+            } else {
+                if (!gg.empty()) ggo.push_back(make_int2(gvmin, gumin));
+                gg.push_back(c);
+                gvmin = gvmax = cv;
+                gumin = gumax = cu;
+            }
             const bool fits = !ga.empty() && c - ga.back() < AG && std::max(vmax, cv) - std::min(vmin, cv) <= WV - BOX &&
                               std::max(umax, cu) - std::min(umin, cu) <= WU - BOX;
             if (fits) {
@@ -904,23 +1156,33 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
             }
         }
         go.push_back(make_int2(vmin - BOX / 2, umin - BOX / 2));
+        ggo.push_back(make_int2(gvmin, gumin));
         gd.push_back(h_nc);
         ga.push_back(h_nc);
+        gg.push_back(h_nc);
         S->ngrp_d = (int)gd.size() - 1;
         S->ngrp_a = (int)ga.size() - 1;
+        S->ngrp_g = (int)gg.size() - 1;
         if (hipMalloc((void **)&S->grp_d, 4 * gd.size()) != hipSuccess ||
             hipMalloc((void **)&S->grp_a, 4 * ga.size()) != hipSuccess ||
-            hipMalloc((void **)&S->grp_org, sizeof(int2) * go.size()) != hipSuccess)
+            hipMalloc((void **)&S->grp_org, sizeof(int2) * go.size()) != hipSuccess ||
+            hipMalloc((void **)&S->grp_g, 4 * gg.size()) != hipSuccess ||
+            hipMalloc((void **)&S->grp_gorg, sizeof(int2) * ggo.size()) != hipSuccess)
             return fail(WP_ENOMEM, "groups");
         WP_HIP(hipMemcpyAsync(S->grp_d, gd.data(), 4 * gd.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipMemcpyAsync(S->grp_a, ga.data(), 4 * ga.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipMemcpyAsync(S->grp_org, go.data(), sizeof(int2) * go.size(), hipMemcpyHostToDevice, s));
+        WP_HIP(hipMemcpyAsync(S->grp_g, gg.data(), 4 * gg.size(), hipMemcpyHostToDevice, s));
+        WP_HIP(hipMemcpyAsync(S->grp_gorg, ggo.data(), sizeof(int2) * ggo.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipStreamSynchronize(s));
         // last hidden layer of every surrogate row, in slot order
         if (hipMalloc((void **)&S->h3, (size_t)Ms * H * 2) != hipSuccess) return fail(WP_ENOMEM, "hidden features");
-        // the degridding's bfloat16 copy of the grid, with wrapped columns
+        // the degridding's bfloat16 copy of the grid, with wrapped columns; the ring gridding's per-cell s
         if (hipMalloc((void **)&S->gbf, (size_t)p->Ng * (p->Ng + 2 * PADC) * 4) != hipSuccess)
             return fail(WP_ENOMEM, "bfloat16 grid");
+        if (hipMalloc((void **)&S->Sg, (size_t)h_nc * ND * 2) != hipSuccess ||
+            hipMalloc((void **)&S->cY, (size_t)h_nc * sizeof(float4)) != hipSuccess)
+            return fail(WP_ENOMEM, "per-cell s");
         for (int64_t j0 = 0; j0 < Ms; j0 += m->max_batch) {
             const int n = (int)std::min<int64_t>(m->max_batch, Ms - j0);
             hipLaunchKernelGGL(k_feat_slots, dim3((3 * n + 255) / 256), dim3(256), 0, s, (const float *)feat.p,
@@ -945,7 +1207,7 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
 wp_status wp_surrogate_destroy(wp_surrogate *S) {
     if (!S) return WP_OK;
     void *bufs[] = {S->slot_vis, S->cell_key, S->cell_start, S->grp_d, S->grp_a, S->grp_org, S->h3, S->Bdeg,
-                    S->Bgrd, S->b4, S->wmax, S->fb, S->gbf};
+                    S->Bgrd, S->b4, S->wmax, S->fb, S->gbf, S->Bgrd2, S->Sg, S->cY, S->grp_g, S->grp_gorg};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     free(S);

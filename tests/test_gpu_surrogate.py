@@ -135,6 +135,32 @@ def test_grid_add_matches_oracle_with_exact_cell_sums(setup):
     sur.close()
 
 
+def test_grid_forms_agree(setup):
+    """The LDS-ring gridding (form 2, the default: per-cell s in bfloat16, then 8 slices of 256 outputs
+    per group of <= 128 cells) against the register-staged one (form 1, groups of <= 32 cells): the
+    same bfloat16 products, summed in other groups, so they differ by the 32-bit fixed-point
+    quantisation of each window (2^-22 of a group's largest output bound per contribution) and FP32
+    rounding."""
+    d = setup
+    plan = d["plan"]
+    sur = W.Surrogate(plan, d["mlp"], _dev(d["u"]), _dev(d["v"]), _dev(d["w"]))
+    Ng = d["s"].Ng
+    rng = np.random.default_rng(31)
+    yy = _dev((rng.normal(size=d["M"]) + 1j * rng.normal(size=d["M"])).astype(np.complex64))
+    out = {}
+    try:
+        for form in (1, 2):
+            plan.set_tuning("sur_grid", form)
+            g = torch.zeros(Ng * Ng, dtype=torch.complex64, device="cuda")
+            out[form] = sur.grid_add(yy, g).cpu().numpy()
+    finally:
+        plan.set_tuning("sur_grid", 0)
+    g1, g2 = out[1], out[2]
+    assert np.linalg.norm(g1 - g2) <= 1e-5 * np.linalg.norm(g1)
+    assert np.max(np.abs(g1 - g2)) <= 1e-4 * np.max(np.abs(g1))
+    sur.close()
+
+
 def _fallback_setup(d, every=5):
     eps = np.zeros(d["M"], dtype=np.float32)
     eps[::every] = 1.0                  # these rows fail the check
