@@ -77,7 +77,7 @@ struct wp_surrogate {
     uint16_t *Sg;       // [ncell][ND] s of each cell in bfloat16, rewritten by every gridding
     float4 *cY;         // [ncell] (sum of y re, sum of y im, bound on the cell's outputs / s_out, 0)
     int *grp_g;         // [ngrp_g + 1] first cell of each ring-gridding group
-    int2 *grp_gorg;     // [ngrp_g] smallest (v, u) of each ring-gridding group's cells
+    int4 *grp_gorg;     // [ngrp_g] smallest (v, u) of each ring-gridding group's cells, and its (v, u) spans
     int ngrp_g;
 };
 
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(256) void k_sur_cell_s(const float2 *__restrict__ y
 // atomics.  The eight slices of a group are consecutive blocks on one XCD, so they share its s in L2.
 __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__restrict__ Sg,
                                                           const float4 *__restrict__ cY, int logNg,
-                                                          const int *__restrict__ grp, const int2 *__restrict__ org,
+                                                          const int *__restrict__ grp, const int4 *__restrict__ org,
                                                           int ngrp, const int *__restrict__ cell_key,
                                                           const uint16_t *__restrict__ Bgrd2,
                                                           const float *__restrict__ b4, float s_out,
@@ -839,30 +839,13 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     __shared__ __align__(16) unsigned char ring[3 * STG];
     __shared__ int s_woff[DG];
     __shared__ float2 s_Y[DG];
-    __shared__ int s_gmax;
+    __shared__ float s_gm[DG / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 2, wn = wave & 3;
     const int lb = (int)xcd_block(blockIdx.x, (int64_t)ngrp * NSL);
     const int g = lb / NSL, sl = lb % NSL;
     const int c0 = grp[g], nc = grp[g + 1] - c0;
-    const int2 o0 = org[g];                          // smallest (v, u) of the group's cells
     const int Ng = 1 << logNg;
-    if (tid == 0) s_gmax = 0;
-    __syncthreads();
-    for (int i = tid; i < DG; i += DNT) {
-        int woff = 0;
-        float2 Yi = make_float2(0.f, 0.f);
-        if (i < nc) {
-            int cv, cu;
-            demorton2(cell_key[c0 + i], cv, cu);
-            woff = (cv - o0.x) * GWC + (cu - o0.y);
-            const float4 cy = cY[c0 + i];
-            Yi = make_float2(cy.x, cy.y);
-            atomicMax(&s_gmax, __float_as_int(cy.z));    // non-negative floats order like their bit patterns
-        }
-        s_woff[i] = woff;
-        s_Y[i] = Yi;
-    }
     // this lane's pieces: A row ra (a cell of the group; rows past it repeat the last cell, unused), B rows rb0, rb1
     const int ra = 16 * wave + (lane >> 2), rb0 = 32 * wave + (lane >> 2), rb1 = rb0 + 16;
     const int ca = swz(ra, lane & 3), cb0 = swz(rb0, lane & 3), cb1 = swz(rb1, lane & 3);
@@ -885,6 +868,29 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
         __builtin_amdgcn_global_load_lds((const void *)(gBt + b_off1), lds_dst(st + RA + (32 * wave + 16) * 64), 16,
                                          0, 0);
     };
+    // the first two stages go out first; the group's cells, needed only after the products, load into
+    // registers while they land (no barrier before the loop)
+    issue(0, ic<0>{});
+    issue(1, ic<1>{});
+    int ckey = 0;
+    float4 cy = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < nc && tid < DG) {
+        ckey = cell_key[c0 + tid];
+        cy = cY[c0 + tid];
+    }
+    const int4 o0 = org[g];                          // smallest (v, u) of the group's cells, their spans
+    // this lane's two outputs (one per fn): window offset within a cell's box rows, component, bias weights
+    int wo[2], comp[2];
+    float br[2], bi[2];
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn) {
+        const int oo = 256 * sl + 64 * wn + 32 * fn + (lane & 31);
+        const int p = oo >> 1;
+        comp[fn] = oo & 1;
+        wo[fn] = ((p >> 5) - 4 * sl) * GWC + (p & (BOX - 1));
+        br[fn] = b4[2 * p];
+        bi[fn] = b4[2 * p + 1];
+    }
     f32x16 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -903,8 +909,6 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
         const unsigned char *st = stage(sc);
         mma_ring<2, 2>(acc, st, st + RA, 64 * wm, 64 * wn, lane);
     };
-    issue(0, ic<0>{});
-    issue(1, ic<1>{});
     for (int t = 0; t < NSTEP - 1; t += 3) {
         step(t, ic<0>{});
         step(t + 1, ic<1>{});
@@ -912,49 +916,56 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     }
     step(NSTEP - 1, ic<0>{});
     __syncthreads();                                 // the ring becomes the window
+    static_assert(DG <= DNT && DG % 64 == 0, "one thread per cell of the group");
+    if (tid < DG) {
+        int woff = 0;
+        if (tid < nc) {
+            int cv, cu;
+            demorton2(ckey, cv, cu);
+            woff = (cv - o0.x) * GWC + (cu - o0.y);
+        }
+        s_woff[tid] = woff;
+        s_Y[tid] = make_float2(cy.x, cy.y);
+        float m = cy.z;                              // the cells' largest bound (zero past the group)
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if (lane == 0) s_gm[tid >> 6] = m;
+    }
     int2 *win = (int2 *)ring;                        // [GWR][GWC] fixed point (re, im)
     static_assert((size_t)GWR * GWC * 8 <= 3 * (size_t)STG, "window must fit the ring");
-    for (int e = tid; e < GWR * GWC; e += DNT) win[e] = make_int2(0, 0);
+    // only the rows and columns the group's boxes reach: (span_v + 4) x (span_u + 32)
+    const int wr = o0.z + 4, wc = o0.w + BOX, wn_el = wr * wc;
+    for (int e = tid; e < wn_el; e += DNT) win[(e / wc) * GWC + e % wc] = make_int2(0, 0);
+    __syncthreads();
     // the scale: at most DG cells reach one window cell, each by at most the group's largest bound, so
     // every sum stays within 2^29 < 2^31
-    const float gmax = __int_as_float(s_gmax);
+    float gmax = s_gm[0];
+#pragma unroll
+    for (int w2 = 1; w2 < DG / 64; ++w2) gmax = fmaxf(gmax, s_gm[w2]);
     const float q = gmax > 0.f ? 536870912.0f / (gmax * s_out * (float)DG) : 1.0f;
     const float qs = q * s_out;
-    // this lane's two outputs (one per fn): window offset within a cell's box rows, component, bias weights
-    int wo[2], comp[2];
-    float br[2], bi[2];
-#pragma unroll
-    for (int fn = 0; fn < 2; ++fn) {
-        const int oo = 256 * sl + 64 * wn + 32 * fn + (lane & 31);
-        const int p = oo >> 1;
-        comp[fn] = oo & 1;
-        wo[fn] = ((p >> 5) - 4 * sl) * GWC + (p & (BOX - 1));
-        br[fn] = b4[2 * p];
-        bi[fn] = b4[2 * p + 1];
-    }
-    __syncthreads();
 #pragma unroll
     for (int fm = 0; fm < 2; ++fm)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int i = 64 * wm + 32 * fm + acc_row(r, lane);
             if (i < nc) {
-                const int wc = s_woff[i];
+                const int woff = s_woff[i];
                 const float2 Y = s_Y[i];
 #pragma unroll
                 for (int fn = 0; fn < 2; ++fn) {
                     const float bias = comp[fn] == 0 ? br[fn] * Y.x + bi[fn] * Y.y : br[fn] * Y.y - bi[fn] * Y.x;
-                    atomicAdd((int *)&win[wc + wo[fn]] + comp[fn], __float2int_rn(qs * (acc[fm][fn][r] + bias)));
+                    atomicAdd((int *)&win[woff + wo[fn]] + comp[fn], __float2int_rn(qs * (acc[fm][fn][r] + bias)));
                 }
             }
         }
     __syncthreads();
     const float iq = 1.0f / q;
     const int gv0 = o0.x - BOX / 2 + 4 * sl, gu0 = o0.y - BOX / 2;
-    for (int e = tid; e < GWR * GWC; e += DNT) {
-        const int2 wi = win[e];
+    for (int e = tid; e < wn_el; e += DNT) {
+        const int ry = e / wc, rx = e % wc;
+        const int2 wi = win[ry * GWC + rx];
         if (wi.x != 0 || wi.y != 0) {
-            const int gy = (gv0 + e / GWC) & (Ng - 1), gx = (gu0 + e % GWC) & (Ng - 1);
+            const int gy = (gv0 + ry) & (Ng - 1), gx = (gu0 + rx) & (Ng - 1);
             float *dst = (float *)&grid[(int64_t)gy * Ng + gx];
             atomicAdd(dst, (float)wi.x * iq);
             atomicAdd(dst + 1, (float)wi.y * iq);
@@ -1124,7 +1135,8 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
         WP_HIP(hipMemcpyAsync(cstart.data(), S->cell_start, 4 * (size_t)(h_nc + 1), hipMemcpyDeviceToHost, s));
         WP_HIP(hipStreamSynchronize(s));
         std::vector<int> gd, ga, gg;
-        std::vector<int2> go, ggo;
+        std::vector<int2> go;
+        std::vector<int4> ggo;
         int vmin = 0, vmax = 0, umin = 0, umax = 0;
         int gvmin = 0, gvmax = 0, gumin = 0, gumax = 0;
         for (int c = 0; c < h_nc; ++c) {
@@ -1139,7 +1151,7 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
                 gvmin = std::min(gvmin, cv); gvmax = std::max(gvmax, cv);
                 gumin = std::min(gumin, cu); gumax = std::max(gumax, cu);
             } else {
-                if (!gg.empty()) ggo.push_back(make_int2(gvmin, gumin));
+                if (!gg.empty()) ggo.push_back(make_int4(gvmin, gumin, gvmax - gvmin, gumax - gumin));
                 gg.push_back(c);
                 gvmin = gvmax = cv;
                 gumin = gumax = cu;
@@ -1157,7 +1169,7 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
             }
         }
         go.push_back(make_int2(vmin - BOX / 2, umin - BOX / 2));
-        ggo.push_back(make_int2(gvmin, gumin));
+        ggo.push_back(make_int4(gvmin, gumin, gvmax - gvmin, gumax - gumin));
         gd.push_back(h_nc);
         ga.push_back(h_nc);
         gg.push_back(h_nc);
@@ -1168,13 +1180,13 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
             hipMalloc((void **)&S->grp_a, 4 * ga.size()) != hipSuccess ||
             hipMalloc((void **)&S->grp_org, sizeof(int2) * go.size()) != hipSuccess ||
             hipMalloc((void **)&S->grp_g, 4 * gg.size()) != hipSuccess ||
-            hipMalloc((void **)&S->grp_gorg, sizeof(int2) * ggo.size()) != hipSuccess)
+            hipMalloc((void **)&S->grp_gorg, sizeof(int4) * ggo.size()) != hipSuccess)
             return fail(WP_ENOMEM, "groups");
         WP_HIP(hipMemcpyAsync(S->grp_d, gd.data(), 4 * gd.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipMemcpyAsync(S->grp_a, ga.data(), 4 * ga.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipMemcpyAsync(S->grp_org, go.data(), sizeof(int2) * go.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipMemcpyAsync(S->grp_g, gg.data(), 4 * gg.size(), hipMemcpyHostToDevice, s));
-        WP_HIP(hipMemcpyAsync(S->grp_gorg, ggo.data(), sizeof(int2) * ggo.size(), hipMemcpyHostToDevice, s));
+        WP_HIP(hipMemcpyAsync(S->grp_gorg, ggo.data(), sizeof(int4) * ggo.size(), hipMemcpyHostToDevice, s));
         WP_HIP(hipStreamSynchronize(s));
         // last hidden layer of every surrogate row, in slot order
         if (hipMalloc((void **)&S->h3, (size_t)Ms * H * 2) != hipSuccess) return fail(WP_ENOMEM, "hidden features");
