@@ -144,7 +144,9 @@ wp_status wp_plan_destroy(wp_plan *plan);
  * loads in flight per lane: 4, 8 or 16 (not every pair exists: an apply with
  * an unavailable pair returns WP_EINVAL); the gather knobs apply to the form
  * without a block table.  "solve_graph": 1 replays the primal-dual loop of wp_solve from a captured
- * HIP graph, 0 (automatic) or 2 launches its kernels one by one.  "exact_rows": how the exact chirp's
+ * HIP graph, 0 (automatic) or 2 launches its kernels one by one.  "solve_streams": 2 runs the
+ * wavelet analysis and most of the synthesis of each iteration on a second stream of the plan,
+ * ordered by events, 0 (automatic) or 1 keeps one stream.  "exact_rows": how the exact chirp's
  * rows are made: 1 from the separable expansion at any Ng, 2 whole in 2-D (Ng <= 512), 0 automatic
  * (whole up to Ng = 512, the expansion above).  "gather_chunk": entries a wavefront of the blocked
  * gather stages at a time (256, 512, 768 or 1024); "gather_block_entries": the entry

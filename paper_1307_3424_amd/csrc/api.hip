@@ -166,6 +166,12 @@ wp_status wp_plan_create(wp_plan **out, int N, double fov_L, int kb_W, double kb
 
 wp_status wp_plan_destroy(wp_plan *p) {
     if (!p) return WP_OK;
+    if (p->aux_stream) {
+        (void)hipStreamSynchronize(p->aux_stream);
+        (void)hipStreamDestroy(p->aux_stream);
+        for (hipEvent_t e : p->aux_ev)
+            if (e) (void)hipEventDestroy(e);
+    }
     if (p->apod) (void)hipFree(p->apod);
     if (p->tw32) (void)hipFree(p->tw32);
     if (p->tw64) (void)hipFree(p->tw64);
@@ -201,6 +207,11 @@ wp_status wp_plan_set_tuning(wp_plan *p, const char *key, int value) {
     if (!std::strcmp(key, "exact_rows")) {
         if (value < 0 || value > 2) return wp_set_error(WP_EINVAL, "exact_rows %d: 0, 1 or 2", value);
         p->exact_rows = value;
+        return WP_OK;
+    }
+    if (!std::strcmp(key, "solve_streams")) {
+        if (value < 0 || value > 2) return wp_set_error(WP_EINVAL, "solve_streams %d: 0, 1 or 2", value);
+        p->solve_streams = value;
         return WP_OK;
     }
     if (!std::strcmp(key, "solve_graph")) {

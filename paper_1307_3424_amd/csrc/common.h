@@ -36,6 +36,9 @@ struct wp_plan {
     int exact_rows;                       // exact chirp rows: 0 automatic, 1 separable expansion, 2 whole 2-D
     int sur_degrid;                       // surrogate degridding: 0 automatic (2), 1 register-staged, 2 LDS ring
     int sur_grid;                         // surrogate gridding: 0 automatic (2), 1 register-staged, 2 LDS ring
+    int solve_streams;                    // solver loop with wavelets: 0 automatic (1), 1 one stream, 2 two streams
+    hipStream_t aux_stream;               // the solver's second stream (made on first use, default priority)
+    hipEvent_t aux_ev[3];                 // its events
     float *apod;    // [N]  1 / g(xi), xi = (p - N/2) / Ng       (device)
     float2 *tw32;   // [Ng] exp(-2 pi i k / Ng), FP32             (device)
     double2 *tw64;  // [Ng] exp(-2 pi i k / Ng), FP64             (device)

@@ -183,6 +183,28 @@ def test_solve_plain_form_matches_oracle_snr():
     assert np.all(xg >= 0)
 
 
+def test_solve_two_streams_match_one():
+    """With wavelets the loop can run on two streams (the analysis of xb and the next synthesis up to
+    its last level beside Phi xb, the ball step and Phi^H v2): the same kernels on the same buffers in
+    an order the events fix, so the iterates equal the one-stream loop's; twice in a row, with eager
+    work on the caller's stream in between."""
+    wl, x, u, v, w, s, A, AH, y, eps, x0 = _tiny_problem()
+    plan = wp.Plan(wl.N, wl.L)
+    G = wp.build_G(plan, dev(u), dev(v), dev(w), wl.E)
+    yd = c64(y)
+    nu = solver.power_norm2(A, AH, x0, 50)
+    plan.set_tuning("solve_streams", 1)
+    ref = wp.solve(plan, G, yd, eps, nu, 40, levels=4).cpu().numpy()
+    plan.set_tuning("solve_streams", 2)
+    for rep in range(2):
+        got = wp.solve(plan, G, yd, eps, nu, 40, levels=4).cpu().numpy()
+        assert relerr(got, ref) < 1e-6, rep
+        wp.apply_Phi(plan, G, c64(x))
+        torch.cuda.synchronize()
+    x_ref = solver.solve(y, A, AH, (wl.N, wl.N), eps, nu, 40, levels=4)
+    assert relerr(ref.reshape(wl.N, wl.N), x_ref) < 1e-4
+
+
 @pytest.mark.parametrize("levels", [4, 0])
 def test_solve_graph_replays_match_direct_launches(levels):
     """The solver loop replayed from a captured HIP graph (chunks of 10 iterations) against the same
@@ -194,6 +216,7 @@ def test_solve_graph_replays_match_direct_launches(levels):
     yd = c64(y)
     nu = solver.power_norm2(A, AH, x0, 50)
     plan.set_tuning("solve_graph", 2)
+    plan.set_tuning("solve_streams", 1)              # the graph captures the one-stream loop
     ref = wp.solve(plan, G, yd, eps, nu, 35, levels=levels).cpu().numpy()
     plan.set_tuning("solve_graph", 1)
     for rep in range(3):
