@@ -129,15 +129,19 @@ SOURCES = {"spmv": ("spmv.hip", "gather_block.h"), "surrogate": ("surrogate.hip"
 
 
 def source_hash(kind="spmv"):
-    """First 16 hex digits of the SHA-256 of the kernels' sources: traffic counters stay valid while these
-    files are unchanged."""
+    """First 16 hex digits of the SHA-256 of the kernels' code (comments removed, whitespace runs
+    collapsed): traffic counters stay valid while the code of these files is unchanged."""
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1307_3424_amd", "csrc")
     for f in SOURCES[kind]:
         path = os.path.join(csrc, f)
         if os.path.exists(path):
-            h.update(open(path, "rb").read())
+            code = open(path, encoding="utf-8").read()
+            code = re.sub(r"/\*.*?\*/", " ", code, flags=re.S)
+            code = re.sub(r"//[^\n]*", " ", code)
+            h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

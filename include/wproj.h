@@ -467,13 +467,15 @@ typedef struct wp_surrogate wp_surrogate;
  * network's current parameters).  eps (device float32 [M], caller order, may be NULL: no
  * fallback) are the per-row energy errors; rows with eps > tol or eps not a number fall back.
  * *Mf_out (host, may be NULL) receives the number of fallback rows.  Allocates device
- * memory owned by the object; synchronises. */
+ * memory owned by the object (512 B per surrogate row for its hidden layer, 1040 B per
+ * occupied cell for the gridding's per-cell sums, Ng (Ng + 32) 4 B for the degridding's
+ * bfloat16 grid copy, 6 MB of weights); synchronises. */
 wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *plan, wp_mlp *mlp, int64_t M,
                               const double *u, const double *v, const double *w, const float *eps,
                               double tol, int64_t *Mf_out, void *stream);
 wp_status wp_surrogate_destroy(wp_surrogate *sur);
 /* info5 (host): M, Ms (surrogate rows), Mf (fallback rows), occupied cells,
- * (degridding groups << 32) | gridding groups. */
+ * (degridding groups << 32) | groups of the register-staged gridding. */
 wp_status wp_surrogate_info(const wp_surrogate *sur, int64_t *info5);
 /* slot_vis[r] = caller index of slot r (device int32 [M]). */
 wp_status wp_surrogate_slots(const wp_surrogate *sur, int *slot_vis, void *stream);

@@ -11,10 +11,11 @@
 //           r_c[j] = sum_p (W4[2p][j] + i W4[2p+1][j]) X(c + p),  beta_c = sum_p b4_p X(c + p);
 //   grid    sum_{k in c} conj(t_k(p)) y_k = s_out (sum_j (W4[2p][j] - i W4[2p+1][j]) s_c[j] + conj(b4_p) Y_c),
 //           s_c[j] = sum_{k in c} h_kj y_k,  Y_c = sum_{k in c} y_k.
-// r is one dense product per group of cells, [cells x 2048 box values] x [2048 x 512], and
-// the box contributions one per 8 x 8 tile of cells, [cells x 512] x [512 x 2048], both on
-// bfloat16 MFMA with FP32 accumulation.  The hidden layers run once, at set-up.  The taps
-// are never stored.
+// r is one dense product per group of up to 128 cells, [cells x 2048 box values] x [2048 x 512]
+// (as two workgroups of 256 outputs), and the box contributions one per group and slice of 256
+// outputs, [cells x 512] x [512 x 256] (the default forms; the register-staged gridding takes groups
+// of up to 32 cells and all 2048 outputs), both on bfloat16 MFMA with FP32 accumulation.  The
+// hidden layers run once, at set-up.  The taps are never stored.
 //
 // Visibility order ("slots"): slots [0, Ms) hold the surrogate rows sorted by the Z-order
 // code of their nearest cell; slots [Ms, M) the fallback rows in the caller's order, which
