@@ -458,6 +458,9 @@ wp_status wp_mlp_row_check(const wp_plan *plan, wp_mlp *mlp, int nw, int nd, con
  * of their nearest cell; slots [Ms, M) the fallback rows, in the order of the coordinates
  * that wp_surrogate_fallback_coords returns.  The fallback G must be built from exactly those
  * coordinates; its own G.order then decides the order within [Ms, M).
+ * The object holds the products' workspaces (the degridding's bfloat16 grid copy, the
+ * gridding's per-cell sums): its applies on different streams that overlap in time race on
+ * them, so use one object per stream (calls in order on one stream are safe).
  * ------------------------------------------------------------------------------------- */
 typedef struct wp_surrogate wp_surrogate;
 
