@@ -26,6 +26,7 @@
 // adjoint work list sizes; pass 2 (fill) recomputes the row factors and writes
 // the taps.
 #include <cfloat>
+#include <climits>
 #include <cstdio>
 
 #include "builder_exact.h"
@@ -570,7 +571,99 @@ __global__ void k_t_fill(const int64_t *__restrict__ rowptr, const int *__restri
     (void)perm;
 }
 
-// order each cell's entries by sorted row index (shell sort, one thread per cell)
+// order each cell's entries by sorted row index: a bitonic sort of (row, position) pairs in LDS, then
+// the values moved with their rows (a row has at most one entry per cell, so the keys are distinct
+// and the order is unique).  Cells of at most TS_CAP entries take one wavefront each, cells of up to
+// TS_BIG one workgroup each, longer cells a thread each (shell sort in global memory).
+constexpr int TS_CAP = 1024, TS_BIG = 4096;
+
+// sort one cell's n entries (1 < n <= CAP) in LDS with the NT threads of a group; sync() orders the
+// group's LDS accesses
+template <typename TapT, int CAP, int NT, typename Sync>
+__device__ inline void sort_cell(int64_t b, int n, int lt, int *key, unsigned short *pos, TapT *val,
+                                 int *__restrict__ trow, TapT *__restrict__ tval, Sync sync) {
+    int P = 2;
+    while (P < n) P <<= 1;
+    for (int i = lt; i < P; i += NT) {
+        key[i] = i < n ? trow[b + i] : INT_MAX;  // padding sorts last
+        pos[i] = (unsigned short)i;
+        if (i < n) val[i] = tval[b + i];
+    }
+    sync();
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lt; i < P; i += NT) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const int k0 = key[i], k1 = key[ixj];
+                    if ((i & k) == 0 ? (k0 > k1) : (k0 < k1)) {
+                        key[i] = k1;
+                        key[ixj] = k0;
+                        const unsigned short p0 = pos[i];
+                        pos[i] = pos[ixj];
+                        pos[ixj] = p0;
+                    }
+                }
+            }
+            sync();
+        }
+    }
+    for (int i = lt; i < n; i += NT) {
+        trow[b + i] = key[i];
+        tval[b + i] = val[pos[i]];
+    }
+}
+
+__global__ void k_zero_int(int *p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+// cells of at most TS_CAP entries: one wavefront each, four per workgroup; cells of TS_CAP + 1 ..
+// TS_BIG entries are appended to big[] (count in *nbig) for k_t_sort_big
+template <typename TapT>
+__global__ __launch_bounds__(256) void k_t_sort_small(const int64_t *__restrict__ tcolptr, int64_t cells,
+                                                      int *__restrict__ trow, TapT *__restrict__ tval,
+                                                      int *__restrict__ big, int *__restrict__ nbig) {
+    __shared__ int s_key[4][TS_CAP];
+    __shared__ unsigned short s_pos[4][TS_CAP];
+    __shared__ TapT s_val[4][TS_CAP];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t c = (int64_t)blockIdx.x * 4 + wv;
+    if (c >= cells) return;                      // per wavefront: nothing below syncs the workgroup
+    const int64_t b = tcolptr[c];
+    const int n = (int)(tcolptr[c + 1] - b);
+    if (n > TS_CAP) {
+        if (n <= TS_BIG && lane == 0) big[atomicAdd(nbig, 1)] = (int)c;
+        return;
+    }
+    if (n <= 1) return;
+    sort_cell<TapT, TS_CAP, 64>(b, n, lane, s_key[wv], s_pos[wv], s_val[wv], trow, tval, [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    });
+}
+
+// the listed cells of TS_CAP + 1 .. TS_BIG entries: one workgroup per cell (workgroups loop over the list)
+template <typename TapT>
+__global__ __launch_bounds__(256) void k_t_sort_big(const int64_t *__restrict__ tcolptr, const int *__restrict__ big,
+                                                    const int *__restrict__ nbig, int *__restrict__ trow,
+                                                    TapT *__restrict__ tval) {
+    __shared__ int s_key[TS_BIG];
+    __shared__ unsigned short s_pos[TS_BIG];
+    __shared__ TapT s_val[TS_BIG];
+    const int nb = *nbig;
+    for (int q = blockIdx.x; q < nb; q += gridDim.x) {
+        const int64_t c = big[q];
+        const int64_t b = tcolptr[c];
+        const int n = (int)(tcolptr[c + 1] - b);
+        sort_cell<TapT, TS_BIG, 256>(b, n, threadIdx.x, s_key, s_pos, s_val, trow, tval, [] { __syncthreads(); });
+        __syncthreads();                         // the next cell reuses the arrays
+    }
+}
+
+// the same order for the cells the LDS sorts leave (more than TS_BIG entries): shell sort, one
+// thread per cell
 template <typename TapT>
 __global__ void k_t_sort(const int64_t *__restrict__ tcolptr, int64_t cells, int *__restrict__ trow,
                          TapT *__restrict__ tval) {
@@ -578,6 +671,7 @@ __global__ void k_t_sort(const int64_t *__restrict__ tcolptr, int64_t cells, int
     if (c >= cells) return;
     const int64_t b = tcolptr[c];
     const int n = (int)(tcolptr[c + 1] - b);
+    if (n <= TS_BIG) return;
     int *kr = trow + b;
     TapT *kv = tval + b;
     int gap = 1;
@@ -1033,12 +1127,25 @@ wp_status launch_build_fill(const wp_plan *p, int64_t M, const double *u, const 
             hipLaunchKernelGGL((k_t_fill<float2>), gR, dim3(nthr), 0, s, G->rowptr, G->col, (const float2 *)G->val,
                                G->perm, M, G->tcolptr, cnt, G->trow, (float2 *)G->tval);
         const dim3 gC((unsigned)((cells + nthr - 1) / nthr));
-        if (G->taps != WP_TAPS_C64)
+        // cnt (free again after the fill) lists the cells of TS_CAP + 1 .. TS_BIG entries, counted in gpos[0]
+        int *nbig = (int *)(ws + L.gpos);
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, nbig, 1);
+        const dim3 gS((unsigned)((cells + 3) / 4)), gB(1024);
+        if (G->taps != WP_TAPS_C64) {
+            hipLaunchKernelGGL((k_t_sort_small<uint32_t>), gS, dim3(256), 0, s, G->tcolptr, cells, G->trow,
+                               (uint32_t *)G->tval, cnt, nbig);
+            hipLaunchKernelGGL((k_t_sort_big<uint32_t>), gB, dim3(256), 0, s, G->tcolptr, cnt, nbig, G->trow,
+                               (uint32_t *)G->tval);
             hipLaunchKernelGGL((k_t_sort<uint32_t>), gC, dim3(nthr), 0, s, G->tcolptr, cells, G->trow,
                                (uint32_t *)G->tval);
-        else
+        } else {
+            hipLaunchKernelGGL((k_t_sort_small<float2>), gS, dim3(256), 0, s, G->tcolptr, cells, G->trow,
+                               (float2 *)G->tval, cnt, nbig);
+            hipLaunchKernelGGL((k_t_sort_big<float2>), gB, dim3(256), 0, s, G->tcolptr, cnt, nbig, G->trow,
+                               (float2 *)G->tval);
             hipLaunchKernelGGL((k_t_sort<float2>), gC, dim3(nthr), 0, s, G->tcolptr, cells, G->trow,
                                (float2 *)G->tval);
+        }
         if ((st = wp_check_launch("build_G_fill transpose")) != WP_OK) return st;
         if (G->tblk) {
             // cnt (free again) holds the block-start flags; their scan gives each block's index

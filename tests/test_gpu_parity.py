@@ -241,24 +241,45 @@ def test_gather_with_crowded_cells():
     assert np.all(Xg[X_ref == 0] == 0)             # empty cells are written as zeros
 
 
-def test_transposed_copy_structure():
-    wl = synth.workload(1)
-    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
-    plan = wp.Plan(wl.N, wl.L)
-    G = build(plan, u, v, w, wl.E)
+def _check_transposed_copy(G, M, Ng):
     rp, col, val, perm, inv = gpu_rows(G)
     tcp = G.tcolptr.cpu().numpy()
     trow = G.trow.cpu().numpy()[:G.nnz]
     tval = G.tval.cpu().numpy()[:G.nnz]
     assert tcp[0] == 0 and tcp[-1] == G.nnz and np.all(np.diff(tcp) >= 0)
     # same (row, cell, value) triples as the rows, each cell's entries ordered by sorted row
-    rows_of = np.repeat(np.arange(wl.M), np.diff(rp))
+    rows_of = np.repeat(np.arange(M), np.diff(rp))
     a = np.lexsort((rows_of, col))
     cells_t = np.repeat(np.arange(tcp.size - 1), np.diff(tcp))
     assert np.array_equal(col[a], cells_t)
     assert np.array_equal(rows_of[a], trow)
     assert np.array_equal(val[a], tval)
-    assert np.array_equal(G.tblk.cpu().numpy(), gather_table_model(tcp, wl.Ng ** 2))
+    assert np.array_equal(G.tblk.cpu().numpy(), gather_table_model(tcp, Ng ** 2))
+    return np.diff(tcp)
+
+
+def test_transposed_copy_structure():
+    wl = synth.workload(1)
+    _, u, v, w = synth.workload_inputs(wl, with_sky=False)
+    plan = wp.Plan(wl.N, wl.L)
+    G = build(plan, u, v, w, wl.E)
+    _check_transposed_copy(G, wl.M, wl.Ng)
+
+
+def test_transposed_copy_crowded_cells():
+    """Cells of up to 2500 entries (the builder sorts cells of more than 1024 entries by another
+    path than the rest) keep the same structure."""
+    wl = synth.workload(0)
+    N, M = wl.N, 2500
+    rng = np.random.default_rng(41)
+    cell = 1.0 / (2 * wl.L)
+    u = 3.2 * cell + rng.uniform(-0.3, 0.3, M) * cell
+    v = -5.7 * cell + rng.uniform(-0.3, 0.3, M) * cell
+    w = rng.uniform(0, synth.configs.w_for_support(8, 4, wl.L), M)
+    plan = wp.Plan(N, wl.L)
+    G = build(plan, u, v, w, 0.99)
+    lengths = _check_transposed_copy(G, M, 2 * N)
+    assert lengths.max() > 1024 and np.any((lengths > 1) & (lengths <= 1024))
 
 
 def test_phi_plain_form_sampled_rows():
