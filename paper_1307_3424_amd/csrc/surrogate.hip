@@ -365,7 +365,7 @@ constexpr int PADC = 16;
 constexpr int RA = DG * 64, RB = DBN * 64;              // bytes of a stage: A rows, B rows
 constexpr int STG = RA + RB;
 constexpr int RPASS2 = 64;                              // cells per epilogue pass
-static_assert((size_t)RPASS2 * RLD * 4 + (2 * DG + 1) * 4 <= 3 * (size_t)STG, "epilogue must fit the ring");
+static_assert((size_t)RPASS2 * RLD * 4 + (6 * DG + 1) * 4 <= 3 * (size_t)STG, "epilogue must fit the ring");
 static_assert((KDEP / BK) % 3 == 1, "the step loop runs in threes plus one");
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -434,11 +434,9 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid_ring(const uint32_t *__re
                                                             const float *__restrict__ b4, float s_out,
                                                             float2 *__restrict__ y) {
     __shared__ __align__(16) unsigned char ring[3 * STG];
-    __shared__ float2 s_b4[BOX * BOX];               // output bias
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 2, wn = wave & 3;
     const int part = blockIdx.y;
-    for (int i = tid; i < BOX * BOX; i += DNT) s_b4[i] = ((const float2 *)b4)[i];
     const int g = (int)xcd_block(blockIdx.x, ngrp);
     const int c0 = grp[g], nc = grp[g + 1] - c0;
     const int Ng = 1 << logNg, RS = Ng + 2 * PADC;
@@ -479,11 +477,12 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid_ring(const uint32_t *__re
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    // bias term of each cell: thread -> cell si, one 16-byte chunk (4 box cells) of the step's 16
-    const int si = tid >> 2, sq = tid & 3;
+    // bias term of each cell: thread -> cell si, one 16-byte chunk sq (4 box cells) of the step's 16; the
+    // chunk is the same over a wave, so its four output biases are scalar loads
+    const int si = tid & (DG - 1), sq = wave >> 1;
+    static_assert(DNT == 4 * DG, "four chunks per cell");
     float bacc = 0.0f;
     constexpr int NSTEP = KDEP / BK;
-    __syncthreads();                                 // s_b4
     auto step = [&](int t, auto sc) {
         constexpr int S = decltype(sc)::value;
         if (t + 1 < NSTEP) wait_vm_lgkm0<3>(); else wait_vm_lgkm0<0>();
@@ -493,12 +492,12 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid_ring(const uint32_t *__re
         const unsigned char *st = stage(sc);
         {
             const u32x4 a = *(const u32x4 *)(st + si * 64 + swz(si, sq) * 16);
-            const int p0 = 16 * t + 4 * sq;
+            const float *bq = b4 + 2 * (16 * t + 4 * sq);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const float xr = __uint_as_float(a[e] << 16), xi = __uint_as_float(a[e] & 0xffff0000u);
-                const float2 bb = s_b4[p0 + e];
-                bacc += part == 0 ? bb.x * xr - bb.y * xi : bb.x * xi + bb.y * xr;
+                const float br = bq[2 * e], bim = bq[2 * e + 1];
+                bacc += part == 0 ? br * xr - bim * xi : br * xi + bim * xr;
             }
         }
         mma_ring<2, 2>(acc, st, st + RA, 64 * wm, 64 * wn, lane);
@@ -515,10 +514,11 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid_ring(const uint32_t *__re
     float *Rl = (float *)ring;                       // [RPASS2][RLD] FP32
     int *s_cs = (int *)(ring + RPASS2 * RLD * 4);
     float *s_beta = (float *)(s_cs + DG + 1);
+    float *s_bp = s_beta + DG;                       // [4][DG] the chunks' partial sums
     for (int i = tid; i <= nc; i += DNT) s_cs[i] = cell_start[c0 + i];
-    bacc += __shfl_xor(bacc, 1);
-    bacc += __shfl_xor(bacc, 2);
-    if (sq == 0) s_beta[si] = bacc;
+    s_bp[sq * DG + si] = bacc;
+    __syncthreads();
+    if (tid < DG) s_beta[tid] = (s_bp[tid] + s_bp[DG + tid]) + (s_bp[2 * DG + tid] + s_bp[3 * DG + tid]);
     const int lg = wave * 4 + (lane >> 4), lj = lane & 15;   // 32 groups of 16 lanes; lane lj of its group
     for (int pass = 0; pass < DG / RPASS2; ++pass) {
         const int c_lo = RPASS2 * pass;
@@ -838,8 +838,8 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
                                                           const float *__restrict__ b4, float s_out,
                                                           float2 *__restrict__ grid) {
     __shared__ __align__(16) unsigned char ring[3 * STG];
-    __shared__ int s_woff[DG];
-    __shared__ float2 s_Y[DG];
+    __shared__ __align__(16) int s_woff[DG];
+    __shared__ __align__(16) float2 s_Y[DG];
     __shared__ float s_gm[DG / 64];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 2, wn = wave & 3;
@@ -944,18 +944,24 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     for (int w2 = 1; w2 < DG / 64; ++w2) gmax = fmaxf(gmax, s_gm[w2]);
     const float q = gmax > 0.f ? 536870912.0f / (gmax * s_out * (float)DG) : 1.0f;
     const float qs = q * s_out;
+    // a lane's rows come in fours (registers 4 r4 .. 4 r4 + 3 hold rows i0 .. i0 + 3): one 16-byte read of
+    // their window offsets and two of their sums of y; rows past the group add zero at offset 0
 #pragma unroll
     for (int fm = 0; fm < 2; ++fm)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = 64 * wm + 32 * fm + acc_row(r, lane);
-            if (i < nc) {
-                const int woff = s_woff[i];
-                const float2 Y = s_Y[i];
+        for (int r4 = 0; r4 < 4; ++r4) {
+            const int i0 = 64 * wm + 32 * fm + acc_row(4 * r4, lane);
+            const int4 wf = *(const int4 *)&s_woff[i0];
+            const float4 ya = *(const float4 *)&s_Y[i0], yb = *(const float4 *)&s_Y[i0 + 2];
+            const int wv[4] = {wf.x, wf.y, wf.z, wf.w};
+            const float yr[4] = {ya.x, ya.z, yb.x, yb.z}, yi[4] = {ya.y, ya.w, yb.y, yb.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float qe = i0 + e < nc ? qs : 0.0f;      // finite sums times zero: a zero add, no branch
 #pragma unroll
                 for (int fn = 0; fn < 2; ++fn) {
-                    const float bias = comp[fn] == 0 ? br[fn] * Y.x + bi[fn] * Y.y : br[fn] * Y.y - bi[fn] * Y.x;
-                    atomicAdd((int *)&win[woff + wo[fn]] + comp[fn], __float2int_rn(qs * (acc[fm][fn][r] + bias)));
+                    const float bias = comp[fn] == 0 ? br[fn] * yr[e] + bi[fn] * yi[e] : br[fn] * yi[e] - bi[fn] * yr[e];
+                    atomicAdd((int *)&win[wv[e] + wo[fn]] + comp[fn], __float2int_rn(qe * (acc[fm][fn][4 * r4 + e] + bias)));
                 }
             }
         }
