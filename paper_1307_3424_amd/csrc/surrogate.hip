@@ -21,6 +21,7 @@
 // code of their nearest cell; slots [Ms, M) the fallback rows in the caller's order, which
 // is the order of the coordinates wp_surrogate_fallback_coords returns (build the fallback
 // G from those, in caller order, or keep its sorted order consistently).
+#include <climits>
 #include <cmath>
 #include <type_traits>
 #include <vector>
@@ -535,6 +536,14 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid_ring(const uint32_t *__re
         }
         __syncthreads();
         const int vb = s_cs[c_lo], ve = s_cs[c_hi];
+        // the cell of visibility v is c_lo plus the number of the pass's later cells starting at or before
+        // v: lane lj holds the starts of cells c_lo + 1 + 4 lj .. + 3 (past the pass: never at or before v)
+        int cs4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = c_lo + 1 + 4 * lj + k;
+            cs4[k] = c < c_hi ? s_cs[c] : INT_MAX;
+        }
         // visibilities v0 = vb + lg + 64 i and v0 + 32: hidden units 8 lj .. 8 lj + 7 and 128 + 8 lj .. + 7
         for (int v0 = vb + lg; v0 < ve; v0 += 64) {
             const int v1 = v0 + 32;
@@ -546,12 +555,8 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_degrid_ring(const uint32_t *__re
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const int v = q == 0 ? v0 : (ok1 ? v1 : v0);
-                int lo = c_lo, hi = c_hi - 1;        // cell of visibility v
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (s_cs[mid] <= v) lo = mid; else hi = mid - 1;
-                }
-                cl[q] = lo;
+                const int n = (cs4[0] <= v) + (cs4[1] <= v) + (cs4[2] <= v) + (cs4[3] <= v);
+                cl[q] = c_lo + (int)dpp_sum16((float)n);   // at most 64: exact in FP32
             }
             float sum[2];
 #pragma unroll
