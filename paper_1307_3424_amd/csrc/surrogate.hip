@@ -906,6 +906,9 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
     constexpr int NSTEP = ND / BK;
     static_assert(NSTEP % 3 == 1, "the step loop runs in threes plus one");
+    // a group cut short by its span has fewer than DG cells; the rows past it repeat its last cell, and
+    // a wave none of whose rows holds a cell of the group skips the products
+    const bool busy = 64 * wm < nc;
     auto step = [&](int t, auto sc) {
         constexpr int S = decltype(sc)::value;
         if (t + 1 < NSTEP) wait_vm_lgkm0<3>(); else wait_vm_lgkm0<0>();
@@ -913,7 +916,7 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         if (t + 2 < NSTEP) issue(t + 2, ic<(S + 2) % 3>{});
         const unsigned char *st = stage(sc);
-        mma_ring<2, 2>(acc, st, st + RA, 64 * wm, 64 * wn, lane);
+        if (busy) mma_ring<2, 2>(acc, st, st + RA, 64 * wm, 64 * wn, lane);
     };
     for (int t = 0; t < NSTEP - 1; t += 3) {
         step(t, ic<0>{});
@@ -955,6 +958,7 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     for (int fm = 0; fm < 2; ++fm)
 #pragma unroll
         for (int r4 = 0; r4 < 4; ++r4) {
+            if (64 * wm + 32 * fm + 8 * r4 >= nc) continue;   // no cell of the group in these rows
             const int i0 = 64 * wm + 32 * fm + acc_row(4 * r4, lane);
             const int4 wf = *(const int4 *)&s_woff[i0];
             const float4 ya = *(const float4 *)&s_Y[i0], yb = *(const float4 *)&s_Y[i0 + 2];
