@@ -952,6 +952,14 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     for (int w2 = 1; w2 < DG / 64; ++w2) gmax = fmaxf(gmax, s_gm[w2]);
     const float q = gmax > 0.f ? 536870912.0f / (gmax * s_out * (float)DG) : 1.0f;
     const float qs = q * s_out;
+    // this lane's output of a cell adds the bias ca Re Y + cb Im Y (the real or the imaginary part of
+    // conj(b4) Y, by the lane's component); the coefficients carry the fixed-point scale
+    float caq[2], cbq[2];
+#pragma unroll
+    for (int fn = 0; fn < 2; ++fn) {
+        caq[fn] = (comp[fn] == 0 ? br[fn] : -bi[fn]) * qs;
+        cbq[fn] = (comp[fn] == 0 ? bi[fn] : br[fn]) * qs;
+    }
     // a lane's rows come in fours (registers 4 r4 .. 4 r4 + 3 hold rows i0 .. i0 + 3): one 16-byte read of
     // their window offsets and two of their sums of y; rows past the group add zero at offset 0
 #pragma unroll
@@ -966,11 +974,12 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
             const float yr[4] = {ya.x, ya.z, yb.x, yb.z}, yi[4] = {ya.y, ya.w, yb.y, yb.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float qe = i0 + e < nc ? qs : 0.0f;      // finite sums times zero: a zero add, no branch
+                // rows past the group: Y is zero and the finite sums are scaled by zero, a zero add, no branch
+                const float qe = i0 + e < nc ? qs : 0.0f;
 #pragma unroll
                 for (int fn = 0; fn < 2; ++fn) {
-                    const float bias = comp[fn] == 0 ? br[fn] * yr[e] + bi[fn] * yi[e] : br[fn] * yi[e] - bi[fn] * yr[e];
-                    atomicAdd((int *)&win[wv[e] + wo[fn]] + comp[fn], __float2int_rn(qe * (acc[fm][fn][4 * r4 + e] + bias)));
+                    const float bq = fmaf(caq[fn], yr[e], cbq[fn] * yi[e]);
+                    atomicAdd((int *)&win[wv[e] + wo[fn]] + comp[fn], __float2int_rn(fmaf(acc[fm][fn][4 * r4 + e], qe, bq)));
                 }
             }
         }
