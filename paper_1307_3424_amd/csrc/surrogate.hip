@@ -76,7 +76,8 @@ struct wp_surrogate {
     uint32_t *gbf;      // [Ng][Ng + 2 PADC] the degridding's grid in bfloat16 pairs, columns wrapped by PADC
     // the gridding through the LDS ring
     uint16_t *Bgrd2;    // [NSL][ND / 32][256][32] weights of each slice of 256 outputs, step-major
-    uint16_t *Sg;       // [ncell][ND] s of each cell in bfloat16, rewritten by every gridding
+    uint16_t *Sg;       // [ncell + 1][ND] s of each cell in bfloat16, rewritten by every gridding; the last row
+                        // stays zero (the A rows past a group of the ring gridding)
     float4 *cY;         // [ncell] (sum of y re, sum of y im, bound on the cell's outputs / s_out, 0)
     int *grp_g;         // [ngrp_g + 1] first cell of each ring-gridding group
     int4 *grp_gorg;     // [ngrp_g] smallest (v, u) of each ring-gridding group's cells, and its (v, u) spans
@@ -835,7 +836,7 @@ __global__ __launch_bounds__(256) void k_sur_cell_s(const float2 *__restrict__ y
 // the degridding (16 steps of 32), then added in 32-bit fixed point into an LDS window over the ring
 // (the slice's box rows of every cell: (span + 4) x (span + 32) cells) and flushed to the grid with
 // atomics.  The eight slices of a group are consecutive blocks on one XCD, so they share its s in L2.
-__global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__restrict__ Sg,
+__global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__restrict__ Sg, int zrow,
                                                           const float4 *__restrict__ cY, int logNg,
                                                           const int *__restrict__ grp, const int4 *__restrict__ org,
                                                           int ngrp, const int *__restrict__ cell_key,
@@ -852,10 +853,10 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     const int g = lb / NSL, sl = lb % NSL;
     const int c0 = grp[g], nc = grp[g + 1] - c0;
     const int Ng = 1 << logNg;
-    // this lane's pieces: A row ra (a cell of the group; rows past it repeat the last cell, unused), B rows rb0, rb1
+    // this lane's pieces: A row ra (a cell of the group; rows past it read the zero row zrow), B rows rb0, rb1
     const int ra = 16 * wave + (lane >> 2), rb0 = 32 * wave + (lane >> 2), rb1 = rb0 + 16;
     const int ca = swz(ra, lane & 3), cb0 = swz(rb0, lane & 3), cb1 = swz(rb1, lane & 3);
-    const char *arow = (const char *)(Sg + (int64_t)(c0 + min(ra, nc - 1)) * ND) + 16 * ca;
+    const char *arow = (const char *)(Sg + (int64_t)(ra < nc ? c0 + ra : zrow) * ND) + 16 * ca;
     const char *gB = (const char *)(Bgrd2 + (int64_t)sl * 256 * ND);     // [step][256][32]
     const uint32_t b_off0 = 2u * (uint32_t)(rb0 * 32 + 8 * cb0), b_off1 = 2u * (uint32_t)(rb1 * 32 + 8 * cb1);
     auto stage = [&](auto sc) -> unsigned char * {
@@ -933,7 +934,7 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
             demorton2(ckey, cv, cu);
             woff = (cv - o0.x) * GWC + (cu - o0.y);
         }
-        s_woff[tid] = woff;
+        s_woff[tid] = 8 * woff;                      // bytes
         s_Y[tid] = make_float2(cy.x, cy.y);
         float m = cy.z;                              // the cells' largest bound (zero past the group)
         for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
@@ -953,15 +954,20 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     const float q = gmax > 0.f ? 536870912.0f / (gmax * s_out * (float)DG) : 1.0f;
     const float qs = q * s_out;
     // this lane's output of a cell adds the bias ca Re Y + cb Im Y (the real or the imaginary part of
-    // conj(b4) Y, by the lane's component); the coefficients carry the fixed-point scale
+    // conj(b4) Y, by the lane's component); the coefficients carry the fixed-point scale.  Its byte
+    // offset within a cell's place in the window: wob.
     float caq[2], cbq[2];
+    int wob[2];
 #pragma unroll
     for (int fn = 0; fn < 2; ++fn) {
         caq[fn] = (comp[fn] == 0 ? br[fn] : -bi[fn]) * qs;
         cbq[fn] = (comp[fn] == 0 ? bi[fn] : br[fn]) * qs;
+        wob[fn] = 8 * wo[fn] + 4 * comp[fn];
     }
     // a lane's rows come in fours (registers 4 r4 .. 4 r4 + 3 hold rows i0 .. i0 + 3): one 16-byte read of
-    // their window offsets and two of their sums of y; rows past the group add zero at offset 0
+    // their window offsets and two of their sums of y.  Rows past the group (products of the zero row,
+    // Y zero) add zero at offset 0.
+    char *winb = (char *)win;
 #pragma unroll
     for (int fm = 0; fm < 2; ++fm)
 #pragma unroll
@@ -973,15 +979,12 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
             const int wv[4] = {wf.x, wf.y, wf.z, wf.w};
             const float yr[4] = {ya.x, ya.z, yb.x, yb.z}, yi[4] = {ya.y, ya.w, yb.y, yb.w};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                // rows past the group: Y is zero and the finite sums are scaled by zero, a zero add, no branch
-                const float qe = i0 + e < nc ? qs : 0.0f;
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
                 for (int fn = 0; fn < 2; ++fn) {
                     const float bq = fmaf(caq[fn], yr[e], cbq[fn] * yi[e]);
-                    atomicAdd((int *)&win[wv[e] + wo[fn]] + comp[fn], __float2int_rn(fmaf(acc[fm][fn][4 * r4 + e], qe, bq)));
+                    atomicAdd((int *)(winb + wv[e] + wob[fn]), __float2int_rn(fmaf(acc[fm][fn][4 * r4 + e], qs, bq)));
                 }
-            }
         }
     __syncthreads();
     const float iq = 1.0f / q;
@@ -1028,7 +1031,8 @@ wp_status sur_grid_add(const wp_plan *p, const wp_surrogate *S, const float2 *y,
                            (int)S->ncell, S->h3, S->wmax, S->Sg, S->cY);
         wp_status st = wp_check_launch("k_sur_cell_s");
         if (st != WP_OK) return st;
-        hipLaunchKernelGGL(k_sur_grid_ring, dim3((unsigned)((int64_t)S->ngrp_g * NSL)), dim3(DNT), 0, s, S->Sg, S->cY,
+        hipLaunchKernelGGL(k_sur_grid_ring, dim3((unsigned)((int64_t)S->ngrp_g * NSL)), dim3(DNT), 0, s, S->Sg,
+                           (int)S->ncell, S->cY,
                            p->logNg, S->grp_g, S->grp_gorg, S->ngrp_g, S->cell_key, S->Bgrd2, S->b4, S->s_out, grid);
         return wp_check_launch("k_sur_grid_ring");
     }
@@ -1218,9 +1222,10 @@ wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *p, wp_mlp *m, i
         // the degridding's bfloat16 copy of the grid, with wrapped columns; the ring gridding's per-cell s
         if (hipMalloc((void **)&S->gbf, (size_t)p->Ng * (p->Ng + 2 * PADC) * 4) != hipSuccess)
             return fail(WP_ENOMEM, "bfloat16 grid");
-        if (hipMalloc((void **)&S->Sg, (size_t)h_nc * ND * 2) != hipSuccess ||
+        if (hipMalloc((void **)&S->Sg, (size_t)(h_nc + 1) * ND * 2) != hipSuccess ||
             hipMalloc((void **)&S->cY, (size_t)h_nc * sizeof(float4)) != hipSuccess)
             return fail(WP_ENOMEM, "per-cell s");
+        WP_HIP(hipMemsetAsync(S->Sg + (size_t)h_nc * ND, 0, ND * 2, s));
         for (int64_t j0 = 0; j0 < Ms; j0 += m->max_batch) {
             const int n = (int)std::min<int64_t>(m->max_batch, Ms - j0);
             hipLaunchKernelGGL(k_feat_slots, dim3((3 * n + 255) / 256), dim3(256), 0, s, (const float *)feat.p,
