@@ -943,8 +943,10 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     int2 *win = (int2 *)ring;                        // [GWR][GWC] fixed point (re, im)
     static_assert((size_t)GWR * GWC * 8 <= 3 * (size_t)STG, "window must fit the ring");
     // only the rows and columns the group's boxes reach: (span_v + 4) x (span_u + 32)
-    const int wr = o0.z + 4, wc = o0.w + BOX, wn_el = wr * wc;
-    for (int e = tid; e < wn_el; e += DNT) win[(e / wc) * GWC + e % wc] = make_int2(0, 0);
+    // a wave per window row, a lane per column
+    const int wr = o0.z + 4, wc = o0.w + BOX;
+    for (int ry = wave; ry < wr; ry += DNT / 64)
+        for (int rx = lane; rx < wc; rx += 64) win[ry * GWC + rx] = make_int2(0, 0);
     __syncthreads();
     // the scale: at most DG cells reach one window cell, each by at most the group's largest bound, so
     // every sum stays within 2^29 < 2^31
@@ -989,16 +991,16 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
     __syncthreads();
     const float iq = 1.0f / q;
     const int gv0 = o0.x - BOX / 2 + 4 * sl, gu0 = o0.y - BOX / 2;
-    for (int e = tid; e < wn_el; e += DNT) {
-        const int ry = e / wc, rx = e % wc;
-        const int2 wi = win[ry * GWC + rx];
-        if (wi.x != 0 || wi.y != 0) {
-            const int gy = (gv0 + ry) & (Ng - 1), gx = (gu0 + rx) & (Ng - 1);
-            float *dst = (float *)&grid[(int64_t)gy * Ng + gx];
-            atomicAdd(dst, (float)wi.x * iq);
-            atomicAdd(dst + 1, (float)wi.y * iq);
+    for (int ry = wave; ry < wr; ry += DNT / 64)
+        for (int rx = lane; rx < wc; rx += 64) {
+            const int2 wi = win[ry * GWC + rx];
+            if (wi.x != 0 || wi.y != 0) {
+                const int gy = (gv0 + ry) & (Ng - 1), gx = (gu0 + rx) & (Ng - 1);
+                float *dst = (float *)&grid[(int64_t)gy * Ng + gx];
+                atomicAdd(dst, (float)wi.x * iq);
+                atomicAdd(dst + 1, (float)wi.y * iq);
+            }
         }
-    }
 }
 
 wp_status check_sur(const wp_plan *p, const wp_surrogate *s) {
