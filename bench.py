@@ -755,7 +755,7 @@ def bench_surrogate(args, wl):
     gb = gather_bytes(G, wl.M, plan.Ng, 8)
     deg_kernel = "k_degrid_sep" if G.use_factors else "k_degrid"
     # hidden layers, per-cell s and sums, the bfloat16 grid copy, the fallback rows' G, the check table
-    sur_bytes = (sur.Ms * 512 + sur.ncell * (1024 + 16) + plan.Ng * (plan.Ng + 32) * 4 +
+    sur_bytes = (sur.Ms * 512 + (sur.ncell + 1) * 1024 + sur.ncell * 16 + plan.Ng * (plan.Ng + 32) * 4 +
                  (Gf.nbytes() if Gf is not None else 0) + table.numel() * 4)
     out = {
         "metric": METRIC,

@@ -471,8 +471,8 @@ typedef struct wp_surrogate wp_surrogate;
  * fallback) are the per-row energy errors; rows with eps > tol or eps not a number fall back.
  * *Mf_out (host, may be NULL) receives the number of fallback rows.  Allocates device
  * memory owned by the object (512 B per surrogate row for its hidden layer, 1040 B per
- * occupied cell for the gridding's per-cell sums, Ng (Ng + 32) 4 B for the degridding's
- * bfloat16 grid copy, 6 MB of weights); synchronises. */
+ * occupied cell for the gridding's per-cell sums and 1 KB more, Ng (Ng + 32) 4 B for the
+ * degridding's bfloat16 grid copy, 6 MB of weights); synchronises. */
 wp_status wp_surrogate_create(wp_surrogate **out, const wp_plan *plan, wp_mlp *mlp, int64_t M,
                               const double *u, const double *v, const double *w, const float *eps,
                               double tol, int64_t *Mf_out, void *stream);

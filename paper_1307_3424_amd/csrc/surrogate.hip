@@ -907,8 +907,8 @@ __global__ __launch_bounds__(DNT, 4) void k_sur_grid_ring(const uint16_t *__rest
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
     constexpr int NSTEP = ND / BK;
     static_assert(NSTEP % 3 == 1, "the step loop runs in threes plus one");
-    // a group cut short by its span has fewer than DG cells; the rows past it repeat its last cell, and
-    // a wave none of whose rows holds a cell of the group skips the products
+    // a group cut short by its span has fewer than DG cells; the rows past it read the zero row, and a
+    // wave none of whose rows holds a cell of the group skips the products
     const bool busy = 64 * wm < nc;
     auto step = [&](int t, auto sc) {
         constexpr int S = decltype(sc)::value;
