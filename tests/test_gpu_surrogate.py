@@ -161,6 +161,46 @@ def test_grid_forms_agree(setup):
     sur.close()
 
 
+def test_grid_short_groups_match_oracle(setup):
+    """Sparse visibilities only (uniform over the band, few per cell): the default gridding's groups
+    are cut short by their span, so most hold far fewer than 128 cells.  Their row blocks past the
+    group read the zero row of the per-cell s and waves with no cell of the group skip the products;
+    the sums must still match the oracle's rows and the register-staged form."""
+    d = setup
+    plan = d["plan"]
+    M = 400
+    L, u, v, w, _ = _coords(M, d["N"], 41, frac_dense=0.0)
+    sur = W.Surrogate(plan, d["mlp"], _dev(u), _dev(v), _dev(w))
+    slot = sur.slots().cpu().numpy()
+    cu, _ = S.nearest_cell(u * 2 * L)
+    cv, _ = S.nearest_cell(v * 2 * L)
+    _, first = np.unique(cv * 100000 + cu, return_index=True)
+    assert first.size > 300            # mostly one visibility per cell: sparse cells, short groups
+    rng = np.random.default_rng(42)
+    yc = np.zeros(M, dtype=np.complex128)
+    yc[first] = rng.choice([-2.0, -1.0, 1.0, 2.0], first.size) + 1j * rng.choice([-2.0, -1.0, 1.0, 2.0], first.size)
+    y_slot = _dev(yc[slot].astype(np.complex64))
+    Ng = d["s"].Ng
+    out = {}
+    try:
+        for form in (1, 2):
+            plan.set_tuning("sur_grid", form)
+            g = torch.zeros(Ng * Ng, dtype=torch.complex64, device="cuda")
+            out[form] = sur.grid_add(y_slot, g).cpu().numpy()
+    finally:
+        plan.set_tuning("sur_grid", 0)
+    cols, t = S.surrogate_rows(d["net"], u, v, w, d["s"], q=S.round_bf16)
+    ref = np.zeros(Ng * Ng, dtype=np.complex128)
+    np.add.at(ref, cols.ravel(), (np.conj(t) * yc[:, None]).ravel())
+    got = out[2]
+    assert np.linalg.norm(got - ref) <= 5e-4 * np.linalg.norm(ref)
+    assert np.max(np.abs(got - ref)) <= 5e-3 * np.max(np.abs(ref))
+    assert np.linalg.norm(out[1] - got) <= 1e-5 * np.linalg.norm(out[1])
+    # nothing outside the union of the rows' boxes
+    assert np.all(got[np.setdiff1d(np.arange(Ng * Ng), np.unique(cols))] == 0)
+    sur.close()
+
+
 def _fallback_setup(d, every=5):
     eps = np.zeros(d["M"], dtype=np.float32)
     eps[::every] = 1.0                  # these rows fail the check
