@@ -750,10 +750,10 @@ def bench_surrogate(args, wl):
     dom = (("k_sur_cell_s", "k_sur_grid_ring"), "gridding, k_sur_cell_s + k_sur_grid_ring", grd_tf, ms_sgrid) \
         if ms_sgrid >= ms_sdeg else (("k_grid_bf16_pad", "k_sur_degrid_ring"),
                                      "degridding, k_grid_bf16_pad + k_sur_degrid_ring", deg_tf, ms_sdeg)
+    tag = wl.name
     # HBM bytes of the timed pair of kernels (both counted, as the launch time counts both)
     dom_tr = [profiled_traffic(tag, k, "surrogate") for k in dom[0]]
     dom_traffic = sum(dom_tr) if all(v is not None for v in dom_tr) else None
-    tag = wl.name
     db = factor_degrid_bytes(G, wl.M, plan.Ng) if G.use_factors else degrid_bytes(G, wl.M, plan.Ng, 8)
     gb = gather_bytes(G, wl.M, plan.Ng, 8)
     deg_kernel = "k_degrid_sep" if G.use_factors else "k_degrid"
