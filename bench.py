@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--channels", type=int, default=0, help="batched form: first K channels only (0: all)")
     ap.add_argument("--train-epochs", type=int, default=300, help="surrogate form: training passes")
     ap.add_argument("--tol", type=float, default=1e-3, help="surrogate form: per-row energy error tolerance")
+    ap.add_argument("--pixels", type=int, default=0,
+                    help="surrogate form: image side N instead of the workload's (the same M visibilities on a "
+                         "smaller image: more of them per grid cell)")
     ap.add_argument("--check-nw", type=int, default=257, help="surrogate form: check lattice nodes along w")
     ap.add_argument("--check-nd", type=int, default=33, help="surrogate form: check lattice nodes per offset axis")
     ap.add_argument("--save-params", default=None,
@@ -917,6 +920,11 @@ def main():
         sys.exit(2)
     import synth
     wl = synth.workload(args.workload)
+    if args.pixels:
+        if not wl.train_samples or args.pixels < 64 or args.pixels & (args.pixels - 1):
+            print(json.dumps({"error": "--pixels takes a power of two >= 64 and only the surrogate form"}))
+            sys.exit(2)
+        wl = wl.scaled(N=args.pixels, name=f"{wl.name}-at-{args.pixels}px")
     if wl.channels is not None:
         out = bench_batched(args, wl)
     elif wl.train_samples:
