@@ -1,5 +1,6 @@
 """Host logic of bench.py (CPU only): the one-GPU guard and the algorithmic byte counts behind the
 roofline figures."""
+import ast as _ast
 import os
 import subprocess
 import sys
@@ -69,3 +70,54 @@ def test_traffic_is_reported_only_for_the_profiled_source(tmp_path, monkeypatch)
     (prof / "traffic_surrogate-2048.md").write_text(f"surrogate_source_sha256_16={hs}\ntraffic_bytes.k_sur_grid=99\n")
     assert bench.profiled_traffic("surrogate-2048", "k_sur_grid", "surrogate") == 99.0
     assert bench.profiled_traffic("surrogate-2048", "k_sur_grid") is None
+
+
+# ---- a nested scope (comprehension, lambda, inner function) that reads a name its enclosing
+# function binds only on a later line raises NameError when it runs; the timed GPU runs reach such
+# lines only at their end, so the benchmark's and the binding's sources are checked here
+
+_NESTED = (_ast.ListComp, _ast.SetComp, _ast.DictComp, _ast.GeneratorExp, _ast.Lambda, _ast.FunctionDef,
+           _ast.AsyncFunctionDef)
+
+
+def _late_free_reads(src):
+    out = []
+    for fn in _ast.walk(_ast.parse(src)):
+        if not isinstance(fn, (_ast.FunctionDef, _ast.AsyncFunctionDef)):
+            continue
+        own, nested, stack = [], [], list(_ast.iter_child_nodes(fn))
+        while stack:
+            n = stack.pop()
+            if isinstance(n, _NESTED):
+                nested.append(n)
+                continue
+            own.append(n)
+            stack.extend(_ast.iter_child_nodes(n))
+        first = {}
+        for n in own:
+            if isinstance(n, _ast.Name) and isinstance(n.ctx, _ast.Store):
+                first[n.id] = min(first.get(n.id, n.lineno), n.lineno)
+        params = {a.arg for a in _ast.walk(fn.args) if isinstance(a, _ast.arg)}
+        for sc in nested:
+            inner = {n.id for n in _ast.walk(sc) if isinstance(n, _ast.Name) and isinstance(n.ctx, _ast.Store)}
+            inner |= {a.arg for a in _ast.walk(sc) if isinstance(a, _ast.arg)}
+            for n in _ast.walk(sc):
+                if (isinstance(n, _ast.Name) and isinstance(n.ctx, _ast.Load) and n.id in first
+                        and n.id not in inner and n.id not in params and first[n.id] > sc.lineno):
+                    out.append((fn.name, n.id, n.lineno))
+    return out
+
+
+def test_late_free_read_check_catches_the_pattern():
+    bad = "def f():\n    xs = [t + k for k in (1, 2)]\n    t = 3\n    return xs\n"
+    good = "def f():\n    t = 3\n    xs = [t + k for k in (1, 2)]\n    return xs\n"
+    assert _late_free_reads(bad) == [("f", "t", 2)]
+    assert _late_free_reads(good) == []
+
+
+def test_no_late_free_reads_in_benchmark_and_binding():
+    import glob
+    files = [os.path.join(ROOT, "bench.py"), os.path.join(ROOT, "__graft_entry__.py")]
+    files += sorted(glob.glob(os.path.join(ROOT, "paper_1307_3424_amd", "*.py")))
+    for f in files:
+        assert _late_free_reads(open(f).read()) == [], f
